@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (numpy Gauss-Legendre, scipy spherical harmonics), a closed form
+(sphere identities, Hadamard-Rybczynski, Marangoni), an invariant (round trip,
+unitarity, Minkowski), a value the paper prints (double-layer identity,
+Sec. 2.3.1), or brute force on small inputs (resample-and-evaluate rotation).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial.legendre import leggauss
+from scipy.special import sph_harm_y
+
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def const_field(orc, p, e):
+    c = np.zeros((3, orc.ncoef(p), 2))
+    c[:, 0, 0] = np.asarray(e) * np.sqrt(4 * np.pi)
+    return c
+
+
+def random_field(rng, p, ncomp=None):
+    shape = (orc_ncoef(p), 2) if ncomp is None else (ncomp, orc_ncoef(p), 2)
+    c = rng.standard_normal(shape)
+    idx0 = [n * (n + 1) // 2 for n in range(p + 1)]
+    c[..., idx0, 1] = 0.0           # m = 0 real
+    c[..., p * (p + 1) // 2 + p, 1] = 0.0   # Im at m = p not grid-representable
+    return c
+
+
+def orc_ncoef(p):
+    return (p + 1) * (p + 2) // 2
+
+
+def grid(q):
+    t, w = leggauss(q + 1)
+    th = np.arccos(t[::-1])
+    ph = np.pi * np.arange(2 * q) / q
+    return th, ph
+
+
+def scipy_synth(c, p, th, ph):
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    f = np.zeros(TH.shape)
+    for n in range(p + 1):
+        for m in range(n + 1):
+            y = sph_harm_y(n, m, TH, PH)
+            a = c[n * (n + 1) // 2 + m, 0] + 1j * c[n * (n + 1) // 2 + m, 1]
+            f += (1.0 if m == 0 else 2.0) * (a * y).real
+    return f
+
+
+# --- grid, Legendre functions, transforms ------------------------------------
+
+@pytest.mark.parametrize("q", [1, 2, 8, 16, 33, 48, 96])
+def test_gauss_legendre_vs_numpy(orc, q):
+    t, w = orc.gauss_legendre(q)
+    tr, wr = leggauss(q + 1)
+    assert np.allclose(t, tr[::-1], atol=1e-14, rtol=0)
+    assert np.allclose(w, wr[::-1], atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("t", [0.93, 0.2, -0.61])
+def test_legendre_vs_scipy(orc, t):
+    nmax = 24
+    P = orc.legendre(nmax, t)
+    th = np.arccos(t)
+    for n in range(nmax + 1):
+        for m in range(n + 1):
+            ref = sph_harm_y(n, m, th, 0.0).real
+            assert abs(P[n * (n + 1) // 2 + m] - ref) < 1e-13 * max(1.0, abs(ref)), (n, m)
+
+
+def test_legendre_theta_derivatives_vs_finite_difference(orc):
+    nmax = 12
+    for th in [0.3, 1.1, 2.6]:
+        P, D1, D2 = orc.legendre_dtheta(nmax, np.cos(th))
+        h = 1e-3   # fourth-order central differences
+        F = {s: orc.legendre(nmax, np.cos(th + s * h)) for s in (-2, -1, 1, 2)}
+        fd1 = (-F[2] + 8 * F[1] - 8 * F[-1] + F[-2]) / (12 * h)
+        fd2 = (-F[2] + 16 * F[1] - 30 * P + 16 * F[-1] - F[-2]) / (12 * h * h)
+        assert np.abs(D1 - fd1).max() < 1e-8
+        assert np.abs(D2 - fd2).max() < 1e-6
+
+
+@pytest.mark.parametrize("p", [5, 12])
+def test_synthesis_vs_scipy_basis(orc, p):
+    rng = np.random.default_rng(11)
+    c = random_field(rng, p)
+    th, ph = grid(p)
+    assert np.abs(orc.synth(p, c, p) - scipy_synth(c, p, th, ph)).max() < 1e-12
+    # on a finer grid too (zero padding)
+    th2, ph2 = grid(2 * p)
+    assert np.abs(orc.synth(p, c, 2 * p) - scipy_synth(c, p, th2, ph2)).max() < 1e-12
+
+
+def test_synthesis_derivatives_vs_finite_difference(orc):
+    p = 7
+    rng = np.random.default_rng(12)
+    c = random_field(rng, p)
+    th, ph = grid(p)
+    h = 1e-5
+    for (dt, dp) in [(1, 0), (0, 1), (1, 1), (2, 0), (0, 2)]:
+        g = orc.synth(p, c, p, dt, dp)
+        for j in [0, 3, p]:
+            for k in [0, 5]:
+                def f(a, b):
+                    return orc.eval_point(p, c, a, b)
+                a, b = th[j], ph[k]
+                if (dt, dp) == (1, 0):
+                    fd = (f(a + h, b) - f(a - h, b)) / (2 * h)
+                elif (dt, dp) == (0, 1):
+                    fd = (f(a, b + h) - f(a, b - h)) / (2 * h)
+                elif (dt, dp) == (1, 1):
+                    fd = (f(a + h, b + h) - f(a + h, b - h) - f(a - h, b + h) + f(a - h, b - h)) / (4 * h * h)
+                elif (dt, dp) == (2, 0):
+                    fd = (f(a + 1e-3, b) - 2 * f(a, b) + f(a - 1e-3, b)) / 1e-6
+                else:
+                    fd = (f(a, b + 1e-3) - 2 * f(a, b) + f(a, b - 1e-3)) / 1e-6
+                assert abs(g[j, k] - fd) < 2e-5 * max(1.0, abs(fd)), (dt, dp, j, k)
+
+
+@pytest.mark.parametrize("p", [4, 16])
+def test_round_trip_band_limited(orc, p):
+    rng = np.random.default_rng(13)
+    c = random_field(rng, p)
+    g = orc.synth(p, c, p)
+    assert np.abs(orc.analyze(g, p, p) - c).max() < 1e-13
+    # analysis from a finer grid (no Nyquist order there)
+    g2 = orc.synth(p, c, 3 * p)
+    assert np.abs(orc.analyze(g2, 3 * p, p) - c).max() < 1e-13
+
+
+def test_discrete_orthogonality_and_nyquist_half_weight(orc):
+    """Analysis of a single basis function returns it alone (Sec. 2.1); the
+    order m = q recovers Re f_q^q exactly (half weight) and drops Im f_q^q."""
+    p = 6
+    for n in range(p + 1):
+        for m in range(n + 1):
+            c = np.zeros((orc.ncoef(p), 2))
+            c[n * (n + 1) // 2 + m, 0] = 1.0
+            back = orc.analyze(orc.synth(p, c, p), p, p)
+            assert np.abs(back - c).max() < 1e-13, (n, m)
+    c = np.zeros((orc.ncoef(p), 2))
+    c[p * (p + 1) // 2 + p] = [0.7, 0.4]
+    back = orc.analyze(orc.synth(p, c, p), p, p)
+    assert abs(back[p * (p + 1) // 2 + p, 0] - 0.7) < 1e-13
+    assert abs(back[p * (p + 1) // 2 + p, 1]) < 1e-14
+
+
+# --- Wigner d and rotation ---------------------------------------------------
+
+def test_wigner_degree_one_closed_form(orc):
+    b = 0.7
+    d = orc.wigner_d(1, b)
+    c, s = np.cos(b), np.sin(b)
+    r2 = np.sqrt(2.0)
+    ref = np.array([[(1 + c) / 2, s / r2, (1 - c) / 2],
+                    [-s / r2, c, s / r2],
+                    [(1 - c) / 2, -s / r2, (1 + c) / 2]])
+    assert np.abs(d - ref).max() < 1e-15
+
+
+@pytest.mark.parametrize("n", [2, 17, 32, 48])
+def test_wigner_unitarity_and_identity(orc, n):
+    for b in [0.0, 0.4, np.pi / 2, 2.9]:
+        d = orc.wigner_d(n, b)
+        assert np.abs(d @ d.T - np.eye(2 * n + 1)).max() < 1e-13
+        if b == 0.0:
+            assert np.abs(d - np.eye(2 * n + 1)).max() < 1e-15
+        # d_{m'm}(b) = (-1)^{m'-m} d_{mm'}(b)
+        m = np.arange(-n, n + 1)
+        sgn = (-1.0) ** (m[:, None] - m[None, :])
+        assert np.abs(d - sgn * d.T).max() < 1e-13
+
+
+def test_wigner_composition(orc):
+    """d(b1 + b2) = d(b1) d(b2): rotations about one axis compose."""
+    n = 9
+    d1, d2, d12 = orc.wigner_d(n, 0.3), orc.wigner_d(n, 0.9), orc.wigner_d(n, 1.2)
+    assert np.abs(d1 @ d2 - d12).max() < 1e-13
+
+
+def test_rotation_resample_and_evaluate(orc):
+    """Brute force: f'(s) must equal f(R_z(alpha) R_y(beta) s) at arbitrary s."""
+    p = 8
+    rng = np.random.default_rng(14)
+    c = random_field(rng, p)
+    for beta, alpha in [(0.45, 1.3), (2.2, 4.0), (np.pi / 2, 0.0)]:
+        rc = orc.rotate(p, c, beta, alpha)
+        Rz = np.array([[np.cos(alpha), -np.sin(alpha), 0], [np.sin(alpha), np.cos(alpha), 0], [0, 0, 1]])
+        Ry = np.array([[np.cos(beta), 0, np.sin(beta)], [0, 1, 0], [-np.sin(beta), 0, np.cos(beta)]])
+        R = Rz @ Ry
+        for a, b in rng.uniform([0, 0], [np.pi, 2 * np.pi], size=(6, 2)):
+            s = np.array([np.sin(a) * np.cos(b), np.sin(a) * np.sin(b), np.cos(a)])
+            s2 = R @ s
+            a2, b2 = np.arccos(np.clip(s2[2], -1, 1)), np.arctan2(s2[1], s2[0])
+            assert abs(orc.eval_point(p, rc, a, b) - orc.eval_point(p, c, a2, b2)) < 1e-13
+        # the north pole of the rotated field is the original field at (beta, alpha)
+        pole = sum(rc[n * (n + 1) // 2, 0] * np.sqrt((2 * n + 1) / (4 * np.pi)) for n in range(p + 1))
+        assert abs(pole - orc.eval_point(p, c, beta, alpha)) < 1e-13
+
+
+# --- geometry and force ------------------------------------------------------
+
+def test_sphere_geometry(orc):
+    p, R, c0 = 10, 1.7, np.array([0.3, -1.0, 2.0])
+    xc = W.sphere(p, R, c0)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    assert np.abs(K - 1.0 / R).max() < 1e-13
+    assert np.abs(n - (x - c0[:, None]) / R).max() < 1e-13
+    th, ph = grid(p)
+    assert np.abs(Wa - R ** 2 * np.repeat(np.sin(th), 2 * p)).max() < 1e-13
+    assert abs(orc.surface_integral(p, xc, p) - 4 * np.pi * R ** 2) < 1e-12
+    assert abs(orc.volume(p, xc) - 4 / 3 * np.pi * R ** 3) < 1e-12
+
+
+def test_ellipsoid_volume_and_pole_curvature(orc):
+    """Ellipsoid (a, b, c) = linear map of the unit sphere: V = 4/3 pi abc exact;
+    mean curvature at (0, 0, c) is (c/a^2 + c/b^2)/2 (textbook closed form)."""
+    p = 12
+    a, b, c = 1.3, 0.8, 1.9
+    xc = W.sphere(p)
+    xc[0] *= a
+    xc[1] *= b
+    xc[2] *= c
+    assert abs(orc.volume(p, xc, p) - 4 / 3 * np.pi * a * b * c) < 1e-12
+    # north pole via a rotated copy is not needed: the nearest grid latitude
+    # converges; use a fine grid and the first latitude row
+    q = 64
+    x, n, Wa, K = orc.geometry(p, xc, q)
+    th, ph = grid(q)
+    # closed-form mean curvature of the ellipsoid at every node
+    X = x.T
+    g = np.stack([X[:, 0] / a ** 2, X[:, 1] / b ** 2, X[:, 2] / c ** 2], axis=1)
+    gn = np.linalg.norm(g, axis=1)
+    # H = (|x|^2 - a^2 - b^2 - c^2 + ... ) standard: H = (x^2/a^4 (b^2+c^2)... ) use implicit-surface formula
+    A = np.diag([1 / a ** 2, 1 / b ** 2, 1 / c ** 2])
+    Hs = []
+    for gi, ni in zip(g, gn):
+        nn = gi / ni
+        P = np.eye(3) - np.outer(nn, nn)
+        Hs.append(np.trace(P @ A @ P) / (2 * ni))
+    Hs = np.array(Hs)
+    assert np.abs(K - Hs).max() < 1e-10
+    assert np.abs(n.T - g / gn[:, None]).max() < 1e-12
+
+
+def test_minkowski_and_area_on_perturbed_drop(orc):
+    """For any closed surface, int K n dS = 0 (Minkowski); converges with q."""
+    p = 12
+    rng = np.random.default_rng(15)
+    xc = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.05)
+    errs = []
+    for q in [2 * p, 4 * p]:
+        x, n, Wa, K = orc.geometry(p, xc, q)
+        v = [orc.surface_integral(p, xc, q, K * n[c]) for c in range(3)]
+        errs.append(np.abs(v).max())
+    assert errs[1] < 1e-9
+    # area: independent of the grid once resolved
+    a1, a2 = orc.surface_integral(p, xc, 3 * p), orc.surface_integral(p, xc, 5 * p)
+    assert abs(a1 - a2) < 1e-12
+
+
+def test_force_uniform_tension_sphere(orc):
+    p, R = 8, 1.4
+    xc = W.sphere(p, R, (0.5, 0, 0))
+    fc = orc.force(p, xc, None, 0, 0, 0, 1.0, 2)
+    nc = W.sphere(p, 1.0)       # coefficients of the outward normal of a sphere
+    assert np.abs(fc - 2.0 / R * nc).max() < 1e-13
+
+
+def test_force_marangoni_surface_gradient(orc):
+    """sigma = 1 - E xs Gamma with Gamma = e.n on a sphere of radius R:
+    f = 2 sigma n / R - grad sigma with grad sigma = -E xs (I - nn) e / R."""
+    p, R = 8, 1.3
+    c0 = np.array([0.2, 0.1, -0.4])
+    xc = W.sphere(p, R, c0)
+    e = np.array([0.4, -0.3, 0.5])
+    nc = W.sphere(p, 1.0)
+    gc = sum(e[k] * nc[k] for k in range(3))
+    E, xs = 0.7, 0.5
+    fc = orc.force(p, xc, gc, 1, E, xs, 1.0, 2)
+    f = np.stack([orc.synth(p, fc[k], p).ravel() for k in range(3)], axis=1)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    nn = n.T
+    sig = 1 - E * xs * (nn @ e)
+    grad = -E * xs * (e[None, :] - nn * (nn @ e)[:, None]) / R
+    ref = 2 * sig[:, None] * nn / R - grad
+    assert np.abs(f - ref).max() < 1e-12
+    # Langmuir: sigma = 1 + E ln(1 - xs Gamma), d sigma = -E xs dGamma / (1 - xs Gamma).
+    # sigma is not band-limited: compare with the degree-p analysis of the
+    # closed-form force sampled on the same de-aliasing grid (degree 4p).
+    gc2 = gc.copy()
+    gc2[0, 0] += 1.0 * np.sqrt(4 * np.pi)  # Gamma = 1 + e.n > 0
+    ug = 4
+    fc = orc.force(p, xc, gc2, 2, E, xs, 1.0, ug)
+    x, n, Wa, K = orc.geometry(p, xc, ug * p)
+    nn = n.T
+    G = 1 + nn @ e
+    sig = 1 + E * np.log(1 - xs * G)
+    grad = (-E * xs / (1 - xs * G))[:, None] * (e[None, :] - nn * (nn @ e)[:, None]) / R
+    ref = 2 * sig[:, None] * nn / R - grad
+    refc = np.stack([orc.analyze(ref[:, k], ug * p, p) for k in range(3)])
+    assert np.abs(fc - refc).max() < 1e-13
+
+
+# --- singular rule -----------------------------------------------------------
+
+def test_laplace_pole_rule_exact_on_unit_sphere(orc):
+    """Theorem 1 with the Laplace kernel, recovered from the Stokeslet trace
+    (G_kk = 4/r): int Y_l^m(y)/|x0 - y| dS = 4 pi/(2l+1) Y_l^m(x0) on the unit
+    sphere, exactly for band-limited densities."""
+    p = 8
+    xc = W.sphere(p)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    tg = np.arange(0, orc.npts(p), 7)
+    for l in range(p + 1):
+        for m in [0, l // 2, l]:
+            g = np.zeros((orc.ncoef(p), 2))
+            g[l * (l + 1) // 2 + m, 0] = 0.5 if m > 0 else 1.0
+            lap = 0.0
+            for k in range(3):
+                dens = np.zeros((3, orc.ncoef(p), 2))
+                dens[k] = g
+                lap = lap + orc.singular(p, xc, dens, 0, tg)[:, k] / 4.0
+            gv = orc.synth(p, g, p).ravel()[tg]
+            assert np.abs(lap - 4 * np.pi / (2 * l + 1) * gv).max() < 1e-12, (l, m)
+
+
+def test_sphere_single_layer_identities(orc):
+    """On a sphere (radius R, centre c), for x0 on it:
+    int G ds = (16 pi R / 3) I;  int G.n ds = 0;  int G.(Om x n) = (8 pi/3) Om x (x0 - c)."""
+    p, R = 10, 1.3
+    c0 = np.array([0.2, -0.1, 0.3])
+    xc = W.sphere(p, R, c0)
+    e = np.array([0.3, -0.5, 0.8])
+    S = orc.singular(p, xc, const_field(orc, p, e), 0)
+    assert np.abs(S - 16 * np.pi * R / 3 * e).max() < 1e-12
+    S = orc.singular(p, xc, W.sphere(p, 1.0), 0)
+    assert np.abs(S).max() < 1e-12
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    Om = np.array([0.2, 0.7, -0.4])
+    f = np.cross(Om[None, :], n.T)
+    fc = np.stack([orc.analyze(f[:, k], p, p) for k in range(3)])
+    S = orc.singular(p, xc, fc, 0)
+    assert np.abs(S - 8 * np.pi / 3 * np.cross(Om[None, :], x.T - c0)).max() < 1e-12
+
+
+def test_double_layer_identity_paper_values(orc):
+    """Sec. 2.3.1: int T.n ds = 0 / 4 pi / 8 pi outside / on / inside."""
+    gold = json.load(open(os.path.join(GOLD, "dl_identity.json")))
+    p, R = 10, 1.1
+    c0 = np.array([0.1, 0.2, 0.3])
+    xc = W.sphere(p, R, c0)
+    e = np.array([0.6, -0.2, 0.5])
+    dens = const_field(orc, p, e)
+    on = orc.singular(p, xc, dens, 1)
+    assert np.abs(on - gold["on"] * e).max() < 1e-12
+    inside = orc.regular(p, 4 * p, xc, dens, 1, [c0 + 0.1])
+    assert np.abs(inside[0] - gold["inside"] * e).max() < 1e-12
+    outside = orc.regular(p, 4 * p, xc, dens, 1, [c0 + np.array([2.5, 0.3, 0.0])])
+    assert np.abs(outside[0] - gold["outside"] * e).max() < 1e-12
+    # DL of u = n on a sphere: -4 pi n
+    D = orc.singular(p, xc, W.sphere(p, 1.0), 1)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    assert np.abs(D + 4 * np.pi * n.T).max() < 1e-12
+
+
+def test_any_closed_surface_identities_converge(orc):
+    """S[n] = 0 and D[const] = 4 pi const on a perturbed drop, up to quadrature
+    error that falls with the singular grid degree."""
+    p = 8
+    rng = np.random.default_rng(16)
+    xc = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.05)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    ncoef = np.stack([orc.analyze(n[k].reshape(p + 1, 2 * p), p, p) for k in range(3)])
+    tg = np.arange(0, orc.npts(p), 5)
+    e = np.array([0.0, 0.0, 1.0])
+    errs = []
+    for qs in [p, 2 * p, 4 * p]:
+        D = orc.singular(p, xc, const_field(orc, p, e), 1, tg, qs)
+        errs.append(np.abs(D - 4 * np.pi * e).max())
+    assert errs[2] < errs[0] and errs[2] < 1e-6
+    S = orc.singular(p, xc, xc * 0 + ncoef, 0, tg, 4 * p)
+    # n is projected to degree p, so S[n] vanishes only up to that projection
+    assert np.abs(S).max() < 1e-2
+
+
+def test_exterior_single_and_double_layer_of_constant(orc):
+    p, R = 12, 1.3
+    c0 = np.array([0.2, -0.1, 0.3])
+    xc = W.sphere(p, R, c0)
+    e = np.array([0.3, -0.5, 0.8])
+    d = np.array([[3.0, 0.4, -0.2]]) + c0
+    out = orc.regular(p, 4 * p, xc, const_field(orc, p, e), 0, d)
+    dd = d[0] - c0
+    r = np.linalg.norm(dd)
+    G = np.eye(3) / r + np.outer(dd, dd) / r ** 3
+    ex = 4 * np.pi * R ** 2 * G @ e + 4 * np.pi * R ** 4 / 3 * (np.eye(3) / r ** 3 - 3 * np.outer(dd, dd) / r ** 5) @ e
+    assert np.abs(out[0] - ex).max() < 1e-13
+    out = orc.regular(p, 4 * p, xc, const_field(orc, p, e), 1, d)
+    assert np.abs(out).max() < 1e-14
+
+
+def test_regular_rule_converges_with_upsampling(orc):
+    """Two perturbed drops 0.3 apart: the regular rule on grids of degree
+    2p, 4p, 8p converges (Sec. 2.3, region Omega_1)."""
+    p = 8
+    rng = np.random.default_rng(17)
+    xa = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.05)
+    xb = W.perturbed_sphere(rng, p, 1.0, (2.3, 0, 0), 0.05)
+    fb = orc.force(p, xb, None, 0, 0, 0, 1.0, 2)
+    x, n, Wa, K = orc.geometry(p, xa, p)
+    tg = x.T[np.argsort(-x[0])[:10]]   # the ten nodes nearest the other drop
+    v = [orc.regular(p, u * p, xb, fb, 0, tg) for u in (2, 4, 8)]
+    assert np.abs(v[2] - v[1]).max() < 0.05 * np.abs(v[1] - v[0]).max() + 1e-12
+
+
+# --- system level: solves with closed forms -----------------------------------
+
+@pytest.mark.parametrize("lam", [5.0, 1.0, 0.3])
+def test_hadamard_rybczynski(orc, lam):
+    """f = alpha (e.(x - c)) n on a sphere: u = V e - V (I - nn) e / (2 (1 + lam)),
+    V = -(2/3) alpha R^2 (1 + lam)/(2 + 3 lam) (translating drop)."""
+    p, R, alpha = 8, 1.2, 0.7
+    c0 = np.array([0.1, 0.2, -0.3])
+    xc = W.sphere(p, R, c0)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    e = np.array([0.3, -0.5, 0.8])
+    e /= np.linalg.norm(e)
+    f = (alpha * ((x.T - c0) @ e))[:, None] * n.T
+    fc = np.stack([orc.analyze(f[:, k], p, p) for k in range(3)])
+    sysm = orc.System([orc.Drop(p, xc, lam, None, fc)], orc.Options(gmres_tol=1e-13))
+    uc, it, hist = sysm.solve()
+    ug = sysm.velocity_grid(uc)[0]
+    V = -(2 / 3) * alpha * R ** 2 * (1 + lam) / (2 + 3 * lam)
+    nn = n.T
+    ex = V * e[None, :] - V * (e[None, :] - nn * (nn @ e)[:, None]) / (2 * (1 + lam))
+    assert np.abs(ug - ex).max() < 1e-13
+
+
+@pytest.mark.parametrize("lam", [5.0, 2.0])
+def test_marangoni_sphere(orc, lam):
+    """sigma = s0 + s1 e.n: u = s1/(2 + 3 lam) [-(2/3) e + (I - nn) e]."""
+    p = 8
+    R = 1.2
+    c0 = np.array([0.1, 0.2, -0.3])
+    xc = W.sphere(p, R, c0)
+    x, n, Wa, K = orc.geometry(p, xc, p)
+    e = np.array([0.3, -0.5, 0.8])
+    e /= np.linalg.norm(e)
+    s0, s1 = 0.8, 0.3
+    gc = np.zeros((orc.ncoef(p), 2))
+    gc[0, 0] = (1 - s0) * np.sqrt(4 * np.pi)
+    nco = W.sphere(p, 1.0)
+    for k in range(3):
+        gc -= s1 * e[k] * nco[k]
+    sysm = orc.System([orc.Drop(p, xc, lam, gc)], orc.Options(eos=1, E=1.0, xs=1.0, gmres_tol=1e-13))
+    uc, it, hist = sysm.solve()
+    ug = sysm.velocity_grid(uc)[0]
+    nn = n.T
+    ex = s1 / (2 + 3 * lam) * (-(2 / 3) * e[None, :] + (e[None, :] - nn * (nn @ e)[:, None]))
+    assert np.abs(ug - ex).max() < 1e-13
+
+
+def test_uniform_tension_sphere_is_at_rest(orc):
+    p = 10
+    xc = W.sphere(p, 1.0)
+    for lam in [1.0, 3.0]:
+        sysm = orc.System([orc.Drop(p, xc, lam)], orc.Options(gmres_tol=1e-13))
+        uc, it, hist = sysm.solve()
+        assert np.abs(sysm.velocity_grid(uc)[0]).max() < 1e-13
+
+
+def test_two_spheres_rigid_translation_zero_exterior_double_layer(orc):
+    """A rigid translation u = e on both drops gives D_j[u] = 4 pi e on drop j
+    and 0 from the other drop: the raw double layer equals e on every drop."""
+    p = 8
+    xa = W.sphere(p, 1.0, (0, 0, 0))
+    xb = W.sphere(p, 0.9, (2.4, 0.1, 0))
+    e = np.array([0.2, 0.5, -0.3])
+    us = [const_field(orc, p, e), const_field(orc, p, e)]
+    # default split: Omega_0 targets on the standard grid carry its quadrature error
+    sysm = orc.System([orc.Drop(p, xa, 2.0), orc.Drop(p, xb, 3.0)], orc.Options(U_tilde=4))
+    for i in range(2):
+        D = sysm.layer(i, us, 1) / (4 * np.pi)
+        assert np.abs(D - e).max() < 1e-6
+    # every target on the 8x upsampled grid: resolved to roundoff
+    sysm = orc.System([orc.Drop(p, xa, 2.0), orc.Drop(p, xb, 3.0)], orc.Options(U_tilde=8, A_tilde=1e30))
+    for i in range(2):
+        D = sysm.layer(i, us, 1) / (4 * np.pi)
+        assert np.abs(D - e).max() < 1e-13
+
+
+def test_gmres_textbook(orc):
+    rng = np.random.default_rng(18)
+    n = 60
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) * 0.1
+    b = rng.standard_normal(n)
+    x, it, hist = orc.gmres(lambda v: A @ v, b, 1e-13, 10, 500)
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    assert np.abs(x - np.linalg.solve(A, b)).max() < 1e-11
+
+
+def test_regions_two_spheres(orc):
+    """Node distance between two spheres along x: the nearest target of drop 0
+    is in Omega_1/2 of drop 1, the far side in Omega_0 (Sec. 2.3)."""
+    p = 8
+    xa = W.sphere(p, 1.0, (0, 0, 0))
+    xb = W.sphere(p, 1.0, (2.5, 0, 0))
+    sysm = orc.System([orc.Drop(p, xa, 1.0), orc.Drop(p, xb, 1.0)], orc.Options(A_tilde=5.0))
+    reg, dist = sysm.regions(0, 1)
+    x = sysm.nodes(0)
+    # brute force distances
+    y = sysm.nodes(1)
+    bd = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)).min(1)
+    assert np.abs(dist - bd).max() < 1e-14
+    h = np.pi / (p + 1)
+    assert np.all(reg[dist > 5 * h] == 0) and np.all(reg[(dist <= 5 * h) & (dist > h)] == 1)
+    assert np.all(reg[dist <= h] == 2)
+    assert reg[np.argmax(x[:, 0])] != 0 and reg[np.argmin(x[:, 0])] == 0

@@ -1,0 +1,182 @@
+"""Seeded synthetic drop configurations (inputs only; no method arithmetic).
+
+Shared by the oracle tests, the HIP parity tests and the benchmark. Every
+generator returns plain numpy arrays in the coefficient layout used by both
+sides: a real field of degree p is (ncoef(p), 2) with complex index
+n(n+1)/2 + m (m >= 0) and [..., 0] = Re, [..., 1] = Im; a vector field is
+(3, ncoef(p), 2). The spherical-harmonic basis is orthonormal with the
+Condon-Shortley phase, so the unit sphere is
+
+    x = -sqrt(2 pi/3) R  at (n, m) = (1, 1)           (real part)
+    y =  sqrt(2 pi/3) R  at (1, 1)                    (imaginary part)
+    z =  sqrt(4 pi/3) R  at (1, 0)
+    centre c:  sqrt(4 pi) c  at (0, 0).
+
+Random numbers come from numpy's PCG64 with the seed stated per workload.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SQ2PI3 = np.sqrt(2.0 * np.pi / 3.0)
+SQ4PI3 = np.sqrt(4.0 * np.pi / 3.0)
+SQ4PI = np.sqrt(4.0 * np.pi)
+
+
+def ncoef(p: int) -> int:
+    return (p + 1) * (p + 2) // 2
+
+
+def idx(n: int, m: int) -> int:
+    return n * (n + 1) // 2 + m
+
+
+@dataclass
+class DropSpec:
+    p: int
+    xc: np.ndarray                 # (3, ncoef(p), 2)
+    lam: float = 1.0
+    gc: np.ndarray | None = None   # (ncoef(p), 2) or None
+    centre: np.ndarray = field(default_factory=lambda: np.zeros(3))
+    radius: float = 1.0
+
+
+@dataclass
+class Workload:
+    name: str
+    drops: list
+    eos: int = 0            # 0 uniform, 1 linear, 2 Langmuir
+    E: float = 0.0
+    xs: float = 0.0
+    sigma0: float = 1.0
+    A_tilde: float = 5.0
+    U_tilde: int = 4
+    U_sing: int = 1
+    U_geom: int = 2
+    U0: tuple = (0.0, 0.0, 0.0)
+    gradU: tuple = (0.0,) * 9
+    gmres_tol: float = 1e-10
+    notes: str = ""
+
+
+def sphere(p: int, R: float = 1.0, c=(0.0, 0.0, 0.0)) -> np.ndarray:
+    xc = np.zeros((3, ncoef(p), 2))
+    xc[0, idx(1, 1), 0] = -SQ2PI3 * R
+    xc[1, idx(1, 1), 1] = SQ2PI3 * R
+    xc[2, idx(1, 0), 0] = SQ4PI3 * R
+    for k in range(3):
+        xc[k, 0, 0] = SQ4PI * c[k]
+    return xc
+
+
+def perturbation(rng: np.random.Generator, p: int, A: float, lmin: int = 2, power: float = 3.0) -> np.ndarray:
+    """Random coefficients N(0,1) A l^-power for lmin <= l <= p on each Cartesian
+    component; m = 0 real, m > 0 complex with Re and Im each of variance
+    (A l^-power)^2 / 2; Im at m = p zero so the field is representable on the
+    degree-p grid."""
+    d = np.zeros((3, ncoef(p), 2))
+    for k in range(3):
+        for l in range(lmin, p + 1):
+            s = A * l ** (-power)
+            d[k, idx(l, 0), 0] = rng.standard_normal() * s
+            for m in range(1, l + 1):
+                d[k, idx(l, m), 0] = rng.standard_normal() * s / np.sqrt(2.0)
+                d[k, idx(l, m), 1] = rng.standard_normal() * s / np.sqrt(2.0)
+                if m == p:
+                    d[k, idx(l, m), 1] = 0.0
+    return d
+
+
+def perturbed_sphere(rng, p, R, c, A):
+    """Unit sphere plus perturbation, scaled by R, translated by c."""
+    xc = (sphere(p, 1.0) + perturbation(rng, p, A)) * R
+    for k in range(3):
+        xc[k, 0, 0] += SQ4PI * c[k]
+    return xc
+
+
+def bound_radius(xc: np.ndarray, c) -> float:
+    """Upper bound of max |x - c| over the surface: the sum of coefficient
+    moduli times the sup norm sqrt((2l+1)/4pi) of each basis function."""
+    p = int(round((np.sqrt(8 * xc.shape[1] + 1) - 3) / 2))
+    b2 = 0.0
+    tot = np.zeros(3)
+    for k in range(3):
+        for l in range(1, p + 1):
+            sup = np.sqrt((2 * l + 1) / (4 * np.pi))
+            for m in range(0, l + 1):
+                mod = np.hypot(*xc[k, idx(l, m)])
+                tot[k] += (1.0 if m == 0 else 2.0) * mod * sup
+    b2 = np.sqrt(np.sum(tot ** 2))
+    return float(b2)
+
+
+def random_centres(rng, radii_bound, box_lo, box_hi, gap, max_tries=200000):
+    """Random sequential addition: centre i uniform in [lo_i, hi_i]^3, accepted
+    when the bounding-sphere gap to every accepted centre is >= gap."""
+    cs = []
+    for i, b in enumerate(radii_bound):
+        for _ in range(max_tries):
+            c = rng.uniform(box_lo[i], box_hi[i], size=3)
+            if all(np.linalg.norm(c - cj) - b - radii_bound[j] >= gap for j, cj in enumerate(cs)):
+                cs.append(c)
+                break
+        else:
+            raise RuntimeError("random sequential addition failed")
+    return np.array(cs)
+
+
+# ----------------------------------------------------------------------------
+# The five workloads.
+# ----------------------------------------------------------------------------
+
+def single_drop(p=16, A=0.05, seed=1, perturbed=True) -> Workload:
+    """One drop of degree p (default 16): unit sphere plus N(0,1) 0.05 l^-3
+    perturbations, lambda 1, uniform tension 1; single-layer velocity at all
+    grid points."""
+    rng = np.random.default_rng(seed)
+    xc = perturbed_sphere(rng, p, 1.0, (0, 0, 0), A) if perturbed else sphere(p)
+    return Workload(name=f"single_drop_p{p}", drops=[DropSpec(p, xc, 1.0)], eos=0, sigma0=1.0,
+                    notes="uniform tension 1, lambda 1")
+
+
+def two_drops(p=32, A=0.1, gap=0.2, lams=(1.0, 5.0), seed=2) -> Workload:
+    """Two drops of degree p (default 32), perturbations N(0,1) 0.1 l^-3,
+    centres 2 + gap apart along x, lambda (1, 5), surfactant
+    Gamma = 1 + 0.2 Y_2^0 with the linear equation of state sigma = 1 - E xs Gamma
+    (E = 0.5, xs = 0.6), Omega_1 upsampling 4, GMRES tolerance 1e-10."""
+    rng = np.random.default_rng(seed)
+    drops = []
+    for i, c in enumerate([(0.0, 0.0, 0.0), (2.0 + gap, 0.0, 0.0)]):
+        xc = perturbed_sphere(rng, p, 1.0, c, A)
+        gc = np.zeros((ncoef(p), 2))
+        gc[idx(0, 0), 0] = SQ4PI
+        gc[idx(2, 0), 0] = 0.2
+        drops.append(DropSpec(p, xc, lams[i], gc, np.array(c, float), 1.0))
+    return Workload(name=f"two_drops_p{p}", drops=drops, eos=1, E=0.5, xs=0.6, A_tilde=5.0, U_tilde=4,
+                    gmres_tol=1e-10, notes="gap 0.2 nominal; Gamma = 1 + 0.2 Y_2^0; sigma = 1 - 0.3 Gamma")
+
+
+def many_drops(nd=64, p=16, A=0.05, box=12.0, gap=0.3, seed=3) -> Workload:
+    """nd drops (default 64) of degree p (default 16), radii U[0.8, 1.2],
+    centres by random sequential addition in a cube of side 12 with bounding
+    gap >= 0.3, lambda uniform in {1, 2, 5}, uniform tension; every pair on the
+    2x upsampled grid (Omega_1 everywhere)."""
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(0.8, 1.2, size=nd)
+    shapes = [(sphere(p) + perturbation(rng, p, A)) for _ in range(nd)]
+    bounds = [bound_radius(s * r, (0, 0, 0)) for s, r in zip(shapes, R)]
+    lo = [b for b in bounds]
+    hi = [box - b for b in bounds]
+    cs = random_centres(rng, bounds, lo, hi, gap)
+    lams = rng.choice([1.0, 2.0, 5.0], size=nd)
+    drops = []
+    for i in range(nd):
+        xc = shapes[i] * R[i]
+        for k in range(3):
+            xc[k, 0, 0] += SQ4PI * cs[i, k]
+        drops.append(DropSpec(p, xc, float(lams[i]), None, cs[i], float(R[i])))
+    return Workload(name=f"many_drops_n{nd}_p{p}", drops=drops, eos=0, sigma0=1.0, A_tilde=1e30, U_tilde=2,
+                    notes="all pairs on the 2x upsampled grid")
