@@ -1,0 +1,187 @@
+/*
+ * bim.h -- C ABI of the MI355X (gfx950) Stokes layer-potential library.
+ *
+ * Method: C. Sorgentone, A.-K. Tornberg, "A highly accurate boundary integral
+ * equation method for surfactant-laden drops in 3D" (arXiv:1707.02156).
+ * The library evaluates, for N drops whose surfaces are spherical-harmonic
+ * expansions, the interfacial velocity of the second-kind boundary integral
+ * equation of Sec. 1:
+ *
+ *   (lambda_i + 1) u(x0) = 2 u_inf(x0) - 1/(4 pi) sum_j int_{gamma_j} f . G ds
+ *                          + sum_j (lambda_j - 1)/(4 pi) int_{gamma_j} u . T . n ds
+ *
+ * with G = I/r + xh xh/r^3, T = -6 xh xh xh / r^5, xh = x0 - x, solved in the
+ * Galerkin form of Sec. 1.2 (unknowns: spherical-harmonic coefficients of u).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Degree-q grid (Sec. 2.1): q+1 Gauss-Legendre latitudes, theta ascending
+ *   (index j = 0..q), times 2q longitudes phi_k = pi k / q (k = 0..2q-1);
+ *   N(q) = 2q(q+1) nodes, flat index j*2q + k.
+ * Basis (Sec. 1.1, Appendix A): Y_n^m = Ptilde_n^m(cos theta) e^{i m phi},
+ *   orthonormal, Condon-Shortley phase.
+ * Real scalar field of degree p: the m >= 0 coefficients f_n^m as interleaved
+ *   (re, im) doubles at complex index n(n+1)/2 + m, i.e. (p+1)(p+2) doubles;
+ *   f_n^{-m} = (-1)^m conj(f_n^m) is implied (Sec. 1.2). Im f_n^0 and
+ *   Im f_p^p must be zero (the latter is not representable on the grid).
+ * Multi-drop vector arrays are component-major:
+ *   coef[c][drop][(p_d+1)(p_d+2)]   and   grid[c][drop][N(p_d)],
+ *   c = 0,1,2 (x, y, z); drops in the order given to bim_set_drops.
+ *
+ * Ownership: the caller owns every pointer it passes; the library copies
+ * inputs into context-owned device memory and writes outputs into the
+ * caller's buffers. mem_kind 0 = host pointer, 1 = device pointer (HIP
+ * device memory on the context's device). Device outputs are written
+ * asynchronously on the context stream; host outputs are complete on return.
+ *
+ * Errors: every function returns a status (0 = BIM_OK, < 0 = error). No C++
+ * exception or abort crosses the ABI. bim_last_error() gives a per-context
+ * message. A context is not thread-safe; use one per thread or stream.
+ */
+#ifndef BIM_H
+#define BIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BIM_OK = 0,
+    BIM_EINVAL = -1,   /* invalid argument or input (p out of range, NaN, lambda < 0, empty drop) */
+    BIM_ENOMEM = -2,   /* device or host allocation failed */
+    BIM_EDEVICE = -3,  /* HIP runtime error */
+    BIM_ENOCONV = -4,  /* GMRES did not reach the tolerance; output holds the last iterate */
+    BIM_ESTATE = -5    /* call out of order (e.g. evaluation before bim_set_drops) */
+};
+
+enum { BIM_MEM_HOST = 0, BIM_MEM_DEVICE = 1 };
+
+enum { BIM_EOS_UNIFORM = 0, BIM_EOS_LINEAR = 1, BIM_EOS_LANGMUIR = 2 };
+
+enum { BIM_PREC_FP64 = 0, BIM_PREC_MIXED = 1 };
+
+typedef struct bim_ctx_s *bim_ctx;
+
+typedef struct {
+    int device;          /* HIP device ordinal */
+    int precision;       /* BIM_PREC_FP64 (only FP64 is implemented; MIXED is rejected) */
+    double A_tilde;      /* Omega_1 threshold in units of h (Sec. 2.3; paper uses 5) */
+    int U_tilde;         /* Omega_1 grid degree factor: sources on the degree U_tilde*p grid */
+    int U_sing;          /* singular rule grid degree factor (q = U_sing*p; 1 = paper) */
+    int U_geom;          /* de-aliasing grid factor for curvature and force (Sec. 1.3) */
+    int lambda_rule;     /* 0: double layer of drop j weighted by lambda_j (source);
+                            1: weighted by lambda_i of the target drop (as printed) */
+    double gmres_tol;    /* relative residual tolerance (Euclidean norm of coefficients) */
+    int gmres_restart;   /* Krylov dimension before restart */
+    int gmres_maxit;     /* total iteration cap */
+    void *stream;        /* hipStream_t to run on; NULL = the context creates its own */
+} bim_options;
+
+typedef struct {
+    int gmres_iterations;     /* Arnoldi steps performed (0 if all lambda = 1) */
+    double gmres_residual;    /* final relative residual */
+    int n_targets;            /* grid targets over all drops */
+    int n_omega1;             /* (target, source drop) pairs in Omega_1 */
+    int n_omega2;             /* pairs in Omega_2 (evaluated with the Omega_1 rule) */
+    int n_matvec;             /* operator applications in the solve */
+    double ms_total;          /* wall time of the call */
+} bim_report;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int bim_version(void);
+/* Static string for a status code. */
+const char *bim_status_string(int status);
+/* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
+ * gmres_tol 1e-10, restart 50, maxit 500, device 0, FP64, stream NULL. */
+int bim_default_options(bim_options *opt);
+
+/* Create a context on opt->device. Allocates nothing large until drops are set. */
+int bim_create(const bim_options *opt, bim_ctx *out);
+int bim_destroy(bim_ctx ctx);
+const char *bim_last_error(bim_ctx ctx);
+
+/* Drop surfaces x(theta, phi) = sum x_n^m Y_n^m (Sec. 1.1, eq. of the surface
+ * expansion). p[d] in [2, 64]; xcoef component-major as in the header;
+ * lambda[d] >= 0 is the viscosity ratio of drop d. Builds or reuses the
+ * per-degree tables (Gauss-Legendre grid, Legendre functions, Wigner-d
+ * rotations of Appendix B). Resets the surfactant to uniform tension 1. */
+int bim_set_drops(bim_ctx ctx, int n_drops, const int *p, const double *xcoef,
+                  const double *lambda, int mem_kind);
+
+/* Surface tension from the surfactant concentration Gamma (Sec. 1, equation
+ * of state): eos UNIFORM sigma = sigma0 (gamma_coef may be NULL);
+ * LINEAR sigma = 1 - E xs Gamma; LANGMUIR sigma = 1 + E ln(1 - xs Gamma).
+ * gamma_coef: one scalar field per drop, [drop][(p+1)(p+2)]. */
+int bim_set_tension(bim_ctx ctx, const double *gamma_coef, int eos, double E, double xs,
+                    double sigma0, int mem_kind);
+
+/* Far field u_inf(x) = U0 + gradU x (gradU row-major 3x3). */
+int bim_set_farfield(bim_ctx ctx, const double U0[3], const double gradU[9]);
+
+/* Interfacial force f = 2 sigma K n - grad_gamma sigma (Sec. 1), computed on
+ * the degree U_geom*p grid and analysed to degree p (Sec. 1.3). Output:
+ * coefficients, component-major. */
+int bim_force(bim_ctx ctx, double *f_coef, int mem_kind);
+
+/* Region of every grid target w.r.t. every drop (Sec. 2.3): -1 own drop,
+ * 0 Omega_0 (dist > A_tilde h_j), 1 Omega_1 (h_j < dist <= A_tilde h_j),
+ * 2 Omega_2 (dist <= h_j); dist = distance to the nearest node of drop j's
+ * degree-p grid, h_j = R_j pi/(p_j+1), R_j the volume-equivalent radius.
+ * regions: int8 [target][drop]; dist (may be NULL): double [target][drop]
+ * (own-drop entries are 0). Targets are numbered over all drops in order. */
+int bim_regions(bim_ctx ctx, int8_t *regions, double *dist, int mem_kind);
+
+/* Single-layer velocity at every grid target:
+ *   out(x0) = -1/(8 pi) sum_j int_{gamma_j} f . G ds
+ * (the velocity for lambda = 1 and u_inf = 0). The self term uses the
+ * rotated-pole singular rule (Sec. 2.2, Theorem 1, Appendix B); other drops
+ * use the regular rule on the standard or upsampled grid by region (Sec. 2.1,
+ * 2.3). f_coef = NULL uses the interfacial force. out: grid, component-major. */
+int bim_single_layer(bim_ctx ctx, const double *f_coef, double *out, int mem_kind);
+
+/* Double layer of a velocity given by coefficients u_coef (component-major):
+ * mode 0: out = grid values of 1/(4 pi) sum_j int_{gamma_j} u . T . n ds (unweighted);
+ * mode 1: out = coefficients of the Galerkin second-kind operator
+ *         (lambda_i + 1) u_i - P_i[ sum_j (lambda_j - 1)/(4 pi) D_j[u] ],
+ *         P_i the analysis of Sec. 2.1 on drop i's grid. */
+int bim_apply_double_layer(bim_ctx ctx, const double *u_coef, double *out, int mode, int mem_kind);
+
+/* Full velocity: right-hand side 2 u_inf - (1/4pi) sum_j S_j[f], Galerkin
+ * projection and GMRES solve of the second-kind equation when any lambda != 1.
+ * out_kind bit 0: 0 = grid values, 1 = coefficients; bit 1: 0 = host, 1 = device.
+ * rep may be NULL. Returns BIM_ENOCONV (with the last iterate written) if GMRES
+ * stops at gmres_maxit above the tolerance. */
+int bim_eval_velocity(bim_ctx ctx, double *u_out, int out_kind, bim_report *rep);
+
+/* Stand-alone transforms on the context's device and stream (Sec. 1.1, 2.1).
+ * Synthesis: nf scalar fields of degree p (each (p+1)(p+2) doubles,
+ * consecutive) to grid values on the degree-q grid (q >= p), derivative
+ * orders (dt, dp) in theta and phi, dt + dp <= 2; grid [field][N(q)].
+ * Analysis: nf grid fields on the degree-q grid to coefficients of degree
+ * p <= q. Pointers are device pointers when mem_kind = 1. */
+int bim_sh_synthesize(bim_ctx ctx, int p, int q, int nf, const double *coef, int dt, int dp,
+                      double *grid, int mem_kind);
+int bim_sh_analyze(bim_ctx ctx, int q, int p, int nf, const double *grid, double *coef, int mem_kind);
+
+/* Block until all work queued by the context is complete. */
+int bim_synchronize(bim_ctx ctx);
+
+/* Host-side tables (no device needed; the same routines build the device
+ * tables). Gauss-Legendre nodes t[0..q] (descending, theta ascending) and
+ * weights of the degree-q grid (Sec. 2.1). */
+int bim_host_gauss_legendre(int q, double *t, double *w);
+/* Ptilde_n^m(t) and its first and second theta-derivatives at -1 < t < 1 for
+ * 0 <= m <= n <= nmax, at index n(n+1)/2 + m (Sec. 1.1, Appendix A). D1 and D2
+ * may be NULL. */
+int bim_host_legendre(int nmax, double t, double *P, double *D1, double *D2);
+/* Wigner small-d matrix of degree n at angle beta (Appendix B):
+ * d[(m'+n)(2n+1) + (m+n)] = d^n_{m'm}(beta), -n <= m', m <= n. */
+int bim_host_wigner_d(int n, double beta, double *d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIM_H */

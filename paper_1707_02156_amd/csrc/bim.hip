@@ -1,0 +1,1090 @@
+// Context and C ABI of the Stokes layer-potential library (see include/bim.h).
+//
+// One call of bim_eval_velocity runs, on the context stream:
+//   1. nodes: synthesis of x, x_theta, x_phi on the standard (degree p) and
+//      upsampled (degree U_tilde p) grid of every drop -> positions, weighted
+//      normals and area elements, enclosed volume (Sec. 2.1);
+//   2. force: synthesis on the degree U_geom p grid, f = 2 sigma K n - grad sigma,
+//      analysis to degree p (Sec. 1, Sec. 1.3);
+//   3. regions: node distance of every target to every other drop (Sec. 2.3),
+//      compacted into pair work lists on the host (one device-to-host copy);
+//   4. single layer: rotated-pole singular rule per drop (Sec. 2.2, App. B) and
+//      pair sums on the standard / upsampled grids;
+//   5. right-hand side 2 u_inf - S/(4 pi), Galerkin projection (Sec. 1.2), and
+//      GMRES on (lambda+1) u - P[sum_j (lambda_j - 1)/(4 pi) D_j[u]] when any
+//      lambda != 1.
+#include "internal.hpp"
+#include "../../include/bim.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace bim {
+
+void launch_synth(hipStream_t st, int p, int q, int nmax, const double *L, const double *cs, int nf,
+                  const double *coef, long cstride, int dt, int dp, double *G, double *out, long ostride);
+void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, const double *wq, const double *cs,
+                    int nf, const double *v, long vstride, double *F, double *coef, long cstride);
+void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f);
+void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, double *sx, double *swN,
+                  double *swW, long sstride, double *vol);
+void launch_classify(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
+                     const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
+                     int8_t *reg, double *dist);
+void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, const double *cs, const double *xc,
+                   long xstride, const double *dc, long dstride, double *R);
+void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
+                     const double *wsing, const double *cs, double *out, long ostride, double scale);
+void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
+                 long tstride, const double *sx, const double *swN, const double *swW, const double *sd,
+                 long sstride, double *out, long ostride);
+void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const double *s, double a, const double *U0,
+                const double *gU_dev, double *b);
+void launch_scale_add(hipStream_t st, long n, double a, const double *x, double b, double *y);
+void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x, double *y);
+void launch_dots(hipStream_t st, long n, int k, const double *V, long ld, const double *w, double *h);
+void launch_orth_update(hipStream_t st, long n, int k, const double *V, long ld, const double *h, double *w);
+void launch_add_into(hipStream_t st, int k, const double *a, double *b);
+void launch_normalize(hipStream_t st, long n, const double *w, double *v, double *nrm);
+void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
+
+static const double kPi = 3.14159265358979323846;
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define HIPC(expr)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw Error{e_ == hipErrorOutOfMemory ? BIM_ENOMEM : BIM_EDEVICE,                      \
+                        std::string(#expr) + ": " + hipGetErrorString(e_)};                         \
+    } while (0)
+
+#define REQUIRE(cond, code, msg) \
+    do {                         \
+        if (!(cond)) throw Error{code, msg}; \
+    } while (0)
+
+// Device buffer owned by a context.
+struct DBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b)
+    {
+        if (b <= bytes && ptr) return;
+        release();
+        if (b == 0) b = 8;
+        HIPC(hipMalloc(&ptr, b));
+        bytes = b;
+    }
+    double *d() const { return static_cast<double *>(ptr); }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Tables of a degree-q grid with Legendre functions up to degree nmax.
+struct GridTab {
+    int q = 0, nmax = 0;
+    DBuf L, wq, wreg, wsing, cs;
+    std::vector<double> t, w, th;
+};
+
+struct RotTab {
+    int p = 0;
+    DBuf Ap, Am;
+};
+
+struct Drop {
+    int p;
+    double lam;
+    long coff;  // offset (doubles) inside one component block of coefficients
+    long toff;  // offset of its standard-grid nodes
+    long uoff;  // offset of its upsampled-grid nodes
+    int qu, qg, qs;
+};
+
+struct Ctx {
+    bim_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    int nd = 0;
+    std::vector<Drop> drops;
+    long Ctot = 0;  // doubles per component block of coefficients
+    long T = 0;     // standard-grid nodes (targets) over all drops
+    long S1 = 0;    // upsampled nodes over all drops
+
+    int eos = BIM_EOS_UNIFORM;
+    double E = 0.0, xs = 0.0, sigma0 = 1.0;
+    bool have_gamma = false;
+    double U0[3] = {0, 0, 0}, gradU[9] = {0};
+
+    DBuf xc, gc, fc, gU;
+    DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
+    DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
+    DBuf tdrop, vol, hj, noff, ncnt;
+    DBuf reg, dist;
+    DBuf tlist;
+    std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
+    struct WList {
+        std::vector<double> wt;
+        DBuf d0, d1;
+        int n0 = 0, n1 = 0;
+    };
+    std::vector<std::unique_ptr<WList>> wlists;
+    std::vector<int8_t> reg_h;
+    int n_om1 = 0, n_om2 = 0;
+    DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
+    DBuf synbuf, Gbuf, Rbuf, Fbuf;
+    DBuf V, hbuf, ybuf, wvec, xsol, rvec;
+    double *hhost = nullptr;       // pinned
+
+    bool nodes_ok = false, force_ok = false, regions_ok = false;
+    std::map<std::pair<int, int>, std::unique_ptr<GridTab>> grids;
+    std::map<int, std::unique_ptr<RotTab>> rots;
+
+    ~Ctx()
+    {
+        grids.clear();
+        rots.clear();
+        if (hhost) (void)hipHostFree(hhost);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+// --------------------------------------------------------------------------
+// tables
+// --------------------------------------------------------------------------
+static GridTab &grid(Ctx &c, int q, int nmax)
+{
+    auto key = std::make_pair(q, nmax);
+    auto it = c.grids.find(key);
+    if (it != c.grids.end()) return *it->second;
+    auto g = std::make_unique<GridTab>();
+    g->q = q;
+    g->nmax = nmax;
+    gauss_legendre(q, g->t, g->w);
+    g->th.resize(q + 1);
+    const int nc = ncoef(nmax);
+    std::vector<double> L((size_t)3 * (q + 1) * nc), wq(q + 1), wreg(q + 1), wsing(q + 1), cs(4 * q);
+    for (int j = 0; j <= q; ++j) {
+        g->th[j] = std::acos(g->t[j]);
+        legendre_table(nmax, g->t[j], &L[(size_t)j * nc], &L[((size_t)(q + 1) + j) * nc],
+                       &L[((size_t)2 * (q + 1) + j) * nc]);
+        const double s = std::sin(g->th[j]);
+        wq[j] = kPi / q * g->w[j];
+        wreg[j] = wq[j] / s;
+        wsing[j] = wq[j] * legendre_sum(q, g->t[j]) * 2.0 * std::sin(g->th[j] / 2.0) / s;
+    }
+    for (int i = 0; i < 2 * q; ++i) {
+        cs[i] = std::cos(kPi * i / q);
+        cs[2 * q + i] = std::sin(kPi * i / q);
+    }
+    auto up = [&](DBuf &b, const std::vector<double> &v) {
+        b.ensure(v.size() * sizeof(double));
+        HIPC(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    up(g->L, L);
+    up(g->wq, wq);
+    up(g->wreg, wreg);
+    up(g->wsing, wsing);
+    up(g->cs, cs);
+    auto &ref = *g;
+    c.grids[key] = std::move(g);
+    return ref;
+}
+
+static RotTab &rot(Ctx &c, int p)
+{
+    auto it = c.rots.find(p);
+    if (it != c.rots.end()) return *it->second;
+    auto r = std::make_unique<RotTab>();
+    r->p = p;
+    GridTab &g = grid(c, p, p);
+    std::vector<double> Ap, Am;
+    rotation_tables(p, g.th, Ap, Am);
+    r->Ap.ensure(Ap.size() * sizeof(double));
+    r->Am.ensure(Am.size() * sizeof(double));
+    HIPC(hipMemcpy(r->Ap.ptr, Ap.data(), Ap.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(r->Am.ptr, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto &ref = *r;
+    c.rots[p] = std::move(r);
+    return ref;
+}
+
+// --------------------------------------------------------------------------
+// transforms on the context stream
+// --------------------------------------------------------------------------
+static void synth(Ctx &c, int p, int q, int nf, const double *coef, long cstride, int dt, int dp, double *out,
+                  long ostride)
+{
+    GridTab &g = grid(c, q, p);
+    c.Gbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
+    launch_synth(c.stream, p, q, p, g.L.d(), g.cs.d(), nf, coef, cstride, dt, dp, c.Gbuf.d(), out, ostride);
+}
+
+static void analyze(Ctx &c, int q, int p, int nf, const double *v, long vstride, double *coef, long cstride)
+{
+    GridTab &g = grid(c, q, p);
+    c.Fbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
+    launch_analyze(c.stream, q, p, p, g.L.d(), g.wq.d(), g.cs.d(), nf, v, vstride, c.Fbuf.d(), coef, cstride);
+}
+
+// x, x_theta, x_phi of drop d on the degree-q grid into synbuf [9][npts(q)]
+static void synth_surface(Ctx &c, const Drop &d, int q)
+{
+    const long np = npts(q);
+    c.synbuf.ensure((size_t)21 * np * sizeof(double));
+    double *s = c.synbuf.d();
+    const double *x = c.xc.d() + d.coff;
+    synth(c, d.p, q, 3, x, c.Ctot, 0, 0, s, np);
+    synth(c, d.p, q, 3, x, c.Ctot, 1, 0, s + 3 * np, np);
+    synth(c, d.p, q, 3, x, c.Ctot, 0, 1, s + 6 * np, np);
+}
+
+static void build_nodes(Ctx &c)
+{
+    if (c.nodes_ok) return;
+    c.vol.ensure(c.nd * sizeof(double));
+    HIPC(hipMemsetAsync(c.vol.ptr, 0, c.nd * sizeof(double), c.stream));
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        synth_surface(c, d, d.p);
+        launch_nodes(c.stream, d.p, c.synbuf.d(), grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff,
+                     c.s0N.d() + d.toff, c.s0W.d() + d.toff, c.T, c.vol.d() + i);
+        synth_surface(c, d, d.qu);
+        launch_nodes(c.stream, d.qu, c.synbuf.d(), grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
+                     c.s1N.d() + d.uoff, c.s1W.d() + d.uoff, c.S1, nullptr);
+    }
+    c.nodes_ok = true;
+}
+
+static void build_force(Ctx &c)
+{
+    if (c.force_ok) return;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        const int q = d.qg;
+        const long np = npts(q);
+        synth_surface(c, d, q);
+        double *s = c.synbuf.d();
+        const double *x = c.xc.d() + d.coff;
+        synth(c, d.p, q, 3, x, c.Ctot, 2, 0, s + 9 * np, np);
+        synth(c, d.p, q, 3, x, c.Ctot, 1, 1, s + 12 * np, np);
+        synth(c, d.p, q, 3, x, c.Ctot, 0, 2, s + 15 * np, np);
+        if (c.eos != BIM_EOS_UNIFORM) {
+            const double *g = c.gc.d() + d.coff;
+            synth(c, d.p, q, 1, g, 0, 0, 0, s + 18 * np, np);
+            synth(c, d.p, q, 1, g, 0, 1, 0, s + 19 * np, np);
+            synth(c, d.p, q, 1, g, 0, 0, 1, s + 20 * np, np);
+        }
+        c.tmp.ensure((size_t)3 * std::max<long>(np, c.T) * sizeof(double));
+        launch_force(c.stream, (int)np, s, c.eos, c.E, c.xs, c.sigma0, c.tmp.d());
+        analyze(c, q, d.p, 3, c.tmp.d(), np, c.fc.d() + d.coff, c.Ctot);
+    }
+    c.force_ok = true;
+}
+
+// Regions and pair work lists (Sec. 2.3).
+static void build_regions(Ctx &c)
+{
+    if (c.regions_ok) return;
+    build_nodes(c);
+    std::vector<double> vol(c.nd), h(c.nd);
+    HIPC(hipMemcpyAsync(vol.data(), c.vol.ptr, c.nd * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < c.nd; ++i) {
+        REQUIRE(vol[i] > 0.0 && std::isfinite(vol[i]), BIM_EINVAL, "drop " + std::to_string(i) + " has non-positive volume");
+        const double R = std::cbrt(3.0 * vol[i] / (4.0 * kPi));
+        h[i] = R * kPi / (c.drops[i].p + 1);
+    }
+    c.hj.ensure(c.nd * sizeof(double));
+    HIPC(hipMemcpyAsync(c.hj.ptr, h.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    const long nreg = c.T * c.nd;
+    c.reg.ensure(nreg);
+    c.dist.ensure(nreg * sizeof(double));
+    launch_classify(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.tx.d(), c.T, c.noff.as<int>(),
+                    c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(), c.dist.d());
+    c.reg_h.resize(nreg);
+    HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    // work lists: for each (target drop i, source drop j != i): Omega_0 targets
+    // against j's standard grid, Omega_1/2 targets against j's upsampled grid
+    std::vector<int> tl;
+    std::vector<PairWork> w0, w1;
+    const int TILE = 256, CH = 2048;
+    c.n_om1 = c.n_om2 = 0;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &di = c.drops[i];
+        const int nti = npts(di.p);
+        for (int j = 0; j < c.nd; ++j) {
+            if (j == i) continue;
+            const Drop &dj = c.drops[j];
+            for (int kind = 0; kind < 2; ++kind) {
+                const int start = (int)tl.size();
+                for (int t = 0; t < nti; ++t) {
+                    const int8_t r = c.reg_h[(di.toff + t) * c.nd + j];
+                    if ((kind == 0) == (r == 0)) tl.push_back((int)(di.toff + t));
+                    if (kind == 1 && r == 1) ++c.n_om1;
+                    if (kind == 1 && r == 2) ++c.n_om2;
+                }
+                const int cnt = (int)tl.size() - start;
+                const long soff = kind == 0 ? dj.toff : dj.uoff;
+                const int ns = kind == 0 ? npts(dj.p) : npts(dj.qu);
+                for (int a = 0; a < cnt; a += TILE)
+                    for (int b = 0; b < ns; b += CH) {
+                        PairWork pw;
+                        pw.tlist_off = start + a;
+                        pw.ntgt = std::min(TILE, cnt - a);
+                        pw.src_off = (int)(soff + b);
+                        pw.nsrc = std::min(CH, ns - b);
+                        pw.pair = i * c.nd + j;
+                        pw.pad = 0;
+                        pw.w = 0.0;
+                        (kind == 0 ? w0 : w1).push_back(pw);
+                    }
+            }
+        }
+    }
+    c.tlist.ensure(std::max<size_t>(1, tl.size()) * sizeof(int));
+    if (!tl.empty())
+        HIPC(hipMemcpyAsync(c.tlist.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    c.w0h = std::move(w0);
+    c.w1h = std::move(w1);
+    c.wlists.clear();
+    c.regions_ok = true;
+}
+
+// Device work lists for a weight table wt[i * nd + j] (items of zero weight
+// dropped), cached per table.
+static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
+{
+    for (auto &e : c.wlists)
+        if (e->wt == wt) return *e;
+    auto e = std::make_unique<Ctx::WList>();
+    e->wt = wt;
+    for (int u = 0; u < 2; ++u) {
+        const std::vector<PairWork> &src = u == 0 ? c.w0h : c.w1h;
+        std::vector<PairWork> keep;
+        keep.reserve(src.size());
+        for (PairWork pw : src) {
+            pw.w = wt[pw.pair];
+            if (pw.w != 0.0) keep.push_back(pw);
+        }
+        DBuf &db = u == 0 ? e->d0 : e->d1;
+        db.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
+        if (!keep.empty())
+            HIPC(hipMemcpy(db.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice));
+        (u == 0 ? e->n0 : e->n1) = (int)keep.size();
+    }
+    c.wlists.push_back(std::move(e));
+    return *c.wlists.back();
+}
+
+// Pair sums with weight table wt, added into acc.
+static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
+{
+    Ctx::WList &L = work_lists(c, wt);
+    launch_pair(c.stream, kind, L.n0, L.d0.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.tx.d(), c.s0N.d(),
+                c.s0W.d(), c.s0d.d(), c.T, c.acc.d(), c.T);
+    launch_pair(c.stream, kind, L.n1, L.d1.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.s1x.d(), c.s1N.d(),
+                c.s1W.d(), c.s1d.d(), c.S1, c.acc.d(), c.T);
+}
+
+// Density values (3 components, coefficients dens [3][Ctot]) on the standard
+// and upsampled nodes of the drops whose flag is set.
+static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need)
+{
+    for (int i = 0; i < c.nd; ++i) {
+        if (!need[i]) continue;
+        const Drop &d = c.drops[i];
+        synth(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0, 0, c.s0d.d() + d.toff, c.T);
+        synth(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0, 0, c.s1d.d() + d.uoff, c.S1);
+    }
+}
+
+// Singular self-integral of drop i with density coefficients dens [3][Ctot]
+// (kind 0 SL, 1 DL), added into acc with the given scale.
+static void run_singular(Ctx &c, int i, int kind, const double *dens, double scale)
+{
+    const Drop &d = c.drops[i];
+    RotTab &r = rot(c, d.p);
+    GridTab &gp = grid(c, d.p, d.p);
+    GridTab &gs = grid(c, d.qs, d.p);
+    const long nc = ncoef(d.p);
+    c.Rbuf.ensure((size_t)npts(d.p) * 6 * nc * 2 * sizeof(double));
+    launch_rotate(c.stream, d.p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d() + d.coff, c.Ctot, dens + d.coff, c.Ctot,
+                  c.Rbuf.d());
+    launch_singular(c.stream, d.p, d.qs, kind, c.Rbuf.d(), gs.L.d(), (int)nc, gs.wsing.d(), gs.cs.d(),
+                    c.acc.d() + d.toff, c.T, scale);
+}
+
+// Weighted double-layer sum sum_j w(i,j) D_j[u] at all targets into acc.
+static std::vector<double> dl_weights(const Ctx &c)
+{
+    std::vector<double> wt((size_t)c.nd * c.nd);
+    for (int i = 0; i < c.nd; ++i)
+        for (int j = 0; j < c.nd; ++j) {
+            const double lam = c.opt.lambda_rule == 0 ? c.drops[j].lam : c.drops[i].lam;
+            wt[(size_t)i * c.nd + j] = (lam - 1.0) / (4.0 * kPi);
+        }
+    return wt;
+}
+
+static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<double> &wt)
+{
+    build_regions(c);
+    std::vector<char> need(c.nd, 0);
+    for (int j = 0; j < c.nd; ++j)
+        for (int i = 0; i < c.nd; ++i)
+            if (wt[(size_t)i * c.nd + j] != 0.0) need[j] = 1;
+    HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
+    density_nodes(c, ucoef, need);
+    for (int i = 0; i < c.nd; ++i)
+        if (wt[(size_t)i * c.nd + i] != 0.0) run_singular(c, i, 1, ucoef, wt[(size_t)i * c.nd + i]);
+    run_pairs(c, 1, wt);
+}
+
+static void single_layer_grid(Ctx &c, const double *fcoef)
+{
+    build_regions(c);
+    std::vector<char> need(c.nd, 1);
+    HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
+    density_nodes(c, fcoef, need);
+    for (int i = 0; i < c.nd; ++i) run_singular(c, i, 0, fcoef, 1.0);
+    std::vector<double> wt((size_t)c.nd * c.nd, 1.0);
+    run_pairs(c, 0, wt);
+}
+
+// analysis of grid vectors [3][T] into coefficients [3][Ctot]
+static void project(Ctx &c, const double *grid_vals, double *coef)
+{
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        analyze(c, d.p, d.p, 3, grid_vals + d.toff, c.T, coef + d.coff, c.Ctot);
+    }
+}
+
+static void synth_grid_all(Ctx &c, const double *coef, double *grid_vals)
+{
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        synth(c, d.p, d.p, 3, coef + d.coff, c.Ctot, 0, 0, grid_vals + d.toff, c.T);
+    }
+}
+
+// y = A x, the Galerkin second-kind operator (coefficients [3][Ctot]).
+static void apply_operator(Ctx &c, const double *x, double *y, const std::vector<double> &wt)
+{
+    double_layer_grid(c, x, wt);
+    project(c, c.acc.d(), y);
+    launch_op_combine(c.stream, 3 * c.Ctot, c.scl.d(), x, y);
+}
+
+// --------------------------------------------------------------------------
+// GMRES (restarted, classical Gram-Schmidt with one re-orthogonalisation,
+// Givens rotations on the host). Vectors on the device.
+// --------------------------------------------------------------------------
+static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, int &iters, double &relres,
+                 int &nmv)
+{
+    const long n = 3 * c.Ctot;
+    const int m = std::max(1, std::min(c.opt.gmres_restart, 200));
+    c.V.ensure((size_t)(m + 1) * n * sizeof(double));
+    c.hbuf.ensure((size_t)(2 * (m + 2)) * sizeof(double));
+    c.ybuf.ensure((size_t)(m + 2) * sizeof(double));
+    c.wvec.ensure((size_t)n * sizeof(double));
+    c.rvec.ensure((size_t)n * sizeof(double));
+    if (!c.hhost) HIPC(hipHostMalloc((void **)&c.hhost, 4 * 256 * sizeof(double)));
+    double *V = c.V.d(), *h = c.hbuf.d(), *h2 = h + (m + 2), *w = c.wvec.d();
+    HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
+    // ||b||
+    launch_normalize(c.stream, n, b, nullptr, h);
+    HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    const double bn = c.hhost[0];
+    iters = 0;
+    nmv = 0;
+    relres = 0.0;
+    if (bn == 0.0) return BIM_OK;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+    bool first = true;
+    while (true) {
+        // r = b - A x
+        if (first) {
+            HIPC(hipMemcpyAsync(c.rvec.ptr, b, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+        } else {
+            apply_operator(c, x, c.rvec.d(), wt);
+            ++nmv;
+            launch_scale_add(c.stream, n, 1.0, b, -1.0, c.rvec.d());
+        }
+        first = false;
+        launch_normalize(c.stream, n, c.rvec.d(), V, h);
+        HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        const double beta = c.hhost[0];
+        relres = beta / bn;
+        if (relres <= c.opt.gmres_tol) return BIM_OK;
+        if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kdone = 0;
+        bool conv = false;
+        for (int k = 0; k < m; ++k) {
+            apply_operator(c, V + (long)k * n, w, wt);
+            ++nmv;
+            // two classical Gram-Schmidt passes
+            launch_dots(c.stream, n, k + 1, V, n, w, h);
+            launch_orth_update(c.stream, n, k + 1, V, n, h, w);
+            launch_dots(c.stream, n, k + 1, V, n, w, h2);
+            launch_orth_update(c.stream, n, k + 1, V, n, h2, w);
+            launch_add_into(c.stream, k + 1, h2, h);
+            launch_normalize(c.stream, n, w, V + (long)(k + 1) * n, h + k + 1);
+            HIPC(hipMemcpyAsync(c.hhost, h, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+            for (int l = 0; l <= k + 1; ++l) H[(size_t)l * m + k] = c.hhost[l];
+            for (int l = 0; l < k; ++l) {
+                const double t = cs[l] * H[(size_t)l * m + k] + sn[l] * H[(size_t)(l + 1) * m + k];
+                H[(size_t)(l + 1) * m + k] = -sn[l] * H[(size_t)l * m + k] + cs[l] * H[(size_t)(l + 1) * m + k];
+                H[(size_t)l * m + k] = t;
+            }
+            const double den = std::hypot(H[(size_t)k * m + k], H[(size_t)(k + 1) * m + k]);
+            cs[k] = den > 0.0 ? H[(size_t)k * m + k] / den : 1.0;
+            sn[k] = den > 0.0 ? H[(size_t)(k + 1) * m + k] / den : 0.0;
+            H[(size_t)k * m + k] = den;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            ++iters;
+            kdone = k + 1;
+            relres = std::fabs(g[k + 1]) / bn;
+            if (relres <= c.opt.gmres_tol || iters >= c.opt.gmres_maxit) {
+                conv = relres <= c.opt.gmres_tol;
+                break;
+            }
+        }
+        // back substitution
+        std::vector<double> y(kdone);
+        for (int l = kdone - 1; l >= 0; --l) {
+            double s = g[l];
+            for (int q = l + 1; q < kdone; ++q) s -= H[(size_t)l * m + q] * y[q];
+            y[l] = s / H[(size_t)l * m + l];
+        }
+        HIPC(hipMemcpyAsync(c.ybuf.ptr, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        launch_lincomb(c.stream, n, kdone, V, n, c.ybuf.d(), x);
+        HIPC(hipStreamSynchronize(c.stream));
+        if (conv) return BIM_OK;
+        if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
+    }
+}
+
+// --------------------------------------------------------------------------
+// helpers for inputs / outputs
+// --------------------------------------------------------------------------
+static void copy_in(Ctx &c, void *dst, const void *src, size_t bytes, int mem_kind)
+{
+    if (bytes == 0) return;
+    HIPC(hipMemcpyAsync(dst, src, bytes, mem_kind == BIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        c.stream));
+    if (mem_kind != BIM_MEM_DEVICE) HIPC(hipStreamSynchronize(c.stream));
+}
+
+static void copy_out(Ctx &c, void *dst, const void *src, size_t bytes, int mem_kind)
+{
+    if (bytes == 0) return;
+    HIPC(hipMemcpyAsync(dst, src, bytes, mem_kind == BIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        c.stream));
+    if (mem_kind != BIM_MEM_DEVICE) HIPC(hipStreamSynchronize(c.stream));
+}
+
+static void invalidate(Ctx &c)
+{
+    c.nodes_ok = c.force_ok = c.regions_ok = false;
+}
+
+static void require_drops(Ctx &c) { REQUIRE(c.nd > 0, BIM_ESTATE, "no drops set (call bim_set_drops first)"); }
+
+template <class F> static int guarded(Ctx *c, F &&f)
+{
+    if (!c) return BIM_EINVAL;
+    try {
+        HIPC(hipSetDevice(c->device));
+        int rc = f();
+        if (rc == BIM_OK) c->err.clear();
+        return rc;
+    } catch (const Error &e) {
+        c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return BIM_ENOMEM;
+    } catch (const std::exception &e) {
+        c->err = e.what();
+        return BIM_EDEVICE;
+    } catch (...) {
+        c->err = "unknown error";
+        return BIM_EDEVICE;
+    }
+}
+
+}  // namespace bim
+
+using namespace bim;
+
+struct bim_ctx_s {
+    Ctx c;
+};
+
+extern "C" {
+
+int bim_version(void) { return 100; }
+
+const char *bim_status_string(int s)
+{
+    switch (s) {
+    case BIM_OK: return "ok";
+    case BIM_EINVAL: return "invalid argument";
+    case BIM_ENOMEM: return "out of memory";
+    case BIM_EDEVICE: return "device error";
+    case BIM_ENOCONV: return "GMRES did not converge";
+    case BIM_ESTATE: return "invalid call order";
+    default: return "unknown status";
+    }
+}
+
+int bim_default_options(bim_options *o)
+{
+    if (!o) return BIM_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->precision = BIM_PREC_FP64;
+    o->A_tilde = 5.0;
+    o->U_tilde = 4;
+    o->U_sing = 1;
+    o->U_geom = 2;
+    o->lambda_rule = 0;
+    o->gmres_tol = 1e-10;
+    o->gmres_restart = 50;
+    o->gmres_maxit = 500;
+    o->stream = nullptr;
+    return BIM_OK;
+}
+
+int bim_create(const bim_options *opt, bim_ctx *out)
+{
+    if (!opt || !out) return BIM_EINVAL;
+    *out = nullptr;
+    if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
+        !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
+        (opt->lambda_rule != 0 && opt->lambda_rule != 1))
+        return BIM_EINVAL;
+    bim_ctx h = nullptr;
+    try {
+        h = new bim_ctx_s();
+    } catch (...) {
+        return BIM_ENOMEM;
+    }
+    Ctx &c = h->c;
+    c.opt = *opt;
+    c.device = opt->device;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev) {
+        delete h;
+        return BIM_EDEVICE;
+    }
+    if (hipSetDevice(opt->device) != hipSuccess) {
+        delete h;
+        return BIM_EDEVICE;
+    }
+    if (opt->stream) {
+        c.stream = static_cast<hipStream_t>(opt->stream);
+    } else {
+        if (hipStreamCreate(&c.stream) != hipSuccess) {
+            delete h;
+            return BIM_EDEVICE;
+        }
+        c.own_stream = true;
+    }
+    *out = h;
+    return BIM_OK;
+}
+
+int bim_destroy(bim_ctx h)
+{
+    if (!h) return BIM_EINVAL;
+    (void)hipSetDevice(h->c.device);
+    if (h->c.stream) (void)hipStreamSynchronize(h->c.stream);
+    delete h;
+    return BIM_OK;
+}
+
+const char *bim_last_error(bim_ctx h) { return h ? h->c.err.c_str() : "null context"; }
+
+int bim_synchronize(bim_ctx h)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        HIPC(hipStreamSynchronize(h->c.stream));
+        return BIM_OK;
+    });
+}
+
+int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, const double *lambda, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        REQUIRE(n_drops >= 1 && p && xcoef && lambda, BIM_EINVAL, "bim_set_drops: null argument or no drops");
+        REQUIRE(mem_kind == BIM_MEM_HOST || mem_kind == BIM_MEM_DEVICE, BIM_EINVAL, "bad mem_kind");
+        std::vector<Drop> ds(n_drops);
+        long coff = 0, toff = 0, uoff = 0;
+        for (int i = 0; i < n_drops; ++i) {
+            REQUIRE(p[i] >= 2 && p[i] <= 64, BIM_EINVAL, "degree p out of range [2, 64]");
+            REQUIRE(std::isfinite(lambda[i]) && lambda[i] >= 0.0, BIM_EINVAL, "lambda must be finite and >= 0");
+            ds[i].p = p[i];
+            ds[i].lam = lambda[i];
+            ds[i].coff = coff;
+            ds[i].toff = toff;
+            ds[i].uoff = uoff;
+            ds[i].qu = c.opt.U_tilde * p[i];
+            ds[i].qg = c.opt.U_geom * p[i];
+            ds[i].qs = c.opt.U_sing * p[i];
+            REQUIRE(ds[i].qu <= 512 && ds[i].qg <= 512 && ds[i].qs <= 256, BIM_EINVAL, "grid degree too large");
+            coff += 2L * ncoef(p[i]);
+            toff += npts(p[i]);
+            uoff += npts(ds[i].qu);
+        }
+        // validate coefficients on the host
+        std::vector<double> hx((size_t)3 * coff);
+        if (mem_kind == BIM_MEM_DEVICE)
+            HIPC(hipMemcpy(hx.data(), xcoef, hx.size() * sizeof(double), hipMemcpyDeviceToHost));
+        else
+            std::memcpy(hx.data(), xcoef, hx.size() * sizeof(double));
+        for (double v : hx) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surface coefficient");
+        c.nd = n_drops;
+        c.drops = ds;
+        c.Ctot = coff;
+        c.T = toff;
+        c.S1 = uoff;
+        c.xc.ensure(hx.size() * sizeof(double));
+        HIPC(hipMemcpyAsync(c.xc.ptr, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        c.gc.ensure((size_t)coff * sizeof(double));
+        HIPC(hipMemsetAsync(c.gc.ptr, 0, (size_t)coff * sizeof(double), c.stream));
+        c.fc.ensure((size_t)3 * coff * sizeof(double));
+        c.eos = BIM_EOS_UNIFORM;
+        c.sigma0 = 1.0;
+        c.E = c.xs = 0.0;
+        c.have_gamma = false;
+        c.tx.ensure((size_t)3 * c.T * sizeof(double));
+        c.s0N.ensure((size_t)3 * c.T * sizeof(double));
+        c.s0W.ensure((size_t)c.T * sizeof(double));
+        c.s0d.ensure((size_t)3 * c.T * sizeof(double));
+        c.s1x.ensure((size_t)3 * c.S1 * sizeof(double));
+        c.s1N.ensure((size_t)3 * c.S1 * sizeof(double));
+        c.s1W.ensure((size_t)c.S1 * sizeof(double));
+        c.s1d.ensure((size_t)3 * c.S1 * sizeof(double));
+        c.acc.ensure((size_t)3 * c.T * sizeof(double));
+        c.tmp.ensure((size_t)3 * c.T * sizeof(double));
+        c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+        c.xsol.ensure((size_t)3 * c.Ctot * sizeof(double));
+        std::vector<int> tdrop(c.T), noff(c.nd), ncnt(c.nd);
+        for (int i = 0; i < c.nd; ++i) {
+            for (int t = 0; t < npts(ds[i].p); ++t) tdrop[ds[i].toff + t] = i;
+            noff[i] = (int)ds[i].toff;
+            ncnt[i] = npts(ds[i].p);
+        }
+        c.tdrop.ensure(c.T * sizeof(int));
+        c.noff.ensure(c.nd * sizeof(int));
+        c.ncnt.ensure(c.nd * sizeof(int));
+        HIPC(hipMemcpyAsync(c.tdrop.ptr, tdrop.data(), c.T * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipMemcpyAsync(c.noff.ptr, noff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipMemcpyAsync(c.ncnt.ptr, ncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        // Galerkin operator diagonal (lambda_i + 1)
+        std::vector<double> scl((size_t)3 * c.Ctot);
+        for (int comp = 0; comp < 3; ++comp)
+            for (int i = 0; i < c.nd; ++i)
+                for (long e = 0; e < 2L * ncoef(ds[i].p); ++e) scl[comp * c.Ctot + ds[i].coff + e] = ds[i].lam + 1.0;
+        c.scl.ensure(scl.size() * sizeof(double));
+        HIPC(hipMemcpyAsync(c.scl.ptr, scl.data(), scl.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        c.gU.ensure(9 * sizeof(double));
+        HIPC(hipMemcpyAsync(c.gU.ptr, c.gradU, 9 * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        invalidate(c);
+        // tables for every grid in use
+        for (auto &d : ds) {
+            grid(c, d.p, d.p);
+            grid(c, d.qu, d.p);
+            grid(c, d.qg, d.p);
+            grid(c, d.qs, d.p);
+            rot(c, d.p);
+        }
+        HIPC(hipStreamSynchronize(c.stream));
+        return BIM_OK;
+    });
+}
+
+int bim_set_tension(bim_ctx h, const double *gamma_coef, int eos, double E, double xs, double sigma0, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(eos >= 0 && eos <= 2, BIM_EINVAL, "bad equation of state");
+        REQUIRE(eos == BIM_EOS_UNIFORM || gamma_coef, BIM_EINVAL, "gamma_coef required for this equation of state");
+        REQUIRE(std::isfinite(E) && std::isfinite(xs) && std::isfinite(sigma0), BIM_EINVAL, "non-finite parameter");
+        c.eos = eos;
+        c.E = E;
+        c.xs = xs;
+        c.sigma0 = sigma0;
+        if (gamma_coef) {
+            std::vector<double> hg((size_t)c.Ctot);
+            if (mem_kind == BIM_MEM_DEVICE)
+                HIPC(hipMemcpy(hg.data(), gamma_coef, hg.size() * sizeof(double), hipMemcpyDeviceToHost));
+            else
+                std::memcpy(hg.data(), gamma_coef, hg.size() * sizeof(double));
+            for (double v : hg) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surfactant coefficient");
+            HIPC(hipMemcpyAsync(c.gc.ptr, hg.data(), hg.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+            c.have_gamma = true;
+        }
+        c.force_ok = false;
+        return BIM_OK;
+    });
+}
+
+int bim_set_farfield(bim_ctx h, const double U0[3], const double gradU[9])
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        for (int i = 0; i < 3; ++i) c.U0[i] = U0 ? U0[i] : 0.0;
+        for (int i = 0; i < 9; ++i) c.gradU[i] = gradU ? gradU[i] : 0.0;
+        for (int i = 0; i < 3; ++i) REQUIRE(std::isfinite(c.U0[i]), BIM_EINVAL, "non-finite U0");
+        for (int i = 0; i < 9; ++i) REQUIRE(std::isfinite(c.gradU[i]), BIM_EINVAL, "non-finite gradU");
+        c.gU.ensure(9 * sizeof(double));
+        HIPC(hipMemcpyAsync(c.gU.ptr, c.gradU, 9 * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        return BIM_OK;
+    });
+}
+
+int bim_force(bim_ctx h, double *f_coef, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(f_coef, BIM_EINVAL, "null output");
+        build_force(c);
+        copy_out(c, f_coef, c.fc.ptr, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+        return BIM_OK;
+    });
+}
+
+int bim_regions(bim_ctx h, int8_t *regions, double *dist, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        build_regions(c);
+        if (regions) copy_out(c, regions, c.reg.ptr, (size_t)c.T * c.nd, mem_kind);
+        if (dist) copy_out(c, dist, c.dist.ptr, (size_t)c.T * c.nd * sizeof(double), mem_kind);
+        return BIM_OK;
+    });
+}
+
+int bim_single_layer(bim_ctx h, const double *f_coef, double *out, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(out, BIM_EINVAL, "null output");
+        const double *dens;
+        if (f_coef) {
+            c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+            copy_in(c, c.bvec.ptr, f_coef, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+            dens = c.bvec.d();
+        } else {
+            build_force(c);
+            dens = c.fc.d();
+        }
+        single_layer_grid(c, dens);
+        launch_scale_add(c.stream, 3 * c.T, -1.0 / (8.0 * kPi), c.acc.d(), 0.0, c.acc.d());
+        copy_out(c, out, c.acc.ptr, (size_t)3 * c.T * sizeof(double), mem_kind);
+        return BIM_OK;
+    });
+}
+
+int bim_apply_double_layer(bim_ctx h, const double *u_coef, double *out, int mode, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(u_coef && out, BIM_EINVAL, "null argument");
+        REQUIRE(mode == 0 || mode == 1, BIM_EINVAL, "mode must be 0 or 1");
+        c.xsol.ensure((size_t)3 * c.Ctot * sizeof(double));
+        copy_in(c, c.xsol.ptr, u_coef, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+        if (mode == 0) {
+            std::vector<double> wt((size_t)c.nd * c.nd, 1.0 / (4.0 * kPi));
+            double_layer_grid(c, c.xsol.d(), wt);
+            copy_out(c, out, c.acc.ptr, (size_t)3 * c.T * sizeof(double), mem_kind);
+        } else {
+            c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+            apply_operator(c, c.xsol.d(), c.bvec.d(), dl_weights(c));
+            copy_out(c, out, c.bvec.ptr, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+        }
+        return BIM_OK;
+    });
+}
+
+int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(u_out, BIM_EINVAL, "null output");
+        REQUIRE(out_kind >= 0 && out_kind <= 3, BIM_EINVAL, "bad out_kind");
+        auto t0 = std::chrono::steady_clock::now();
+        // a velocity evaluation always recomputes the geometry, the force and
+        // the regions from the drop coefficients
+        invalidate(c);
+        build_force(c);
+        single_layer_grid(c, c.fc.d());
+        // b = 2 u_inf - S / (4 pi) on the grid, then Galerkin projection
+        c.tmp.ensure((size_t)3 * std::max<long>(c.Ctot, c.T) * sizeof(double));
+        launch_rhs(c.stream, (int)c.T, c.tx.d(), c.T, c.acc.d(), -1.0 / (4.0 * kPi), c.U0, c.gU.d(), c.tmp.d());
+        c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+        project(c, c.tmp.d(), c.bvec.d());
+        bool all_one = true;
+        for (auto &d : c.drops) all_one = all_one && d.lam == 1.0;
+        int rc = BIM_OK, iters = 0, nmv = 0;
+        double relres = 0.0;
+        const long n = 3 * c.Ctot;
+        if (all_one) {
+            launch_scale_add(c.stream, n, 0.5, c.bvec.d(), 0.0, c.xsol.d());
+        } else {
+            rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), iters, relres, nmv);
+        }
+        const bool dev = (out_kind & 2) != 0;
+        if (out_kind & 1) {
+            copy_out(c, u_out, c.xsol.ptr, (size_t)n * sizeof(double), dev ? BIM_MEM_DEVICE : BIM_MEM_HOST);
+        } else {
+            synth_grid_all(c, c.xsol.d(), c.tmp.d());
+            copy_out(c, u_out, c.tmp.ptr, (size_t)3 * c.T * sizeof(double), dev ? BIM_MEM_DEVICE : BIM_MEM_HOST);
+        }
+        if (rep) {
+            if (dev) HIPC(hipStreamSynchronize(c.stream));
+            rep->gmres_iterations = iters;
+            rep->gmres_residual = relres;
+            rep->n_targets = (int)c.T;
+            rep->n_omega1 = c.n_om1;
+            rep->n_omega2 = c.n_om2;
+            rep->n_matvec = nmv;
+            rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (rc == BIM_ENOCONV) c.err = "GMRES stopped at maxit above tolerance";
+        return rc;
+    });
+}
+
+int bim_sh_synthesize(bim_ctx h, int p, int q, int nf, const double *coef, int dt, int dp, double *grid_out,
+                      int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        REQUIRE(p >= 0 && q >= p && q >= 1 && q <= 512 && nf >= 1 && coef && grid_out, BIM_EINVAL, "bad arguments");
+        REQUIRE(dt >= 0 && dp >= 0 && dt + dp <= 2, BIM_EINVAL, "derivative order > 2");
+        const size_t cb = (size_t)nf * 2 * ncoef(p) * sizeof(double), gb = (size_t)nf * npts(q) * sizeof(double);
+        DBuf ci, go;
+        const double *cin = coef;
+        double *gout = grid_out;
+        if (mem_kind != BIM_MEM_DEVICE) {
+            ci.ensure(cb);
+            go.ensure(gb);
+            HIPC(hipMemcpyAsync(ci.ptr, coef, cb, hipMemcpyHostToDevice, c.stream));
+            cin = ci.d();
+            gout = go.d();
+        }
+        synth(c, p, q, nf, cin, 2L * ncoef(p), dt, dp, gout, npts(q));
+        if (mem_kind != BIM_MEM_DEVICE) {
+            HIPC(hipMemcpyAsync(grid_out, gout, gb, hipMemcpyDeviceToHost, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+        }
+        return BIM_OK;
+    });
+}
+
+int bim_sh_analyze(bim_ctx h, int q, int p, int nf, const double *grid_in, double *coef, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        REQUIRE(p >= 0 && q >= p && q >= 1 && q <= 512 && nf >= 1 && coef && grid_in, BIM_EINVAL, "bad arguments");
+        const size_t cb = (size_t)nf * 2 * ncoef(p) * sizeof(double), gb = (size_t)nf * npts(q) * sizeof(double);
+        DBuf gi, co;
+        const double *gin = grid_in;
+        double *cout = coef;
+        if (mem_kind != BIM_MEM_DEVICE) {
+            gi.ensure(gb);
+            co.ensure(cb);
+            HIPC(hipMemcpyAsync(gi.ptr, grid_in, gb, hipMemcpyHostToDevice, c.stream));
+            gin = gi.d();
+            cout = co.d();
+        }
+        analyze(c, q, p, nf, gin, npts(q), cout, 2L * ncoef(p));
+        if (mem_kind != BIM_MEM_DEVICE) {
+            HIPC(hipMemcpyAsync(coef, cout, cb, hipMemcpyDeviceToHost, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+        }
+        return BIM_OK;
+    });
+}
+
+// ---- host-side tables (no device needed) ----
+int bim_host_gauss_legendre(int q, double *t, double *w)
+{
+    if (q < 1 || q > 1024 || !t || !w) return BIM_EINVAL;
+    std::vector<double> tv, wv;
+    gauss_legendre(q, tv, wv);
+    std::copy(tv.begin(), tv.end(), t);
+    std::copy(wv.begin(), wv.end(), w);
+    return BIM_OK;
+}
+
+int bim_host_legendre(int nmax, double t, double *P, double *D1, double *D2)
+{
+    if (nmax < 0 || nmax > 1024 || !P || !(t > -1.0 && t < 1.0)) return BIM_EINVAL;
+    legendre_table(nmax, t, P, D1, D2);
+    return BIM_OK;
+}
+
+int bim_host_wigner_d(int n, double beta, double *d)
+{
+    if (n < 0 || n > 256 || !d) return BIM_EINVAL;
+    std::vector<double> all;
+    wigner_table(n, beta, all);
+    const size_t off = (size_t)n * (4 * (size_t)n * n - 1) / 3;
+    std::copy(all.begin() + off, all.end(), d);
+    return BIM_OK;
+}
+
+}  // extern "C"

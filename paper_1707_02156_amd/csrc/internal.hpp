@@ -1,0 +1,38 @@
+// Internal declarations shared by the host code and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace bim {
+
+// complex index of (n, m), m >= 0, in a degree-p coefficient triangle
+inline __host__ __device__ int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+inline __host__ __device__ int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
+inline __host__ __device__ int npts(int q) { return 2 * q * (q + 1); }
+// offset of degree n in a per-latitude rotation table: sum_{k<n} (k+1)^2
+inline __host__ __device__ size_t rot_off(int n) { return (size_t)n * (n + 1) * (2 * n + 1) / 6; }
+inline __host__ __device__ size_t rot_lat_size(int p) { return rot_off(p + 1); }
+
+// ---- host tables (tables.cpp) ----
+void gauss_legendre(int q, std::vector<double> &t, std::vector<double> &w);
+void legendre_table(int nmax, double t, double *P, double *D1, double *D2);
+void wigner_table(int nmax, double beta, std::vector<double> &d);
+void rotation_tables(int p, const std::vector<double> &theta, std::vector<double> &Ap, std::vector<double> &Am);
+double legendre_sum(int q, double t);
+
+// ---- device-side work descriptors ----
+struct PairWork {
+    int tlist_off;  // first entry in the target index list
+    int ntgt;       // targets in this item (<= 256)
+    int src_off;    // first source node in the source arrays
+    int nsrc;       // source nodes in this item
+    int pair;       // target drop * n_drops + source drop
+    int pad;
+    double w;       // weight applied to the sum
+};
+
+}  // namespace bim

@@ -1,0 +1,702 @@
+// gfx950 kernels of the Stokes layer-potential path (FP64).
+//
+// Data layouts (device):
+//   coefficient triangle of a real field: (re, im) doubles at complex index
+//     n(n+1)/2 + m, m >= 0;
+//   Legendre tables of a degree-q grid: L[kind][j][tri(n, m)], kind 0 = Ptilde,
+//     1 = d/dtheta, 2 = d^2/dtheta^2, j = 0..q (theta ascending);
+//   grid values: [field][j * 2q + k];
+//   cos/sin table of a degree-q grid: cs[i] = cos(pi i / q), cs[2q + i] = sin(pi i / q).
+#include "internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace bim {
+
+static constexpr double kPi = 3.14159265358979323846;
+static constexpr double kInvSqrt4Pi = 0.28209479177387814347;
+
+// ----------------------------------------------------------------------------
+// Synthesis (Sec. 1.1 truncated expansion; derivatives by Appendix A):
+// stage 1 (Legendre): G[f][j][m] = sum_{n=m}^{p} c_f[n,m] L[j][tri(n,m)]
+// stage 2 (Fourier):  v[f][j][k] = sum_{m=0}^{p} (m ? 2 : 1) Re[(i m)^dp G e^{i m phi_k}]
+// ----------------------------------------------------------------------------
+__global__ void k_synth_leg(int p, int nj, int ldn, const double *__restrict__ L, int nf,
+                            const double *__restrict__ coef, long cstride, double *__restrict__ G)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)nf * nj * (p + 1);
+    if (idx >= total) return;
+    const int m = idx % (p + 1);
+    const long r = idx / (p + 1);
+    const int j = r % nj;
+    const int f = r / nj;
+    const double *c = coef + f * cstride;
+    const double *Lj = L + (long)j * ldn;
+    double sr = 0.0, si = 0.0;
+    for (int n = m; n <= p; ++n) {
+        const double l = Lj[tri(n, m)];
+        sr = fma(c[2 * tri(n, m)], l, sr);
+        si = fma(c[2 * tri(n, m) + 1], l, si);
+    }
+    G[2 * idx] = sr;
+    G[2 * idx + 1] = si;
+}
+
+__global__ void k_synth_fourier(int p, int q, int nj, int dp, const double *__restrict__ G,
+                                const double *__restrict__ cs, int nf, double *__restrict__ out, long ostride)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nk = 2 * q;
+    const long total = (long)nf * nj * nk;
+    if (idx >= total) return;
+    const int k = idx % nk;
+    const long r = idx / nk;
+    const int j = r % nj;
+    const int f = r / nj;
+    const double *g = G + 2 * ((long)(f * nj + j) * (p + 1));
+    double v = 0.0;
+    int e = 0;  // (m k) mod 2q
+    for (int m = 0; m <= p; ++m) {
+        double ar = g[2 * m], ai = g[2 * m + 1];
+        if (dp == 1) { const double t = -m * ai; ai = m * ar; ar = t; }
+        else if (dp == 2) { ar *= -(double)m * m; ai *= -(double)m * m; }
+        const double c = cs[e], s = cs[nk + e];
+        v += (m ? 2.0 : 1.0) * (ar * c - ai * s);
+        e += k;
+        if (e >= nk) e -= nk;
+    }
+    out[f * ostride + (long)j * nk + k] = v;
+}
+
+// ----------------------------------------------------------------------------
+// Analysis (Sec. 2.1, weight (pi/q) w_j, half weight at m = q):
+// stage 1 (Fourier):  F[f][j][m] = sum_k v[f][j][k] e^{-i m phi_k}, m = 0..p
+// stage 2 (Legendre): c_f[n,m] = sum_j wq_j h_m Ptilde_n^m(t_j) F[f][j][m]
+// ----------------------------------------------------------------------------
+__global__ void k_anal_fourier(int p, int q, const double *__restrict__ v, long vstride,
+                               const double *__restrict__ cs, int nf, double *__restrict__ F)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nj = q + 1, nk = 2 * q;
+    const long total = (long)nf * nj * (p + 1);
+    if (idx >= total) return;
+    const int m = idx % (p + 1);
+    const long r = idx / (p + 1);
+    const int j = r % nj;
+    const int f = r / nj;
+    const double *g = v + f * vstride + (long)j * nk;
+    double sr = 0.0, si = 0.0;
+    int e = 0;
+    for (int k = 0; k < nk; ++k) {
+        sr = fma(g[k], cs[e], sr);
+        si = fma(-g[k], cs[nk + e], si);
+        e += m;
+        if (e >= nk) e -= nk;
+    }
+    F[2 * idx] = sr;
+    F[2 * idx + 1] = si;
+}
+
+__global__ void k_anal_leg(int p, int q, int ldn, const double *__restrict__ L, const double *__restrict__ wq,
+                           int nf, const double *__restrict__ F, double *__restrict__ coef, long cstride)
+{
+    const int nc = ncoef(p);
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)nf * nc;
+    if (idx >= total) return;
+    const int e = idx % nc;
+    const int f = idx / nc;
+    int n = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+    while (tri(n + 1, 0) <= e) ++n;
+    while (tri(n, 0) > e) --n;
+    const int m = e - tri(n, 0);
+    const int nj = q + 1;
+    const double h = (m == q) ? 0.5 : 1.0;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < nj; ++j) {
+        const double w = wq[j] * L[(long)j * ldn + e] * h;
+        const double *Fj = F + 2 * ((long)(f * nj + j) * (p + 1) + m);
+        sr = fma(w, Fj[0], sr);
+        si = fma(w, Fj[1], si);
+    }
+    coef[f * cstride + 2 * e] = sr;
+    coef[f * cstride + 2 * e + 1] = si;
+}
+
+// ----------------------------------------------------------------------------
+// Geometry and interfacial force on the de-aliasing grid (Table 2 with the
+// outward normal n = x_theta x x_phi / W and mean curvature
+// K = -(E N - 2 F M + G L)/(2 W^2); Sec. 1 force f = 2 sigma K n - grad sigma).
+// syn: 21 fields [x(3), xt(3), xp(3), xtt(3), xtp(3), xpp(3), Gam, Gam_t, Gam_p].
+// ----------------------------------------------------------------------------
+__global__ void k_force(int npt, const double *__restrict__ syn, int eos, double E, double xs, double sigma0,
+                        double *__restrict__ f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npt) return;
+    auto F = [&](int fld) { return syn[(long)fld * npt + i]; };
+    const double at[3] = {F(3), F(4), F(5)};
+    const double ap[3] = {F(6), F(7), F(8)};
+    const double Em = ap[0] * ap[0] + ap[1] * ap[1] + ap[2] * ap[2];
+    const double Fm = ap[0] * at[0] + ap[1] * at[1] + ap[2] * at[2];
+    const double Gm = at[0] * at[0] + at[1] * at[1] + at[2] * at[2];
+    const double W2 = Em * Gm - Fm * Fm;
+    const double W = sqrt(W2);
+    double n[3] = {at[1] * ap[2] - at[2] * ap[1], at[2] * ap[0] - at[0] * ap[2], at[0] * ap[1] - at[1] * ap[0]};
+    n[0] /= W; n[1] /= W; n[2] /= W;
+    const double Lm = F(15) * n[0] + F(16) * n[1] + F(17) * n[2];
+    const double Mm = F(12) * n[0] + F(13) * n[1] + F(14) * n[2];
+    const double Nm = F(9) * n[0] + F(10) * n[1] + F(11) * n[2];
+    const double K = -(Em * Nm - 2.0 * Fm * Mm + Gm * Lm) / (2.0 * W2);
+    double sig, ds;
+    if (eos == 0) { sig = sigma0; ds = 0.0; }
+    else if (eos == 1) { sig = 1.0 - E * xs * F(18); ds = -E * xs; }
+    else { const double g = 1.0 - xs * F(18); sig = 1.0 + E * log(g); ds = -E * xs / g; }
+    const double st = ds * F(19), sp = ds * F(20);
+    const double cpn = (Gm * sp - Fm * st) / W2, ctn = (Em * st - Fm * sp) / W2;
+    for (int c = 0; c < 3; ++c) f[(long)c * npt + i] = 2.0 * sig * K * n[c] - (cpn * ap[c] + ctn * at[c]);
+}
+
+// ----------------------------------------------------------------------------
+// Quadrature nodes of one drop on a degree-q grid: positions, the weighted
+// non-normalized normal wN = w_j (x_theta x x_phi), the weighted area element
+// wW = w_j |x_theta x x_phi|, w_j = (pi/q) w_j^G / sin theta_j (Sec. 2.1).
+// Accumulates the enclosed volume (1/3) sum wN . x into vol[0].
+// syn: 9 fields [x(3), xt(3), xp(3)], npt = 2q(q+1).
+// ----------------------------------------------------------------------------
+__global__ void k_nodes(int q, const double *__restrict__ syn, const double *__restrict__ wreg,
+                        double *__restrict__ sx, double *__restrict__ swN, double *__restrict__ swW, long sstride,
+                        double *__restrict__ vol)
+{
+    const int npt = npts(q);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double contrib = 0.0;
+    if (i < npt) {
+        auto F = [&](int fld) { return syn[(long)fld * npt + i]; };
+        const double w = wreg[i / (2 * q)];
+        const double at[3] = {F(3), F(4), F(5)};
+        const double ap[3] = {F(6), F(7), F(8)};
+        const double N[3] = {at[1] * ap[2] - at[2] * ap[1], at[2] * ap[0] - at[0] * ap[2], at[0] * ap[1] - at[1] * ap[0]};
+        for (int c = 0; c < 3; ++c) {
+            sx[c * sstride + i] = F(c);
+            swN[c * sstride + i] = w * N[c];
+        }
+        swW[i] = w * sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        contrib = w * (N[0] * F(0) + N[1] * F(1) + N[2] * F(2)) / 3.0;
+    }
+    if (vol) {
+        // wavefront reduction, one atomic per wave
+        for (int o = 32; o > 0; o >>= 1) contrib += __shfl_down(contrib, o, 64);
+        if ((threadIdx.x & 63) == 0 && contrib != 0.0) atomicAdd(vol, contrib);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Region split (Sec. 2.3): for every target t and source drop j != drop(t),
+// the distance to the nearest node of j's degree-p grid, compared with
+// A_tilde h_j and h_j. reg[t * nd + j] = 0 / 1 / 2, -1 for the own drop.
+// ----------------------------------------------------------------------------
+__global__ void k_classify(int T, int nd, const double *__restrict__ tx, long tstride, const int *__restrict__ tdrop,
+                           const double *__restrict__ sx, long sstride, const int *__restrict__ noff,
+                           const int *__restrict__ ncnt, const double *__restrict__ hj, double A,
+                           int8_t *__restrict__ reg, double *__restrict__ dist)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)T * nd) return;
+    const int j = idx % nd;
+    const int t = idx / nd;
+    if (tdrop[t] == j) {
+        reg[idx] = -1;
+        if (dist) dist[idx] = 0.0;
+        return;
+    }
+    const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
+    double best = 1e300;
+    const int o = noff[j], c = ncnt[j];
+    for (int s = 0; s < c; ++s) {
+        const double dx = x0 - sx[o + s], dy = y0 - sx[sstride + o + s], dz = z0 - sx[2 * sstride + o + s];
+        best = fmin(best, dx * dx + dy * dy + dz * dz);
+    }
+    const double d = sqrt(best);
+    const double h = hj[j];
+    reg[idx] = (d > A * h) ? 0 : (d > h ? 1 : 2);
+    if (dist) dist[idx] = d;
+}
+
+// ----------------------------------------------------------------------------
+// Rotation of the expansion so that each grid target of a drop is at the
+// north pole (Appendix B with gamma = 0):
+//   Re f'^mu_n = sum_nu A+_{nu mu}(theta_j) Re(e^{i nu phi_k} f_n^nu)
+//   Im f'^mu_n = sum_nu A-_{nu mu}(theta_j) Im(e^{i nu phi_k} f_n^nu)
+// R[t][field][tri(n,mu)] complex for fields 0..2 (x) and 3..5 (density).
+// ----------------------------------------------------------------------------
+__global__ void k_rotate(int p, int nt, const double *__restrict__ Ap, const double *__restrict__ Am,
+                         const double *__restrict__ cs, const double *__restrict__ xc, long xstride,
+                         const double *__restrict__ dc, long dstride, double *__restrict__ R)
+{
+    const int nc = ncoef(p);
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nt * 6 * nc) return;
+    const int e = idx % nc;
+    const long r = idx / nc;
+    const int f = r % 6;
+    const int t = r / 6;
+    int n = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+    while (tri(n + 1, 0) <= e) ++n;
+    while (tri(n, 0) > e) --n;
+    const int mu = e - tri(n, 0);
+    const int j = t / (2 * p), k = t % (2 * p);
+    const int nk = 2 * p;
+    const double *c = (f < 3) ? xc + f * xstride : dc + (f - 3) * dstride;
+    const size_t base = rot_lat_size(p) * j + rot_off(n);
+    const double *ap = Ap + base, *am = Am + base;
+    double re = 0.0, im = 0.0;
+    int ph = 0;
+    for (int nu = 0; nu <= n; ++nu) {
+        const double cr = c[2 * tri(n, nu)], ci = c[2 * tri(n, nu) + 1];
+        const double cc = cs[ph], ss = cs[nk + ph];
+        re = fma(ap[nu * (n + 1) + mu], cr * cc - ci * ss, re);
+        im = fma(am[nu * (n + 1) + mu], cr * ss + ci * cc, im);
+        ph += k;
+        if (ph >= nk) ph -= nk;
+    }
+    R[2 * idx] = re;
+    R[2 * idx + 1] = im;
+}
+
+// ----------------------------------------------------------------------------
+// Singular self-integral (Sec. 2.2, Theorem 1) at every grid target of one
+// drop, one workgroup per target. On the degree-qs rotated grid:
+//   Q = sum_{j',k'} omega_{j'} K(x0, x'_{j'k'}) rho'_{j'k'} W'_{j'k'},
+//   omega_{j'} = (pi/qs) w^G_{j'} [sum_{n<=qs} P_n(t_{j'})] 2 sin(theta_{j'}/2) / sin(theta_{j'}),
+// K the Stokeslet (kind 0, density f) or the stresslet (kind 1, density u).
+// Stage A: Legendre sums G = sum_n C^mu_n L_n^mu(t_{j'}) for JB latitudes into LDS
+// (9 sums: x, dx/dtheta, density); stage B: Fourier sums at k' and k'+qs
+// (even/odd orders) and the kernel, accumulated per thread; then a block reduction.
+// ----------------------------------------------------------------------------
+template <int JB>
+__global__ __launch_bounds__(256) void k_singular(int p, int qs, int kind, const double *__restrict__ R,
+                                                  const double *__restrict__ Ls, int ldn,
+                                                  const double *__restrict__ wsing,
+                                                  const double *__restrict__ cs, double *__restrict__ out,
+                                                  long ostride, double scale)
+{
+    extern __shared__ double G[];  // [JB][9][p+1][2]
+    __shared__ double x0s[3];
+    __shared__ double red[3][4];
+    const int t = blockIdx.x;
+    const int nc = ncoef(p);
+    const int nk = 2 * qs;
+    const double *Rt = R + (long)t * 6 * nc * 2;
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int n = 0; n <= p; ++n) s += Rt[2 * (threadIdx.x * nc + tri(n, 0))] * sqrt(2.0 * n + 1.0) * kInvSqrt4Pi;
+        x0s[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const double x0 = x0s[0], y0 = x0s[1], z0 = x0s[2];
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    const int P1 = p + 1;
+    for (int jb0 = 0; jb0 <= qs; jb0 += JB) {
+        const int nb = min(JB, qs + 1 - jb0);
+        // stage A
+        for (int idx = threadIdx.x; idx < 9 * P1; idx += blockDim.x) {
+            const int type = idx / P1, mu = idx % P1;
+            const int field = (type < 6) ? type % 3 : type - 3;
+            const int kl = (type >= 3 && type < 6) ? 1 : 0;
+            const double *C = Rt + 2 * field * nc;
+            double sr[JB], si[JB];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) { sr[b] = 0.0; si[b] = 0.0; }
+            const double *Lb = Ls + ((long)kl * (qs + 1) + jb0) * ldn;
+            for (int n = mu; n <= p; ++n) {
+                const double cr = C[2 * tri(n, mu)], ci = C[2 * tri(n, mu) + 1];
+#pragma unroll
+                for (int b = 0; b < JB; ++b) {
+                    if (b < nb) {
+                        const double l = Lb[(long)b * ldn + tri(n, mu)];
+                        sr[b] = fma(cr, l, sr[b]);
+                        si[b] = fma(ci, l, si[b]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < JB; ++b)
+                if (b < nb) {
+                    G[2 * ((b * 9 + type) * P1 + mu)] = sr[b];
+                    G[2 * ((b * 9 + type) * P1 + mu) + 1] = si[b];
+                }
+        }
+        __syncthreads();
+        // stage B
+        for (int idx = threadIdx.x; idx < nb * qs; idx += blockDim.x) {
+            const int b = idx / qs, kp = idx % qs;
+            const double *Gb = G + 2 * b * 9 * P1;
+            double ev[12], od[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) { ev[i] = 0.0; od[i] = 0.0; }
+            int e = 0;
+            for (int mu = 0; mu <= p; ++mu) {
+                const double c = cs[e], s = cs[nk + e];
+                const double wm = mu ? 2.0 : 1.0;
+                double v[12];
+#pragma unroll
+                for (int ty = 0; ty < 9; ++ty) {
+                    const double gr = Gb[2 * (ty * P1 + mu)], gi = Gb[2 * (ty * P1 + mu) + 1];
+                    v[ty] = wm * (gr * c - gi * s);
+                }
+#pragma unroll
+                for (int c3 = 0; c3 < 3; ++c3) {
+                    const double gr = Gb[2 * (c3 * P1 + mu)], gi = Gb[2 * (c3 * P1 + mu) + 1];
+                    v[9 + c3] = -wm * mu * (gi * c + gr * s);
+                }
+                if (mu & 1) {
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) od[i] += v[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) ev[i] += v[i];
+                }
+                e += kp;
+                if (e >= nk) e -= nk;
+            }
+            const double om = wsing[jb0 + b];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double sg = side ? -1.0 : 1.0;
+                double v[12];
+#pragma unroll
+                for (int i = 0; i < 12; ++i) v[i] = ev[i] + sg * od[i];
+                // v: x(0..2), x_theta(3..5), density(6..8), x_phi(9..11)
+                const double Nx = v[4] * v[11] - v[5] * v[10];
+                const double Ny = v[5] * v[9] - v[3] * v[11];
+                const double Nz = v[3] * v[10] - v[4] * v[9];
+                const double hx = x0 - v[0], hy = y0 - v[1], hz = z0 - v[2];
+                const double r2 = hx * hx + hy * hy + hz * hz;
+                const double rinv = 1.0 / sqrt(r2);
+                const double hd = hx * v[6] + hy * v[7] + hz * v[8];
+                if (kind == 0) {
+                    const double Wd = om * sqrt(Nx * Nx + Ny * Ny + Nz * Nz) * rinv;
+                    const double r2i = rinv * rinv;
+                    acc0 += Wd * (v[6] + hx * hd * r2i);
+                    acc1 += Wd * (v[7] + hy * hd * r2i);
+                    acc2 += Wd * (v[8] + hz * hd * r2i);
+                } else {
+                    const double hn = hx * Nx + hy * Ny + hz * Nz;
+                    const double r5i = rinv * rinv * rinv * rinv * rinv;
+                    const double s = -6.0 * om * hd * hn * r5i;
+                    acc0 += s * hx;
+                    acc1 += s * hy;
+                    acc2 += s * hz;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // block reduction (256 threads = 4 wavefronts)
+    for (int o = 32; o > 0; o >>= 1) {
+        acc0 += __shfl_down(acc0, o, 64);
+        acc1 += __shfl_down(acc1, o, 64);
+        acc2 += __shfl_down(acc2, o, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[0][wv] = acc0; red[1][wv] = acc1; red[2][wv] = acc2; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const double s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        out[threadIdx.x * ostride + t] += scale * s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Pair sums (Sec. 1 kernels by the regular rule of Sec. 2.1 on the standard
+// or upsampled grid of a source drop, Sec. 2.3). One workgroup per work item:
+// up to 256 targets (one per thread, from an index list) against a range of
+// source nodes staged through LDS in tiles of 256.
+// kind 0 (SL): sum wW G(x0, x) f;   kind 1 (DL): sum -6 xh (xh.u)(xh.wN) / r^5.
+// Results are added atomically: out[c][t] += w * sum.
+// ----------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
+                                              const double *__restrict__ tx, long tstride,
+                                              const double *__restrict__ sx, const double *__restrict__ swN,
+                                              const double *__restrict__ swW, const double *__restrict__ sd,
+                                              long sstride, double *__restrict__ out, long ostride)
+{
+    constexpr int NV = KIND == 0 ? 7 : 9;
+    __shared__ double sh[NV][256];
+    const PairWork w = work[blockIdx.x];
+    const bool active = threadIdx.x < w.ntgt;
+    const int t = active ? tlist[w.tlist_off + threadIdx.x] : 0;
+    const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int s0 = 0; s0 < w.nsrc; s0 += 256) {
+        const int ns = min(256, w.nsrc - s0);
+        if (threadIdx.x < ns) {
+            const long s = w.src_off + s0 + threadIdx.x;
+            sh[0][threadIdx.x] = sx[s];
+            sh[1][threadIdx.x] = sx[sstride + s];
+            sh[2][threadIdx.x] = sx[2 * sstride + s];
+            sh[3][threadIdx.x] = sd[s];
+            sh[4][threadIdx.x] = sd[sstride + s];
+            sh[5][threadIdx.x] = sd[2 * sstride + s];
+            if (KIND == 0) {
+                sh[6][threadIdx.x] = swW[s];
+            } else {
+                sh[6][threadIdx.x] = swN[s];
+                sh[7][threadIdx.x] = swN[sstride + s];
+                sh[8][threadIdx.x] = swN[2 * sstride + s];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            for (int u = 0; u < ns; ++u) {
+                const double hx = x0 - sh[0][u], hy = y0 - sh[1][u], hz = z0 - sh[2][u];
+                const double r2 = hx * hx + hy * hy + hz * hz;
+                const double ri = 1.0 / sqrt(r2);
+                const double hd = hx * sh[3][u] + hy * sh[4][u] + hz * sh[5][u];
+                if (KIND == 0) {
+                    const double wr = sh[6][u] * ri;
+                    const double hdr = hd * ri * ri;
+                    a0 += wr * (sh[3][u] + hx * hdr);
+                    a1 += wr * (sh[4][u] + hy * hdr);
+                    a2 += wr * (sh[5][u] + hz * hdr);
+                } else {
+                    const double hn = hx * sh[6][u] + hy * sh[7][u] + hz * sh[8][u];
+                    const double r2i = ri * ri;
+                    const double s = -6.0 * hd * hn * r2i * r2i * ri;
+                    a0 += s * hx;
+                    a1 += s * hy;
+                    a2 += s * hz;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        atomicAdd(&out[t], w.w * a0);
+        atomicAdd(&out[ostride + t], w.w * a1);
+        atomicAdd(&out[2 * ostride + t], w.w * a2);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Pointwise combinations and GMRES vector kernels (FP64).
+// ----------------------------------------------------------------------------
+// b = 2 (U0 + gradU x) + a * s, over T targets (component-major)
+__global__ void k_rhs(int T, const double *__restrict__ tx, long tstride, const double *__restrict__ s, double a,
+                      double U00, double U01, double U02, const double *__restrict__ gU, double *__restrict__ b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const double x = tx[t], y = tx[tstride + t], z = tx[2 * tstride + t];
+    const double U0[3] = {U00, U01, U02};
+    for (int c = 0; c < 3; ++c) {
+        const double ui = U0[c] + gU[3 * c] * x + gU[3 * c + 1] * y + gU[3 * c + 2] * z;
+        b[c * tstride + t] = 2.0 * ui + a * s[c * tstride + t];
+    }
+}
+
+__global__ void k_scale_add(long n, double a, const double *__restrict__ x, double b, double *__restrict__ y)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+// y_i = s_i * x_i - y_i with s_i = (lambda_drop(i) + 1): the Galerkin operator
+// (lambda + 1) u - P[D u], entries grouped by a per-entry scale array.
+__global__ void k_op_combine(long n, const double *__restrict__ sc, const double *__restrict__ x, double *__restrict__ y)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = sc[i] * x[i] - y[i];
+}
+
+// h[i] = V_i . w for i < k (one block per i), V row-major with leading dim ld.
+__global__ __launch_bounds__(256) void k_dots(long n, int k, const double *__restrict__ V, long ld,
+                                              const double *__restrict__ w, double *__restrict__ h)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x;
+    if (i >= k) return;
+    double s = 0.0;
+    for (long e = threadIdx.x; e < n; e += blockDim.x) s = fma(V[i * ld + e], w[e], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) h[i] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// w -= sum_i h[i] V_i ; hacc[i] += h[i] (accumulates the two Gram-Schmidt passes)
+__global__ void k_orth_update(long n, int k, const double *__restrict__ V, long ld, const double *__restrict__ h,
+                              double *__restrict__ w)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = w[e];
+    for (int i = 0; i < k; ++i) s = fma(-h[i], V[i * ld + e], s);
+    w[e] = s;
+}
+
+__global__ void k_add_into(int k, const double *__restrict__ a, double *__restrict__ b)
+{
+    const int i = threadIdx.x;
+    if (i < k) b[i] += a[i];
+}
+
+// v = w / ||w||, norm written to nrm[0] (single block).
+__global__ __launch_bounds__(256) void k_normalize(long n, const double *__restrict__ w, double *__restrict__ v,
+                                                   double *__restrict__ nrm)
+{
+    __shared__ double red[4];
+    __shared__ double tot;
+    double s = 0.0;
+    for (long e = threadIdx.x; e < n; e += blockDim.x) s = fma(w[e], w[e], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tot = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+        nrm[0] = tot;
+    }
+    __syncthreads();
+    const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+    if (v)
+        for (long e = threadIdx.x; e < n; e += blockDim.x) v[e] = w[e] * inv;
+}
+
+// x += sum_i y[i] V_i
+__global__ void k_lincomb(long n, int k, const double *__restrict__ V, long ld, const double *__restrict__ y,
+                          double *__restrict__ x)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = x[e];
+    for (int i = 0; i < k; ++i) s = fma(y[i], V[i * ld + e], s);
+    x[e] = s;
+}
+
+// ============================================================================
+// Host launchers
+// ============================================================================
+static inline unsigned nblk(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+void launch_synth(hipStream_t st, int p, int q, int nmax, const double *L /*[3][q+1][ncoef(nmax)]*/,
+                  const double *cs, int nf, const double *coef, long cstride, int dt, int dp, double *G,
+                  double *out, long ostride)
+{
+    const int nj = q + 1, ldn = ncoef(nmax);
+    const long n1 = (long)nf * nj * (p + 1);
+    hipLaunchKernelGGL(k_synth_leg, dim3(nblk(n1)), dim3(256), 0, st, p, nj, ldn, L + (long)dt * nj * ldn, nf, coef,
+                       cstride, G);
+    const long n2 = (long)nf * nj * 2 * q;
+    hipLaunchKernelGGL(k_synth_fourier, dim3(nblk(n2)), dim3(256), 0, st, p, q, nj, dp, G, cs, nf, out, ostride);
+}
+
+void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, const double *wq, const double *cs,
+                    int nf, const double *v, long vstride, double *F, double *coef, long cstride)
+{
+    const long n1 = (long)nf * (q + 1) * (p + 1);
+    hipLaunchKernelGGL(k_anal_fourier, dim3(nblk(n1)), dim3(256), 0, st, p, q, v, vstride, cs, nf, F);
+    const long n2 = (long)nf * ncoef(p);
+    hipLaunchKernelGGL(k_anal_leg, dim3(nblk(n2)), dim3(256), 0, st, p, q, ncoef(nmax), L, wq, nf, F, coef,
+                       cstride);
+}
+
+void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f)
+{
+    hipLaunchKernelGGL(k_force, dim3(nblk(npt)), dim3(256), 0, st, npt, syn, eos, E, xs, sigma0, f);
+}
+
+void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, double *sx, double *swN,
+                  double *swW, long sstride, double *vol)
+{
+    hipLaunchKernelGGL(k_nodes, dim3(nblk(npts(q))), dim3(256), 0, st, q, syn, wreg, sx, swN, swW, sstride, vol);
+}
+
+void launch_classify(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
+                     const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
+                     int8_t *reg, double *dist)
+{
+    hipLaunchKernelGGL(k_classify, dim3(nblk((long)T * nd)), dim3(256), 0, st, T, nd, tx, tstride, tdrop, sx,
+                       sstride, noff, ncnt, hj, A, reg, dist);
+}
+
+void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, const double *cs, const double *xc,
+                   long xstride, const double *dc, long dstride, double *R)
+{
+    const int nt = npts(p);
+    hipLaunchKernelGGL(k_rotate, dim3(nblk((long)nt * 6 * ncoef(p))), dim3(256), 0, st, p, nt, Ap, Am, cs, xc,
+                       xstride, dc, dstride, R);
+}
+
+int singular_lds_bytes(int p, int jb) { return jb * 9 * (p + 1) * 2 * (int)sizeof(double); }
+
+void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
+                     const double *wsing, const double *cs, double *out, long ostride, double scale)
+{
+    const int nt = npts(p);
+    if (p <= 48) {
+        hipLaunchKernelGGL(k_singular<8>, dim3(nt), dim3(256), singular_lds_bytes(p, 8), st, p, qs, kind, R, Ls, ldn,
+                           wsing, cs, out, ostride, scale);
+    } else {
+        hipLaunchKernelGGL(k_singular<4>, dim3(nt), dim3(256), singular_lds_bytes(p, 4), st, p, qs, kind, R, Ls, ldn,
+                           wsing, cs, out, ostride, scale);
+    }
+}
+
+void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
+                 long tstride, const double *sx, const double *swN, const double *swW, const double *sd,
+                 long sstride, double *out, long ostride)
+{
+    if (nwork <= 0) return;
+    if (kind == 0)
+        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
+                           sstride, out, ostride);
+    else
+        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
+                           sstride, out, ostride);
+}
+
+void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const double *s, double a, const double *U0,
+                const double *gU_dev, double *b)
+{
+    hipLaunchKernelGGL(k_rhs, dim3(nblk(T)), dim3(256), 0, st, T, tx, tstride, s, a, U0[0], U0[1], U0[2], gU_dev, b);
+}
+
+void launch_scale_add(hipStream_t st, long n, double a, const double *x, double b, double *y)
+{
+    hipLaunchKernelGGL(k_scale_add, dim3(nblk(n)), dim3(256), 0, st, n, a, x, b, y);
+}
+
+void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x, double *y)
+{
+    hipLaunchKernelGGL(k_op_combine, dim3(nblk(n)), dim3(256), 0, st, n, sc, x, y);
+}
+
+void launch_dots(hipStream_t st, long n, int k, const double *V, long ld, const double *w, double *h)
+{
+    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, st, n, k, V, ld, w, h);
+}
+
+void launch_orth_update(hipStream_t st, long n, int k, const double *V, long ld, const double *h, double *w)
+{
+    hipLaunchKernelGGL(k_orth_update, dim3(nblk(n)), dim3(256), 0, st, n, k, V, ld, h, w);
+}
+
+void launch_add_into(hipStream_t st, int k, const double *a, double *b)
+{
+    hipLaunchKernelGGL(k_add_into, dim3(1), dim3(256), 0, st, k, a, b);
+}
+
+void launch_normalize(hipStream_t st, long n, const double *w, double *v, double *nrm)
+{
+    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(256), 0, st, n, w, v, nrm);
+}
+
+void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x)
+{
+    hipLaunchKernelGGL(k_lincomb, dim3(nblk(n)), dim3(256), 0, st, n, k, V, ld, y, x);
+}
+
+}  // namespace bim

@@ -97,20 +97,18 @@ def perturbed_sphere(rng, p, R, c, A):
     return xc
 
 
-def bound_radius(xc: np.ndarray, c) -> float:
-    """Upper bound of max |x - c| over the surface: the sum of coefficient
-    moduli times the sup norm sqrt((2l+1)/4pi) of each basis function."""
-    p = int(round((np.sqrt(8 * xc.shape[1] + 1) - 3) / 2))
-    b2 = 0.0
+def perturbation_bound(d: np.ndarray) -> float:
+    """Upper bound of max |dx| over the sphere for a perturbation field d
+    (3, ncoef, 2): per component, the sum of coefficient moduli (doubled for
+    m > 0) times the sup norm sqrt((2l+1)/4pi) of the basis function."""
+    p = int(round((np.sqrt(8 * d.shape[1] + 1) - 3) / 2))
     tot = np.zeros(3)
     for k in range(3):
-        for l in range(1, p + 1):
+        for l in range(0, p + 1):
             sup = np.sqrt((2 * l + 1) / (4 * np.pi))
             for m in range(0, l + 1):
-                mod = np.hypot(*xc[k, idx(l, m)])
-                tot[k] += (1.0 if m == 0 else 2.0) * mod * sup
-    b2 = np.sqrt(np.sum(tot ** 2))
-    return float(b2)
+                tot[k] += (1.0 if m == 0 else 2.0) * np.hypot(*d[k, idx(l, m)]) * sup
+    return float(np.sqrt(np.sum(tot ** 2)))
 
 
 def random_centres(rng, radii_bound, box_lo, box_hi, gap, max_tries=200000):
@@ -161,15 +159,18 @@ def two_drops(p=32, A=0.1, gap=0.2, lams=(1.0, 5.0), seed=2) -> Workload:
 
 def many_drops(nd=64, p=16, A=0.05, box=12.0, gap=0.3, seed=3) -> Workload:
     """nd drops (default 64) of degree p (default 16), radii U[0.8, 1.2],
-    centres by random sequential addition in a cube of side 12 with bounding
-    gap >= 0.3, lambda uniform in {1, 2, 5}, uniform tension; every pair on the
-    2x upsampled grid (Omega_1 everywhere)."""
+    centres uniform in a cube of side 12 by random sequential addition with
+    bounding-sphere gap >= 0.3 (restricting centres to [R, 12 - R]^3 would need
+    a packing beyond the jamming limit of sequential addition), lambda uniform
+    in {1, 2, 5}, uniform tension; every pair on the 2x upsampled grid
+    (Omega_1 everywhere)."""
     rng = np.random.default_rng(seed)
     R = rng.uniform(0.8, 1.2, size=nd)
-    shapes = [(sphere(p) + perturbation(rng, p, A)) for _ in range(nd)]
-    bounds = [bound_radius(s * r, (0, 0, 0)) for s, r in zip(shapes, R)]
-    lo = [b for b in bounds]
-    hi = [box - b for b in bounds]
+    perts = [perturbation(rng, p, A) for _ in range(nd)]
+    shapes = [sphere(p) + d for d in perts]
+    bounds = [r * (1.0 + perturbation_bound(d)) for d, r in zip(perts, R)]
+    lo = [0.0] * nd
+    hi = [box] * nd
     cs = random_centres(rng, bounds, lo, hi, gap)
     lams = rng.choice([1.0, 2.0, 5.0], size=nd)
     drops = []
