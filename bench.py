@@ -1,14 +1,21 @@
 """Benchmark: target-point Stokes SL+DL evaluations per second on one MI355X.
 
-A step is one full velocity evaluation of the two-drop workload (degree 32
-drops 2.2 radii apart, viscosity ratios 1 and 5, linear equation of state):
-geometry and force, region split, single layer (singular + pair sums),
-Galerkin projection and GMRES on the second-kind equation (tolerance 1e-10),
-velocity synthesis. Target-point evaluations = targets x (1 + operator
+Workload (two drops, the configuration the metric is quoted on): degree-32
+drops with N(0,1) 0.1 l^-3 perturbations, centres 2.2 apart (gap 0.2),
+viscosity ratios 1 and 5, surfactant Gamma = 1 + 0.2 Y_2^0 with the linear
+equation of state, Omega_1 threshold 5h with 4x upsampling, GMRES 1e-10.
+
+A step is one full velocity evaluation: geometry and force, region split,
+single layer (singular + pair sums; the stored singular double-layer rows are
+built in the same pass), Galerkin projection, GMRES on the second-kind
+equation, velocity synthesis. Target-point evaluations = targets x (1 + operator
 applications in the solve). Inputs are resident in device memory before the
 timed region; the output is written to a device tensor.
 
-Prints one JSON line (see the design doc for the roofline and baseline fields).
+Extra fields: "roofline" for the kernel with the largest share of the timed
+region (event times measured live on the library's stream, algorithmic work
+from the library's own counts), and "cpu_baseline": the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -21,45 +28,99 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# MI355X peaks: FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz), HBM3E
+PEAK = {"alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+BOUND = {"sing_fused": "alu", "pair_sl": "alu", "pair_dl": "alu", "dl_apply": "hbm",
+         "synthesis": "hbm", "analysis": "hbm", "sing_v1": "alu", "sing_rotate": "alu", "classify": "alu"}
+KERNELS = list(BOUND)
+
+
+def workload():
+    import workloads as W
+    return W.two_drops()
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The oracle on a bounded sample: single and double layer (singular rule
+    plus pair sums) at batches of grid targets, alternating drops, until the
+    time budget is used. Returns target-point evaluations per second."""
+    import numpy as np
+
+    import oracle
+    o = oracle.Options(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom,
+                       eos=wl.eos, E=wl.E, xs=wl.xs, sigma0=wl.sigma0)
+    s = oracle.System([oracle.Drop(d.p, d.xc, d.lam, d.gc) for d in wl.drops], o)
+    f = [s.force(i) for i in range(len(wl.drops))]
+    for i in range(len(wl.drops)):     # setup outside the clock: regions and tables
+        s.regions(i, 1 - i)
+        s.layer(i, f, 0, targets=np.arange(2))
+    rng = np.random.default_rng(0)
+    evals, t_used, batches = 0, 0.0, 0
+    while t_used < budget_s and batches < 64:
+        i = batches % len(wl.drops)
+        tg = np.sort(rng.choice(oracle.npts(wl.drops[i].p), 64, replace=False))
+        t0 = time.perf_counter()
+        s.layer(i, f, 0, targets=tg)            # single layer at the sample
+        s.layer(i, f, 1, targets=tg)            # double layer at the sample
+        t_used += time.perf_counter() - t0
+        evals += 2 * len(tg)
+        batches += 1
+    return {"value": evals / t_used, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{evals} target-point evaluations (single and double layer, {batches} batches of 64 grid "
+                      f"targets alternating drops) in {t_used:.1f} s"}
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--singular-path", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1707_02156_amd as B
-    import workloads as W
 
     torch.cuda.set_device(0)
+    wl = workload()
     stream = torch.cuda.Stream()
-    wl = W.two_drops()
     with torch.cuda.stream(stream):
         ctx = B.Context(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom,
-                        gmres_tol=wl.gmres_tol, stream=stream.cuda_stream)
+                        gmres_tol=wl.gmres_tol, singular_path=args.singular_path, stream=stream.cuda_stream)
         ctx.set_drops([d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops])
         ctx.set_tension([d.gc for d in wl.drops], wl.eos, wl.E, wl.xs)
         out = torch.zeros(3 * ctx.ntargets(), dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             B.bim_eval_velocity(ctx.h, out)
         torch.cuda.synchronize()
+        B.bim_profile(ctx.h, 1)
         reps = []
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             reps.append(B.bim_eval_velocity(ctx.h, out))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        prof = {k: B.bim_profile_query(ctx.h, k) for k in KERNELS}
+        B.bim_profile(ctx.h, 0)
     ms = (t1 - t0) * 1e3 / args.steps
     T = ctx.ntargets()
     evals = sum(T * (1 + r.n_matvec) for r in reps) / args.steps
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    bound = BOUND[dom]
+    peak, unit = PEAK[bound]
+    per_launch_s = d["ms"] * 1e-3 / max(d["launches"], 1)
+    if bound == "hbm":
+        achieved = d["bytes"] / max(d["launches"], 1) / per_launch_s / 1e9
+    else:
+        achieved = d["flops"] / max(d["launches"], 1) / per_launch_s / 1e12
     res = {
         "metric": "target-pt Stokes SL+DL evals/s",
         "value": evals / (ms * 1e-3),
@@ -73,12 +134,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "two drops, p=32, gap 0.2, lambda (1,5), linear EOS, GMRES 1e-10, U=4",
+        "config": {"workload": "two drops p=32 (gap 0.2, lambda 1 and 5, linear EOS, U=4, A=5h), full velocity "
+                               "solve, GMRES 1e-10",
                    "targets": T, "gmres_iterations": reps[-1].gmres_iterations,
                    "operator_applications": reps[-1].n_matvec},
+        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None,
+                     "avg_launch_us": per_launch_s * 1e6, "launches": d["launches"],
+                     "share_of_step": d["ms"] / (ms * args.steps)},
+        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items() if v["launches"]},
     }
-    print(json.dumps(res), flush=True)
     ctx.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -76,6 +76,9 @@ typedef struct {
     double gmres_tol;    /* relative residual tolerance (Euclidean norm of coefficients) */
     int gmres_restart;   /* Krylov dimension before restart */
     int gmres_maxit;     /* total iteration cap */
+    int singular_path;   /* 0: fused singular kernel, with the drop's double layer on itself stored
+                            as a matrix (N(p) x 6 x (p+1)(p+2) doubles per drop) when a double layer
+                            is applied; 1: rotation and quadrature on every application (no matrix) */
     void *stream;        /* hipStream_t to run on; NULL = the context creates its own */
 } bim_options;
 
@@ -94,7 +97,8 @@ int bim_version(void);
 /* Static string for a status code. */
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
- * gmres_tol 1e-10, restart 50, maxit 500, device 0, FP64, stream NULL. */
+ * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
+ * stream NULL. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */
@@ -167,6 +171,18 @@ int bim_sh_analyze(bim_ctx ctx, int q, int p, int nf, const double *grid, double
 
 /* Block until all work queued by the context is complete. */
 int bim_synchronize(bim_ctx ctx);
+
+/* Kernel timing: HIP events recorded on the context stream around each launch
+ * of the main kernels. enable = 1 clears the totals and starts recording,
+ * 0 stops. Kernel names: "sing_fused" (fused singular rule, with the double
+ * layer rows when built), "dl_apply" (stored double layer times a density),
+ * "pair_sl", "pair_dl" (pair sums), "synthesis", "analysis", "classify",
+ * "sing_rotate" and "sing_v1" (per-application singular path). */
+int bim_profile(bim_ctx ctx, int enable);
+/* Totals since the last enable: launches, summed event time (ms), algorithmic
+ * flops and bytes of those launches. Unknown names give zeros. Synchronizes
+ * the context stream. */
+int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, double *flops, double *bytes);
 
 /* Host-side tables (no device needed; the same routines build the device
  * tables). Gauss-Legendre nodes t[0..q] (descending, theta ascending) and

@@ -36,6 +36,7 @@ class bim_options(ctypes.Structure):
         ("gmres_tol", ctypes.c_double),
         ("gmres_restart", ctypes.c_int),
         ("gmres_maxit", ctypes.c_int),
+        ("singular_path", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -77,6 +78,8 @@ EXPORTS = {
     "bim_sh_synthesize": ([_vp, _i, _i, _i, _vp, _i, _i, _vp, _i], _i),
     "bim_sh_analyze": ([_vp, _i, _i, _i, _vp, _vp, _i], _i),
     "bim_synchronize": ([_vp], _i),
+    "bim_profile": ([_vp, _i], _i),
+    "bim_profile_query": ([_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp], _i),
     "bim_host_gauss_legendre": ([_i, _vp, _vp], _i),
     "bim_host_legendre": ([_i, _d, _vp, _vp, _vp], _i),
     "bim_host_wigner_d": ([_i, _d, _vp], _i),
@@ -224,6 +227,18 @@ def bim_sh_analyze(ctx, q, p, nf, grid, coef):
 
 def bim_synchronize(ctx):
     return _check(ctx, lib().bim_synchronize(ctx))
+
+
+def bim_profile(ctx, enable):
+    return _check(ctx, lib().bim_profile(ctx, int(enable)))
+
+
+def bim_profile_query(ctx, name):
+    n = ctypes.c_int()
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(ctx, lib().bim_profile_query(ctx, name.encode(), ctypes.addressof(n), ctypes.addressof(ms),
+                                        ctypes.addressof(fl), ctypes.addressof(by)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
 
 
 def bim_host_gauss_legendre(q):

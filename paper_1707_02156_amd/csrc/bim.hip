@@ -48,6 +48,25 @@ void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, c
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
                  long tstride, const double *sx, const double *swN, const double *swW, const double *sd,
                  long sstride, double *out, long ostride);
+struct SingArgs {
+    int p, qs, nt;
+    const double *Ap, *Am, *ApT, *AmT;
+    const double *csp;
+    const double *xc;
+    long xstride;
+    const double *dc;
+    long dstride;
+    const double *L;
+    const double *wsing;
+    double *out_sl;
+    long ostride;
+    double scale;
+    double *M;
+};
+bool launch_sing_fused(hipStream_t st, bool sl, bool dl, const SingArgs &a);
+bool sing_fused_fits(int p, int qs, bool sl, bool dl);
+void launch_dl_apply(hipStream_t st, int nt, int nc2, const double *M, const double *u, long ustride, double w,
+                     double *out, long ostride);
 void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const double *s, double a, const double *U0,
                 const double *gU_dev, double *b);
 void launch_scale_add(hipStream_t st, long n, double a, const double *x, double b, double *y);
@@ -113,7 +132,7 @@ struct GridTab {
 
 struct RotTab {
     int p = 0;
-    DBuf Ap, Am;
+    DBuf Ap, Am, ApT, AmT;
 };
 
 struct Drop {
@@ -154,27 +173,119 @@ struct Ctx {
         std::vector<double> wt;
         DBuf d0, d1;
         int n0 = 0, n1 = 0;
+        double pairs0 = 0.0, pairs1 = 0.0;  // target-source pairs per application
     };
     std::vector<std::unique_ptr<WList>> wlists;
     std::vector<int8_t> reg_h;
     int n_om1 = 0, n_om2 = 0;
     DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
     DBuf synbuf, Gbuf, Rbuf, Fbuf;
+    std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
+    std::vector<char> Mok;
     DBuf V, hbuf, ybuf, wvec, xsol, rvec;
     double *hhost = nullptr;       // pinned
 
     bool nodes_ok = false, force_ok = false, regions_ok = false;
+
+    // kernel timing with HIP events on the context stream (bim_profile)
+    struct ProfEntry {
+        int launches = 0;
+        double ms = 0.0, flops = 0.0, bytes = 0.0;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> pend;
+    };
+    bool prof_on = false;
+    std::map<std::string, ProfEntry> prof;
+    std::vector<hipEvent_t> evpool;
     std::map<std::pair<int, int>, std::unique_ptr<GridTab>> grids;
     std::map<int, std::unique_ptr<RotTab>> rots;
 
     ~Ctx()
     {
+        for (auto &kv : prof)
+            for (auto &pr : kv.second.pend) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        for (auto e : evpool) (void)hipEventDestroy(e);
         grids.clear();
         rots.clear();
         if (hhost) (void)hipHostFree(hhost);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
+
+// --------------------------------------------------------------------------
+// kernel timing
+// --------------------------------------------------------------------------
+static hipEvent_t prof_event(Ctx &c)
+{
+    if (!c.evpool.empty()) {
+        hipEvent_t e = c.evpool.back();
+        c.evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    return e;
+}
+
+// Brackets the launches issued in its scope with events when profiling is on;
+// records the algorithmic flops and bytes of those launches.
+struct ProfScope {
+    Ctx &c;
+    Ctx::ProfEntry *e = nullptr;
+    hipEvent_t a = nullptr;
+    ProfScope(Ctx &cc, const char *name, double flops, double bytes) : c(cc)
+    {
+        if (!c.prof_on) return;
+        e = &c.prof[name];
+        e->flops += flops;
+        e->bytes += bytes;
+        e->launches += 1;
+        a = prof_event(c);
+        HIPC(hipEventRecord(a, c.stream));
+    }
+    ~ProfScope()
+    {
+        if (!e) return;
+        hipEvent_t b = prof_event(c);
+        if (hipEventRecord(b, c.stream) == hipSuccess) e->pend.emplace_back(a, b);
+    }
+};
+
+static void prof_drain(Ctx &c)
+{
+    HIPC(hipStreamSynchronize(c.stream));
+    for (auto &kv : c.prof) {
+        for (auto &pr : kv.second.pend) {
+            float ms = 0.0f;
+            HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
+            kv.second.ms += ms;
+            c.evpool.push_back(pr.first);
+            c.evpool.push_back(pr.second);
+        }
+        kv.second.pend.clear();
+    }
+}
+
+// Algorithmic work of the fused singular kernel per target.
+static double sing_flops_per_target(int p, int qs, bool sl, bool dl)
+{
+    const double nc = ncoef(p), P1 = p + 1, Q1 = qs + 1, KK = qs / 2 + 1, NP = npts(qs);
+    const double rot = (double)rot_lat_size(p);
+    const double nx = sl ? 6.0 : 3.0;
+    double f = nx * nc * 6.0 + nx * rot * 4.0;                     // phases + rotation
+    f += (sl ? 9.0 : 6.0) * Q1 * nc * 4.0;                          // Legendre sums
+    f += (sl ? 12.0 : 9.0) * Q1 * KK * P1 * 4.0;                    // Fourier sums
+    if (sl) f += NP * 35.0;                                         // single-layer kernel
+    if (dl) {
+        f += NP * 40.0;                                             // stresslet fields
+        f += 6.0 * Q1 * P1 * KK * 10.0;                             // Fourier analysis
+        f += 6.0 * nc * Q1 * 4.0;                                   // Legendre analysis
+        f += 6.0 * rot * 4.0 + 6.0 * nc * 6.0;                      // adjoint rotation
+    }
+    return f;
+}
 
 // --------------------------------------------------------------------------
 // tables
@@ -227,10 +338,25 @@ static RotTab &rot(Ctx &c, int p)
     GridTab &g = grid(c, p, p);
     std::vector<double> Ap, Am;
     rotation_tables(p, g.th, Ap, Am);
-    r->Ap.ensure(Ap.size() * sizeof(double));
-    r->Am.ensure(Am.size() * sizeof(double));
-    HIPC(hipMemcpy(r->Ap.ptr, Ap.data(), Ap.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPC(hipMemcpy(r->Am.ptr, Am.data(), Am.size() * sizeof(double), hipMemcpyHostToDevice));
+    // transposed blocks ([mu][nu] per degree) for the adjoint rotation
+    std::vector<double> ApT(Ap.size()), AmT(Am.size());
+    const size_t per = rot_lat_size(p);
+    for (int j = 0; j <= p; ++j)
+        for (int n = 0; n <= p; ++n)
+            for (int a = 0; a <= n; ++a)
+                for (int b = 0; b <= n; ++b) {
+                    const size_t o = per * j + rot_off(n);
+                    ApT[o + (size_t)b * (n + 1) + a] = Ap[o + (size_t)a * (n + 1) + b];
+                    AmT[o + (size_t)b * (n + 1) + a] = Am[o + (size_t)a * (n + 1) + b];
+                }
+    auto up = [&](DBuf &b, const std::vector<double> &v) {
+        b.ensure(v.size() * sizeof(double));
+        HIPC(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    up(r->Ap, Ap);
+    up(r->Am, Am);
+    up(r->ApT, ApT);
+    up(r->AmT, AmT);
     auto &ref = *r;
     c.rots[p] = std::move(r);
     return ref;
@@ -244,6 +370,8 @@ static void synth(Ctx &c, int p, int q, int nf, const double *coef, long cstride
 {
     GridTab &g = grid(c, q, p);
     c.Gbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
+    ProfScope ps(c, "synthesis", (double)nf * (q + 1) * ncoef(p) * 4.0 + (double)nf * npts(q) * (p + 1) * 4.0,
+                 (double)nf * (2.0 * ncoef(p) + npts(q)) * 8.0);
     launch_synth(c.stream, p, q, p, g.L.d(), g.cs.d(), nf, coef, cstride, dt, dp, c.Gbuf.d(), out, ostride);
 }
 
@@ -251,6 +379,8 @@ static void analyze(Ctx &c, int q, int p, int nf, const double *v, long vstride,
 {
     GridTab &g = grid(c, q, p);
     c.Fbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
+    ProfScope ps(c, "analysis", (double)nf * (q + 1) * ncoef(p) * 4.0 + (double)nf * npts(q) * (p + 1) * 4.0,
+                 (double)nf * (2.0 * ncoef(p) + npts(q)) * 8.0);
     launch_analyze(c.stream, q, p, p, g.L.d(), g.wq.d(), g.cs.d(), nf, v, vstride, c.Fbuf.d(), coef, cstride);
 }
 
@@ -327,6 +457,7 @@ static void build_regions(Ctx &c)
     const long nreg = c.T * c.nd;
     c.reg.ensure(nreg);
     c.dist.ensure(nreg * sizeof(double));
+    ProfScope ps(c, "classify", 0.0, 0.0);
     launch_classify(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.tx.d(), c.T, c.noff.as<int>(),
                     c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(), c.dist.d());
     c.reg_h.resize(nreg);
@@ -336,7 +467,7 @@ static void build_regions(Ctx &c)
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
     std::vector<int> tl;
     std::vector<PairWork> w0, w1;
-    const int TILE = 256, CH = 2048;
+    const int TILE = 256, CH = 512;
     c.n_om1 = c.n_om2 = 0;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &di = c.drops[i];
@@ -394,7 +525,10 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
         keep.reserve(src.size());
         for (PairWork pw : src) {
             pw.w = wt[pw.pair];
-            if (pw.w != 0.0) keep.push_back(pw);
+            if (pw.w != 0.0) {
+                keep.push_back(pw);
+                (u == 0 ? e->pairs0 : e->pairs1) += (double)pw.ntgt * pw.nsrc;
+            }
         }
         DBuf &db = u == 0 ? e->d0 : e->d1;
         db.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
@@ -410,10 +544,17 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
 static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
 {
     Ctx::WList &L = work_lists(c, wt);
-    launch_pair(c.stream, kind, L.n0, L.d0.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.tx.d(), c.s0N.d(),
-                c.s0W.d(), c.s0d.d(), c.T, c.acc.d(), c.T);
-    launch_pair(c.stream, kind, L.n1, L.d1.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.s1x.d(), c.s1N.d(),
-                c.s1W.d(), c.s1d.d(), c.S1, c.acc.d(), c.T);
+    const double fpp = kind == 0 ? 29.0 : 30.0;  // flops per pair (SL / DL)
+    {
+        ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs0 * fpp, 0.0);
+        launch_pair(c.stream, kind, L.n0, L.d0.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.tx.d(),
+                    c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T, c.acc.d(), c.T);
+    }
+    {
+        ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs1 * fpp, 0.0);
+        launch_pair(c.stream, kind, L.n1, L.d1.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.s1x.d(),
+                    c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1, c.acc.d(), c.T);
+    }
 }
 
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
@@ -429,7 +570,8 @@ static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &n
 }
 
 // Singular self-integral of drop i with density coefficients dens [3][Ctot]
-// (kind 0 SL, 1 DL), added into acc with the given scale.
+// (kind 0 SL, 1 DL), added into acc with the given scale: rotation of the
+// expansion per target, then the fused quadrature (per-application path).
 static void run_singular(Ctx &c, int i, int kind, const double *dens, double scale)
 {
     const Drop &d = c.drops[i];
@@ -438,11 +580,70 @@ static void run_singular(Ctx &c, int i, int kind, const double *dens, double sca
     GridTab &gs = grid(c, d.qs, d.p);
     const long nc = ncoef(d.p);
     c.Rbuf.ensure((size_t)npts(d.p) * 6 * nc * 2 * sizeof(double));
-    launch_rotate(c.stream, d.p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d() + d.coff, c.Ctot, dens + d.coff, c.Ctot,
-                  c.Rbuf.d());
-    launch_singular(c.stream, d.p, d.qs, kind, c.Rbuf.d(), gs.L.d(), (int)nc, gs.wsing.d(), gs.cs.d(),
-                    c.acc.d() + d.toff, c.T, scale);
+    {
+        ProfScope ps(c, "sing_rotate", (double)npts(d.p) * 6.0 * rot_lat_size(d.p) * 4.0, 0.0);
+        launch_rotate(c.stream, d.p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d() + d.coff, c.Ctot, dens + d.coff,
+                      c.Ctot, c.Rbuf.d());
+    }
+    {
+        ProfScope ps(c, "sing_v1", 0.0, 0.0);
+        launch_singular(c.stream, d.p, d.qs, kind, c.Rbuf.d(), gs.L.d(), (int)nc, gs.wsing.d(), gs.cs.d(),
+                        c.acc.d() + d.toff, c.T, scale);
+    }
 }
+
+static bool use_fused(const Ctx &c, const Drop &d, bool sl, bool dl)
+{
+    return c.opt.singular_path == 0 && sing_fused_fits(d.p, d.qs, sl, dl);
+}
+
+// Fused singular pass of drop i: single layer of dens added into acc (if sl),
+// and/or the stored double-layer rows of the drop (if dl).
+static void run_fused(Ctx &c, int i, bool sl, bool dl, const double *dens)
+{
+    const Drop &d = c.drops[i];
+    RotTab &r = rot(c, d.p);
+    GridTab &gp = grid(c, d.p, d.p);
+    GridTab &gs = grid(c, d.qs, d.p);
+    SingArgs a{};
+    a.p = d.p;
+    a.qs = d.qs;
+    a.nt = npts(d.p);
+    a.Ap = r.Ap.d();
+    a.Am = r.Am.d();
+    a.ApT = r.ApT.d();
+    a.AmT = r.AmT.d();
+    a.csp = gp.cs.d();
+    a.xc = c.xc.d() + d.coff;
+    a.xstride = c.Ctot;
+    a.dc = sl ? dens + d.coff : nullptr;
+    a.dstride = c.Ctot;
+    a.L = gs.L.d();
+    a.wsing = gs.wsing.d();
+    a.out_sl = c.acc.d() + d.toff;
+    a.ostride = c.T;
+    a.scale = 1.0;
+    a.M = nullptr;
+    if (dl) {
+        if ((int)c.Mdl.size() < c.nd) {
+            c.Mdl.resize(c.nd);
+            c.Mok.resize(c.nd, 0);
+        }
+        if (!c.Mdl[i]) c.Mdl[i] = std::make_unique<DBuf>();
+        c.Mdl[i]->ensure((size_t)npts(d.p) * 6 * 2 * ncoef(d.p) * sizeof(double));
+        a.M = c.Mdl[i]->d();
+    }
+    {
+        const double nt = npts(d.p);
+        ProfScope ps(c, "sing_fused", nt * sing_flops_per_target(d.p, d.qs, sl, dl),
+                     dl ? nt * 6.0 * 2.0 * ncoef(d.p) * 8.0 : 0.0);
+        REQUIRE(launch_sing_fused(c.stream, sl, dl, a), BIM_EDEVICE, "fused singular kernel does not fit");
+    }
+    HIPC(hipGetLastError());
+    if (dl) c.Mok[i] = 1;
+}
+
+static bool dl_matrix_ready(const Ctx &c, int i) { return i < (int)c.Mok.size() && c.Mok[i]; }
 
 // Weighted double-layer sum sum_j w(i,j) D_j[u] at all targets into acc.
 static std::vector<double> dl_weights(const Ctx &c)
@@ -465,18 +666,42 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
             if (wt[(size_t)i * c.nd + j] != 0.0) need[j] = 1;
     HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     density_nodes(c, ucoef, need);
-    for (int i = 0; i < c.nd; ++i)
-        if (wt[(size_t)i * c.nd + i] != 0.0) run_singular(c, i, 1, ucoef, wt[(size_t)i * c.nd + i]);
+    for (int i = 0; i < c.nd; ++i) {
+        const double w = wt[(size_t)i * c.nd + i];
+        if (w == 0.0) continue;
+        const Drop &d = c.drops[i];
+        if (use_fused(c, d, false, true)) {
+            if (!dl_matrix_ready(c, i)) run_fused(c, i, false, true, nullptr);
+            {
+                const double nt = npts(d.p), nc2 = 2.0 * ncoef(d.p);
+                ProfScope ps(c, "dl_apply", nt * 18.0 * nc2, nt * 6.0 * nc2 * 8.0 + 3.0 * nc2 * 8.0);
+                launch_dl_apply(c.stream, npts(d.p), 2 * ncoef(d.p), c.Mdl[i]->d(), ucoef + d.coff, c.Ctot, w,
+                                c.acc.d() + d.toff, c.T);
+            }
+        } else {
+            run_singular(c, i, 1, ucoef, w);
+        }
+    }
     run_pairs(c, 1, wt);
 }
 
-static void single_layer_grid(Ctx &c, const double *fcoef)
+// Single layer of fcoef at all targets into acc. with_dl[i] also builds the
+// stored double-layer rows of drop i in the same pass.
+static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<char> *with_dl = nullptr)
 {
     build_regions(c);
     std::vector<char> need(c.nd, 1);
     HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     density_nodes(c, fcoef, need);
-    for (int i = 0; i < c.nd; ++i) run_singular(c, i, 0, fcoef, 1.0);
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
+        if (use_fused(c, d, true, dl)) {
+            run_fused(c, i, true, dl, fcoef);
+        } else {
+            run_singular(c, i, 0, fcoef, 1.0);
+        }
+    }
     std::vector<double> wt((size_t)c.nd * c.nd, 1.0);
     run_pairs(c, 0, wt);
 }
@@ -626,6 +851,7 @@ static void copy_out(Ctx &c, void *dst, const void *src, size_t bytes, int mem_k
 static void invalidate(Ctx &c)
 {
     c.nodes_ok = c.force_ok = c.regions_ok = false;
+    std::fill(c.Mok.begin(), c.Mok.end(), 0);
 }
 
 static void require_drops(Ctx &c) { REQUIRE(c.nd > 0, BIM_ESTATE, "no drops set (call bim_set_drops first)"); }
@@ -692,6 +918,7 @@ int bim_default_options(bim_options *o)
     o->gmres_tol = 1e-10;
     o->gmres_restart = 50;
     o->gmres_maxit = 500;
+    o->singular_path = 0;
     o->stream = nullptr;
     return BIM_OK;
 }
@@ -702,7 +929,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
     *out = nullptr;
     if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
-        (opt->lambda_rule != 0 && opt->lambda_rule != 1))
+        (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path != 0 && opt->singular_path != 1))
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {
@@ -787,6 +1014,8 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         for (double v : hx) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surface coefficient");
         c.nd = n_drops;
         c.drops = ds;
+        c.Mdl.clear();
+        c.Mok.assign(n_drops, 0);
         c.Ctot = coff;
         c.T = toff;
         c.S1 = uoff;
@@ -969,14 +1198,19 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
         // the regions from the drop coefficients
         invalidate(c);
         build_force(c);
-        single_layer_grid(c, c.fc.d());
+        bool all_one = true;
+        for (auto &d : c.drops) all_one = all_one && d.lam == 1.0;
+        std::vector<char> with_dl(c.nd, 0);
+        if (!all_one) {
+            const std::vector<double> wt = dl_weights(c);
+            for (int i = 0; i < c.nd; ++i) with_dl[i] = wt[(size_t)i * c.nd + i] != 0.0;
+        }
+        single_layer_grid(c, c.fc.d(), &with_dl);
         // b = 2 u_inf - S / (4 pi) on the grid, then Galerkin projection
         c.tmp.ensure((size_t)3 * std::max<long>(c.Ctot, c.T) * sizeof(double));
         launch_rhs(c.stream, (int)c.T, c.tx.d(), c.T, c.acc.d(), -1.0 / (4.0 * kPi), c.U0, c.gU.d(), c.tmp.d());
         c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
         project(c, c.tmp.d(), c.bvec.d());
-        bool all_one = true;
-        for (auto &d : c.drops) all_one = all_one && d.lam == 1.0;
         int rc = BIM_OK, iters = 0, nmv = 0;
         double relres = 0.0;
         const long n = 3 * c.Ctot;
@@ -1055,6 +1289,33 @@ int bim_sh_analyze(bim_ctx h, int q, int p, int nf, const double *grid_in, doubl
             HIPC(hipMemcpyAsync(coef, cout, cb, hipMemcpyDeviceToHost, c.stream));
             HIPC(hipStreamSynchronize(c.stream));
         }
+        return BIM_OK;
+    });
+}
+
+int bim_profile(bim_ctx h, int enable)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        prof_drain(c);
+        if (enable) c.prof.clear();
+        c.prof_on = enable != 0;
+        return BIM_OK;
+    });
+}
+
+int bim_profile_query(bim_ctx h, const char *name, int *launches, double *ms, double *flops, double *bytes)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        REQUIRE(name, BIM_EINVAL, "null kernel name");
+        prof_drain(c);
+        auto it = c.prof.find(name);
+        const bool f = it != c.prof.end();
+        if (launches) *launches = f ? it->second.launches : 0;
+        if (ms) *ms = f ? it->second.ms : 0.0;
+        if (flops) *flops = f ? it->second.flops : 0.0;
+        if (bytes) *bytes = f ? it->second.bytes : 0.0;
         return BIM_OK;
     });
 }

@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work,
             for (int u = 0; u < ns; ++u) {
                 const double hx = x0 - sh[0][u], hy = y0 - sh[1][u], hz = z0 - sh[2][u];
                 const double r2 = hx * hx + hy * hy + hz * hz;
-                const double ri = 1.0 / sqrt(r2);
+                const double ri = rsqrt(r2);
                 const double hd = hx * sh[3][u] + hy * sh[4][u] + hz * sh[5][u];
                 if (KIND == 0) {
                     const double wr = sh[6][u] * ri;

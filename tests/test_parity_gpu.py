@@ -171,11 +171,13 @@ def test_regions_and_distances(B, orc):
 
 # --- single layer ------------------------------------------------------------------
 
-def test_single_layer_one_drop_p16(B, orc):
-    """Single drop p = 16: every grid target against the oracle's pole rule."""
-    print("single layer p=16", flush=True)
+@pytest.mark.parametrize("path", [0, 1])
+def test_single_layer_one_drop_p16(B, orc, path):
+    """Single drop p = 16: every grid target against the oracle's pole rule
+    (fused kernel and per-application rotation path)."""
+    print(f"single layer p=16 path={path}", flush=True)
     wl = W.single_drop(p=16)
-    c = ctx_for(B, wl)
+    c = ctx_for(B, wl, singular_path=path)
     u = c.single_layer()[0]
     s = osys(orc, wl)
     ref = -s.layer(0, [s.force(0)], 0) / (8 * np.pi)
@@ -229,15 +231,16 @@ def test_single_layer_three_drops_mixed_regions(B, orc):
 
 # --- double layer -----------------------------------------------------------------
 
-def test_double_layer_raw_three_drops(B, orc):
-    print("double layer raw", flush=True)
+@pytest.mark.parametrize("path", [0, 1])
+def test_double_layer_raw_three_drops(B, orc, path):
+    print(f"double layer raw path={path}", flush=True)
     rng = np.random.default_rng(42)
     drops = []
     for p, c0, lam in [(7, (0, 0, 0), 2.0), (9, (2.3, 0.1, 0), 1.0), (8, (0.5, 2.4, 0.3), 4.0)]:
         drops.append(W.DropSpec(p, W.perturbed_sphere(rng, p, 1.0, c0, 0.05), lam))
     wl = W.Workload("three", drops, eos=0, A_tilde=5.0, U_tilde=3)
     us = [random_coef(rng, d.p, 3) for d in drops]
-    c = ctx_for(B, wl)
+    c = ctx_for(B, wl, singular_path=path)
     D = c.double_layer(us, mode=0)
     s = osys(orc, wl)
     for i in range(3):
@@ -249,7 +252,7 @@ def test_double_layer_raw_three_drops(B, orc):
     for i in range(3):
         assert coef_err(A[i], ref[i]) <= TOL, i
     # the target-drop reading of lambda
-    c2 = ctx_for(B, wl, lambda_rule=1)
+    c2 = ctx_for(B, wl, lambda_rule=1, singular_path=path)
     A2 = c2.double_layer(us, mode=1)
     s2 = osys(orc, wl, lambda_rule=1)
     ref2 = s2.split(s2.matvec(np.concatenate([u.ravel() for u in us])))
@@ -257,6 +260,41 @@ def test_double_layer_raw_three_drops(B, orc):
         assert coef_err(A2[i], ref2[i]) <= TOL, i
     c.close()
     c2.close()
+
+
+@pytest.mark.parametrize("p,us", [(5, 1), (11, 2), (24, 1)])
+def test_fused_single_and_double_layer_degrees(B, orc, p, us):
+    """Fused kernel for odd and even degrees and an upsampled singular grid
+    (U_sing = 2): single layer and raw double layer against the oracle."""
+    print(f"fused p={p} U_sing={us}", flush=True)
+    rng = np.random.default_rng(500 + p)
+    wl = W.single_drop(p=p, seed=60 + p)
+    wl.U_sing = us
+    fc = random_coef(rng, p, 3)
+    uc = random_coef(rng, p, 3)
+    c = ctx_for(B, wl)
+    S = c.single_layer([fc])[0]
+    D = c.double_layer([uc], mode=0)[0]
+    s = osys(orc, wl)
+    assert rel_err(S, -s.layer(0, [fc], 0) / (8 * np.pi)) <= TOL
+    assert rel_err(D, s.layer(0, [uc], 1) / (4 * np.pi)) <= TOL
+    c.close()
+
+
+def test_high_degree_uses_rotation_path(B, orc):
+    """p = 53 exceeds the fused kernel's register and LDS budget: the
+    per-application path runs; checked at sampled targets."""
+    print("p=53 fallback", flush=True)
+    rng = np.random.default_rng(53)
+    wl = W.single_drop(p=53, seed=53)
+    uc = random_coef(rng, 53, 3)
+    c = ctx_for(B, wl)
+    D = c.double_layer([uc], mode=0)[0]
+    s = osys(orc, wl)
+    tg = np.sort(rng.choice(B.npts(53), 24, replace=False))
+    ref = s.layer(0, [uc], 1, targets=tg) / (4 * np.pi)
+    assert np.all(np.abs(D[tg] - ref).max(axis=0) <= TOL * np.abs(ref).max(axis=0))
+    c.close()
 
 
 def test_double_layer_identity_on_gpu(B, orc):
@@ -287,13 +325,14 @@ def test_eval_velocity_lambda_one_matches_single_layer(B, orc):
     c.close()
 
 
-def test_eval_velocity_two_drops_gmres(B, orc):
+@pytest.mark.parametrize("path", [0, 1])
+def test_eval_velocity_two_drops_gmres(B, orc, path):
     """Two drops (p = 8, lambda 1 and 5), linear equation of state; GMRES to
     1e-12 on both sides; solutions agree to 1e-10."""
-    print("eval velocity two drops", flush=True)
+    print(f"eval velocity two drops path={path}", flush=True)
     wl = W.two_drops(p=8)
     wl.gmres_tol = 1e-12
-    c = ctx_for(B, wl)
+    c = ctx_for(B, wl, singular_path=path)
     uc, rep = c.eval_velocity(coefficients=True)
     s = osys(orc, wl)
     ref, it, hist = s.solve()
