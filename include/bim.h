@@ -76,9 +76,12 @@ typedef struct {
     double gmres_tol;    /* relative residual tolerance (Euclidean norm of coefficients) */
     int gmres_restart;   /* Krylov dimension before restart */
     int gmres_maxit;     /* total iteration cap */
-    int singular_path;   /* 0: fused singular kernel, with the drop's double layer on itself stored
-                            as a matrix (N(p) x 6 x (p+1)(p+2) doubles per drop) when a double layer
-                            is applied; 1: rotation and quadrature on every application (no matrix) */
+    int singular_path;   /* singular self-integral (Sec. 2.2):
+                            0: batched pipeline over all targets of a drop (Legendre stages on the
+                               matrix cores); the drop's double layer on itself is stored as a matrix
+                               (N(p) x 6 x (p+1)(p+2) doubles per drop) when a double layer is applied;
+                            1: rotation and quadrature on every application (no matrix);
+                            2: one fused workgroup per target (stored matrix as in 0) */
     void *stream;        /* hipStream_t to run on; NULL = the context creates its own */
 } bim_options;
 
@@ -134,7 +137,9 @@ int bim_force(bim_ctx ctx, double *f_coef, int mem_kind);
  * 2 Omega_2 (dist <= h_j); dist = distance to the nearest node of drop j's
  * degree-p grid, h_j = R_j pi/(p_j+1), R_j the volume-equivalent radius.
  * regions: int8 [target][drop]; dist (may be NULL): double [target][drop]
- * (own-drop entries are 0). Targets are numbered over all drops in order. */
+ * (own-drop entries are 0). Targets are numbered over all drops in order.
+ * Requesting dist computes every nearest-node distance; without it, pairs
+ * whose region a bounding-sphere bound already fixes skip the node scan. */
 int bim_regions(bim_ctx ctx, int8_t *regions, double *dist, int mem_kind);
 
 /* Single-layer velocity at every grid target:

@@ -38,9 +38,14 @@ void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, con
 void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f);
 void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, double *sx, double *swN,
                   double *swW, long sstride, double *vol);
-void launch_classify(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
-                     const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
-                     int8_t *reg, double *dist);
+void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
+                        double *cb);
+void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
+                           const double *cb, const double *hj, double A, int exact, int8_t *reg, double *dist,
+                           int *list, int *count);
+void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,
+                          const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
+                          int8_t *reg, double *dist);
 void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, const double *cs, const double *xc,
                    long xstride, const double *dc, long dstride, double *R);
 void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
@@ -64,6 +69,42 @@ struct SingArgs {
     double *M;
 };
 bool launch_sing_fused(hipStream_t st, bool sl, bool dl, const SingArgs &a);
+struct LegBatchH {
+    int R, K;
+    long tab_off, in_row, out_row;
+};
+void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
+                 long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC);
+void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
+                     double *out, long NC);
+int leg_mfma_max_rows();
+int leg_mfma_max_depth();
+size_t fk_lds_bytes(int p, int qs, bool sl, int tg);
+void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
+               const double *wsing, const double *X0, double *part, double *Fa, long NC12);
+void launch_sum_part(hipStream_t st, int nt, int Q1, const double *part, double scale, double *out, long ostride);
+void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, double *X0);
+void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *Bt,
+                   long NC12, int j0, int nj, int tglobal0, double *M);
+void pipe_set_lds_limits();
+struct SynJob {
+    const double *coef;
+    const double *L;
+    double *out;
+    long cstride, ostride, fstride;
+    int p, q, ldn, ncomp, mask;
+};
+struct AnaJob {
+    const double *v;
+    const double *L;
+    const double *wq;
+    double *coef;
+    long vstride, cstride;
+    int p, q, ldn, ncomp;
+};
+void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n);
+void launch_anal_batch(hipStream_t st, const AnaJob *jobs, int n);
+size_t anal_batch_lds(int p, int q);
 bool sing_fused_fits(int p, int qs, bool sl, bool dl);
 void launch_dl_apply(hipStream_t st, int nt, int nc2, const double *M, const double *u, long ustride, double w,
                      double *out, long ostride);
@@ -166,7 +207,8 @@ struct Ctx {
     DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
     DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
     DBuf tdrop, vol, hj, noff, ncnt;
-    DBuf reg, dist;
+    DBuf reg, dist, cbnd, clist, ccount;
+    bool regions_exact = false;  // distances of every pair computed (bim_regions with dist)
     DBuf tlist;
     std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
     struct WList {
@@ -179,7 +221,7 @@ struct Ctx {
     std::vector<int8_t> reg_h;
     int n_om1 = 0, n_om2 = 0;
     DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
-    DBuf synbuf, Gbuf, Rbuf, Fbuf;
+    DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
     DBuf V, hbuf, ybuf, wvec, xsol, rvec;
@@ -199,8 +241,17 @@ struct Ctx {
     std::map<std::pair<int, int>, std::unique_ptr<GridTab>> grids;
     std::map<int, std::unique_ptr<RotTab>> rots;
 
+    // batched singular pipeline: contraction tables per (p, qs) and work buffers
+    struct PipeTab {
+        DBuf syn, ana, bsx, bsd, ban;  // tables and batch descriptors
+        int maxrows_syn = 0, maxrows_ana = 0;
+    };
+    std::map<std::pair<int, int>, std::unique_ptr<PipeTab>> pipes;
+    DBuf pBx, pBd, pGx, pGd, pPart, pX0, pFa, pBt;
+
     ~Ctx()
     {
+        pipes.clear();
         for (auto &kv : prof)
             for (auto &pr : kv.second.pend) {
                 (void)hipEventDestroy(pr.first);
@@ -365,49 +416,145 @@ static RotTab &rot(Ctx &c, int p)
 // --------------------------------------------------------------------------
 // transforms on the context stream
 // --------------------------------------------------------------------------
+// Synthesis job: ncomp components of a degree-p field on the degree-q grid,
+// derivative sets by mask bit (0 value, 1 d/dtheta, 2 d/dphi, 3 d2/dtheta2,
+// 4 d2/dtheta dphi, 5 d2/dphi2); field f (f-th set bit), component c written
+// at out + f * fstride + c * ostride.
+static SynJob syn_job(Ctx &c, int p, int q, int ncomp, const double *coef, long cstride, int mask, double *out,
+                      long ostride, long fstride)
+{
+    GridTab &g = grid(c, q, p);
+    SynJob j;
+    j.coef = coef;
+    j.L = g.L.d();
+    j.out = out;
+    j.cstride = cstride;
+    j.ostride = ostride;
+    j.fstride = fstride;
+    j.p = p;
+    j.q = q;
+    j.ldn = ncoef(p);
+    j.ncomp = ncomp;
+    j.mask = mask;
+    return j;
+}
+
+static void syn_run(Ctx &c, const std::vector<SynJob> &jobs)
+{
+    if (jobs.empty()) return;
+    double fl = 0.0, by = 0.0;
+    for (auto &j : jobs) {
+        const int nout = __builtin_popcount(j.mask);
+        fl += (double)j.ncomp * (j.q + 1) * ncoef(j.p) * 4.0 * 2 + (double)j.ncomp * nout * npts(j.q) * (j.p + 1) * 4.0;
+        by += (double)j.ncomp * (2.0 * ncoef(j.p) + nout * npts(j.q)) * 8.0;
+    }
+    ProfScope ps(c, "synthesis", fl, by);
+    launch_synth_batch(c.stream, jobs.data(), (int)jobs.size());
+}
+
 static void synth(Ctx &c, int p, int q, int nf, const double *coef, long cstride, int dt, int dp, double *out,
                   long ostride)
 {
+    int bit = 0;
+    for (int b = 0; b < 6; ++b) {
+        static const int kt[6] = {0, 1, 0, 2, 1, 0}, kp[6] = {0, 0, 1, 0, 1, 2};
+        if (kt[b] == dt && kp[b] == dp) bit = b;
+    }
+    std::vector<SynJob> jobs;
+    // more than 3 fields: one job per field (a job holds up to 3 components)
+    for (int f = 0; f < nf; f += 3)
+        jobs.push_back(syn_job(c, p, q, std::min(3, nf - f), coef + f * cstride, cstride, 1 << bit, out + f * ostride,
+                               ostride, 0));
+    syn_run(c, jobs);
+}
+
+static AnaJob ana_job(Ctx &c, int q, int p, int ncomp, const double *v, long vstride, double *coef, long cstride)
+{
     GridTab &g = grid(c, q, p);
-    c.Gbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
-    ProfScope ps(c, "synthesis", (double)nf * (q + 1) * ncoef(p) * 4.0 + (double)nf * npts(q) * (p + 1) * 4.0,
-                 (double)nf * (2.0 * ncoef(p) + npts(q)) * 8.0);
-    launch_synth(c.stream, p, q, p, g.L.d(), g.cs.d(), nf, coef, cstride, dt, dp, c.Gbuf.d(), out, ostride);
+    AnaJob j;
+    j.v = v;
+    j.L = g.L.d();
+    j.wq = g.wq.d();
+    j.coef = coef;
+    j.vstride = vstride;
+    j.cstride = cstride;
+    j.p = p;
+    j.q = q;
+    j.ldn = ncoef(p);
+    j.ncomp = ncomp;
+    return j;
+}
+
+static void ana_run(Ctx &c, const std::vector<AnaJob> &jobs)
+{
+    if (jobs.empty()) return;
+    double fl = 0.0, by = 0.0;
+    std::vector<AnaJob> fit;
+    for (auto &j : jobs) {
+        fl += (double)j.ncomp * ((j.q + 1) * ncoef(j.p) * 4.0 + (double)npts(j.q) * (j.p + 1) * 4.0);
+        by += (double)j.ncomp * (2.0 * ncoef(j.p) + npts(j.q)) * 8.0;
+        if (anal_batch_lds(j.p, j.q) <= 163840) {
+            fit.push_back(j);
+        } else {  // grids too large for one block's LDS: two-stage kernels
+            GridTab &g = grid(c, j.q, j.p);
+            c.Fbuf.ensure((size_t)j.ncomp * (j.q + 1) * (j.p + 1) * 2 * sizeof(double));
+            launch_analyze(c.stream, j.q, j.p, j.p, g.L.d(), g.wq.d(), g.cs.d(), j.ncomp, j.v, j.vstride, c.Fbuf.d(),
+                           j.coef, j.cstride);
+        }
+    }
+    ProfScope ps(c, "analysis", fl, by);
+    launch_anal_batch(c.stream, fit.data(), (int)fit.size());
 }
 
 static void analyze(Ctx &c, int q, int p, int nf, const double *v, long vstride, double *coef, long cstride)
 {
-    GridTab &g = grid(c, q, p);
-    c.Fbuf.ensure((size_t)nf * (q + 1) * (p + 1) * 2 * sizeof(double));
-    ProfScope ps(c, "analysis", (double)nf * (q + 1) * ncoef(p) * 4.0 + (double)nf * npts(q) * (p + 1) * 4.0,
-                 (double)nf * (2.0 * ncoef(p) + npts(q)) * 8.0);
-    launch_analyze(c.stream, q, p, p, g.L.d(), g.wq.d(), g.cs.d(), nf, v, vstride, c.Fbuf.d(), coef, cstride);
+    std::vector<AnaJob> jobs;
+    for (int f = 0; f < nf; f += 3)
+        jobs.push_back(ana_job(c, q, p, std::min(3, nf - f), v + f * vstride, vstride, coef + f * cstride, cstride));
+    ana_run(c, jobs);
 }
 
-// x, x_theta, x_phi of drop d on the degree-q grid into synbuf [9][npts(q)]
-static void synth_surface(Ctx &c, const Drop &d, int q)
+// per-drop offsets into the node and force synthesis buffers
+static void syn_layout(const Ctx &c, std::vector<long> &o0, std::vector<long> &o1, std::vector<long> &og, long &tot)
 {
-    const long np = npts(q);
-    c.synbuf.ensure((size_t)21 * np * sizeof(double));
-    double *s = c.synbuf.d();
-    const double *x = c.xc.d() + d.coff;
-    synth(c, d.p, q, 3, x, c.Ctot, 0, 0, s, np);
-    synth(c, d.p, q, 3, x, c.Ctot, 1, 0, s + 3 * np, np);
-    synth(c, d.p, q, 3, x, c.Ctot, 0, 1, s + 6 * np, np);
+    o0.resize(c.nd);
+    o1.resize(c.nd);
+    og.resize(c.nd);
+    tot = 0;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        o0[i] = tot;
+        tot += 9L * npts(d.p);
+        o1[i] = tot;
+        tot += 9L * npts(d.qu);
+        og[i] = tot;
+        tot += 21L * npts(d.qg);
+    }
 }
 
 static void build_nodes(Ctx &c)
 {
     if (c.nodes_ok) return;
+    std::vector<long> o0, o1, og;
+    long tot;
+    syn_layout(c, o0, o1, og, tot);
+    c.synbuf.ensure((size_t)tot * sizeof(double));
     c.vol.ensure(c.nd * sizeof(double));
     HIPC(hipMemsetAsync(c.vol.ptr, 0, c.nd * sizeof(double), c.stream));
+    std::vector<SynJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
-        synth_surface(c, d, d.p);
-        launch_nodes(c.stream, d.p, c.synbuf.d(), grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff,
+        const double *x = c.xc.d() + d.coff;
+        const long n0 = npts(d.p), n1 = npts(d.qu);
+        jobs.push_back(syn_job(c, d.p, d.p, 3, x, c.Ctot, 0x7, c.synbuf.d() + o0[i], n0, 3 * n0));
+        jobs.push_back(syn_job(c, d.p, d.qu, 3, x, c.Ctot, 0x7, c.synbuf.d() + o1[i], n1, 3 * n1));
+    }
+    syn_run(c, jobs);
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        launch_nodes(c.stream, d.p, c.synbuf.d() + o0[i], grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff,
                      c.s0N.d() + d.toff, c.s0W.d() + d.toff, c.T, c.vol.d() + i);
-        synth_surface(c, d, d.qu);
-        launch_nodes(c.stream, d.qu, c.synbuf.d(), grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
+        launch_nodes(c.stream, d.qu, c.synbuf.d() + o1[i], grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
                      c.s1N.d() + d.uoff, c.s1W.d() + d.uoff, c.S1, nullptr);
     }
     c.nodes_ok = true;
@@ -416,26 +563,33 @@ static void build_nodes(Ctx &c)
 static void build_force(Ctx &c)
 {
     if (c.force_ok) return;
+    std::vector<long> o0, o1, og;
+    long tot;
+    syn_layout(c, o0, o1, og, tot);
+    c.synbuf.ensure((size_t)tot * sizeof(double));
+    std::vector<SynJob> jobs;
+    long fmax = 0;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
-        const int q = d.qg;
-        const long np = npts(q);
-        synth_surface(c, d, q);
-        double *s = c.synbuf.d();
-        const double *x = c.xc.d() + d.coff;
-        synth(c, d.p, q, 3, x, c.Ctot, 2, 0, s + 9 * np, np);
-        synth(c, d.p, q, 3, x, c.Ctot, 1, 1, s + 12 * np, np);
-        synth(c, d.p, q, 3, x, c.Ctot, 0, 2, s + 15 * np, np);
-        if (c.eos != BIM_EOS_UNIFORM) {
-            const double *g = c.gc.d() + d.coff;
-            synth(c, d.p, q, 1, g, 0, 0, 0, s + 18 * np, np);
-            synth(c, d.p, q, 1, g, 0, 1, 0, s + 19 * np, np);
-            synth(c, d.p, q, 1, g, 0, 0, 1, s + 20 * np, np);
-        }
-        c.tmp.ensure((size_t)3 * std::max<long>(np, c.T) * sizeof(double));
-        launch_force(c.stream, (int)np, s, c.eos, c.E, c.xs, c.sigma0, c.tmp.d());
-        analyze(c, q, d.p, 3, c.tmp.d(), np, c.fc.d() + d.coff, c.Ctot);
+        const long np = npts(d.qg);
+        double *s = c.synbuf.d() + og[i];
+        jobs.push_back(syn_job(c, d.p, d.qg, 3, c.xc.d() + d.coff, c.Ctot, 0x3f, s, np, 3 * np));
+        if (c.eos != BIM_EOS_UNIFORM)
+            jobs.push_back(syn_job(c, d.p, d.qg, 1, c.gc.d() + d.coff, 0, 0x7, s + 18 * np, 0, np));
+        fmax += 3 * np;
     }
+    syn_run(c, jobs);
+    c.fgrid.ensure((size_t)fmax * sizeof(double));
+    std::vector<AnaJob> ajobs;
+    long fo = 0;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        const long np = npts(d.qg);
+        launch_force(c.stream, (int)np, c.synbuf.d() + og[i], c.eos, c.E, c.xs, c.sigma0, c.fgrid.d() + fo);
+        ajobs.push_back(ana_job(c, d.qg, d.p, 3, c.fgrid.d() + fo, np, c.fc.d() + d.coff, c.Ctot));
+        fo += 3 * np;
+    }
+    ana_run(c, ajobs);
     c.force_ok = true;
 }
 
@@ -457,9 +611,26 @@ static void build_regions(Ctx &c)
     const long nreg = c.T * c.nd;
     c.reg.ensure(nreg);
     c.dist.ensure(nreg * sizeof(double));
-    ProfScope ps(c, "classify", 0.0, 0.0);
-    launch_classify(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.tx.d(), c.T, c.noff.as<int>(),
-                    c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(), c.dist.d());
+    c.cbnd.ensure(4 * c.nd * sizeof(double));
+    c.clist.ensure(std::max<long>(1, nreg) * sizeof(int));
+    c.ccount.ensure(sizeof(int));
+    {
+        ProfScope ps(c, "classify", 0.0, 0.0);
+        launch_drop_bounds(c.stream, c.nd, c.tx.d(), c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.cbnd.d());
+        HIPC(hipMemsetAsync(c.ccount.ptr, 0, sizeof(int), c.stream));
+        launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.cbnd.d(), c.hj.d(),
+                              c.opt.A_tilde, c.regions_exact ? 1 : 0, c.reg.as<int8_t>(), c.dist.d(),
+                              c.clist.as<int>(), c.ccount.as<int>());
+    }
+    int nscan = 0;
+    HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    {
+        ProfScope ps(c, "classify", 0.0, 0.0);
+        launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
+                             c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
+                             c.dist.d());
+    }
     c.reg_h.resize(nreg);
     HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
@@ -467,7 +638,7 @@ static void build_regions(Ctx &c)
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
     std::vector<int> tl;
     std::vector<PairWork> w0, w1;
-    const int TILE = 256, CH = 512;
+    const int TILE = 64, CH = 256;
     c.n_om1 = c.n_om2 = 0;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &di = c.drops[i];
@@ -561,12 +732,14 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
 // and upsampled nodes of the drops whose flag is set.
 static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need)
 {
+    std::vector<SynJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
         if (!need[i]) continue;
         const Drop &d = c.drops[i];
-        synth(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0, 0, c.s0d.d() + d.toff, c.T);
-        synth(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0, 0, c.s1d.d() + d.uoff, c.S1);
+        jobs.push_back(syn_job(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0x1, c.s0d.d() + d.toff, c.T, 0));
+        jobs.push_back(syn_job(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0x1, c.s1d.d() + d.uoff, c.S1, 0));
     }
+    syn_run(c, jobs);
 }
 
 // Singular self-integral of drop i with density coefficients dens [3][Ctot]
@@ -592,10 +765,148 @@ static void run_singular(Ctx &c, int i, int kind, const double *dens, double sca
     }
 }
 
+// --------------------------------------------------------------------------
+// batched singular pipeline (kernels_pipe.hip)
+// --------------------------------------------------------------------------
+static Ctx::PipeTab &pipe_tables(Ctx &c, int p, int qs)
+{
+    auto key = std::make_pair(p, qs);
+    auto it = c.pipes.find(key);
+    if (it != c.pipes.end()) return *it->second;
+    auto t = std::make_unique<Ctx::PipeTab>();
+    GridTab &g = grid(c, qs, p);
+    const int P1 = p + 1, Q1 = qs + 1, nc = ncoef(p);
+    std::vector<double> P((size_t)Q1 * nc), D((size_t)Q1 * nc);
+    for (int j = 0; j < Q1; ++j) legendre_table(p, g.t[j], &P[(size_t)j * nc], &D[(size_t)j * nc], nullptr);
+    // synthesis: per mu, rows [Ptilde(t_j'); dPtilde/dtheta(t_j')] (2 Q1), depth n = mu..p
+    std::vector<double> syn, ana;
+    std::vector<LegBatchH> bx, bd, ba;
+    long koffm = 0;
+    for (int mu = 0; mu < P1; ++mu) {
+        const int K = P1 - mu;
+        LegBatchH h{2 * Q1, K, (long)syn.size(), koffm, (long)mu * 2 * Q1};
+        for (int r = 0; r < 2 * Q1; ++r)
+            for (int kk = 0; kk < K; ++kk) {
+                const int n = mu + kk, j = r % Q1;
+                syn.push_back(r < Q1 ? P[(size_t)j * nc + tri(n, mu)] : D[(size_t)j * nc + tri(n, mu)]);
+            }
+        bx.push_back(h);
+        LegBatchH hd{Q1, K, h.tab_off, koffm, (long)mu * Q1};
+        bd.push_back(hd);
+        // analysis: rows n = mu..p, depth j' = 0..qs
+        LegBatchH ha{K, Q1, (long)ana.size(), (long)mu * Q1, koffm};
+        for (int kk = 0; kk < K; ++kk)
+            for (int j = 0; j < Q1; ++j) ana.push_back(P[(size_t)j * nc + tri(mu + kk, mu)]);
+        ba.push_back(ha);
+        koffm += K;
+    }
+    auto up = [&](DBuf &b, const void *src, size_t bytes) {
+        b.ensure(bytes);
+        HIPC(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+    };
+    up(t->syn, syn.data(), syn.size() * sizeof(double));
+    up(t->ana, ana.data(), ana.size() * sizeof(double));
+    up(t->bsx, bx.data(), bx.size() * sizeof(LegBatchH));
+    up(t->bsd, bd.data(), bd.size() * sizeof(LegBatchH));
+    up(t->ban, ba.data(), ba.size() * sizeof(LegBatchH));
+    t->maxrows_syn = 2 * Q1;
+    t->maxrows_ana = P1;
+    auto &ref = *t;
+    c.pipes[key] = std::move(t);
+    return ref;
+}
+
+static bool pipe_fits(int p, int qs)
+{
+    return 2 * (qs + 1) <= leg_mfma_max_rows() && (p + 1) <= leg_mfma_max_depth() &&
+           (qs + 1) <= leg_mfma_max_depth() && fk_lds_bytes(p, qs, true, 4) <= 163840 &&
+           (size_t)(2 * (p + 1) * (p + 1) + 6 * (p + 1) * 2 + 2 * p * (p + 1) * 2) * 8 <= 163840;
+}
+
+// Singular pass of drop i through the batched pipeline: single layer of dens
+// added into acc (sl) and/or the stored double-layer rows (dl).
+static void run_pipe(Ctx &c, int i, bool sl, bool dl, const double *dens)
+{
+    const Drop &d = c.drops[i];
+    const int p = d.p, qs = d.qs, P1 = p + 1, Q1 = qs + 1, nk = 2 * p, nc = ncoef(p);
+    RotTab &r = rot(c, p);
+    GridTab &gp = grid(c, p, p);
+    GridTab &gs = grid(c, qs, p);
+    Ctx::PipeTab &pt = pipe_tables(c, p, qs);
+    pipe_set_lds_limits();
+    if (dl) {
+        if ((int)c.Mdl.size() < c.nd) {
+            c.Mdl.resize(c.nd);
+            c.Mok.resize(c.nd, 0);
+        }
+        if (!c.Mdl[i]) c.Mdl[i] = std::make_unique<DBuf>();
+        c.Mdl[i]->ensure((size_t)npts(p) * 6 * 2 * nc * sizeof(double));
+    }
+    // latitudes per chunk from a memory budget for the intermediates
+    const double per_lat = (double)nk * 8.0 *
+                           ((double)nc * 6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * 6 + (sl ? (double)P1 * Q1 * 6 : 0.0) +
+                            (dl ? (double)P1 * Q1 * 12 + (double)nc * 12 : 0.0) + Q1 * 3 + 3);
+    const double budget = 768.0 * 1024 * 1024;
+    int nj = std::max(1, std::min(P1, (int)(budget / per_lat)));
+    const long NTc = (long)nj * nk;
+    c.pBx.ensure((size_t)nc * NTc * 6 * 8);
+    if (sl) c.pBd.ensure((size_t)nc * NTc * 6 * 8);
+    c.pGx.ensure((size_t)P1 * 2 * Q1 * NTc * 6 * 8);
+    if (sl) c.pGd.ensure((size_t)P1 * Q1 * NTc * 6 * 8);
+    c.pPart.ensure((size_t)NTc * Q1 * 3 * 8);
+    c.pX0.ensure((size_t)NTc * 3 * 8);
+    if (dl) {
+        c.pFa.ensure((size_t)P1 * Q1 * NTc * 12 * 8);
+        c.pBt.ensure((size_t)nc * NTc * 12 * 8);
+    }
+    const double rotlat = (double)rot_lat_size(p);
+    for (int j0 = 0; j0 < P1; j0 += nj) {
+        const int njc = std::min(nj, P1 - j0);
+        const long nt = (long)njc * nk, NC6 = nt * 6, NC12 = nt * 12;
+        {
+            ProfScope ps(c, "pipe_rotate", nt * (sl ? 6.0 : 3.0) * rotlat * 4.0, nt * (sl ? 2.0 : 1.0) * nc * 6 * 8.0);
+            launch_rot2(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d() + d.coff, c.Ctot,
+                        sl ? dens + d.coff : nullptr, c.Ctot, j0, njc, c.pBx.d(), sl ? c.pBd.d() : nullptr, NC6);
+            launch_pole(c.stream, p, (int)nt, c.pBx.d(), NC6, c.pX0.d());
+        }
+        {
+            ProfScope ps(c, "pipe_legendre", 2.0 * 2 * Q1 * nc * NC6 + (sl ? 2.0 * Q1 * nc * NC6 : 0.0),
+                         8.0 * ((double)nc * NC6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * NC6 + (sl ? (double)P1 * Q1 * NC6 : 0.0)));
+            launch_leg_mfma(c.stream, P1, pt.maxrows_syn, pt.bsx.ptr, pt.syn.d(), c.pBx.d(), c.pGx.d(), NC6);
+            if (sl) launch_leg_mfma(c.stream, P1, Q1, pt.bsd.ptr, pt.syn.d(), c.pBd.d(), c.pGd.d(), NC6);
+        }
+        {
+            const double KK = qs / 2 + 1, NP = npts(qs);
+            double fl = (double)Q1 * KK * P1 * 4.0 * (sl ? 12.0 : 9.0) + (sl ? NP * 35.0 : 0.0);
+            if (dl) fl += NP * 40.0 + 6.0 * Q1 * P1 * KK * 10.0;
+            ProfScope ps(c, "pipe_fourier", nt * fl,
+                         8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)));
+            launch_fk(c.stream, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),
+                      c.pX0.d(), c.pPart.d(), dl ? c.pFa.d() : nullptr, NC12);
+            if (sl) launch_sum_part(c.stream, (int)nt, Q1, c.pPart.d(), 1.0, c.acc.d() + d.toff + (long)j0 * nk, c.T);
+        }
+        if (dl) {
+            {
+                ProfScope ps(c, "pipe_legendre", 2.0 * Q1 * nc * NC12, 8.0 * ((double)P1 * Q1 * NC12 + (double)nc * NC12));
+                launch_leg_mfma(c.stream, P1, pt.maxrows_ana, pt.ban.ptr, pt.ana.d(), c.pFa.d(), c.pBt.d(), NC12);
+            }
+            {
+                ProfScope ps(c, "pipe_adjrot", nt * 6.0 * rotlat * 4.0, 8.0 * ((double)nc * NC12 + (double)nt * 6 * 2 * nc));
+                launch_adjrot(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.pBt.d(), NC12, j0, njc, j0 * nk,
+                              c.Mdl[i]->d());
+            }
+        }
+    }
+    HIPC(hipGetLastError());
+    if (dl) c.Mok[i] = 1;
+}
+
 static bool use_fused(const Ctx &c, const Drop &d, bool sl, bool dl)
 {
-    return c.opt.singular_path == 0 && sing_fused_fits(d.p, d.qs, sl, dl);
+    return c.opt.singular_path == 2 && sing_fused_fits(d.p, d.qs, sl, dl);
 }
+
+static bool use_pipe(const Ctx &c, const Drop &d) { return c.opt.singular_path == 0 && pipe_fits(d.p, d.qs); }
 
 // Fused singular pass of drop i: single layer of dens added into acc (if sl),
 // and/or the stored double-layer rows of the drop (if dl).
@@ -670,8 +981,11 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
         const double w = wt[(size_t)i * c.nd + i];
         if (w == 0.0) continue;
         const Drop &d = c.drops[i];
-        if (use_fused(c, d, false, true)) {
-            if (!dl_matrix_ready(c, i)) run_fused(c, i, false, true, nullptr);
+        if (use_pipe(c, d) || use_fused(c, d, false, true)) {
+            if (!dl_matrix_ready(c, i)) {
+                if (use_pipe(c, d)) run_pipe(c, i, false, true, nullptr);
+                else run_fused(c, i, false, true, nullptr);
+            }
             {
                 const double nt = npts(d.p), nc2 = 2.0 * ncoef(d.p);
                 ProfScope ps(c, "dl_apply", nt * 18.0 * nc2, nt * 6.0 * nc2 * 8.0 + 3.0 * nc2 * 8.0);
@@ -696,8 +1010,12 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
         const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
-        if (use_fused(c, d, true, dl)) {
-            run_fused(c, i, true, dl, fcoef);
+        if (use_pipe(c, d)) {
+            run_pipe(c, i, true, dl, fcoef);
+        } else if (use_fused(c, d, true, dl)) {
+            run_fused(c, i, true, dl, fcoef);             // both in one pass
+        } else if (use_fused(c, d, true, false)) {
+            run_fused(c, i, true, false, fcoef);          // rows built on first use
         } else {
             run_singular(c, i, 0, fcoef, 1.0);
         }
@@ -709,18 +1027,22 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
 // analysis of grid vectors [3][T] into coefficients [3][Ctot]
 static void project(Ctx &c, const double *grid_vals, double *coef)
 {
+    std::vector<AnaJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
-        analyze(c, d.p, d.p, 3, grid_vals + d.toff, c.T, coef + d.coff, c.Ctot);
+        jobs.push_back(ana_job(c, d.p, d.p, 3, grid_vals + d.toff, c.T, coef + d.coff, c.Ctot));
     }
+    ana_run(c, jobs);
 }
 
 static void synth_grid_all(Ctx &c, const double *coef, double *grid_vals)
 {
+    std::vector<SynJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
-        synth(c, d.p, d.p, 3, coef + d.coff, c.Ctot, 0, 0, grid_vals + d.toff, c.T);
+        jobs.push_back(syn_job(c, d.p, d.p, 3, coef + d.coff, c.Ctot, 0x1, grid_vals + d.toff, c.T, 0));
     }
+    syn_run(c, jobs);
 }
 
 // y = A x, the Galerkin second-kind operator (coefficients [3][Ctot]).
@@ -851,6 +1173,7 @@ static void copy_out(Ctx &c, void *dst, const void *src, size_t bytes, int mem_k
 static void invalidate(Ctx &c)
 {
     c.nodes_ok = c.force_ok = c.regions_ok = false;
+    c.regions_exact = false;
     std::fill(c.Mok.begin(), c.Mok.end(), 0);
 }
 
@@ -929,7 +1252,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
     *out = nullptr;
     if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
-        (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path != 0 && opt->singular_path != 1))
+        (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2))
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {
@@ -1135,6 +1458,10 @@ int bim_regions(bim_ctx h, int8_t *regions, double *dist, int mem_kind)
     return guarded(h ? &h->c : nullptr, [&]() {
         Ctx &c = h->c;
         require_drops(c);
+        if (dist && !c.regions_exact) {
+            c.regions_exact = true;
+            c.regions_ok = false;
+        }
         build_regions(c);
         if (regions) copy_out(c, regions, c.reg.ptr, (size_t)c.T * c.nd, mem_kind);
         if (dist) copy_out(c, dist, c.dist.ptr, (size_t)c.T * c.nd * sizeof(double), mem_kind);

@@ -196,11 +196,15 @@ __global__ void k_nodes(int q, const double *__restrict__ syn, const double *__r
 // Region split (Sec. 2.3): for every target t and source drop j != drop(t),
 // the distance to the nearest node of j's degree-p grid, compared with
 // A_tilde h_j and h_j. reg[t * nd + j] = 0 / 1 / 2, -1 for the own drop.
+// Pass 1 (thread per pair): the bounds |x0 - c_j| -/+ b_j of the nearest-node
+// distance (b_j = the largest node distance from the drop's centre c_j) decide
+// pairs whose region they already fix; the others go to a list. Pass 2 (wavefront per
+// listed pair): the nearest-node distance and the region.
 // ----------------------------------------------------------------------------
-__global__ void k_classify(int T, int nd, const double *__restrict__ tx, long tstride, const int *__restrict__ tdrop,
-                           const double *__restrict__ sx, long sstride, const int *__restrict__ noff,
-                           const int *__restrict__ ncnt, const double *__restrict__ hj, double A,
-                           int8_t *__restrict__ reg, double *__restrict__ dist)
+__global__ void k_classify_bound(int T, int nd, const double *__restrict__ tx, long tstride,
+                                 const int *__restrict__ tdrop, const double *__restrict__ cb /*[nd][4]*/,
+                                 const double *__restrict__ hj, double A, int exact, int8_t *__restrict__ reg,
+                                 double *__restrict__ dist, int *__restrict__ list, int *__restrict__ count)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)T * nd) return;
@@ -211,17 +215,89 @@ __global__ void k_classify(int T, int nd, const double *__restrict__ tx, long ts
         if (dist) dist[idx] = 0.0;
         return;
     }
+    bool scan = exact != 0;
+    if (!scan) {
+        const double dx = tx[t] - cb[4 * j], dy = tx[tstride + t] - cb[4 * j + 1], dz = tx[2 * tstride + t] - cb[4 * j + 2];
+        const double dc = sqrt(dx * dx + dy * dy + dz * dz);
+        const double lb = dc - cb[4 * j + 3], ub = dc + cb[4 * j + 3];  // bounds of the nearest-node distance
+        const double h = hj[j];
+        if (lb > A * h) {
+            reg[idx] = 0;
+            if (dist) dist[idx] = lb;
+        } else if (lb > h && ub <= A * h) {
+            reg[idx] = 1;
+            if (dist) dist[idx] = lb;
+        } else {
+            scan = true;
+        }
+    }
+    if (scan) list[atomicAdd(count, 1)] = (int)idx;
+}
+
+__global__ __launch_bounds__(256) void k_classify_scan(int n, const int *__restrict__ list, int nd,
+                                                       const double *__restrict__ tx, long tstride,
+                                                       const double *__restrict__ sx, long sstride,
+                                                       const int *__restrict__ noff, const int *__restrict__ ncnt,
+                                                       const double *__restrict__ hj, double A,
+                                                       int8_t *__restrict__ reg, double *__restrict__ dist)
+{
+    const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wv >= n) return;
+    const int idx = list[wv];
+    const int j = idx % nd;
+    const int t = idx / nd;
     const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
     double best = 1e300;
     const int o = noff[j], c = ncnt[j];
-    for (int s = 0; s < c; ++s) {
+    for (int s = lane; s < c; s += 64) {
         const double dx = x0 - sx[o + s], dy = y0 - sx[sstride + o + s], dz = z0 - sx[2 * sstride + o + s];
         best = fmin(best, dx * dx + dy * dy + dz * dz);
     }
-    const double d = sqrt(best);
-    const double h = hj[j];
-    reg[idx] = (d > A * h) ? 0 : (d > h ? 1 : 2);
-    if (dist) dist[idx] = d;
+    for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_down(best, off, 64));
+    if (lane == 0) {
+        const double d = sqrt(best);
+        const double h = hj[j];
+        reg[idx] = (d > A * h) ? 0 : (d > h ? 1 : 2);
+        if (dist) dist[idx] = d;
+    }
+}
+
+// Centre (mean node position) and bounding radius of each drop's standard nodes.
+__global__ __launch_bounds__(256) void k_drop_bounds(int nd, const double *__restrict__ sx, long sstride,
+                                                     const int *__restrict__ noff, const int *__restrict__ ncnt,
+                                                     double *__restrict__ cb)
+{
+    __shared__ double red[4][4];
+    const int j = blockIdx.x;
+    const int o = noff[j], c = ncnt[j];
+    double s[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < c; i += 256)
+        for (int k = 0; k < 3; ++k) s[k] += sx[k * sstride + o + i];
+    for (int k = 0; k < 3; ++k) {
+        for (int off = 32; off > 0; off >>= 1) s[k] += __shfl_down(s[k], off, 64);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = s[k];
+    }
+    __syncthreads();
+    double cen[3];
+    for (int k = 0; k < 3; ++k) cen[k] = (red[k][0] + red[k][1] + red[k][2] + red[k][3]) / c;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < c; i += 256) {
+        const double dx = sx[o + i] - cen[0], dy = sx[sstride + o + i] - cen[1], dz = sx[2 * sstride + o + i] - cen[2];
+        m = fmax(m, dx * dx + dy * dy + dz * dz);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[3][threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mm = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
+        cb[4 * j] = cen[0];
+        cb[4 * j + 1] = cen[1];
+        cb[4 * j + 2] = cen[2];
+        // bounding radius, enlarged by a relative 1e-12 so the bound stays rigorous under rounding
+        cb[4 * j + 3] = sqrt(mm) * (1.0 + 1e-12) + 1e-300;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -411,68 +487,67 @@ __global__ __launch_bounds__(256) void k_singular(int p, int qs, int kind, const
 
 // ----------------------------------------------------------------------------
 // Pair sums (Sec. 1 kernels by the regular rule of Sec. 2.1 on the standard
-// or upsampled grid of a source drop, Sec. 2.3). One workgroup per work item:
-// up to 256 targets (one per thread, from an index list) against a range of
-// source nodes staged through LDS in tiles of 256.
+// or upsampled grid of a source drop, Sec. 2.3). One wavefront per work item:
+// up to 64 targets (one per lane, from an index list) against a range of
+// source nodes staged through LDS in tiles of 64.
 // kind 0 (SL): sum wW G(x0, x) f;   kind 1 (DL): sum -6 xh (xh.u)(xh.wN) / r^5.
 // Results are added atomically: out[c][t] += w * sum.
 // ----------------------------------------------------------------------------
 template <int KIND>
-__global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
-                                              const double *__restrict__ tx, long tstride,
-                                              const double *__restrict__ sx, const double *__restrict__ swN,
-                                              const double *__restrict__ swW, const double *__restrict__ sd,
-                                              long sstride, double *__restrict__ out, long ostride)
+__global__ __launch_bounds__(64) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
+                                             const double *__restrict__ tx, long tstride,
+                                             const double *__restrict__ sx, const double *__restrict__ swN,
+                                             const double *__restrict__ swW, const double *__restrict__ sd,
+                                             long sstride, double *__restrict__ out, long ostride)
 {
     constexpr int NV = KIND == 0 ? 7 : 9;
-    __shared__ double sh[NV][256];
+    __shared__ double sh[NV][64];
     const PairWork w = work[blockIdx.x];
-    const bool active = threadIdx.x < w.ntgt;
-    const int t = active ? tlist[w.tlist_off + threadIdx.x] : 0;
+    const int lane = threadIdx.x;
+    const bool active = lane < w.ntgt;
+    const int t = active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off];
     const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int s0 = 0; s0 < w.nsrc; s0 += 256) {
-        const int ns = min(256, w.nsrc - s0);
-        if (threadIdx.x < ns) {
-            const long s = w.src_off + s0 + threadIdx.x;
-            sh[0][threadIdx.x] = sx[s];
-            sh[1][threadIdx.x] = sx[sstride + s];
-            sh[2][threadIdx.x] = sx[2 * sstride + s];
-            sh[3][threadIdx.x] = sd[s];
-            sh[4][threadIdx.x] = sd[sstride + s];
-            sh[5][threadIdx.x] = sd[2 * sstride + s];
+    for (int s0 = 0; s0 < w.nsrc; s0 += 64) {
+        const int ns = min(64, w.nsrc - s0);
+        __syncthreads();
+        if (lane < ns) {
+            const long s = (long)w.src_off + s0 + lane;
+            sh[0][lane] = sx[s];
+            sh[1][lane] = sx[sstride + s];
+            sh[2][lane] = sx[2 * sstride + s];
+            sh[3][lane] = sd[s];
+            sh[4][lane] = sd[sstride + s];
+            sh[5][lane] = sd[2 * sstride + s];
             if (KIND == 0) {
-                sh[6][threadIdx.x] = swW[s];
+                sh[6][lane] = swW[s];
             } else {
-                sh[6][threadIdx.x] = swN[s];
-                sh[7][threadIdx.x] = swN[sstride + s];
-                sh[8][threadIdx.x] = swN[2 * sstride + s];
+                sh[6][lane] = swN[s];
+                sh[7][lane] = swN[sstride + s];
+                sh[8][lane] = swN[2 * sstride + s];
             }
         }
         __syncthreads();
-        if (active) {
-            for (int u = 0; u < ns; ++u) {
-                const double hx = x0 - sh[0][u], hy = y0 - sh[1][u], hz = z0 - sh[2][u];
-                const double r2 = hx * hx + hy * hy + hz * hz;
-                const double ri = rsqrt(r2);
-                const double hd = hx * sh[3][u] + hy * sh[4][u] + hz * sh[5][u];
-                if (KIND == 0) {
-                    const double wr = sh[6][u] * ri;
-                    const double hdr = hd * ri * ri;
-                    a0 += wr * (sh[3][u] + hx * hdr);
-                    a1 += wr * (sh[4][u] + hy * hdr);
-                    a2 += wr * (sh[5][u] + hz * hdr);
-                } else {
-                    const double hn = hx * sh[6][u] + hy * sh[7][u] + hz * sh[8][u];
-                    const double r2i = ri * ri;
-                    const double s = -6.0 * hd * hn * r2i * r2i * ri;
-                    a0 += s * hx;
-                    a1 += s * hy;
-                    a2 += s * hz;
-                }
+        for (int u = 0; u < ns; ++u) {
+            const double hx = x0 - sh[0][u], hy = y0 - sh[1][u], hz = z0 - sh[2][u];
+            const double r2 = hx * hx + hy * hy + hz * hz;
+            const double ri = rsqrt(r2);
+            const double hd = hx * sh[3][u] + hy * sh[4][u] + hz * sh[5][u];
+            if (KIND == 0) {
+                const double wr = sh[6][u] * ri;
+                const double hdr = hd * ri * ri;
+                a0 = fma(wr, fma(hx, hdr, sh[3][u]), a0);
+                a1 = fma(wr, fma(hy, hdr, sh[4][u]), a1);
+                a2 = fma(wr, fma(hz, hdr, sh[5][u]), a2);
+            } else {
+                const double hn = hx * sh[6][u] + hy * sh[7][u] + hz * sh[8][u];
+                const double r2i = ri * ri;
+                const double s = -6.0 * hd * hn * r2i * r2i * ri;
+                a0 = fma(s, hx, a0);
+                a1 = fma(s, hy, a1);
+                a2 = fma(s, hz, a2);
             }
         }
-        __syncthreads();
     }
     if (active) {
         atomicAdd(&out[t], w.w * a0);
@@ -614,11 +689,26 @@ void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, 
     hipLaunchKernelGGL(k_nodes, dim3(nblk(npts(q))), dim3(256), 0, st, q, syn, wreg, sx, swN, swW, sstride, vol);
 }
 
-void launch_classify(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
-                     const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
-                     int8_t *reg, double *dist)
+void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
+                        double *cb)
 {
-    hipLaunchKernelGGL(k_classify, dim3(nblk((long)T * nd)), dim3(256), 0, st, T, nd, tx, tstride, tdrop, sx,
+    hipLaunchKernelGGL(k_drop_bounds, dim3(nd), dim3(256), 0, st, nd, sx, sstride, noff, ncnt, cb);
+}
+
+void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
+                           const double *cb, const double *hj, double A, int exact, int8_t *reg, double *dist,
+                           int *list, int *count)
+{
+    hipLaunchKernelGGL(k_classify_bound, dim3(nblk((long)T * nd)), dim3(256), 0, st, T, nd, tx, tstride, tdrop, cb,
+                       hj, A, exact, reg, dist, list, count);
+}
+
+void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,
+                          const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
+                          int8_t *reg, double *dist)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_classify_scan, dim3(nblk((long)n * 64)), dim3(256), 0, st, n, list, nd, tx, tstride, sx,
                        sstride, noff, ncnt, hj, A, reg, dist);
 }
 
@@ -651,10 +741,10 @@ void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, cons
 {
     if (nwork <= 0) return;
     if (kind == 0)
-        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
+        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(64), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
                            sstride, out, ostride);
     else
-        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
+        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(64), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
                            sstride, out, ostride);
 }
 

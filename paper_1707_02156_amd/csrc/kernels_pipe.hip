@@ -1,0 +1,519 @@
+// Singular self-integral as a batched pipeline over all grid targets of a drop
+// (gfx950, FP64). Same quadrature as the fused kernel (Sec. 2.2, Theorem 1,
+// Appendix B), reorganised so the Legendre stages are dense contractions on
+// the matrix cores:
+//
+//   R  k_rot2      rotation of x (and the single-layer density) for every
+//                  target of a latitude, per degree n (Appendix B, gamma = 0);
+//                  output by order mu: B^mu[n - mu][col], col = target*6 + comp*2 + re/im
+//   L  k_leg_mfma  G^mu = T^mu B^mu on v_mfma_f64_16x16x4f64, T^mu the Legendre
+//                  rows [Ptilde_n^mu(t_j'); dPtilde_n^mu/dtheta(t_j')] of the rotated grid
+//   FK k_fk        Fourier sums at the rotated longitudes (symmetries phi -> -phi,
+//                  phi -> phi + pi), the pole-rule kernels, per-latitude partial sums;
+//                  for the double layer the six stresslet fields and their Fourier
+//                  analysis Fa^mu[j'][target*12 + pair*2 + re/im]
+//   LA k_leg_mfma  Legendre analysis Bt^mu = (Ptilde^mu)^T Fa^mu (same kernel)
+//   AR k_adjrot    adjoint rotation -> rows of the stored double layer
+//                  M[t][pair][2 ncoef(p)] (applied by k_dl_apply)
+//
+// Layouts: a triangle-ordered operand stores order mu as the rows n = mu..p at
+// row offset koff(mu) = mu (p+1) - mu (mu-1)/2, each row NC doubles wide.
+#include "internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace bim {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline long koff(int mu, int P1) { return (long)mu * P1 - (long)mu * (mu - 1) / 2; }
+
+// ----------------------------------------------------------------------------
+// R: rotation. Block (n, j). Outputs for targets t = t0 + k (k < 2p) of
+// latitude j: for x (3 components) into Bx and for the density (3) into Bd.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rot2(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
+                                              const double *__restrict__ csp, const double *__restrict__ xc,
+                                              long xstride, const double *__restrict__ dc, long dstride,
+                                              int j0, int tbase, double *__restrict__ Bx, double *__restrict__ Bd,
+                                              long NC)
+{
+    extern __shared__ double sm[];
+    const int n = blockIdx.x, j = j0 + blockIdx.y;
+    const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
+    const int nf = dc ? 6 : 3;
+    double *sAp = sm;                 // [nu][mu]
+    double *sAm = sAp + N1 * N1;
+    double *sC = sAm + N1 * N1;       // [f][nu][2]
+    double *sPh = sC + nf * N1 * 2;   // [k][nu][2] cos, sin of nu phi_k
+    const size_t lat = rot_lat_size(p) * j + rot_off(n);
+    for (int i = threadIdx.x; i < N1 * N1; i += 256) {
+        sAp[i] = Ap[lat + i];
+        sAm[i] = Am[lat + i];
+    }
+    const int b0 = n * (n + 1) / 2;
+    for (int i = threadIdx.x; i < nf * N1; i += 256) {
+        const int f = i / N1, nu = i % N1;
+        const double *c = (f < 3) ? xc + f * xstride : dc + (f - 3) * dstride;
+        sC[2 * i] = c[2 * (b0 + nu)];
+        sC[2 * i + 1] = c[2 * (b0 + nu) + 1];
+    }
+    for (int i = threadIdx.x; i < nk * N1; i += 256) {
+        const int k = i / N1, nu = i % N1;
+        const int e = (int)(((long)nu * k) % nk);
+        sPh[2 * i] = csp[e];
+        sPh[2 * i + 1] = csp[nk + e];
+    }
+    __syncthreads();
+    const int ng = (N1 + 3) / 4;
+    // items: mu-group slowest, then k, then field (fastest) so that writes are contiguous
+    for (int it = threadIdx.x; it < ng * nk * nf; it += 256) {
+        const int f = it % nf;
+        const int r = it / nf;
+        const int k = r % nk, g = r / nk;
+        const int mu0 = 4 * g;
+        double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+        const double *cf = sC + 2 * f * N1;
+        const double *ph = sPh + 2 * k * N1;
+        for (int nu = 0; nu <= n; ++nu) {
+            const double cr = cf[2 * nu], ci = cf[2 * nu + 1];
+            const double cc = ph[2 * nu], ss = ph[2 * nu + 1];
+            const double gr = cr * cc - ci * ss, gi = cr * ss + ci * cc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mu = mu0 + q;
+                if (mu <= n) {
+                    re[q] = fma(sAp[nu * N1 + mu], gr, re[q]);
+                    im[q] = fma(sAm[nu * N1 + mu], gi, im[q]);
+                }
+            }
+        }
+        const int t = tbase + blockIdx.y * nk + k;  // target index within the chunk
+        double *dst = (f < 3) ? Bx : Bd;
+        const int ff = f < 3 ? f : f - 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mu = mu0 + q;
+            if (mu <= n) {
+                double *o = dst + (koff(mu, P1) + (n - mu)) * NC + (long)t * 6 + ff * 2;
+                o[0] = re[q];
+                o[1] = im[q];
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// L / LA: batched contraction on the matrix cores.
+//   OUT^b[r][col] = sum_k TAB^b[r][k] IN^b[k][col],  b = 0..nb-1,
+// with per-batch rows R_b, depth K_b and row offsets; TAB^b row-major R_b x K_b
+// at tab_off[b]. Block: all rows of one batch x 64 columns (4 wavefronts x 16).
+// ----------------------------------------------------------------------------
+struct LegBatch {
+    int R, K;          // rows, depth
+    long tab_off;      // TAB offset (doubles)
+    long in_row;       // first IN row
+    long out_row;      // first OUT row
+};
+
+template <int MT>
+__global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
+                                                  const double *__restrict__ in, double *__restrict__ out, long NC)
+{
+    __shared__ double sT[MT * 16 * 4 * 13];   // rows padded to MT*16, depth padded to 4 per slab (up to 52)
+    const LegBatch b = bt[blockIdx.y];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long col0 = (long)blockIdx.x * 64 + wv * 16;
+    const int Kp = (b.K + 3) & ~3;
+    // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp
+    for (int i = threadIdx.x; i < MT * 16 * Kp; i += 256) {
+        const int r = i / Kp, k = i % Kp;
+        sT[i] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
+    }
+    __syncthreads();
+    d4_t acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = (d4_t){0, 0, 0, 0};
+    const long col = col0 + (lane & 15);
+    const bool cok = col < NC;
+    const int kl = lane >> 4;
+    for (int k0 = 0; k0 < Kp; k0 += 4) {
+        const int k = k0 + kl;
+        const double bv = (cok && k < b.K) ? in[(b.in_row + k) * NC + col] : 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const double av = sT[(m * 16 + (lane & 15)) * Kp + k];
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
+        }
+    }
+    if (!cok) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = m * 16 + 4 * v + kl;
+            if (r < b.R) out[(b.out_row + r) * NC + col] = acc[m][v];
+        }
+}
+
+// ----------------------------------------------------------------------------
+// FK: Fourier sums and kernels. Block: TG consecutive targets x one rotated
+// latitude j'. Gx rows: j' (Ptilde) and Q1 + j' (d/dtheta); Gd row j'.
+// SL: partial[t][j'][3] += omega W (f/r + xh (xh.f)/r^3) summed over the longitudes.
+// DL: Fa^mu[j'][t*12 + pair*2 + {cos, sin}] of the six stresslet fields.
+// ----------------------------------------------------------------------------
+template <bool SL, bool DL, int TG>
+__global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double *__restrict__ Gx,
+                                            const double *__restrict__ Gd, long NC6,
+                                            const double *__restrict__ wsing, const double *__restrict__ X0,
+                                            double *__restrict__ part, double *__restrict__ Fa, long NC12)
+{
+    extern __shared__ double sm[];
+    const int P1 = p + 1, Q1 = qs + 1, nk = 2 * qs;
+    const int jr = blockIdx.y;
+    const int t0 = blockIdx.x * TG;
+    const int ntg = min(TG, nt - t0);
+    // sG[tg][mu][type 0..3][c][re,im] ; type 0 x, 1 x_theta, 2 x_phi (= i mu x), 3 density
+    constexpr int NTY = SL ? 4 : 3;
+    double *sG = sm;
+    const long gsz = (long)TG * P1 * NTY * 6;
+    double *V = sG + gsz;                    // [tg][k'][12]
+    double *red = V + (long)TG * nk * 12;    // [tg][3]
+    for (int i = threadIdx.x; i < TG * 3; i += 256) red[i] = 0.0;
+    // ---- load G (weights w_mu applied; x_phi built from x)
+    for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
+        const int e = i % 6;           // c*2 + re/im
+        const int r = i / 6;
+        const int tg = r % ntg, mu = r / ntg;
+        const long colx = (long)(t0 + tg) * 6 + e;
+        const double w = mu ? 2.0 : 1.0;
+        const double gx = w * Gx[((long)mu * 2 * Q1 + jr) * NC6 + colx];
+        const double gdth = w * Gx[((long)mu * 2 * Q1 + Q1 + jr) * NC6 + colx];
+        double *g = sG + ((long)(tg * P1 + mu) * NTY) * 6;
+        g[e] = gx;
+        g[6 + e] = gdth;
+        if (SL) g[18 + e] = w * Gd[((long)mu * Q1 + jr) * NC6 + colx];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < P1 * ntg * 3; i += 256) {
+        const int c = i % 3;
+        const int r = i / 3;
+        const int tg = r % ntg, mu = r / ntg;
+        double *g = sG + ((long)(tg * P1 + mu) * NTY) * 6;
+        // (i mu) (gr + i gi) = (-mu gi) + i (mu gr)
+        g[12 + 2 * c] = -mu * g[2 * c + 1];
+        g[12 + 2 * c + 1] = mu * g[2 * c];
+    }
+    __syncthreads();
+    const bool even = (qs & 1) == 0;
+    const int nkk = even ? qs / 2 + 1 : qs;
+    const double dphi = 3.14159265358979323846 / qs;
+    // ---- F: point values
+    for (int it = threadIdx.x; it < ntg * nkk * 3; it += 256) {
+        const int c = it % 3;
+        const int r = it / 3;
+        const int kk = r % nkk, tg = r / nkk;
+        const double *g = sG + (long)tg * P1 * NTY * 6 + 2 * c;
+        double sn, cs;
+        sincos(dphi * kk, &sn, &cs);
+        double cm = 1.0, sm_ = 0.0;
+        double CE[NTY], CO[NTY], SE[NTY], SO[NTY];
+#pragma unroll
+        for (int q = 0; q < NTY; ++q) { CE[q] = 0; CO[q] = 0; SE[q] = 0; SO[q] = 0; }
+        int mu = 0;
+        for (; mu + 1 <= p; mu += 2) {
+            const double *ge = g + (long)mu * NTY * 6, *go = ge + NTY * 6;
+#pragma unroll
+            for (int q = 0; q < NTY; ++q) {
+                CE[q] = fma(ge[6 * q], cm, CE[q]);
+                SE[q] = fma(ge[6 * q + 1], sm_, SE[q]);
+            }
+            double c2 = cm * cs - sm_ * sn;
+            double s2 = fma(sm_, cs, cm * sn);
+#pragma unroll
+            for (int q = 0; q < NTY; ++q) {
+                CO[q] = fma(go[6 * q], c2, CO[q]);
+                SO[q] = fma(go[6 * q + 1], s2, SO[q]);
+            }
+            cm = c2 * cs - s2 * sn;
+            sm_ = fma(s2, cs, c2 * sn);
+        }
+        if (mu <= p) {  // last order (even)
+            const double *ge = g + (long)mu * NTY * 6;
+#pragma unroll
+            for (int q = 0; q < NTY; ++q) {
+                CE[q] = fma(ge[6 * q], cm, CE[q]);
+                SE[q] = fma(ge[6 * q + 1], sm_, SE[q]);
+            }
+        }
+        double *Vb = V + (long)tg * nk * 12;
+        // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
+        auto put = [&](int kp, double s1, double s2) {
+            double *v = Vb + (long)kp * 12;
+            v[c] = (CE[0] - s1 * SE[0]) + s2 * (CO[0] - s1 * SO[0]);
+            v[3 + c] = (CE[1] - s1 * SE[1]) + s2 * (CO[1] - s1 * SO[1]);
+            v[6 + c] = (CE[2] - s1 * SE[2]) + s2 * (CO[2] - s1 * SO[2]);
+            if (SL) v[9 + c] = (CE[3] - s1 * SE[3]) + s2 * (CO[3] - s1 * SO[3]);
+        };
+        put(kk, 1.0, 1.0);
+        put(kk + qs, 1.0, -1.0);
+        if (even && kk != 0 && kk != qs / 2) {
+            put(nk - kk, -1.0, 1.0);
+            put(qs - kk, -1.0, -1.0);
+        }
+    }
+    __syncthreads();
+    // ---- K: kernels
+    const double om = wsing[jr];
+    for (int it = threadIdx.x; it < ntg * nk; it += 256) {
+        const int tg = it / nk;
+        double *v = V + (long)it * 12;
+        const int t = t0 + tg;
+        const double xt0 = v[3], xt1 = v[4], xt2 = v[5];
+        const double xp0 = v[6], xp1 = v[7], xp2 = v[8];
+        const double N0 = xt1 * xp2 - xt2 * xp1;
+        const double N1 = xt2 * xp0 - xt0 * xp2;
+        const double N2 = xt0 * xp1 - xt1 * xp0;
+        const double h0 = X0[3 * t] - v[0], h1 = X0[3 * t + 1] - v[1], h2 = X0[3 * t + 2] - v[2];
+        const double r2 = h0 * h0 + h1 * h1 + h2 * h2;
+        const double ri = rsqrt(r2);
+        if (SL) {
+            const double f0 = v[9], f1 = v[10], f2 = v[11];
+            const double hf = h0 * f0 + h1 * f1 + h2 * f2;
+            const double Wr = om * sqrt(N0 * N0 + N1 * N1 + N2 * N2) * ri;
+            const double q = hf * ri * ri;
+            atomicAdd(&red[3 * tg], Wr * fma(h0, q, f0));
+            atomicAdd(&red[3 * tg + 1], Wr * fma(h1, q, f1));
+            atomicAdd(&red[3 * tg + 2], Wr * fma(h2, q, f2));
+        }
+        if (DL) {
+            const double hn = h0 * N0 + h1 * N1 + h2 * N2;
+            const double r2i = ri * ri;
+            const double s = -6.0 * om * hn * r2i * r2i * ri;
+            v[0] = s * h0 * h0;
+            v[1] = s * h0 * h1;
+            v[2] = s * h0 * h2;
+            v[3] = s * h1 * h1;
+            v[4] = s * h1 * h2;
+            v[5] = s * h2 * h2;
+        }
+    }
+    __syncthreads();
+    if (SL)
+        for (int i = threadIdx.x; i < ntg * 3; i += 256) part[((long)(t0 + i / 3) * Q1 + jr) * 3 + i % 3] = red[i];
+    if (DL) {
+        // ---- FA: Fourier analysis of the six stresslet fields
+        for (int it = threadIdx.x; it < P1 * ntg * 6; it += 256) {
+            const int pr = it % 6;
+            const int r = it / 6;
+            const int tg = r % ntg, mu = r / ntg;
+            const double *Vb = V + (long)tg * nk * 12 + pr;
+            double sn, cs;
+            sincos(dphi * mu, &sn, &cs);
+            double ck = 1.0, sk = 0.0;
+            const double sg = (mu & 1) ? -1.0 : 1.0;
+            double fc = 0.0, fs = 0.0;
+            for (int kk = 0; kk < nkk; ++kk) {
+                const double K1 = Vb[(long)kk * 12];
+                const double K3 = Vb[(long)(kk + qs) * 12];
+                double K2 = 0.0, K4 = 0.0;
+                if (even && kk != 0 && kk != qs / 2) {
+                    K2 = Vb[(long)(nk - kk) * 12];
+                    K4 = Vb[(long)(qs - kk) * 12];
+                }
+                fc = fma(ck, (K1 + K2) + sg * (K3 + K4), fc);
+                fs = fma(sk, (K1 - K2) + sg * (K3 - K4), fs);
+                const double c2 = ck * cs - sk * sn;
+                sk = fma(sk, cs, ck * sn);
+                ck = c2;
+            }
+            double *o = Fa + ((long)mu * Q1 + jr) * NC12 + (long)(t0 + tg) * 12 + pr * 2;
+            o[0] = fc;
+            o[1] = fs;
+        }
+    }
+}
+
+// part[t][j'][3] summed over j' into out (scaled, added).
+__global__ void k_sum_part(int nt, int Q1, const double *__restrict__ part, double scale, double *__restrict__ out,
+                           long ostride)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt * 3) return;
+    const int t = i / 3, c = i % 3;
+    double s = 0.0;
+    for (int j = 0; j < Q1; ++j) s += part[((long)t * Q1 + j) * 3 + c];
+    out[c * ostride + t] += scale * s;
+}
+
+// Pole values x0 of every target: sum_n Re x'^0_n sqrt((2n+1)/4pi) from the
+// mu = 0 block of the rotated x (col = t*6 + c*2).
+__global__ void k_pole(int p, int nt, const double *__restrict__ Bx, long NC, double *__restrict__ X0)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt * 3) return;
+    const int t = i / 3, c = i % 3;
+    double s = 0.0;
+    for (int n = 0; n <= p; ++n) s += Bx[(long)n * NC + (long)t * 6 + 2 * c] * sqrt((2.0 * n + 1.0) / (4.0 * 3.14159265358979323846));
+    X0[3 * t + c] = s;
+}
+
+// ----------------------------------------------------------------------------
+// AR: adjoint rotation. Block (n, j, target group of 16 of latitude j).
+// a_mu = w_mu Bt^mu[n][.. cos], b_mu = -w_mu Bt^mu[n][.. sin];
+// alpha_nu = sum_mu A+_{nu mu} a_mu, beta_nu = sum_mu A-_{nu mu} b_mu;
+// M[t][pair][2 tri(n,nu)] = alpha cos(nu phi_k) + beta sin, [+1] = -alpha sin + beta cos.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adjrot(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
+                                                const double *__restrict__ csp, const double *__restrict__ Bt,
+                                                long NC12, int j0, int tbase, int tglobal0,
+                                                double *__restrict__ M)
+{
+    extern __shared__ double sm[];
+    const int n = blockIdx.x, j = j0 + blockIdx.y;
+    const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
+    const int kg0 = blockIdx.z * 16;
+    const int nkg = min(16, nk - kg0);
+    double *sAp = sm;
+    double *sAm = sAp + N1 * N1;
+    double *sB = sAm + N1 * N1;        // [kg][pair][mu][2]
+    const size_t lat = rot_lat_size(p) * j + rot_off(n);
+    for (int i = threadIdx.x; i < N1 * N1; i += 256) {
+        sAp[i] = Ap[lat + i];
+        sAm[i] = Am[lat + i];
+    }
+    for (int i = threadIdx.x; i < nkg * 6 * N1; i += 256) {
+        const int mu = i % N1;
+        const int r = i / N1;
+        const int pr = r % 6, kg = r / 6;
+        const int t = tbase + blockIdx.y * nk + kg0 + kg;
+        const double w = mu ? 2.0 : 1.0;
+        const double *src = Bt + (koff(mu, P1) + (n - mu)) * NC12 + (long)t * 12 + pr * 2;
+        sB[2 * i] = w * src[0];
+        sB[2 * i + 1] = -w * src[1];
+    }
+    __syncthreads();
+    const int nc2 = 2 * ncoef(p);
+    const int ng = (N1 + 3) / 4;
+    for (int it = threadIdx.x; it < nkg * 6 * ng; it += 256) {
+        const int g = it % ng;
+        const int r = it / ng;
+        const int pr = r % 6, kg = r / 6;
+        const int nu0 = 4 * g;
+        const double *bb = sB + 2 * ((kg * 6 + pr) * N1);
+        double al[4] = {0, 0, 0, 0}, be[4] = {0, 0, 0, 0};
+        for (int mu = 0; mu <= n; ++mu) {
+            const double a = bb[2 * mu], b = bb[2 * mu + 1];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int nu = nu0 + q;
+                if (nu <= n) {
+                    al[q] = fma(sAp[nu * N1 + mu], a, al[q]);
+                    be[q] = fma(sAm[nu * N1 + mu], b, be[q]);
+                }
+            }
+        }
+        const int k = kg0 + kg;
+        const long tg = tglobal0 + (long)blockIdx.y * nk + k;   // target index within the drop
+        double *Mt = M + (tg * 6 + pr) * nc2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int nu = nu0 + q;
+            if (nu <= n) {
+                const int e = (int)(((long)nu * k) % nk);
+                const double cc = csp[e], ss = csp[nk + e];
+                Mt[2 * (n * (n + 1) / 2 + nu)] = al[q] * cc + be[q] * ss;
+                Mt[2 * (n * (n + 1) / 2 + nu) + 1] = -al[q] * ss + be[q] * cc;
+            }
+        }
+    }
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// allow up to 160 KB of dynamic LDS for the kernels that size it by degree
+void pipe_set_lds_limits()
+{
+    static bool done = false;
+    if (done) return;
+    done = true;
+    (void)hipFuncSetAttribute((const void *)k_rot2, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    (void)hipFuncSetAttribute((const void *)k_adjrot, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    (void)hipFuncSetAttribute((const void *)k_fk<true, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    (void)hipFuncSetAttribute((const void *)k_fk<true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    (void)hipFuncSetAttribute((const void *)k_fk<false, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+}
+
+void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
+                 long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC)
+{
+    const int P1 = p + 1, nk = 2 * p;
+    const int nf = dc ? 6 : 3;
+    const size_t lds = (size_t)(2 * P1 * P1 + nf * P1 * 2 + nk * P1 * 2) * sizeof(double);
+    hipLaunchKernelGGL(k_rot2, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride, j0, 0, Bx,
+                       Bd, NC);
+}
+
+void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
+                     double *out, long NC)
+{
+    const dim3 grid(cdiv(NC, 64), nbatch);
+    const LegBatch *b = static_cast<const LegBatch *>(batches);
+    const int MT = (maxrows + 15) / 16;
+    switch (MT) {
+    case 1: hipLaunchKernelGGL(k_leg_mfma<1>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 2: hipLaunchKernelGGL(k_leg_mfma<2>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 3: hipLaunchKernelGGL(k_leg_mfma<3>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 4: hipLaunchKernelGGL(k_leg_mfma<4>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 5: hipLaunchKernelGGL(k_leg_mfma<5>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 6: hipLaunchKernelGGL(k_leg_mfma<6>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    default: hipLaunchKernelGGL(k_leg_mfma<7>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    }
+}
+
+int leg_mfma_max_rows() { return 7 * 16; }
+int leg_mfma_max_depth() { return 52; }
+
+size_t fk_lds_bytes(int p, int qs, bool sl, int tg)
+{
+    const int nty = sl ? 4 : 3;
+    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * 12 + (size_t)tg * 3) * sizeof(double);
+}
+
+void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
+               const double *wsing, const double *X0, double *part, double *Fa, long NC12)
+{
+    constexpr int TG = 4;
+    const dim3 grid(cdiv(nt, TG), qs + 1);
+    const size_t lds = fk_lds_bytes(p, qs, sl, TG);
+    if (sl && dl)
+        hipLaunchKernelGGL((k_fk<true, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+    else if (sl)
+        hipLaunchKernelGGL((k_fk<true, false, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+    else
+        hipLaunchKernelGGL((k_fk<false, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+}
+
+void launch_sum_part(hipStream_t st, int nt, int Q1, const double *part, double scale, double *out, long ostride)
+{
+    hipLaunchKernelGGL(k_sum_part, dim3(cdiv((long)nt * 3, 256)), dim3(256), 0, st, nt, Q1, part, scale, out, ostride);
+}
+
+void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, double *X0)
+{
+    hipLaunchKernelGGL(k_pole, dim3(cdiv((long)nt * 3, 256)), dim3(256), 0, st, p, nt, Bx, NC, X0);
+}
+
+void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *Bt,
+                   long NC12, int j0, int nj, int tglobal0, double *M)
+{
+    const int P1 = p + 1, nk = 2 * p;
+    const size_t lds = (size_t)(2 * P1 * P1 + 16 * 6 * P1 * 2) * sizeof(double);
+    hipLaunchKernelGGL(k_adjrot, dim3(P1, nj, cdiv(nk, 16)), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, j0, 0,
+                       tglobal0, M);
+}
+
+}  // namespace bim

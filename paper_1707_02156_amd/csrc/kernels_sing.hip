@@ -68,10 +68,15 @@ __host__ __device__ inline long sing_lds_doubles(int p, int qs, int JB, bool SL,
     return creg + gsz + vsz + misc;
 }
 
+// threads per workgroup: 1024 for the single layer alone (16 wavefronts hide
+// the latency of the table reads), 512 when the double-layer rows are built
+// (their register accumulators need up to 256 VGPRs per lane)
+template <bool SL, bool DL> struct SingThreads { static constexpr int value = DL ? 512 : 1024; };
+
 template <bool SL, bool DL, int JB, int NB>
-__global__ __launch_bounds__(256) void k_sing_fused(SingArgs a)
+__global__ __launch_bounds__(DL ? 512 : 1024) void k_sing_fused(SingArgs a)
 {
-    constexpr int NTH = 256;
+    constexpr int NTH = SingThreads<SL, DL>::value;
     extern __shared__ double lds[];
     const int p = a.p, qs = a.qs;
     const int nc = ncoef(p), P1 = p + 1, nk = 2 * qs;
@@ -440,41 +445,43 @@ template <bool SL, bool DL, int JB, int NB> static void launch_one(hipStream_t s
         (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
         attr_set = true;
     }
-    hipLaunchKernelGGL(fn, dim3(a.nt), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(fn, dim3(a.nt), dim3(SingThreads<SL, DL>::value), lds, st, a);
+}
+
+// Register-resident adjoint accumulators per thread for the double-layer rows.
+static inline long dl_entries(int p, int nth) { return (6L * ncoef(p) + nth - 1) / nth; }
+
+template <bool SL, bool DL, int NB> static bool launch_nb(hipStream_t st, const SingArgs &a, int jbmax)
+{
+    for (int jb : {8, 4, 2, 1}) {
+        if (jb > jbmax) continue;
+        const long need = sing_lds_doubles(a.p, a.qs, jb, SL, DL) * 8;
+        if (need > 163840) continue;
+        if (jb == 8) launch_one<SL, DL, 8, NB>(st, a, need);
+        else if (jb == 4) launch_one<SL, DL, 4, NB>(st, a, need);
+        else if (jb == 2) launch_one<SL, DL, 2, NB>(st, a, need);
+        else launch_one<SL, DL, 1, NB>(st, a, need);
+        return true;
+    }
+    return false;
 }
 
 template <bool SL, bool DL> static bool launch_sl_dl(hipStream_t st, const SingArgs &a)
 {
-    const int p = a.p;
-    const long nc = ncoef(p);
-    const int JBs[4] = {8, 4, 2, 1};
-    int JB = 0;
-    for (int jb : JBs)
-        if (sing_lds_doubles(p, a.qs, jb, SL, DL) * 8 <= 163840) { JB = jb; break; }
-    if (JB == 0) return false;
-    const size_t lds = (size_t)sing_lds_doubles(p, a.qs, JB, SL, DL) * 8;
-    const long need = DL ? (6 * nc + 255) / 256 : 1;
-    // NB classes
-#define BIM_SING_CASE(NBV)                                                               \
-    if (need <= NBV) {                                                                   \
-        if (JB == 8) launch_one<SL, DL, 8, NBV>(st, a, lds);                             \
-        else if (JB == 4) launch_one<SL, DL, 4, NBV>(st, a, lds);                        \
-        else if (JB == 2) launch_one<SL, DL, 2, NBV>(st, a, lds);                        \
-        else launch_one<SL, DL, 1, NBV>(st, a, lds);                                     \
-        return true;                                                                     \
-    }
-    if (!DL) {
-        BIM_SING_CASE(1)
+    if constexpr (!DL) {
+        return launch_nb<SL, DL, 1>(st, a, 8);
+    } else {
+        const long need = dl_entries(a.p, 512);
+        if (need <= 2) return launch_nb<SL, DL, 2>(st, a, 8);
+        if (need <= 4) return launch_nb<SL, DL, 4>(st, a, 8);
+        if (need <= 7) return launch_nb<SL, DL, 7>(st, a, 8);
+        if (need <= 11) return launch_nb<SL, DL, 11>(st, a, 4);
+        if constexpr (!SL) {
+            if (need <= 15) return launch_nb<SL, DL, 15>(st, a, 4);
+            if (need <= 17) return launch_nb<SL, DL, 17>(st, a, 4);
+        }
         return false;
     }
-    BIM_SING_CASE(4)
-    BIM_SING_CASE(8)
-    BIM_SING_CASE(14)
-    BIM_SING_CASE(21)
-    BIM_SING_CASE(29)
-    BIM_SING_CASE(34)
-#undef BIM_SING_CASE
-    return false;
 }
 
 // Returns false when the degree does not fit the fused kernel (caller falls back).
@@ -486,14 +493,15 @@ bool launch_sing_fused(hipStream_t st, bool sl, bool dl, const SingArgs &a)
     return true;
 }
 
+// Whether the fused kernel handles this degree (single layer, double-layer rows, or both at once).
 bool sing_fused_fits(int p, int qs, bool sl, bool dl)
 {
-    for (int jb : {8, 4, 2, 1})
-        if (sing_lds_doubles(p, qs, jb, sl, dl) * 8 <= 163840) {
-            if (dl && (6L * ncoef(p) + 255) / 256 > 34) return false;
-            return true;
-        }
-    return false;
+    bool lds_ok = false;
+    for (int jb : {4, 2, 1})
+        if (sing_lds_doubles(p, qs, jb, sl, dl) * 8 <= 163840) lds_ok = true;
+    if (!lds_ok) return false;
+    if (!dl) return true;
+    return dl_entries(p, 512) <= (sl ? 11 : 17);
 }
 
 void launch_dl_apply(hipStream_t st, int nt, int nc2, const double *M, const double *u, long ustride, double w,

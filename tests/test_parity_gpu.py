@@ -171,7 +171,7 @@ def test_regions_and_distances(B, orc):
 
 # --- single layer ------------------------------------------------------------------
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 def test_single_layer_one_drop_p16(B, orc, path):
     """Single drop p = 16: every grid target against the oracle's pole rule
     (fused kernel and per-application rotation path)."""
@@ -231,7 +231,7 @@ def test_single_layer_three_drops_mixed_regions(B, orc):
 
 # --- double layer -----------------------------------------------------------------
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 def test_double_layer_raw_three_drops(B, orc, path):
     print(f"double layer raw path={path}", flush=True)
     rng = np.random.default_rng(42)
@@ -325,7 +325,7 @@ def test_eval_velocity_lambda_one_matches_single_layer(B, orc):
     c.close()
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 def test_eval_velocity_two_drops_gmres(B, orc, path):
     """Two drops (p = 8, lambda 1 and 5), linear equation of state; GMRES to
     1e-12 on both sides; solutions agree to 1e-10."""
