@@ -50,9 +50,9 @@ void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, co
                    long xstride, const double *dc, long dstride, double *R);
 void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
                      const double *wsing, const double *cs, double *out, long ostride, double scale);
+int pair_sources_per_item();
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const double *sx, const double *swN, const double *swW, const double *sd,
-                 long sstride, double *out, long ostride);
+                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride);
 struct SingArgs {
     int p, qs, nt;
     const double *Ap, *Am, *ApT, *AmT;
@@ -73,6 +73,7 @@ struct LegBatchH {
     int R, K;
     long tab_off, in_row, out_row;
 };
+size_t rot_lds_bytes(int p);
 void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
                  long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC);
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
@@ -112,10 +113,15 @@ void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const dou
                 const double *gU_dev, double *b);
 void launch_scale_add(hipStream_t st, long n, double a, const double *x, double b, double *y);
 void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x, double *y);
-void launch_dots(hipStream_t st, long n, int k, const double *V, long ld, const double *w, double *h);
-void launch_orth_update(hipStream_t st, long n, int k, const double *V, long ld, const double *h, double *w);
-void launch_add_into(hipStream_t st, int k, const double *a, double *b);
-void launch_normalize(hipStream_t st, long n, const double *w, double *v, double *nrm);
+long gs_blocks(long n);
+int gs_max_vectors();
+void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, double *w, double *part,
+                    unsigned *cnt, double *h);
+void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long ld, const double *h1, double *w,
+                           double *part, unsigned *cnt, double *h2);
+void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
+                           double *part, unsigned *cnt, double *h);
+void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 
 static const double kPi = 3.14159265358979323846;
@@ -213,9 +219,9 @@ struct Ctx {
     std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
     struct WList {
         std::vector<double> wt;
-        DBuf d0, d1;
-        int n0 = 0, n1 = 0;
-        double pairs0 = 0.0, pairs1 = 0.0;  // target-source pairs per application
+        DBuf d;
+        int n = 0;
+        double pairs = 0.0;  // target-source pairs per application
     };
     std::vector<std::unique_ptr<WList>> wlists;
     std::vector<int8_t> reg_h;
@@ -224,7 +230,7 @@ struct Ctx {
     DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
-    DBuf V, hbuf, ybuf, wvec, xsol, rvec;
+    DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt;
     double *hhost = nullptr;       // pinned
 
     bool nodes_ok = false, force_ok = false, regions_ok = false;
@@ -638,7 +644,7 @@ static void build_regions(Ctx &c)
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
     std::vector<int> tl;
     std::vector<PairWork> w0, w1;
-    const int TILE = 64, CH = 256;
+    const int TILE = 64, CH = pair_sources_per_item();
     c.n_om1 = c.n_om2 = 0;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &di = c.drops[i];
@@ -665,7 +671,7 @@ static void build_regions(Ctx &c)
                         pw.src_off = (int)(soff + b);
                         pw.nsrc = std::min(CH, ns - b);
                         pw.pair = i * c.nd + j;
-                        pw.pad = 0;
+                        pw.pad = kind;
                         pw.w = 0.0;
                         (kind == 0 ? w0 : w1).push_back(pw);
                     }
@@ -690,42 +696,34 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
         if (e->wt == wt) return *e;
     auto e = std::make_unique<Ctx::WList>();
     e->wt = wt;
-    for (int u = 0; u < 2; ++u) {
-        const std::vector<PairWork> &src = u == 0 ? c.w0h : c.w1h;
-        std::vector<PairWork> keep;
-        keep.reserve(src.size());
-        for (PairWork pw : src) {
+    std::vector<PairWork> keep;
+    keep.reserve(c.w0h.size() + c.w1h.size());
+    for (int u = 0; u < 2; ++u)
+        for (PairWork pw : (u == 0 ? c.w0h : c.w1h)) {
             pw.w = wt[pw.pair];
             if (pw.w != 0.0) {
                 keep.push_back(pw);
-                (u == 0 ? e->pairs0 : e->pairs1) += (double)pw.ntgt * pw.nsrc;
+                e->pairs += (double)pw.ntgt * pw.nsrc;
             }
         }
-        DBuf &db = u == 0 ? e->d0 : e->d1;
-        db.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
-        if (!keep.empty())
-            HIPC(hipMemcpy(db.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice));
-        (u == 0 ? e->n0 : e->n1) = (int)keep.size();
-    }
+    e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
+    if (!keep.empty())
+        HIPC(hipMemcpy(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice));
+    e->n = (int)keep.size();
     c.wlists.push_back(std::move(e));
     return *c.wlists.back();
 }
 
-// Pair sums with weight table wt, added into acc.
+// Pair sums with weight table wt, added into acc: one launch over the items
+// of both source grids.
 static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
 {
     Ctx::WList &L = work_lists(c, wt);
     const double fpp = kind == 0 ? 29.0 : 30.0;  // flops per pair (SL / DL)
-    {
-        ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs0 * fpp, 0.0);
-        launch_pair(c.stream, kind, L.n0, L.d0.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.tx.d(),
-                    c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T, c.acc.d(), c.T);
-    }
-    {
-        ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs1 * fpp, 0.0);
-        launch_pair(c.stream, kind, L.n1, L.d1.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, c.s1x.d(),
-                    c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1, c.acc.d(), c.T);
-    }
+    ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs * fpp, 0.0);
+    const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
+    const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
+    launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T);
 }
 
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
@@ -819,8 +817,7 @@ static Ctx::PipeTab &pipe_tables(Ctx &c, int p, int qs)
 static bool pipe_fits(int p, int qs)
 {
     return 2 * (qs + 1) <= leg_mfma_max_rows() && (p + 1) <= leg_mfma_max_depth() &&
-           (qs + 1) <= leg_mfma_max_depth() && fk_lds_bytes(p, qs, true, 4) <= 163840 &&
-           (size_t)(2 * (p + 1) * (p + 1) + 6 * (p + 1) * 2 + 2 * p * (p + 1) * 2) * 8 <= 163840;
+           (qs + 1) <= leg_mfma_max_depth() && fk_lds_bytes(p, qs, true, 4) <= 163840 && rot_lds_bytes(p) <= 163840;
 }
 
 // Singular pass of drop i through the batched pipeline: single layer of dens
@@ -1061,17 +1058,23 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
                  int &nmv)
 {
     const long n = 3 * c.Ctot;
-    const int m = std::max(1, std::min(c.opt.gmres_restart, 200));
+    const int m = std::max(1, std::min(c.opt.gmres_restart, gs_max_vectors() - 1));
     c.V.ensure((size_t)(m + 1) * n * sizeof(double));
     c.hbuf.ensure((size_t)(2 * (m + 2)) * sizeof(double));
     c.ybuf.ensure((size_t)(m + 2) * sizeof(double));
     c.wvec.ensure((size_t)n * sizeof(double));
     c.rvec.ensure((size_t)n * sizeof(double));
+    c.gspart.ensure((size_t)gs_blocks(n) * (m + 2) * sizeof(double));
+    if (!c.gscnt.ptr) {
+        c.gscnt.ensure(sizeof(unsigned));
+        HIPC(hipMemsetAsync(c.gscnt.ptr, 0, sizeof(unsigned), c.stream));
+    }
     if (!c.hhost) HIPC(hipHostMalloc((void **)&c.hhost, 4 * 256 * sizeof(double)));
-    double *V = c.V.d(), *h = c.hbuf.d(), *h2 = h + (m + 2), *w = c.wvec.d();
+    double *V = c.V.d(), *h = c.hbuf.d(), *h2 = h + (m + 2), *w = c.wvec.d(), *part = c.gspart.d();
+    unsigned *cnt = (unsigned *)c.gscnt.ptr;
     HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
     // ||b||
-    launch_normalize(c.stream, n, b, nullptr, h);
+    launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, const_cast<double *>(b), part, cnt, h);
     HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
     const double bn = c.hhost[0];
@@ -1091,7 +1094,8 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
             launch_scale_add(c.stream, n, 1.0, b, -1.0, c.rvec.d());
         }
         first = false;
-        launch_normalize(c.stream, n, c.rvec.d(), V, h);
+        launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, c.rvec.d(), part, cnt, h);
+        launch_gs_scale(c.stream, n, c.rvec.d(), h, V);
         HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
         const double beta = c.hhost[0];
@@ -1106,13 +1110,11 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         for (int k = 0; k < m; ++k) {
             apply_operator(c, V + (long)k * n, w, wt);
             ++nmv;
-            // two classical Gram-Schmidt passes
-            launch_dots(c.stream, n, k + 1, V, n, w, h);
-            launch_orth_update(c.stream, n, k + 1, V, n, h, w);
-            launch_dots(c.stream, n, k + 1, V, n, w, h2);
-            launch_orth_update(c.stream, n, k + 1, V, n, h2, w);
-            launch_add_into(c.stream, k + 1, h2, h);
-            launch_normalize(c.stream, n, w, V + (long)(k + 1) * n, h + k + 1);
+            // two classical Gram-Schmidt passes, then the new basis vector
+            launch_gs_dots(c.stream, n, k + 1, V, n, w, part, cnt, h);
+            launch_gs_update_dots(c.stream, n, k + 1, V, n, h, w, part, cnt, h2);
+            launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h);
+            launch_gs_scale(c.stream, n, w, h + k + 1, V + (long)(k + 1) * n);
             HIPC(hipMemcpyAsync(c.hhost, h, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, c.stream));
             HIPC(hipStreamSynchronize(c.stream));
             for (int l = 0; l <= k + 1; ++l) H[(size_t)l * m + k] = c.hhost[l];

@@ -27,12 +27,18 @@ double legendre_sum(int q, double t);
 // ---- device-side work descriptors ----
 struct PairWork {
     int tlist_off;  // first entry in the target index list
-    int ntgt;       // targets in this item (<= 256)
+    int ntgt;       // targets in this item (<= 64)
     int src_off;    // first source node in the source arrays
-    int nsrc;       // source nodes in this item
+    int nsrc;       // source nodes in this item (<= 256)
     int pair;       // target drop * n_drops + source drop
-    int pad;
+    int pad;        // source grid: 0 standard, 1 upsampled
     double w;       // weight applied to the sum
+};
+
+// One source grid for the pair sums: component-major arrays [3][stride].
+struct PairSrc {
+    const double *x, *wN, *wW, *d;
+    long stride;
 };
 
 }  // namespace bim

@@ -487,69 +487,80 @@ __global__ __launch_bounds__(256) void k_singular(int p, int qs, int kind, const
 
 // ----------------------------------------------------------------------------
 // Pair sums (Sec. 1 kernels by the regular rule of Sec. 2.1 on the standard
-// or upsampled grid of a source drop, Sec. 2.3). One wavefront per work item:
-// up to 64 targets (one per lane, from an index list) against a range of
-// source nodes staged through LDS in tiles of 64.
+// or upsampled grid of a source drop, Sec. 2.3). One block per work item: up
+// to 64 targets (one per lane, from an index list) against up to 256 sources
+// of one grid, staged once through LDS; the four wavefronts of the block take
+// a quarter of the sources each and combine before the atomic add.
 // kind 0 (SL): sum wW G(x0, x) f;   kind 1 (DL): sum -6 xh (xh.u)(xh.wN) / r^5.
 // Results are added atomically: out[c][t] += w * sum.
 // ----------------------------------------------------------------------------
+constexpr int kPairSrc = 256;  // sources per work item (one LDS tile)
+
 template <int KIND>
-__global__ __launch_bounds__(64) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
-                                             const double *__restrict__ tx, long tstride,
-                                             const double *__restrict__ sx, const double *__restrict__ swN,
-                                             const double *__restrict__ swW, const double *__restrict__ sd,
-                                             long sstride, double *__restrict__ out, long ostride)
+__global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
+                                              const double *__restrict__ tx, long tstride, PairSrc g0, PairSrc g1,
+                                              double *__restrict__ out, long ostride)
 {
-    constexpr int NV = KIND == 0 ? 7 : 9;
-    __shared__ double sh[NV][64];
+    // source record in LDS: DL (x,y)(z,u0)(u1,u2)(n0,n1)(n2,-); SL (x,y)(z,f0)(f1,f2)(wW,-)
+    constexpr int NP = KIND == 0 ? 4 : 5;
+    __shared__ double2 sh[kPairSrc][NP];
+    __shared__ double red[3][3][64];
     const PairWork w = work[blockIdx.x];
-    const int lane = threadIdx.x;
+    const PairSrc &G = w.pad ? g1 : g0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ns = w.nsrc;
+    for (int i = threadIdx.x; i < ns; i += 256) {
+        const long s = (long)w.src_off + i;
+        const long st = G.stride;
+        sh[i][0] = make_double2(G.x[s], G.x[st + s]);
+        sh[i][1] = make_double2(G.x[2 * st + s], G.d[s]);
+        sh[i][2] = make_double2(G.d[st + s], G.d[2 * st + s]);
+        if (KIND == 0) {
+            sh[i][3] = make_double2(G.wW[s], 0.0);
+        } else {
+            sh[i][3] = make_double2(G.wN[s], G.wN[st + s]);
+            sh[i][4] = make_double2(G.wN[2 * st + s], 0.0);
+        }
+    }
     const bool active = lane < w.ntgt;
     const int t = active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off];
     const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
+    __syncthreads();
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int s0 = 0; s0 < w.nsrc; s0 += 64) {
-        const int ns = min(64, w.nsrc - s0);
-        __syncthreads();
-        if (lane < ns) {
-            const long s = (long)w.src_off + s0 + lane;
-            sh[0][lane] = sx[s];
-            sh[1][lane] = sx[sstride + s];
-            sh[2][lane] = sx[2 * sstride + s];
-            sh[3][lane] = sd[s];
-            sh[4][lane] = sd[sstride + s];
-            sh[5][lane] = sd[2 * sstride + s];
-            if (KIND == 0) {
-                sh[6][lane] = swW[s];
-            } else {
-                sh[6][lane] = swN[s];
-                sh[7][lane] = swN[sstride + s];
-                sh[8][lane] = swN[2 * sstride + s];
-            }
-        }
-        __syncthreads();
-        for (int u = 0; u < ns; ++u) {
-            const double hx = x0 - sh[0][u], hy = y0 - sh[1][u], hz = z0 - sh[2][u];
-            const double r2 = hx * hx + hy * hy + hz * hz;
-            const double ri = rsqrt(r2);
-            const double hd = hx * sh[3][u] + hy * sh[4][u] + hz * sh[5][u];
-            if (KIND == 0) {
-                const double wr = sh[6][u] * ri;
-                const double hdr = hd * ri * ri;
-                a0 = fma(wr, fma(hx, hdr, sh[3][u]), a0);
-                a1 = fma(wr, fma(hy, hdr, sh[4][u]), a1);
-                a2 = fma(wr, fma(hz, hdr, sh[5][u]), a2);
-            } else {
-                const double hn = hx * sh[6][u] + hy * sh[7][u] + hz * sh[8][u];
-                const double r2i = ri * ri;
-                const double s = -6.0 * hd * hn * r2i * r2i * ri;
-                a0 = fma(s, hx, a0);
-                a1 = fma(s, hy, a1);
-                a2 = fma(s, hz, a2);
-            }
+    const int u1 = min(ns, (wv + 1) * 64);
+#pragma unroll 4
+    for (int u = wv * 64; u < u1; ++u) {
+        const double2 p0 = sh[u][0], p1 = sh[u][1], p2 = sh[u][2], p3 = sh[u][3];
+        const double hx = x0 - p0.x, hy = y0 - p0.y, hz = z0 - p1.x;
+        const double r2 = hx * hx + hy * hy + hz * hz;
+        const double ri = rsqrt(r2);
+        const double hd = hx * p1.y + hy * p2.x + hz * p2.y;
+        if (KIND == 0) {
+            const double wr = p3.x * ri;
+            const double hdr = hd * ri * ri;
+            a0 = fma(wr, fma(hx, hdr, p1.y), a0);
+            a1 = fma(wr, fma(hy, hdr, p2.x), a1);
+            a2 = fma(wr, fma(hz, hdr, p2.y), a2);
+        } else {
+            const double2 p4 = sh[u][4];
+            const double hn = hx * p3.x + hy * p3.y + hz * p4.x;
+            const double r2i = ri * ri;
+            const double sc = -6.0 * hd * hn * r2i * r2i * ri;
+            a0 = fma(sc, hx, a0);
+            a1 = fma(sc, hy, a1);
+            a2 = fma(sc, hz, a2);
         }
     }
-    if (active) {
+    if (wv > 0) {
+        red[wv - 1][0][lane] = a0;
+        red[wv - 1][1][lane] = a1;
+        red[wv - 1][2][lane] = a2;
+    }
+    __syncthreads();
+    if (wv == 0 && active) {
+        a0 += (red[0][0][lane] + red[1][0][lane]) + red[2][0][lane];
+        a1 += (red[0][1][lane] + red[1][1][lane]) + red[2][1][lane];
+        a2 += (red[0][2][lane] + red[1][2][lane]) + red[2][2][lane];
         atomicAdd(&out[t], w.w * a0);
         atomicAdd(&out[ostride + t], w.w * a1);
         atomicAdd(&out[2 * ostride + t], w.w * a2);
@@ -587,57 +598,111 @@ __global__ void k_op_combine(long n, const double *__restrict__ sc, const double
     if (i < n) y[i] = sc[i] * x[i] - y[i];
 }
 
-// h[i] = V_i . w for i < k (one block per i), V row-major with leading dim ld.
-__global__ __launch_bounds__(256) void k_dots(long n, int k, const double *__restrict__ V, long ld,
-                                              const double *__restrict__ w, double *__restrict__ h)
+// ----------------------------------------------------------------------------
+// Gram-Schmidt passes of the Arnoldi step. A block owns kGsChunk entries of w
+// (kGsR per lane, in registers); its four wavefronts split the basis vectors
+// (i = wave, wave + 4, ...) so that each lane has few dependent loads in flight.
+// Block partial sums go to part[i][b]; the last block to finish (ticket on
+// cnt) adds them in block order, so results do not depend on scheduling, and
+// resets cnt for the next launch.
+//   UPD:  w -= sum_{i<kv} hin[i] V_i
+//   !NRM: hout[i] = V_i . w for i < kv
+//   NRM:  hacc[i] += hin[i] for i < kv (UPD only) and hacc[kv] = ||w||
+// ----------------------------------------------------------------------------
+constexpr int kGsR = 4, kGsChunk = 64 * kGsR;
+
+template <bool UPD, bool NRM>
+__global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__restrict__ V, long ld,
+                                            const double *__restrict__ hin, double *__restrict__ w,
+                                            double *__restrict__ part, unsigned *__restrict__ cnt,
+                                            double *__restrict__ hout)
 {
-    __shared__ double red[4];
-    const int i = blockIdx.x;
-    if (i >= k) return;
-    double s = 0.0;
-    for (long e = threadIdx.x; e < n; e += blockDim.x) s = fma(V[i * ld + e], w[e], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __shared__ double sacc[4][kGsChunk];
+    __shared__ bool last;
+    const int nb = gridDim.x, b = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long e0 = (long)b * kGsChunk + lane;
+    double x[kGsR];
+    bool ok[kGsR];
+#pragma unroll
+    for (int r = 0; r < kGsR; ++r) {
+        const long e = e0 + r * 64;
+        ok[r] = e < n;
+        x[r] = ok[r] ? w[e] : 0.0;
+    }
+    if (UPD) {
+        double acc[kGsR] = {};
+#pragma unroll 4
+        for (int i = wv; i < kv; i += 4) {
+            const double hi = hin[i];
+            const double *Vi = V + i * ld + e0;
+#pragma unroll
+            for (int r = 0; r < kGsR; ++r)
+                if (ok[r]) acc[r] = fma(hi, Vi[r * 64], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < kGsR; ++r) sacc[wv][r * 64 + lane] = acc[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kGsR; ++r) {
+            const int j = r * 64 + lane;
+            x[r] -= (sacc[0][j] + sacc[1][j]) + (sacc[2][j] + sacc[3][j]);
+            if (wv == 0 && ok[r]) w[e0 + r * 64] = x[r];
+        }
+    }
+    if (NRM) {
+        if (wv == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < kGsR; ++r) s = fma(x[r], x[r], s);
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            if (lane == 0) part[b] = s;
+        }
+    } else {
+#pragma unroll 2
+        for (int i = wv; i < kv; i += 4) {
+            const double *Vi = V + i * ld + e0;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < kGsR; ++r)
+                if (ok[r]) s = fma(Vi[r * 64], x[r], s);
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            if (lane == 0) part[(long)i * nb + b] = s;
+        }
+    }
+    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) h[i] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) last = atomicAdd(cnt, 1u) == (unsigned)(nb - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int nsum = NRM ? 1 : kv;
+    for (int i = threadIdx.x; i < nsum; i += 256) {
+        const double *pi = part + (long)i * nb;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int q = 0;
+        for (; q + 4 <= nb; q += 4) {
+            s0 += __hip_atomic_load(pi + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s1 += __hip_atomic_load(pi + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s2 += __hip_atomic_load(pi + q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s3 += __hip_atomic_load(pi + q + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        for (; q < nb; ++q) s0 += __hip_atomic_load(pi + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double s = (s0 + s1) + (s2 + s3);
+        if (NRM) hout[kv] = sqrt(s);
+        else hout[i] = s;
+    }
+    if (NRM && UPD)
+        for (int i = threadIdx.x; i < kv; i += 256) hout[i] += hin[i];
+    if (threadIdx.x == 0) atomicExch(cnt, 0u);
 }
 
-// w -= sum_i h[i] V_i ; hacc[i] += h[i] (accumulates the two Gram-Schmidt passes)
-__global__ void k_orth_update(long n, int k, const double *__restrict__ V, long ld, const double *__restrict__ h,
-                              double *__restrict__ w)
+// v = w / nrm[0] (v may alias w); a zero norm leaves v = 0
+__global__ void k_gs_scale(long n, const double *__restrict__ w, const double *__restrict__ nrm, double *v)
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    double s = w[e];
-    for (int i = 0; i < k; ++i) s = fma(-h[i], V[i * ld + e], s);
-    w[e] = s;
-}
-
-__global__ void k_add_into(int k, const double *__restrict__ a, double *__restrict__ b)
-{
-    const int i = threadIdx.x;
-    if (i < k) b[i] += a[i];
-}
-
-// v = w / ||w||, norm written to nrm[0] (single block).
-__global__ __launch_bounds__(256) void k_normalize(long n, const double *__restrict__ w, double *__restrict__ v,
-                                                   double *__restrict__ nrm)
-{
-    __shared__ double red[4];
-    __shared__ double tot;
-    double s = 0.0;
-    for (long e = threadIdx.x; e < n; e += blockDim.x) s = fma(w[e], w[e], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        tot = sqrt((red[0] + red[1]) + (red[2] + red[3]));
-        nrm[0] = tot;
-    }
-    __syncthreads();
-    const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
-    if (v)
-        for (long e = threadIdx.x; e < n; e += blockDim.x) v[e] = w[e] * inv;
+    const double t = nrm[0];
+    v[e] = t > 0.0 ? w[e] / t : 0.0;
 }
 
 // x += sum_i y[i] V_i
@@ -735,17 +800,16 @@ void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, c
     }
 }
 
+int pair_sources_per_item() { return kPairSrc; }
+
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const double *sx, const double *swN, const double *swW, const double *sd,
-                 long sstride, double *out, long ostride)
+                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride)
 {
     if (nwork <= 0) return;
     if (kind == 0)
-        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(64), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
-                           sstride, out, ostride);
+        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, out, ostride);
     else
-        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(64), 0, st, work, tlist, tx, tstride, sx, swN, swW, sd,
-                           sstride, out, ostride);
+        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, out, ostride);
 }
 
 void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const double *s, double a, const double *U0,
@@ -764,24 +828,40 @@ void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x
     hipLaunchKernelGGL(k_op_combine, dim3(nblk(n)), dim3(256), 0, st, n, sc, x, y);
 }
 
-void launch_dots(hipStream_t st, long n, int k, const double *V, long ld, const double *w, double *h)
+long gs_blocks(long n) { return (n + kGsChunk - 1) / kGsChunk; }
+int gs_max_vectors() { return 256; }
+
+// pass 1 of classical Gram-Schmidt: h[i] = V_i . w, i < kv
+void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, double *w, double *part,
+                    unsigned *cnt, double *h)
 {
-    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, st, n, k, V, ld, w, h);
+    hipLaunchKernelGGL((k_gs<false, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, nullptr, w, part,
+                       cnt, h);
 }
 
-void launch_orth_update(hipStream_t st, long n, int k, const double *V, long ld, const double *h, double *w)
+// w -= V h1, then h2[i] = V_i . w
+void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long ld, const double *h1, double *w,
+                           double *part, unsigned *cnt, double *h2)
 {
-    hipLaunchKernelGGL(k_orth_update, dim3(nblk(n)), dim3(256), 0, st, n, k, V, ld, h, w);
+    hipLaunchKernelGGL((k_gs<true, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h1, w, part, cnt,
+                       h2);
 }
 
-void launch_add_into(hipStream_t st, int k, const double *a, double *b)
+// w -= V h2, h[i] += h2[i], h[kv] = ||w||; with kv = 0 just h[0] = ||w||
+void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
+                           double *part, unsigned *cnt, double *h)
 {
-    hipLaunchKernelGGL(k_add_into, dim3(1), dim3(256), 0, st, k, a, b);
+    if (kv > 0)
+        hipLaunchKernelGGL((k_gs<true, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h2, w, part, cnt,
+                           h);
+    else
+        hipLaunchKernelGGL((k_gs<false, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, 0, V, ld, nullptr, w, part,
+                           cnt, h);
 }
 
-void launch_normalize(hipStream_t st, long n, const double *w, double *v, double *nrm)
+void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v)
 {
-    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(256), 0, st, n, w, v, nrm);
+    hipLaunchKernelGGL(k_gs_scale, dim3(nblk(n)), dim3(256), 0, st, n, w, nrm, v);
 }
 
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x)

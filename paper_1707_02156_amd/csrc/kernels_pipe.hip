@@ -3,9 +3,10 @@
 // Appendix B), reorganised so the Legendre stages are dense contractions on
 // the matrix cores:
 //
-//   R  k_rot2      rotation of x (and the single-layer density) for every
-//                  target of a latitude, per degree n (Appendix B, gamma = 0);
-//                  output by order mu: B^mu[n - mu][col], col = target*6 + comp*2 + re/im
+//   R  k_rot_mfma  rotation of x (and the single-layer density) for every
+//                  target of a latitude, per degree n (Appendix B, gamma = 0), as
+//                  GEMMs on the matrix cores; output by order mu:
+//                  B^mu[n - mu][col], col = target*6 + comp*2 + re/im
 //   L  k_leg_mfma  G^mu = T^mu B^mu on v_mfma_f64_16x16x4f64, T^mu the Legendre
 //                  rows [Ptilde_n^mu(t_j'); dPtilde_n^mu/dtheta(t_j')] of the rotated grid
 //   FK k_fk        Fourier sums at the rotated longitudes (symmetries phi -> -phi,
@@ -13,7 +14,7 @@
 //                  for the double layer the six stresslet fields and their Fourier
 //                  analysis Fa^mu[j'][target*12 + pair*2 + re/im]
 //   LA k_leg_mfma  Legendre analysis Bt^mu = (Ptilde^mu)^T Fa^mu (same kernel)
-//   AR k_adjrot    adjoint rotation -> rows of the stored double layer
+//   AR k_adjrot_mfma adjoint rotation (matrix cores) -> rows of the stored double layer
 //                  M[t][pair][2 ncoef(p)] (applied by k_dl_apply)
 //
 // Layouts: a triangle-ordered operand stores order mu as the rows n = mu..p at
@@ -29,27 +30,38 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 __host__ __device__ inline long koff(int mu, int P1) { return (long)mu * P1 - (long)mu * (mu - 1) / 2; }
 
 // ----------------------------------------------------------------------------
-// R: rotation. Block (n, j). Outputs for targets t = t0 + k (k < 2p) of
-// latitude j: for x (3 components) into Bx and for the density (3) into Bd.
+// R: rotation on the matrix cores. Block (n, latitude j), 256 threads. For the
+// 2p targets k of latitude j and the nf fields f (x, then the density):
+//   Re f'^mu_n(k, f) = sum_nu A+_{nu mu} Re g^nu,  Im f'^mu_n = sum_nu A-_{nu mu} Im g^nu,
+//   g^nu = e^{i nu phi_k} c^nu_{n,f},
+// two GEMMs (mu x nu) x (nu x col), col = k nf + f, on v_mfma_f64_16x16x4f64:
+// A = A+/- from LDS (zero padded to a multiple of 16), B = g formed in
+// registers per lane, one 16-column tile per wavefront at a time.
+// Output by order mu: B^mu[koff(mu) + n - mu][t*6 + comp*2 + re/im].
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rot2(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
-                                              const double *__restrict__ csp, const double *__restrict__ xc,
-                                              long xstride, const double *__restrict__ dc, long dstride,
-                                              int j0, int tbase, double *__restrict__ Bx, double *__restrict__ Bd,
-                                              long NC)
+constexpr int kRotMaxPad = 64;  // degree p <= 63
+
+__global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
+                                                  const double *__restrict__ csp, const double *__restrict__ xc,
+                                                  long xstride, const double *__restrict__ dc, long dstride,
+                                                  int j0, int tbase, double *__restrict__ Bx,
+                                                  double *__restrict__ Bd, long NC)
 {
     extern __shared__ double sm[];
     const int n = blockIdx.x, j = j0 + blockIdx.y;
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
     const int nf = dc ? 6 : 3;
-    double *sAp = sm;                 // [nu][mu]
-    double *sAm = sAp + N1 * N1;
-    double *sC = sAm + N1 * N1;       // [f][nu][2]
-    double *sPh = sC + nf * N1 * 2;   // [k][nu][2] cos, sin of nu phi_k
+    const int MT = (N1 + 15) / 16, NP = MT * 16, KS = (N1 + 3) / 4;
+    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded
+    double *sAm = sAp + NP * NP;
+    double *sC = sAm + NP * NP;        // [f][nu][re,im]
+    double *sCS = sC + nf * N1 * 2;    // cos, sin of the target longitudes [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
-    for (int i = threadIdx.x; i < N1 * N1; i += 256) {
-        sAp[i] = Ap[lat + i];
-        sAm[i] = Am[lat + i];
+    for (int i = threadIdx.x; i < NP * NP; i += 256) {
+        const int nu = i / NP, mu = i % NP;
+        const bool in = nu < N1 && mu < N1;
+        sAp[i] = in ? Ap[lat + nu * N1 + mu] : 0.0;
+        sAm[i] = in ? Am[lat + nu * N1 + mu] : 0.0;
     }
     const int b0 = n * (n + 1) / 2;
     for (int i = threadIdx.x; i < nf * N1; i += 256) {
@@ -58,48 +70,57 @@ __global__ __launch_bounds__(256) void k_rot2(int p, const double *__restrict__ 
         sC[2 * i] = c[2 * (b0 + nu)];
         sC[2 * i + 1] = c[2 * (b0 + nu) + 1];
     }
-    for (int i = threadIdx.x; i < nk * N1; i += 256) {
-        const int k = i / N1, nu = i % N1;
-        const int e = (int)(((long)nu * k) % nk);
-        sPh[2 * i] = csp[e];
-        sPh[2 * i + 1] = csp[nk + e];
-    }
+    for (int i = threadIdx.x; i < 2 * nk; i += 256) sCS[i] = csp[i];
     __syncthreads();
-    const int ng = (N1 + 3) / 4;
-    // items: mu-group slowest, then k, then field (fastest) so that writes are contiguous
-    for (int it = threadIdx.x; it < ng * nk * nf; it += 256) {
-        const int f = it % nf;
-        const int r = it / nf;
-        const int k = r % nk, g = r / nk;
-        const int mu0 = 4 * g;
-        double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int ncol = nk * nf, NT = (ncol + 15) / 16;
+    for (int nt = wv; nt < NT; nt += 4) {
+        const int col = nt * 16 + r16;
+        const bool cok = col < ncol;
+        const int k = cok ? col / nf : 0, f = cok ? col % nf : 0;
         const double *cf = sC + 2 * f * N1;
-        const double *ph = sPh + 2 * k * N1;
-        for (int nu = 0; nu <= n; ++nu) {
-            const double cr = cf[2 * nu], ci = cf[2 * nu + 1];
-            const double cc = ph[2 * nu], ss = ph[2 * nu + 1];
-            const double gr = cr * cc - ci * ss, gi = cr * ss + ci * cc;
+        d4_t ap[4], am[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int mu = mu0 + q;
-                if (mu <= n) {
-                    re[q] = fma(sAp[nu * N1 + mu], gr, re[q]);
-                    im[q] = fma(sAm[nu * N1 + mu], gi, im[q]);
-                }
+        for (int m = 0; m < 4; ++m) ap[m] = am[m] = (d4_t){0, 0, 0, 0};
+        // e = nu k mod nk, stepped by 4k as nu advances by 4
+        int e = (k4 * k) % nk;
+        const int step = (4 * k) % nk;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int nu = ks * 4 + k4;
+            double gr = 0.0, gi = 0.0;
+            if (cok && nu < N1) {
+                const double cr = cf[2 * nu], ci = cf[2 * nu + 1];
+                const double cs = sCS[e], sn = sCS[nk + e];
+                gr = cr * cs - ci * sn;
+                gi = fma(cr, sn, ci * cs);
             }
+            e += step;
+            if (e >= nk) e -= nk;
+            const double *pa = sAp + nu * NP + r16, *pm = sAm + nu * NP + r16;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (m < MT) {
+                    ap[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[m * 16], gr, ap[m], 0, 0, 0);
+                    am[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(pm[m * 16], gi, am[m], 0, 0, 0);
+                }
         }
-        const int t = tbase + blockIdx.y * nk + k;  // target index within the chunk
+        if (!cok) continue;
+        const int t = tbase + blockIdx.y * nk + k;
         double *dst = (f < 3) ? Bx : Bd;
         const int ff = f < 3 ? f : f - 3;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int mu = mu0 + q;
-            if (mu <= n) {
-                double *o = dst + (koff(mu, P1) + (n - mu)) * NC + (long)t * 6 + ff * 2;
-                o[0] = re[q];
-                o[1] = im[q];
-            }
-        }
+        for (int m = 0; m < 4; ++m)
+            if (m < MT)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int mu = m * 16 + 4 * v + k4;
+                    if (mu <= n) {
+                        double *o = dst + (koff(mu, P1) + (n - mu)) * NC + (long)t * 6 + ff * 2;
+                        o[0] = ap[m][v];
+                        o[1] = am[m][v];
+                    }
+                }
     }
 }
 
@@ -359,73 +380,80 @@ __global__ void k_pole(int p, int nt, const double *__restrict__ Bx, long NC, do
 }
 
 // ----------------------------------------------------------------------------
-// AR: adjoint rotation. Block (n, j, target group of 16 of latitude j).
-// a_mu = w_mu Bt^mu[n][.. cos], b_mu = -w_mu Bt^mu[n][.. sin];
-// alpha_nu = sum_mu A+_{nu mu} a_mu, beta_nu = sum_mu A-_{nu mu} b_mu;
+// AR: adjoint rotation on the matrix cores. Block (n, latitude j), 256 threads.
+// a_mu = w_mu Bt^mu[n][.. cos], b_mu = -w_mu Bt^mu[n][.. sin] (w_0 = 1, else 2);
+// alpha_nu = sum_mu A+_{nu mu} a_mu, beta_nu = sum_mu A-_{nu mu} b_mu as two GEMMs
+// (nu x mu) x (mu x col), col = k*6 + pair over the 2p targets of the latitude;
+// both results of one (nu, col) land in the same lane, which writes
 // M[t][pair][2 tri(n,nu)] = alpha cos(nu phi_k) + beta sin, [+1] = -alpha sin + beta cos.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adjrot(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
-                                                const double *__restrict__ csp, const double *__restrict__ Bt,
-                                                long NC12, int j0, int tbase, int tglobal0,
-                                                double *__restrict__ M)
+__global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__restrict__ Ap,
+                                                     const double *__restrict__ Am, const double *__restrict__ csp,
+                                                     const double *__restrict__ Bt, long NC12, int j0, int tbase,
+                                                     int tglobal0, double *__restrict__ M)
 {
     extern __shared__ double sm[];
     const int n = blockIdx.x, j = j0 + blockIdx.y;
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
-    const int kg0 = blockIdx.z * 16;
-    const int nkg = min(16, nk - kg0);
-    double *sAp = sm;
-    double *sAm = sAp + N1 * N1;
-    double *sB = sAm + N1 * N1;        // [kg][pair][mu][2]
+    const int MT = (N1 + 15) / 16, NP = MT * 16, KS = (N1 + 3) / 4;
+    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded
+    double *sAm = sAp + NP * NP;
+    double *sCS = sAm + NP * NP;       // [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
-    for (int i = threadIdx.x; i < N1 * N1; i += 256) {
-        sAp[i] = Ap[lat + i];
-        sAm[i] = Am[lat + i];
+    for (int i = threadIdx.x; i < NP * NP; i += 256) {
+        const int nu = i / NP, mu = i % NP;
+        const bool in = nu < N1 && mu < N1;
+        sAp[i] = in ? Ap[lat + nu * N1 + mu] : 0.0;
+        sAm[i] = in ? Am[lat + nu * N1 + mu] : 0.0;
     }
-    for (int i = threadIdx.x; i < nkg * 6 * N1; i += 256) {
-        const int mu = i % N1;
-        const int r = i / N1;
-        const int pr = r % 6, kg = r / 6;
-        const int t = tbase + blockIdx.y * nk + kg0 + kg;
-        const double w = mu ? 2.0 : 1.0;
-        const double *src = Bt + (koff(mu, P1) + (n - mu)) * NC12 + (long)t * 12 + pr * 2;
-        sB[2 * i] = w * src[0];
-        sB[2 * i + 1] = -w * src[1];
-    }
+    for (int i = threadIdx.x; i < 2 * nk; i += 256) sCS[i] = csp[i];
     __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int ncol = nk * 6, NT = (ncol + 15) / 16;
     const int nc2 = 2 * ncoef(p);
-    const int ng = (N1 + 3) / 4;
-    for (int it = threadIdx.x; it < nkg * 6 * ng; it += 256) {
-        const int g = it % ng;
-        const int r = it / ng;
-        const int pr = r % 6, kg = r / 6;
-        const int nu0 = 4 * g;
-        const double *bb = sB + 2 * ((kg * 6 + pr) * N1);
-        double al[4] = {0, 0, 0, 0}, be[4] = {0, 0, 0, 0};
-        for (int mu = 0; mu <= n; ++mu) {
-            const double a = bb[2 * mu], b = bb[2 * mu + 1];
+    for (int nt = wv; nt < NT; nt += 4) {
+        const int col = nt * 16 + r16;
+        const bool cok = col < ncol;
+        const int k = cok ? col / 6 : 0, pr = cok ? col % 6 : 0;
+        const long tcol = (long)(tbase + blockIdx.y * nk + k) * 12 + pr * 2;
+        d4_t al[4], be[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int nu = nu0 + q;
-                if (nu <= n) {
-                    al[q] = fma(sAp[nu * N1 + mu], a, al[q]);
-                    be[q] = fma(sAm[nu * N1 + mu], b, be[q]);
+        for (int m = 0; m < 4; ++m) al[m] = be[m] = (d4_t){0, 0, 0, 0};
+        for (int ks = 0; ks < KS; ++ks) {
+            const int mu = ks * 4 + k4;
+            double av = 0.0, bv = 0.0;
+            if (cok && mu < N1) {
+                const double2 v = *reinterpret_cast<const double2 *>(Bt + (koff(mu, P1) + (n - mu)) * NC12 + tcol);
+                const double w = mu ? 2.0 : 1.0;
+                av = w * v.x;
+                bv = -w * v.y;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (m < MT) {
+                    const int nu = m * 16 + r16;
+                    al[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAp[nu * NP + mu], av, al[m], 0, 0, 0);
+                    be[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAm[nu * NP + mu], bv, be[m], 0, 0, 0);
                 }
-            }
         }
-        const int k = kg0 + kg;
-        const long tg = tglobal0 + (long)blockIdx.y * nk + k;   // target index within the drop
-        double *Mt = M + (tg * 6 + pr) * nc2;
+        if (!cok) continue;
+        const long tg = tglobal0 + (long)blockIdx.y * nk + k;  // target index within the drop
+        double *Mt = M + (tg * 6 + pr) * nc2 + n * (n + 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int nu = nu0 + q;
-            if (nu <= n) {
-                const int e = (int)(((long)nu * k) % nk);
-                const double cc = csp[e], ss = csp[nk + e];
-                Mt[2 * (n * (n + 1) / 2 + nu)] = al[q] * cc + be[q] * ss;
-                Mt[2 * (n * (n + 1) / 2 + nu) + 1] = -al[q] * ss + be[q] * cc;
-            }
-        }
+        for (int m = 0; m < 4; ++m)
+            if (m < MT)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int nu = m * 16 + 4 * v + k4;
+                    if (nu <= n) {
+                        const int e = (int)(((long)nu * k) % nk);
+                        const double cc = sCS[e], ss = sCS[nk + e];
+                        const double a_ = al[m][v], b_ = be[m][v];
+                        *reinterpret_cast<double2 *>(Mt + 2 * nu) =
+                            make_double2(fma(a_, cc, b_ * ss), fma(-a_, ss, b_ * cc));
+                    }
+                }
     }
 }
 
@@ -440,8 +468,6 @@ void pipe_set_lds_limits()
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void *)k_rot2, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-    (void)hipFuncSetAttribute((const void *)k_adjrot, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
     (void)hipFuncSetAttribute((const void *)k_fk<true, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
     (void)hipFuncSetAttribute((const void *)k_fk<true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
     (void)hipFuncSetAttribute((const void *)k_fk<false, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
@@ -450,11 +476,17 @@ void pipe_set_lds_limits()
 void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
                  long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC)
 {
-    const int P1 = p + 1, nk = 2 * p;
+    const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
     const int nf = dc ? 6 : 3;
-    const size_t lds = (size_t)(2 * P1 * P1 + nf * P1 * 2 + nk * P1 * 2) * sizeof(double);
-    hipLaunchKernelGGL(k_rot2, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride, j0, 0, Bx,
-                       Bd, NC);
+    const size_t lds = (size_t)(2 * NP * NP + nf * P1 * 2 + 2 * nk) * sizeof(double);
+    hipLaunchKernelGGL(k_rot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride, j0, 0,
+                       Bx, Bd, NC);
+}
+
+size_t rot_lds_bytes(int p)
+{
+    const int P1 = p + 1, NP = (P1 + 15) / 16 * 16;
+    return P1 > kRotMaxPad ? (size_t)1 << 40 : (size_t)(2 * NP * NP + 6 * P1 * 2 + 4 * p) * sizeof(double);
 }
 
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
@@ -510,10 +542,9 @@ void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, doubl
 void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *Bt,
                    long NC12, int j0, int nj, int tglobal0, double *M)
 {
-    const int P1 = p + 1, nk = 2 * p;
-    const size_t lds = (size_t)(2 * P1 * P1 + 16 * 6 * P1 * 2) * sizeof(double);
-    hipLaunchKernelGGL(k_adjrot, dim3(P1, nj, cdiv(nk, 16)), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, j0, 0,
-                       tglobal0, M);
+    const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
+    const size_t lds = (size_t)(2 * NP * NP + 2 * nk) * sizeof(double);
+    hipLaunchKernelGGL(k_adjrot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, j0, 0, tglobal0, M);
 }
 
 }  // namespace bim

@@ -373,7 +373,8 @@ def test_hadamard_rybczynski_on_gpu(B, orc):
 
 def test_two_drops_p32_sampled_singular_and_pairs(B, orc):
     """The full two-drop workload (p = 32, gap 0.2, U = 4): force, regions,
-    and the single layer at 96 sampled targets per drop."""
+    the single layer and the raw double layer of a random density at 96
+    sampled targets per drop."""
     print("two drops p=32 sampled", flush=True)
     wl = W.two_drops()
     c = ctx_for(B, wl)
@@ -383,6 +384,8 @@ def test_two_drops_p32_sampled_singular_and_pairs(B, orc):
         assert coef_err(fg[i], s.force(i)) <= TOL
     u = c.single_layer()
     rng = np.random.default_rng(9)
+    dens = [random_coef(rng, 32, 3) for _ in range(2)]
+    D = c.double_layer(dens, mode=0)
     reg, _ = c.regions()
     for i in range(2):
         n = B.npts(32)
@@ -394,6 +397,8 @@ def test_two_drops_p32_sampled_singular_and_pairs(B, orc):
         got = u[i][tg]
         scale = np.abs(ref).max(axis=0)
         assert np.all(np.abs(got - ref).max(axis=0) <= TOL * scale)
+        refd = s.layer(i, dens, 1, targets=tg) / (4 * np.pi)
+        assert np.all(np.abs(D[i][tg] - refd).max(axis=0) <= TOL * np.abs(refd).max(axis=0))
     c.close()
 
 

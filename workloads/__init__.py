@@ -181,3 +181,110 @@ def many_drops(nd=64, p=16, A=0.05, box=12.0, gap=0.3, seed=3) -> Workload:
         drops.append(DropSpec(p, xc, float(lams[i]), None, cs[i], float(R[i])))
     return Workload(name=f"many_drops_n{nd}_p{p}", drops=drops, eos=0, sigma0=1.0, A_tilde=1e30, U_tilde=2,
                     notes="all pairs on the 2x upsampled grid")
+
+
+def random_rotation(rng) -> np.ndarray:
+    """Uniformly distributed rotation matrix (QR of a Gaussian matrix with the
+    sign convention that makes the factorisation unique, determinant +1)."""
+    Q, Rm = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q = Q * np.sign(np.diag(Rm))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def p2_spheroid(p: int, R: float, eps: float) -> np.ndarray:
+    """Body-frame surface r(theta) = R (1 + eps P_2(cos theta)) s_hat, exactly a
+    degree-3 expansion. With u = cos(theta):
+      z = R [(1 + 2 eps/5) P_1(u) + (3 eps/5) P_3(u)]
+      sin(theta) (1 + eps P_2(u)) = -(1 - eps/5) P_1^1(u) - (eps/5) P_3^1(u)
+    (P_n^m with the Condon-Shortley phase), converted to the orthonormal basis
+    with the factors sqrt((2n+1)/(4 pi) (n-m)!/(n+m)!)."""
+    xc = np.zeros((3, ncoef(p), 2))
+    N10, N30 = np.sqrt(3 / (4 * np.pi)), np.sqrt(7 / (4 * np.pi))
+    N11, N31 = np.sqrt(3 / (8 * np.pi)), np.sqrt(7 / (48 * np.pi))
+    c1 = -(1.0 - eps / 5.0) / N11
+    c3 = -(eps / 5.0) / N31
+    # x = h(theta) cos(phi): real part of the m = 1 coefficient is c_n / 2
+    xc[0, idx(1, 1), 0] = c1 / 2
+    xc[0, idx(3, 1), 0] = c3 / 2
+    # y = h(theta) sin(phi): imaginary part -c_n / 2
+    xc[1, idx(1, 1), 1] = -c1 / 2
+    xc[1, idx(3, 1), 1] = -c3 / 2
+    xc[2, idx(1, 0), 0] = (1.0 + 2.0 * eps / 5.0) / N10
+    xc[2, idx(3, 0), 0] = (3.0 * eps / 5.0) / N30
+    return xc * R
+
+
+def p2_surface_points(R: float, eps: float, Q: np.ndarray, c, nt: int = 96, nphi: int = 192) -> np.ndarray:
+    """Points of the rotated, translated spheroid c + Q r(theta) s_hat on a
+    uniform (theta, phi) sample; used only to place drops."""
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    ph = np.arange(nphi) * 2 * np.pi / nphi
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    r = R * (1.0 + eps * 0.5 * (3 * np.cos(T) ** 2 - 1))
+    s = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1).reshape(-1, 3)
+    return (r.reshape(-1, 1) * s) @ Q.T + np.asarray(c, float)
+
+
+def rotate_coefficients(xc: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """Rigid rotation of the surface: every coefficient triple (x, y, z)_n^m is
+    multiplied by Q (real and imaginary parts alike)."""
+    return np.einsum("ij,jkr->ikr", Q, xc)
+
+
+def scalar_field(rng, p: int, A: float, power: float, mean: float) -> np.ndarray:
+    """Real scalar expansion: mean at l = 0 (times sqrt(4 pi)), N(0,1) A l^-power
+    for 1 <= l <= p, split over Re/Im like perturbation(); Im at m = p zero."""
+    g = np.zeros((ncoef(p), 2))
+    g[0, 0] = SQ4PI * mean
+    for l in range(1, p + 1):
+        s = A * l ** (-power)
+        g[idx(l, 0), 0] = rng.standard_normal() * s
+        for m in range(1, l + 1):
+            g[idx(l, m), 0] = rng.standard_normal() * s / np.sqrt(2.0)
+            g[idx(l, m), 1] = rng.standard_normal() * s / np.sqrt(2.0)
+            if m == p:
+                g[idx(l, m), 1] = 0.0
+    return g
+
+
+def deformed_drops(npairs=8, p=48, eps=4.0 / 9.0, A=0.05, gap=0.1, spacing=8.0, lam=3.0, seed=5) -> Workload:
+    """2 npairs drops (default 16) of degree p (default 48): P_2 spheroids with
+    eps = 4/9, i.e. Taylor deformation (L - B)/(L + B) = 0.3, each randomly
+    oriented, plus N(0,1) 0.05 l^-3 noise; lambda 3. Drops come in pairs whose
+    centres sit on a 2x2x2 lattice of spacing 8; within a pair the separation
+    along a random direction is bisected until the noise-free surfaces are 0.1
+    apart (sampled surfaces). Surfactant Gamma = 1 + sum_{l>=1} N(0,1) 0.05 l^-2
+    Y_l^m of degree p with the linear equation of state sigma = 1 - 0.3 Gamma."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    drops = []
+    lattice = [np.array([i, j, k], float) * spacing for i in range(2) for j in range(2) for k in range(2)]
+    for pc in lattice[:npairs]:
+        Qa, Qb = random_rotation(rng), random_rotation(rng)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        pa = p2_surface_points(1.0, eps, Qa, (0, 0, 0))
+        tree = cKDTree(pa[pa @ d > 0])           # the half of A that faces B
+        pb0 = p2_surface_points(1.0, eps, Qb, (0, 0, 0))
+        pb0 = pb0[pb0 @ d < 0]                   # the half of B that faces A
+        lo, hi = 0.5, 2.0 * (1.0 + eps) + gap + 1.0
+        for _ in range(44):
+            mid = 0.5 * (lo + hi)
+            dist = tree.query(pb0 + mid * d, k=1, distance_upper_bound=4.0 * gap)[0].min()
+            if dist > gap:
+                hi = mid
+            else:
+                lo = mid
+        sep = hi
+        for Q, c in ((Qa, pc - 0.5 * sep * d), (Qb, pc + 0.5 * sep * d)):
+            xc = rotate_coefficients(p2_spheroid(p, 1.0, eps), Q) + perturbation(rng, p, A)
+            for k in range(3):
+                xc[k, 0, 0] += SQ4PI * c[k]
+            gc = scalar_field(rng, p, 0.05, 2.0, 1.0)
+            drops.append(DropSpec(p, xc, lam, gc, c, 1.0))
+    return Workload(name=f"deformed_drops_n{2 * npairs}_p{p}", drops=drops, eos=1, E=0.5, xs=0.6, A_tilde=5.0,
+                    U_tilde=4, gmres_tol=1e-10,
+                    notes="P2 spheroids eps 4/9 (D = 0.3), pairs 0.1 apart (noise-free), lambda 3")
