@@ -200,7 +200,9 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     const long gsz = (long)TG * P1 * NTY * 6;
     double *V = sG + gsz;                    // [tg][k'][12]
     double *red = V + (long)TG * nk * 12;    // [tg][3]
+    double *sCS = red + TG * 3;              // cos, sin of pi e / qs, e < 2 qs
     for (int i = threadIdx.x; i < TG * 3; i += 256) red[i] = 0.0;
+    for (int e = threadIdx.x; e < nk; e += 256) sincos(3.14159265358979323846 * e / qs, &sCS[nk + e], &sCS[e]);
     // ---- load G (weights w_mu applied; x_phi built from x)
     for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
         const int e = i % 6;           // c*2 + re/im
@@ -228,16 +230,15 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     __syncthreads();
     const bool even = (qs & 1) == 0;
     const int nkk = even ? qs / 2 + 1 : qs;
-    const double dphi = 3.14159265358979323846 / qs;
-    // ---- F: point values
+    // ---- F: point values. cos/sin(mu phi) by the three-term recurrence
+    // c_{mu+1} = 2 cos(phi) c_mu - c_{mu-1} (same for sin), error O(p^2 eps)
     for (int it = threadIdx.x; it < ntg * nkk * 3; it += 256) {
         const int c = it % 3;
         const int r = it / 3;
         const int kk = r % nkk, tg = r / nkk;
         const double *g = sG + (long)tg * P1 * NTY * 6 + 2 * c;
-        double sn, cs;
-        sincos(dphi * kk, &sn, &cs);
-        double cm = 1.0, sm_ = 0.0;
+        const double c1 = sCS[kk], s1 = sCS[nk + kk], tc = 2.0 * c1;
+        double c0 = 1.0, s0 = 0.0, cm1 = c1, sm1 = -s1;  // orders mu and mu - 1
         double CE[NTY], CO[NTY], SE[NTY], SO[NTY];
 #pragma unroll
         for (int q = 0; q < NTY; ++q) { CE[q] = 0; CO[q] = 0; SE[q] = 0; SO[q] = 0; }
@@ -246,35 +247,36 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
             const double *ge = g + (long)mu * NTY * 6, *go = ge + NTY * 6;
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CE[q] = fma(ge[6 * q], cm, CE[q]);
-                SE[q] = fma(ge[6 * q + 1], sm_, SE[q]);
+                CE[q] = fma(ge[6 * q], c0, CE[q]);
+                SE[q] = fma(ge[6 * q + 1], s0, SE[q]);
             }
-            double c2 = cm * cs - sm_ * sn;
-            double s2 = fma(sm_, cs, cm * sn);
+            const double c1n = fma(tc, c0, -cm1), s1n = fma(tc, s0, -sm1);
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CO[q] = fma(go[6 * q], c2, CO[q]);
-                SO[q] = fma(go[6 * q + 1], s2, SO[q]);
+                CO[q] = fma(go[6 * q], c1n, CO[q]);
+                SO[q] = fma(go[6 * q + 1], s1n, SO[q]);
             }
-            cm = c2 * cs - s2 * sn;
-            sm_ = fma(s2, cs, c2 * sn);
+            cm1 = c1n;
+            sm1 = s1n;
+            c0 = fma(tc, c1n, -c0);
+            s0 = fma(tc, s1n, -s0);
         }
         if (mu <= p) {  // last order (even)
             const double *ge = g + (long)mu * NTY * 6;
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CE[q] = fma(ge[6 * q], cm, CE[q]);
-                SE[q] = fma(ge[6 * q + 1], sm_, SE[q]);
+                CE[q] = fma(ge[6 * q], c0, CE[q]);
+                SE[q] = fma(ge[6 * q + 1], s0, SE[q]);
             }
         }
         double *Vb = V + (long)tg * nk * 12;
         // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
-        auto put = [&](int kp, double s1, double s2) {
+        auto put = [&](int kp, double f1, double f2) {
             double *v = Vb + (long)kp * 12;
-            v[c] = (CE[0] - s1 * SE[0]) + s2 * (CO[0] - s1 * SO[0]);
-            v[3 + c] = (CE[1] - s1 * SE[1]) + s2 * (CO[1] - s1 * SO[1]);
-            v[6 + c] = (CE[2] - s1 * SE[2]) + s2 * (CO[2] - s1 * SO[2]);
-            if (SL) v[9 + c] = (CE[3] - s1 * SE[3]) + s2 * (CO[3] - s1 * SO[3]);
+            v[c] = (CE[0] - f1 * SE[0]) + f2 * (CO[0] - f1 * SO[0]);
+            v[3 + c] = (CE[1] - f1 * SE[1]) + f2 * (CO[1] - f1 * SO[1]);
+            v[6 + c] = (CE[2] - f1 * SE[2]) + f2 * (CO[2] - f1 * SO[2]);
+            if (SL) v[9 + c] = (CE[3] - f1 * SE[3]) + f2 * (CO[3] - f1 * SO[3]);
         };
         put(kk, 1.0, 1.0);
         put(kk + qs, 1.0, -1.0);
@@ -286,54 +288,93 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     __syncthreads();
     // ---- K: kernels
     const double om = wsing[jr];
-    for (int it = threadIdx.x; it < ntg * nk; it += 256) {
-        const int tg = it / nk;
-        double *v = V + (long)it * 12;
+    for (int it = threadIdx.x; it < ((ntg * nk + 63) & ~63); it += 256) {
+        const bool ok = it < ntg * nk;
+        const int tg = ok ? it / nk : 0;
+        double *v = V + (long)(ok ? it : 0) * 12;
         const int t = t0 + tg;
-        const double xt0 = v[3], xt1 = v[4], xt2 = v[5];
-        const double xp0 = v[6], xp1 = v[7], xp2 = v[8];
-        const double N0 = xt1 * xp2 - xt2 * xp1;
-        const double N1 = xt2 * xp0 - xt0 * xp2;
-        const double N2 = xt0 * xp1 - xt1 * xp0;
-        const double h0 = X0[3 * t] - v[0], h1 = X0[3 * t + 1] - v[1], h2 = X0[3 * t + 2] - v[2];
-        const double r2 = h0 * h0 + h1 * h1 + h2 * h2;
-        const double ri = rsqrt(r2);
-        if (SL) {
-            const double f0 = v[9], f1 = v[10], f2 = v[11];
-            const double hf = h0 * f0 + h1 * f1 + h2 * f2;
-            const double Wr = om * sqrt(N0 * N0 + N1 * N1 + N2 * N2) * ri;
-            const double q = hf * ri * ri;
-            atomicAdd(&red[3 * tg], Wr * fma(h0, q, f0));
-            atomicAdd(&red[3 * tg + 1], Wr * fma(h1, q, f1));
-            atomicAdd(&red[3 * tg + 2], Wr * fma(h2, q, f2));
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+        if (ok) {
+            const double xt0 = v[3], xt1 = v[4], xt2 = v[5];
+            const double xp0 = v[6], xp1 = v[7], xp2 = v[8];
+            const double N0 = xt1 * xp2 - xt2 * xp1;
+            const double N1 = xt2 * xp0 - xt0 * xp2;
+            const double N2 = xt0 * xp1 - xt1 * xp0;
+            const double h0 = X0[3 * t] - v[0], h1 = X0[3 * t + 1] - v[1], h2 = X0[3 * t + 2] - v[2];
+            const double r2 = h0 * h0 + h1 * h1 + h2 * h2;
+            const double ri = rsqrt(r2);
+            if (SL) {
+                const double f0 = v[9], f1 = v[10], f2 = v[11];
+                const double hf = h0 * f0 + h1 * f1 + h2 * f2;
+                const double Wr = om * sqrt(N0 * N0 + N1 * N1 + N2 * N2) * ri;
+                const double q = hf * ri * ri;
+                e0 = Wr * fma(h0, q, f0);
+                e1 = Wr * fma(h1, q, f1);
+                e2 = Wr * fma(h2, q, f2);
+            }
+            if (DL) {
+                const double hn = h0 * N0 + h1 * N1 + h2 * N2;
+                const double r2i = ri * ri;
+                const double sc = -6.0 * om * hn * r2i * r2i * ri;
+                v[0] = sc * h0 * h0;
+                v[1] = sc * h0 * h1;
+                v[2] = sc * h0 * h2;
+                v[3] = sc * h1 * h1;
+                v[4] = sc * h1 * h2;
+                v[5] = sc * h2 * h2;
+            }
         }
-        if (DL) {
-            const double hn = h0 * N0 + h1 * N1 + h2 * N2;
-            const double r2i = ri * ri;
-            const double s = -6.0 * om * hn * r2i * r2i * ri;
-            v[0] = s * h0 * h0;
-            v[1] = s * h0 * h1;
-            v[2] = s * h0 * h2;
-            v[3] = s * h1 * h1;
-            v[4] = s * h1 * h2;
-            v[5] = s * h2 * h2;
+        if (SL) {
+            // one target per wavefront (2 qs = 64): reduce in registers; otherwise LDS atomics
+            const int tgw = __shfl(tg, 0, 64), okw = __shfl((int)ok, 63, 64);
+            if (okw && __all(tg == tgw)) {
+                for (int o = 32; o > 0; o >>= 1) {
+                    e0 += __shfl_down(e0, o, 64);
+                    e1 += __shfl_down(e1, o, 64);
+                    e2 += __shfl_down(e2, o, 64);
+                }
+                if ((threadIdx.x & 63) == 0) {
+                    atomicAdd(&red[3 * tg], e0);
+                    atomicAdd(&red[3 * tg + 1], e1);
+                    atomicAdd(&red[3 * tg + 2], e2);
+                }
+            } else if (ok) {
+                atomicAdd(&red[3 * tg], e0);
+                atomicAdd(&red[3 * tg + 1], e1);
+                atomicAdd(&red[3 * tg + 2], e2);
+            }
         }
     }
     __syncthreads();
     if (SL)
         for (int i = threadIdx.x; i < ntg * 3; i += 256) part[((long)(t0 + i / 3) * Q1 + jr) * 3 + i % 3] = red[i];
     if (DL) {
-        // ---- FA: Fourier analysis of the six stresslet fields
-        for (int it = threadIdx.x; it < P1 * ntg * 6; it += 256) {
+        // ---- FA: Fourier analysis of the six stresslet fields. One item = four
+        // orders of one parity (mu = base + 2q), sharing the symmetric
+        // combinations of the four points kk, -kk, kk + qs, qs - kk.
+        const int nE = p / 2 + 1, nO = (p + 1) / 2;
+        const int NGe = (nE + 3) / 4, NG = NGe + (nO + 3) / 4;
+        for (int it = threadIdx.x; it < NG * ntg * 6; it += 256) {
             const int pr = it % 6;
             const int r = it / 6;
-            const int tg = r % ntg, mu = r / ntg;
+            const int tg = r % ntg, gidx = r / ntg;
+            const bool odd = gidx >= NGe;
+            const int base = odd ? 8 * (gidx - NGe) + 1 : 8 * gidx;
+            const double sg = odd ? -1.0 : 1.0;
             const double *Vb = V + (long)tg * nk * 12 + pr;
-            double sn, cs;
-            sincos(dphi * mu, &sn, &cs);
-            double ck = 1.0, sk = 0.0;
-            const double sg = (mu & 1) ? -1.0 : 1.0;
-            double fc = 0.0, fs = 0.0;
+            double tq[4], cq[4], sq[4], cp[4], sp[4], fc[4], fs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mu = min(base + 2 * q, p);
+                const double c1 = sCS[mu], s1 = sCS[nk + mu];
+                tq[q] = 2.0 * c1;
+                cq[q] = 1.0;
+                sq[q] = 0.0;
+                cp[q] = c1;
+                sp[q] = -s1;
+                fc[q] = 0.0;
+                fs[q] = 0.0;
+            }
             for (int kk = 0; kk < nkk; ++kk) {
                 const double K1 = Vb[(long)kk * 12];
                 const double K3 = Vb[(long)(kk + qs) * 12];
@@ -342,15 +383,28 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                     K2 = Vb[(long)(nk - kk) * 12];
                     K4 = Vb[(long)(qs - kk) * 12];
                 }
-                fc = fma(ck, (K1 + K2) + sg * (K3 + K4), fc);
-                fs = fma(sk, (K1 - K2) + sg * (K3 - K4), fs);
-                const double c2 = ck * cs - sk * sn;
-                sk = fma(sk, cs, ck * sn);
-                ck = c2;
+                const double A = fma(sg, K3 + K4, K1 + K2);
+                const double Bv = fma(sg, K3 - K4, K1 - K2);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    fc[q] = fma(cq[q], A, fc[q]);
+                    fs[q] = fma(sq[q], Bv, fs[q]);
+                    const double cn = fma(tq[q], cq[q], -cp[q]), sn = fma(tq[q], sq[q], -sp[q]);
+                    cp[q] = cq[q];
+                    sp[q] = sq[q];
+                    cq[q] = cn;
+                    sq[q] = sn;
+                }
             }
-            double *o = Fa + ((long)mu * Q1 + jr) * NC12 + (long)(t0 + tg) * 12 + pr * 2;
-            o[0] = fc;
-            o[1] = fs;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mu = base + 2 * q;
+                if (mu <= p) {
+                    double *o = Fa + ((long)mu * Q1 + jr) * NC12 + (long)(t0 + tg) * 12 + pr * 2;
+                    o[0] = fc[q];
+                    o[1] = fs[q];
+                }
+            }
         }
     }
 }
@@ -512,7 +566,8 @@ int leg_mfma_max_depth() { return 52; }
 size_t fk_lds_bytes(int p, int qs, bool sl, int tg)
 {
     const int nty = sl ? 4 : 3;
-    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * 12 + (size_t)tg * 3) * sizeof(double);
+    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * 12 + (size_t)tg * 3 + 4 * (size_t)qs) *
+           sizeof(double);
 }
 
 void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
