@@ -12,10 +12,12 @@ equation, velocity synthesis. Target-point evaluations = targets x (1 + operator
 applications in the solve). Inputs are resident in device memory before the
 timed region; the output is written to a device tensor.
 
-Extra fields: "roofline" for the kernel with the largest share of the timed
-region (event times measured live on the library's stream, algorithmic work
-from the library's own counts), and "cpu_baseline": the CPU oracle timed on a
-bounded sample of the same workload.
+Extra fields: "roofline" for the kernel with the largest share of a step
+(chosen from a short breakdown pass with every kernel timed; in the timed
+region only that kernel is bracketed by HIP events on the library's stream,
+since each event pair delays the next launch; algorithmic work from the
+library's own counts), "kernels_ms_per_step" from the breakdown pass, and
+"cpu_baseline": the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -100,6 +102,16 @@ def main():
         for _ in range(args.warmup):
             B.bim_eval_velocity(ctx.h, out)
         torch.cuda.synchronize()
+        # kernel breakdown: a few untimed steps with every kernel bracketed by events
+        nprof = max(1, min(3, args.steps))
+        B.bim_profile(ctx.h, 1)
+        for _ in range(nprof):
+            B.bim_eval_velocity(ctx.h, out)
+        brk = {k: B.bim_profile_query(ctx.h, k) for k in KERNELS}
+        B.bim_profile(ctx.h, 0)
+        dom = max(brk, key=lambda k: brk[k]["ms"])
+        # timed region: events only around the dominant kernel
+        B.bim_profile_select(ctx.h, [dom])
         B.bim_profile(ctx.h, 1)
         reps = []
         torch.cuda.synchronize()
@@ -108,13 +120,12 @@ def main():
             reps.append(B.bim_eval_velocity(ctx.h, out))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = {k: B.bim_profile_query(ctx.h, k) for k in KERNELS}
+        d = B.bim_profile_query(ctx.h, dom)
         B.bim_profile(ctx.h, 0)
+        B.bim_profile_select(ctx.h, None)
     ms = (t1 - t0) * 1e3 / args.steps
     T = ctx.ntargets()
     evals = sum(T * (1 + r.n_matvec) for r in reps) / args.steps
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    d = prof[dom]
     bound = BOUND[dom]
     peak, unit = PEAK[bound]
     per_launch_s = d["ms"] * 1e-3 / max(d["launches"], 1)
@@ -143,7 +154,7 @@ def main():
                      "frac": achieved / peak, "traffic": None,
                      "avg_launch_us": per_launch_s * 1e6, "launches": d["launches"],
                      "share_of_step": d["ms"] / (ms * args.steps)},
-        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items() if v["launches"]},
+        "kernels_ms_per_step": {k: round(v["ms"] / nprof, 4) for k, v in brk.items() if v["launches"]},
     }
     ctx.close()
     if not args.no_cpu_baseline:

@@ -179,11 +179,18 @@ int bim_synchronize(bim_ctx ctx);
 
 /* Kernel timing: HIP events recorded on the context stream around each launch
  * of the main kernels. enable = 1 clears the totals and starts recording,
- * 0 stops. Kernel names: "sing_fused" (fused singular rule, with the double
- * layer rows when built), "dl_apply" (stored double layer times a density),
- * "pair_sl", "pair_dl" (pair sums), "synthesis", "analysis", "classify",
- * "sing_rotate" and "sing_v1" (per-application singular path). */
+ * 0 stops. Kernel names: "pipe_rotate", "pipe_legendre", "pipe_fourier",
+ * "pipe_adjrot" (batched singular pipeline), "sing_fused" (fused singular
+ * rule), "sing_rotate" and "sing_v1" (per-application singular path),
+ * "dl_apply" (stored double layer times a density), "pair_sl", "pair_dl"
+ * (pair sums), "synthesis", "analysis", "classify". Each timed launch adds an
+ * event pair to the stream, which delays the next launch by a few
+ * microseconds; bim_profile_select limits timing to chosen kernels. */
 int bim_profile(bim_ctx ctx, int enable);
+/* Restricts event timing to the kernels named in a comma-separated list
+ * (NULL or "" = all kernels). Launch counts, flops and bytes are still
+ * totalled for every kernel. Takes effect at the next bim_profile(ctx, 1). */
+int bim_profile_select(bim_ctx ctx, const char *names);
 /* Totals since the last enable: launches, summed event time (ms), algorithmic
  * flops and bytes of those launches. Unknown names give zeros. Synchronizes
  * the context stream. */

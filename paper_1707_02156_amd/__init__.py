@@ -79,6 +79,7 @@ EXPORTS = {
     "bim_sh_analyze": ([_vp, _i, _i, _i, _vp, _vp, _i], _i),
     "bim_synchronize": ([_vp], _i),
     "bim_profile": ([_vp, _i], _i),
+    "bim_profile_select": ([_vp, ctypes.c_char_p], _i),
     "bim_profile_query": ([_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp], _i),
     "bim_host_gauss_legendre": ([_i, _vp, _vp], _i),
     "bim_host_legendre": ([_i, _d, _vp, _vp, _vp], _i),
@@ -231,6 +232,12 @@ def bim_synchronize(ctx):
 
 def bim_profile(ctx, enable):
     return _check(ctx, lib().bim_profile(ctx, int(enable)))
+
+
+def bim_profile_select(ctx, names=None):
+    """Time only the named kernels (iterable of names; None = all)."""
+    arg = None if not names else ",".join(names).encode()
+    return _check(ctx, lib().bim_profile_select(ctx, arg))
 
 
 def bim_profile_query(ctx, name):

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -120,7 +121,8 @@ void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, do
 void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long ld, const double *h1, double *w,
                            double *part, unsigned *cnt, double *h2);
 void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
-                           double *part, unsigned *cnt, double *h);
+                           double *part, unsigned *cnt, double *h, const GivensArgs &ga = GivensArgs{});
+void launch_backsub(hipStream_t st, int k, const double *H, long ldH, const double *g, double *y);
 void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 
@@ -230,7 +232,8 @@ struct Ctx {
     DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
-    DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt;
+    DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt, givbuf;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
 
     bool nodes_ok = false, force_ok = false, regions_ok = false;
@@ -243,6 +246,7 @@ struct Ctx {
     };
     bool prof_on = false;
     std::map<std::string, ProfEntry> prof;
+    std::set<std::string> prof_sel;  // kernels timed with events (empty = all)
     std::vector<hipEvent_t> evpool;
     std::map<std::pair<int, int>, std::unique_ptr<GridTab>> grids;
     std::map<int, std::unique_ptr<RotTab>> rots;
@@ -267,6 +271,8 @@ struct Ctx {
         grids.clear();
         rots.clear();
         if (hhost) (void)hipHostFree(hhost);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -295,10 +301,12 @@ struct ProfScope {
     ProfScope(Ctx &cc, const char *name, double flops, double bytes) : c(cc)
     {
         if (!c.prof_on) return;
-        e = &c.prof[name];
-        e->flops += flops;
-        e->bytes += bytes;
-        e->launches += 1;
+        Ctx::ProfEntry *pe = &c.prof[name];
+        pe->flops += flops;
+        pe->bytes += bytes;
+        pe->launches += 1;
+        if (!c.prof_sel.empty() && !c.prof_sel.count(name)) return;
+        e = pe;
         a = prof_event(c);
         HIPC(hipEventRecord(a, c.stream));
     }
@@ -1052,37 +1060,55 @@ static void apply_operator(Ctx &c, const double *x, double *y, const std::vector
 
 // --------------------------------------------------------------------------
 // GMRES (restarted, classical Gram-Schmidt with one re-orthogonalisation,
-// Givens rotations on the host). Vectors on the device.
+// Givens rotations and back substitution on the device). The host enqueues
+// Arnoldi step k + 1 before it reads the residual estimate of step k (one
+// step behind, through an event), so the device never waits for the host; a
+// step enqueued after convergence is discarded.
 // --------------------------------------------------------------------------
 static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, int &iters, double &relres,
                  int &nmv)
 {
     const long n = 3 * c.Ctot;
     const int m = std::max(1, std::min(c.opt.gmres_restart, gs_max_vectors() - 1));
+    const long ldH = m + 2;
     c.V.ensure((size_t)(m + 1) * n * sizeof(double));
     c.hbuf.ensure((size_t)(2 * (m + 2)) * sizeof(double));
     c.ybuf.ensure((size_t)(m + 2) * sizeof(double));
     c.wvec.ensure((size_t)n * sizeof(double));
     c.rvec.ensure((size_t)n * sizeof(double));
     c.gspart.ensure((size_t)gs_blocks(n) * (m + 2) * sizeof(double));
+    c.givbuf.ensure((size_t)(ldH * m + 3 * (m + 2) + 2) * sizeof(double));
     if (!c.gscnt.ptr) {
         c.gscnt.ensure(sizeof(unsigned));
         HIPC(hipMemsetAsync(c.gscnt.ptr, 0, sizeof(unsigned), c.stream));
     }
     if (!c.hhost) HIPC(hipHostMalloc((void **)&c.hhost, 4 * 256 * sizeof(double)));
+    if (!c.ev[0]) {
+        HIPC(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
+    }
     double *V = c.V.d(), *h = c.hbuf.d(), *h2 = h + (m + 2), *w = c.wvec.d(), *part = c.gspart.d();
     unsigned *cnt = (unsigned *)c.gscnt.ptr;
+    GivensArgs ga;
+    ga.H = c.givbuf.d();
+    ga.ldH = ldH;
+    ga.cs = ga.H + ldH * m;
+    ga.sn = ga.cs + (m + 2);
+    ga.g = ga.sn + (m + 2);
+    double *resd = ga.g + (m + 2);  // residual estimates of the two latest steps
     HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
     // ||b||
     launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, const_cast<double *>(b), part, cnt, h);
     HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
     const double bn = c.hhost[0];
+    ga.bnorm = bn;
     iters = 0;
     nmv = 0;
     relres = 0.0;
     if (bn == 0.0) return BIM_OK;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+    double *gh = c.hhost + 256;  // host image of g at a restart
+    volatile double *resh = c.hhost + 2;
     bool first = true;
     while (true) {
         // r = b - A x
@@ -1102,50 +1128,41 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         relres = beta / bn;
         if (relres <= c.opt.gmres_tol) return BIM_OK;
         if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
+        std::fill(gh, gh + m + 2, 0.0);
+        gh[0] = beta;
+        HIPC(hipMemcpyAsync(ga.g, gh, (m + 2) * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        const int kmax = std::min(m, c.opt.gmres_maxit - iters);
         int kdone = 0;
         bool conv = false;
-        for (int k = 0; k < m; ++k) {
+        // step k: Arnoldi vector k + 1, column k of R, residual estimate -> resh[k & 1]
+        auto step = [&](int k) {
             apply_operator(c, V + (long)k * n, w, wt);
-            ++nmv;
-            // two classical Gram-Schmidt passes, then the new basis vector
+            GivensArgs gk = ga;
+            gk.res = resd + (k & 1);
             launch_gs_dots(c.stream, n, k + 1, V, n, w, part, cnt, h);
             launch_gs_update_dots(c.stream, n, k + 1, V, n, h, w, part, cnt, h2);
-            launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h);
+            launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h, gk);
             launch_gs_scale(c.stream, n, w, h + k + 1, V + (long)(k + 1) * n);
-            HIPC(hipMemcpyAsync(c.hhost, h, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            HIPC(hipStreamSynchronize(c.stream));
-            for (int l = 0; l <= k + 1; ++l) H[(size_t)l * m + k] = c.hhost[l];
-            for (int l = 0; l < k; ++l) {
-                const double t = cs[l] * H[(size_t)l * m + k] + sn[l] * H[(size_t)(l + 1) * m + k];
-                H[(size_t)(l + 1) * m + k] = -sn[l] * H[(size_t)l * m + k] + cs[l] * H[(size_t)(l + 1) * m + k];
-                H[(size_t)l * m + k] = t;
-            }
-            const double den = std::hypot(H[(size_t)k * m + k], H[(size_t)(k + 1) * m + k]);
-            cs[k] = den > 0.0 ? H[(size_t)k * m + k] / den : 1.0;
-            sn[k] = den > 0.0 ? H[(size_t)(k + 1) * m + k] / den : 0.0;
-            H[(size_t)k * m + k] = den;
-            H[(size_t)(k + 1) * m + k] = 0.0;
-            g[k + 1] = -sn[k] * g[k];
-            g[k] = cs[k] * g[k];
+            HIPC(hipMemcpyAsync((void *)(resh + (k & 1)), resd + (k & 1), sizeof(double), hipMemcpyDeviceToHost,
+                                c.stream));
+            HIPC(hipEventRecord(c.ev[k & 1], c.stream));
+        };
+        step(0);
+        for (int k = 0; k < kmax; ++k) {
+            if (k + 1 < kmax) step(k + 1);  // enqueue the next step before waiting on this one
+            HIPC(hipEventSynchronize(c.ev[k & 1]));
+            const double r = resh[k & 1];
             ++iters;
+            ++nmv;
             kdone = k + 1;
-            relres = std::fabs(g[k + 1]) / bn;
-            if (relres <= c.opt.gmres_tol || iters >= c.opt.gmres_maxit) {
-                conv = relres <= c.opt.gmres_tol;
+            relres = r;
+            if (r <= c.opt.gmres_tol) {
+                conv = true;
                 break;
             }
         }
-        // back substitution
-        std::vector<double> y(kdone);
-        for (int l = kdone - 1; l >= 0; --l) {
-            double s = g[l];
-            for (int q = l + 1; q < kdone; ++q) s -= H[(size_t)l * m + q] * y[q];
-            y[l] = s / H[(size_t)l * m + l];
-        }
-        HIPC(hipMemcpyAsync(c.ybuf.ptr, y.data(), kdone * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        // x += V y with R y = g over the completed steps
+        launch_backsub(c.stream, kdone, ga.H, ldH, ga.g, c.ybuf.d());
         launch_lincomb(c.stream, n, kdone, V, n, c.ybuf.d(), x);
         HIPC(hipStreamSynchronize(c.stream));
         if (conv) return BIM_OK;
@@ -1629,6 +1646,26 @@ int bim_profile(bim_ctx h, int enable)
         prof_drain(c);
         if (enable) c.prof.clear();
         c.prof_on = enable != 0;
+        return BIM_OK;
+    });
+}
+
+int bim_profile_select(bim_ctx h, const char *names)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        c.prof_sel.clear();
+        if (names) {
+            std::string s(names), cur;
+            for (char ch : s + ",") {
+                if (ch == ',') {
+                    if (!cur.empty()) c.prof_sel.insert(cur);
+                    cur.clear();
+                } else if (ch != ' ') {
+                    cur += ch;
+                }
+            }
+        }
         return BIM_OK;
     });
 }

@@ -35,6 +35,16 @@ struct PairWork {
     double w;       // weight applied to the sum
 };
 
+// Device state of the GMRES least-squares problem (Givens rotations applied
+// on the device): R by columns, rotations, right-hand side g, and the
+// residual estimate |g[k+1]| / ||b|| of the latest column.
+struct GivensArgs {
+    double *H = nullptr;
+    long ldH = 0;
+    double *cs = nullptr, *sn = nullptr, *g = nullptr, *res = nullptr;
+    double bnorm = 1.0;
+};
+
 // One source grid for the pair sums: component-major arrays [3][stride].
 struct PairSrc {
     const double *x, *wN, *wW, *d;

@@ -615,7 +615,7 @@ template <bool UPD, bool NRM>
 __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__restrict__ V, long ld,
                                             const double *__restrict__ hin, double *__restrict__ w,
                                             double *__restrict__ part, unsigned *__restrict__ cnt,
-                                            double *__restrict__ hout)
+                                            double *__restrict__ hout, GivensArgs ga)
 {
     __shared__ double sacc[4][kGsChunk];
     __shared__ bool last;
@@ -693,7 +693,47 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
     }
     if (NRM && UPD)
         for (int i = threadIdx.x; i < kv; i += 256) hout[i] += hin[i];
+    if (NRM && UPD && ga.H) {
+        // Givens update of the least-squares problem for column k = kv - 1:
+        // previous rotations on the new column of H (h[0..k+1], kept as it is
+        // for the normalisation that follows), then the rotation that zeroes
+        // h[k+1]; g updated and the residual estimate |g[k+1]| / ||b|| stored.
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int kc = kv - 1;
+            double *col = ga.H + (long)kc * ga.ldH;  // column kc of R, rows 0..kc+1
+            for (int l = 0; l <= kc + 1; ++l) col[l] = hout[l];
+            for (int l = 0; l < kc; ++l) {
+                const double t = ga.cs[l] * col[l] + ga.sn[l] * col[l + 1];
+                col[l + 1] = -ga.sn[l] * col[l] + ga.cs[l] * col[l + 1];
+                col[l] = t;
+            }
+            const double den = hypot(col[kc], col[kc + 1]);
+            const double cr = den > 0.0 ? col[kc] / den : 1.0, sr = den > 0.0 ? col[kc + 1] / den : 0.0;
+            ga.cs[kc] = cr;
+            ga.sn[kc] = sr;
+            col[kc] = den;
+            col[kc + 1] = 0.0;
+            const double gk = ga.g[kc];
+            ga.g[kc + 1] = -sr * gk;
+            ga.g[kc] = cr * gk;
+            ga.res[0] = fabs(ga.g[kc + 1]) / ga.bnorm;
+        }
+    }
     if (threadIdx.x == 0) atomicExch(cnt, 0u);
+}
+
+// y = R^-1 g for the leading k x k block of the upper triangular R stored by
+// columns (leading dimension ldH); one thread (k is at most the restart length).
+__global__ void k_backsub(int k, const double *__restrict__ H, long ldH, const double *__restrict__ g,
+                          double *__restrict__ y)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int l = k - 1; l >= 0; --l) {
+        double s = g[l];
+        for (int q = l + 1; q < k; ++q) s -= H[(long)q * ldH + l] * y[q];
+        y[l] = s / H[(long)l * ldH + l];
+    }
 }
 
 // v = w / nrm[0] (v may alias w); a zero norm leaves v = 0
@@ -836,7 +876,7 @@ void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, do
                     unsigned *cnt, double *h)
 {
     hipLaunchKernelGGL((k_gs<false, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, nullptr, w, part,
-                       cnt, h);
+                       cnt, h, GivensArgs{});
 }
 
 // w -= V h1, then h2[i] = V_i . w
@@ -844,19 +884,25 @@ void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long
                            double *part, unsigned *cnt, double *h2)
 {
     hipLaunchKernelGGL((k_gs<true, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h1, w, part, cnt,
-                       h2);
+                       h2, GivensArgs{});
 }
 
-// w -= V h2, h[i] += h2[i], h[kv] = ||w||; with kv = 0 just h[0] = ||w||
+// w -= V h2, h[i] += h2[i], h[kv] = ||w||; with kv = 0 just h[0] = ||w||.
+// With ga.H set (kv > 0) the last block also applies the Givens update.
 void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
-                           double *part, unsigned *cnt, double *h)
+                           double *part, unsigned *cnt, double *h, const GivensArgs &ga)
 {
     if (kv > 0)
         hipLaunchKernelGGL((k_gs<true, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h2, w, part, cnt,
-                           h);
+                           h, ga);
     else
         hipLaunchKernelGGL((k_gs<false, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, 0, V, ld, nullptr, w, part,
-                           cnt, h);
+                           cnt, h, GivensArgs{});
+}
+
+void launch_backsub(hipStream_t st, int k, const double *H, long ldH, const double *g, double *y)
+{
+    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(64), 0, st, k, H, ldH, g, y);
 }
 
 void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v)

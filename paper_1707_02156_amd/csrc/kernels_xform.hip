@@ -4,7 +4,7 @@
 // for many (drop, grid, field) jobs in one launch; the job list travels in the
 // kernel arguments.
 //
-// Synthesis block = (job, latitude j): Legendre sums G[c][kind][m] =
+// Synthesis block = (job, latitude j, range of 64 longitudes): Legendre sums G[c][kind][m] =
 // sum_n c_n^m L_kind(t_j) for the kinds the requested derivatives need, into
 // LDS; then each thread forms points k and k + q of one output field with the
 // even/odd split e^{i m (phi + pi)} = (-1)^m e^{i m phi}.
@@ -35,12 +35,16 @@ struct SynJobs {
     SynJob j[kMaxSynJobs];
 };
 
+constexpr int kSynK = 64;  // longitudes k (and k + q) per synthesis block
+
 __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
 {
     __shared__ double G[3 * 3 * 65 * 2];  // [c][kind][m][re,im]
     const SynJob &J = jobs.j[blockIdx.y];
     const int j = blockIdx.x;
-    if (j > J.q) return;
+    const int k0 = blockIdx.z * kSynK;
+    if (j > J.q || k0 >= J.q) return;
+    const int kn = min(kSynK, J.q - k0);
     const int p = J.p, P1 = p + 1, q = J.q, nk = 2 * q;
     int kinds = 0;  // bit 0: Ptilde, 1: d/dtheta, 2: d2/dtheta2
     for (int b = 0; b < 6; ++b)
@@ -55,6 +59,7 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
         const double *Lj = J.L + ((long)kind * nq + j) * J.ldn;
         double sr = 0.0, si = 0.0;
         int e = m * (m + 1) / 2 + m;
+#pragma unroll 4
         for (int n = m; n <= p; ++n) {
             const double l = Lj[e];
             sr = fma(cf[2 * e], l, sr);
@@ -69,9 +74,9 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
     for (int b = 0; b < 6; ++b)
         if (J.mask >> b & 1) fidx[nout++] = b;
     const double dphi = 3.14159265358979323846 / q;
-    for (int it = threadIdx.x; it < J.ncomp * nout * q; it += 256) {
-        const int k = it % q;
-        const int r = it / q;
+    for (int it = threadIdx.x; it < J.ncomp * nout * kn; it += 256) {
+        const int k = k0 + it % kn;
+        const int r = it / kn;
         const int fo = r % nout, c = r / nout;
         const int b = fidx[fo], dt = kDt[b], dp = kDp[b];
         const double *g = G + 2 * ((c * 3 + dt) * P1);
@@ -137,6 +142,7 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
         double sn, cs;
         sincos(dphi * m, &sn, &cs);
         double ck = 1.0, sk = 0.0, fr = 0.0, fi = 0.0;
+#pragma unroll 4
         for (int k = 0; k < nk; ++k) {
             fr = fma(row[k], ck, fr);
             fi = fma(-row[k], sk, fi);
@@ -159,6 +165,7 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
         const int e = n * (n + 1) / 2 + m;
         const double h = (m == q) ? 0.5 : 1.0;
         double sr = 0.0, si = 0.0;
+#pragma unroll 4
         for (int j = 0; j < nj; ++j) {
             const double w = J.wq[j] * J.L[(long)j * J.ldn + e] * h;
             sr = fma(w, F[2 * (j * kAnaMC + mm)], sr);
@@ -182,7 +189,7 @@ void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n)
             b.j[i] = jobs[o + i];
             maxq = std::max(maxq, jobs[o + i].q);
         }
-        hipLaunchKernelGGL(k_synth_batch, dim3(maxq + 1, b.n), dim3(256), 0, st, b);
+        hipLaunchKernelGGL(k_synth_batch, dim3(maxq + 1, b.n, (maxq + kSynK - 1) / kSynK), dim3(256), 0, st, b);
     }
 }
 
