@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--singular-path", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the workload, copy a buffer of this size three times (a plain copy of known "
+                         "size against which the HBM byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",
@@ -91,6 +94,14 @@ def main():
     import paper_1707_02156_amd as B
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = workload()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):

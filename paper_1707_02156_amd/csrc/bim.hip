@@ -32,8 +32,6 @@
 
 namespace bim {
 
-void launch_synth(hipStream_t st, int p, int q, int nmax, const double *L, const double *cs, int nf,
-                  const double *coef, long cstride, int dt, int dp, double *G, double *out, long ostride);
 void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, const double *wq, const double *cs,
                     int nf, const double *v, long vstride, double *F, double *coef, long cstride);
 void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f);

@@ -17,59 +17,6 @@ static constexpr double kPi = 3.14159265358979323846;
 static constexpr double kInvSqrt4Pi = 0.28209479177387814347;
 
 // ----------------------------------------------------------------------------
-// Synthesis (Sec. 1.1 truncated expansion; derivatives by Appendix A):
-// stage 1 (Legendre): G[f][j][m] = sum_{n=m}^{p} c_f[n,m] L[j][tri(n,m)]
-// stage 2 (Fourier):  v[f][j][k] = sum_{m=0}^{p} (m ? 2 : 1) Re[(i m)^dp G e^{i m phi_k}]
-// ----------------------------------------------------------------------------
-__global__ void k_synth_leg(int p, int nj, int ldn, const double *__restrict__ L, int nf,
-                            const double *__restrict__ coef, long cstride, double *__restrict__ G)
-{
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long total = (long)nf * nj * (p + 1);
-    if (idx >= total) return;
-    const int m = idx % (p + 1);
-    const long r = idx / (p + 1);
-    const int j = r % nj;
-    const int f = r / nj;
-    const double *c = coef + f * cstride;
-    const double *Lj = L + (long)j * ldn;
-    double sr = 0.0, si = 0.0;
-    for (int n = m; n <= p; ++n) {
-        const double l = Lj[tri(n, m)];
-        sr = fma(c[2 * tri(n, m)], l, sr);
-        si = fma(c[2 * tri(n, m) + 1], l, si);
-    }
-    G[2 * idx] = sr;
-    G[2 * idx + 1] = si;
-}
-
-__global__ void k_synth_fourier(int p, int q, int nj, int dp, const double *__restrict__ G,
-                                const double *__restrict__ cs, int nf, double *__restrict__ out, long ostride)
-{
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nk = 2 * q;
-    const long total = (long)nf * nj * nk;
-    if (idx >= total) return;
-    const int k = idx % nk;
-    const long r = idx / nk;
-    const int j = r % nj;
-    const int f = r / nj;
-    const double *g = G + 2 * ((long)(f * nj + j) * (p + 1));
-    double v = 0.0;
-    int e = 0;  // (m k) mod 2q
-    for (int m = 0; m <= p; ++m) {
-        double ar = g[2 * m], ai = g[2 * m + 1];
-        if (dp == 1) { const double t = -m * ai; ai = m * ar; ar = t; }
-        else if (dp == 2) { ar *= -(double)m * m; ai *= -(double)m * m; }
-        const double c = cs[e], s = cs[nk + e];
-        v += (m ? 2.0 : 1.0) * (ar * c - ai * s);
-        e += k;
-        if (e >= nk) e -= nk;
-    }
-    out[f * ostride + (long)j * nk + k] = v;
-}
-
-// ----------------------------------------------------------------------------
 // Analysis (Sec. 2.1, weight (pi/q) w_j, half weight at m = q):
 // stage 1 (Fourier):  F[f][j][m] = sum_k v[f][j][k] e^{-i m phi_k}, m = 0..p
 // stage 2 (Legendre): c_f[n,m] = sum_j wq_j h_m Ptilde_n^m(t_j) F[f][j][m]
@@ -760,18 +707,6 @@ __global__ void k_lincomb(long n, int k, const double *__restrict__ V, long ld, 
 // Host launchers
 // ============================================================================
 static inline unsigned nblk(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
-
-void launch_synth(hipStream_t st, int p, int q, int nmax, const double *L /*[3][q+1][ncoef(nmax)]*/,
-                  const double *cs, int nf, const double *coef, long cstride, int dt, int dp, double *G,
-                  double *out, long ostride)
-{
-    const int nj = q + 1, ldn = ncoef(nmax);
-    const long n1 = (long)nf * nj * (p + 1);
-    hipLaunchKernelGGL(k_synth_leg, dim3(nblk(n1)), dim3(256), 0, st, p, nj, ldn, L + (long)dt * nj * ldn, nf, coef,
-                       cstride, G);
-    const long n2 = (long)nf * nj * 2 * q;
-    hipLaunchKernelGGL(k_synth_fourier, dim3(nblk(n2)), dim3(256), 0, st, p, q, nj, dp, G, cs, nf, out, ostride);
-}
 
 void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, const double *wq, const double *cs,
                     int nf, const double *v, long vstride, double *F, double *coef, long cstride)

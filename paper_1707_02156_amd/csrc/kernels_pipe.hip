@@ -51,17 +51,17 @@ __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restric
     const int n = blockIdx.x, j = j0 + blockIdx.y;
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
     const int nf = dc ? 6 : 3;
-    const int MT = (N1 + 15) / 16, NP = MT * 16, KS = (N1 + 3) / 4;
-    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded
-    double *sAm = sAp + NP * NP;
-    double *sC = sAm + NP * NP;        // [f][nu][re,im]
+    const int MT = (N1 + 15) / 16, NP = MT * 16, NS = NP + 1, KS = (N1 + 3) / 4;
+    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded, row stride NS
+    double *sAm = sAp + NP * NS;
+    double *sC = sAm + NP * NS;        // [f][nu][re,im]
     double *sCS = sC + nf * N1 * 2;    // cos, sin of the target longitudes [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
     for (int i = threadIdx.x; i < NP * NP; i += 256) {
         const int nu = i / NP, mu = i % NP;
         const bool in = nu < N1 && mu < N1;
-        sAp[i] = in ? Ap[lat + nu * N1 + mu] : 0.0;
-        sAm[i] = in ? Am[lat + nu * N1 + mu] : 0.0;
+        sAp[nu * NS + mu] = in ? Ap[lat + nu * N1 + mu] : 0.0;
+        sAm[nu * NS + mu] = in ? Am[lat + nu * N1 + mu] : 0.0;
     }
     const int b0 = n * (n + 1) / 2;
     for (int i = threadIdx.x; i < nf * N1; i += 256) {
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restric
             }
             e += step;
             if (e >= nk) e -= nk;
-            const double *pa = sAp + nu * NP + r16, *pm = sAm + nu * NP + r16;
+            const double *pa = sAp + nu * NS + r16, *pm = sAm + nu * NS + r16;
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 if (m < MT) {
@@ -141,15 +141,15 @@ template <int MT>
 __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
                                                   const double *__restrict__ in, double *__restrict__ out, long NC)
 {
-    __shared__ double sT[MT * 16 * 4 * 13];   // rows padded to MT*16, depth padded to 4 per slab (up to 52)
+    __shared__ double sT[MT * 16 * 53];   // rows padded to MT*16, depth padded to 4 (up to 52), odd row stride
     const LegBatch b = bt[blockIdx.y];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const long col0 = (long)blockIdx.x * 64 + wv * 16;
-    const int Kp = (b.K + 3) & ~3;
-    // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp
+    const int Kp = (b.K + 3) & ~3, Ks = Kp + 1;
+    // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp, row stride Ks
     for (int i = threadIdx.x; i < MT * 16 * Kp; i += 256) {
         const int r = i / Kp, k = i % Kp;
-        sT[i] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
+        sT[r * Ks + k] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
     }
     __syncthreads();
     d4_t acc[MT];
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
         const double bv = (cok && k < b.K) ? in[(b.in_row + k) * NC + col] : 0.0;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            const double av = sT[(m * 16 + (lane & 15)) * Kp + k];
+            const double av = sT[(m * 16 + (lane & 15)) * Ks + k];
             acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
         }
     }
@@ -183,6 +183,10 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
 // SL: partial[t][j'][3] += omega W (f/r + xh (xh.f)/r^3) summed over the longitudes.
 // DL: Fa^mu[j'][t*12 + pair*2 + {cos, sin}] of the six stresslet fields.
 // ----------------------------------------------------------------------------
+// point records of 12 fields padded to an odd number of doubles, so that
+// lanes reading consecutive points hit distinct LDS banks
+constexpr int kVS = 13;
+
 template <bool SL, bool DL, int TG>
 __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double *__restrict__ Gx,
                                             const double *__restrict__ Gd, long NC6,
@@ -198,8 +202,8 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     constexpr int NTY = SL ? 4 : 3;
     double *sG = sm;
     const long gsz = (long)TG * P1 * NTY * 6;
-    double *V = sG + gsz;                    // [tg][k'][12]
-    double *red = V + (long)TG * nk * 12;    // [tg][3]
+    double *V = sG + gsz;                    // [tg][k'][kVS]: 12 fields, padded
+    double *red = V + (long)TG * nk * kVS;   // [tg][3]
     double *sCS = red + TG * 3;              // cos, sin of pi e / qs, e < 2 qs
     for (int i = threadIdx.x; i < TG * 3; i += 256) red[i] = 0.0;
     for (int e = threadIdx.x; e < nk; e += 256) sincos(3.14159265358979323846 * e / qs, &sCS[nk + e], &sCS[e]);
@@ -269,10 +273,10 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 SE[q] = fma(ge[6 * q + 1], s0, SE[q]);
             }
         }
-        double *Vb = V + (long)tg * nk * 12;
+        double *Vb = V + (long)tg * nk * kVS;
         // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
         auto put = [&](int kp, double f1, double f2) {
-            double *v = Vb + (long)kp * 12;
+            double *v = Vb + (long)kp * kVS;
             v[c] = (CE[0] - f1 * SE[0]) + f2 * (CO[0] - f1 * SO[0]);
             v[3 + c] = (CE[1] - f1 * SE[1]) + f2 * (CO[1] - f1 * SO[1]);
             v[6 + c] = (CE[2] - f1 * SE[2]) + f2 * (CO[2] - f1 * SO[2]);
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     for (int it = threadIdx.x; it < ((ntg * nk + 63) & ~63); it += 256) {
         const bool ok = it < ntg * nk;
         const int tg = ok ? it / nk : 0;
-        double *v = V + (long)(ok ? it : 0) * 12;
+        double *v = V + (long)(ok ? it : 0) * kVS;
         const int t = t0 + tg;
         double e0 = 0.0, e1 = 0.0, e2 = 0.0;
         if (ok) {
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
             const bool odd = gidx >= NGe;
             const int base = odd ? 8 * (gidx - NGe) + 1 : 8 * gidx;
             const double sg = odd ? -1.0 : 1.0;
-            const double *Vb = V + (long)tg * nk * 12 + pr;
+            const double *Vb = V + (long)tg * nk * kVS + pr;
             double tq[4], cq[4], sq[4], cp[4], sp[4], fc[4], fs[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -376,12 +380,12 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 fs[q] = 0.0;
             }
             for (int kk = 0; kk < nkk; ++kk) {
-                const double K1 = Vb[(long)kk * 12];
-                const double K3 = Vb[(long)(kk + qs) * 12];
+                const double K1 = Vb[(long)kk * kVS];
+                const double K3 = Vb[(long)(kk + qs) * kVS];
                 double K2 = 0.0, K4 = 0.0;
                 if (even && kk != 0 && kk != qs / 2) {
-                    K2 = Vb[(long)(nk - kk) * 12];
-                    K4 = Vb[(long)(qs - kk) * 12];
+                    K2 = Vb[(long)(nk - kk) * kVS];
+                    K4 = Vb[(long)(qs - kk) * kVS];
                 }
                 const double A = fma(sg, K3 + K4, K1 + K2);
                 const double Bv = fma(sg, K3 - K4, K1 - K2);
@@ -449,16 +453,16 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
     extern __shared__ double sm[];
     const int n = blockIdx.x, j = j0 + blockIdx.y;
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
-    const int MT = (N1 + 15) / 16, NP = MT * 16, KS = (N1 + 3) / 4;
-    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded
-    double *sAm = sAp + NP * NP;
-    double *sCS = sAm + NP * NP;       // [2][nk]
+    const int MT = (N1 + 15) / 16, NP = MT * 16, NS = NP + 1, KS = (N1 + 3) / 4;
+    double *sAp = sm;                  // [nu][mu], NP x NP, zero padded, row stride NS
+    double *sAm = sAp + NP * NS;
+    double *sCS = sAm + NP * NS;       // [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
     for (int i = threadIdx.x; i < NP * NP; i += 256) {
         const int nu = i / NP, mu = i % NP;
         const bool in = nu < N1 && mu < N1;
-        sAp[i] = in ? Ap[lat + nu * N1 + mu] : 0.0;
-        sAm[i] = in ? Am[lat + nu * N1 + mu] : 0.0;
+        sAp[nu * NS + mu] = in ? Ap[lat + nu * N1 + mu] : 0.0;
+        sAm[nu * NS + mu] = in ? Am[lat + nu * N1 + mu] : 0.0;
     }
     for (int i = threadIdx.x; i < 2 * nk; i += 256) sCS[i] = csp[i];
     __syncthreads();
@@ -487,8 +491,8 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
             for (int m = 0; m < 4; ++m)
                 if (m < MT) {
                     const int nu = m * 16 + r16;
-                    al[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAp[nu * NP + mu], av, al[m], 0, 0, 0);
-                    be[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAm[nu * NP + mu], bv, be[m], 0, 0, 0);
+                    al[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAp[nu * NS + mu], av, al[m], 0, 0, 0);
+                    be[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(sAm[nu * NS + mu], bv, be[m], 0, 0, 0);
                 }
         }
         if (!cok) continue;
@@ -532,7 +536,7 @@ void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, cons
 {
     const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
     const int nf = dc ? 6 : 3;
-    const size_t lds = (size_t)(2 * NP * NP + nf * P1 * 2 + 2 * nk) * sizeof(double);
+    const size_t lds = (size_t)(2 * NP * (NP + 1) + nf * P1 * 2 + 2 * nk) * sizeof(double);
     hipLaunchKernelGGL(k_rot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride, j0, 0,
                        Bx, Bd, NC);
 }
@@ -540,7 +544,7 @@ void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, cons
 size_t rot_lds_bytes(int p)
 {
     const int P1 = p + 1, NP = (P1 + 15) / 16 * 16;
-    return P1 > kRotMaxPad ? (size_t)1 << 40 : (size_t)(2 * NP * NP + 6 * P1 * 2 + 4 * p) * sizeof(double);
+    return P1 > kRotMaxPad ? (size_t)1 << 40 : (size_t)(2 * NP * (NP + 1) + 6 * P1 * 2 + 4 * p) * sizeof(double);
 }
 
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
@@ -566,7 +570,7 @@ int leg_mfma_max_depth() { return 52; }
 size_t fk_lds_bytes(int p, int qs, bool sl, int tg)
 {
     const int nty = sl ? 4 : 3;
-    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * 12 + (size_t)tg * 3 + 4 * (size_t)qs) *
+    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * kVS + (size_t)tg * 3 + 4 * (size_t)qs) *
            sizeof(double);
 }
 
@@ -598,7 +602,7 @@ void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, co
                    long NC12, int j0, int nj, int tglobal0, double *M)
 {
     const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
-    const size_t lds = (size_t)(2 * NP * NP + 2 * nk) * sizeof(double);
+    const size_t lds = (size_t)(2 * NP * (NP + 1) + 2 * nk) * sizeof(double);
     hipLaunchKernelGGL(k_adjrot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, j0, 0, tglobal0, M);
 }
 
