@@ -29,7 +29,7 @@ struct PairWork {
     int tlist_off;  // first entry in the target index list
     int ntgt;       // targets in this item (<= 64)
     int src_off;    // first source node in the source arrays
-    int nsrc;       // source nodes in this item (<= 256)
+    int nsrc;       // source nodes in this item
     int pair;       // target drop * n_drops + source drop
     int pad;        // source grid: 0 standard, 1 upsampled
     double w;       // weight applied to the sum
