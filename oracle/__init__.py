@@ -73,6 +73,12 @@ def lib():
         L.orc_regular.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_regular.restype = ctypes.c_int
         L.orc_min_node_distance.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp]
+        L.orc_eval_point_d.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int]
+        L.orc_eval_point_d.restype = ctypes.c_double
+        L.orc_closest_point.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_closest_point.restype = ctypes.c_int
+        L.orc_nearest_node.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _ip]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -227,6 +233,45 @@ def regular(ps: int, q: int, xc, dc, kind: int, x0):
     return out
 
 
+def eval_point_d(p: int, c, theta: float, phi: float, dt: int = 0, dp: int = 0) -> float:
+    """d^dt/dtheta^dt d^dp/dphi^dp of a real degree-p expansion at one point."""
+    return lib().orc_eval_point_d(p, _p(_c(c)), float(theta), float(phi), int(dt), int(dp))
+
+
+def closest_point(p: int, xc, x0, theta0: float, phi0: float):
+    """Closest point of a drop to x0 (Sec. 2.3): Newton on the gradient of
+    |x(theta, phi) - x0|^2 / 2 with a Levenberg-Marquardt shift. Returns
+    (theta, phi, x_star (3,), iterations)."""
+    res = np.zeros(5)
+    x0 = _c(np.asarray(x0, dtype=float).reshape(3))
+    it = lib().orc_closest_point(p, _p(_c(xc)), _p(x0), float(theta0), float(phi0), _p(res))
+    return res[0], res[1], res[2:5].copy(), it
+
+
+def nearest_node(ps: int, xc, x0):
+    """Index j*2ps + k of the nearest node of the degree-ps grid to each target."""
+    x0 = _c(np.asarray(x0).reshape(-1, 3))
+    idx = np.zeros(len(x0), dtype=np.int32)
+    if len(x0):
+        lib().orc_nearest_node(ps, _p(_c(xc)), len(x0), _p(x0), idx.ctypes.data_as(_ip))
+    return idx
+
+
+def lagrange(s_nodes, values, s):
+    """Value at s of the polynomial through (s_nodes[l], values[l]) (values may
+    be vectors), in Lagrange form."""
+    s_nodes = np.asarray(s_nodes, dtype=float)
+    values = np.asarray(values, dtype=float)
+    out = np.zeros(values.shape[1:])
+    for l in range(len(s_nodes)):
+        w = 1.0
+        for m in range(len(s_nodes)):
+            if m != l:
+                w *= (s - s_nodes[m]) / (s_nodes[l] - s_nodes[m])
+        out = out + w * values[l]
+    return out
+
+
 def min_node_distance(ps: int, xc, x0):
     xc = _c(xc)
     x0 = _c(np.asarray(x0).reshape(-1, 3))
@@ -253,6 +298,8 @@ class Options:
     U0: tuple = (0.0, 0.0, 0.0)
     gradU: tuple = (0.0,) * 9
     lambda_rule: int = 0      # 0: source-drop lambda_j, 1: target-drop lambda_i
+    near_rule: int = 0        # Omega_2 targets: 0 the Omega_1 rule, 1 the special quadrature of Sec. 2.3
+    near_L: int = 8           # interpolation points x_l = x* + h sqrt(l) d, l = 1..L (Sec. 5: L = 8)
     gmres_tol: float = 1e-10
     gmres_restart: int = 50
     gmres_maxit: int = 500
@@ -327,12 +374,66 @@ class System:
         out = np.zeros((len(targets), 3))
         dj = self.drops[j]
         far = np.nonzero(r == 0)[0]
-        near = np.nonzero(r != 0)[0]
+        special = self.opt.near_rule == 1
+        near = np.nonzero((r == 1) | ((r == 2) & (not special)))[0]
+        nearest = np.nonzero((r == 2) & special)[0]
         if len(far):
             out[far] = regular(dj.p, dj.p, dj.xc, dens, kind, x0[far])
         if len(near):
             out[near] = regular(dj.p, self.opt.U_tilde * dj.p, dj.xc, dens, kind, x0[near])
+        for a in nearest:
+            out[a] = self.nearest_value(j, dens, kind, x0[a])
         return out
+
+    # nearest region (Sec. 2.3) ------------------------------------------
+    def closest(self, j, x0):
+        """Closest point on drop j to x0 by Newton from the nearest grid node."""
+        dj = self.drops[j]
+        k = int(nearest_node(dj.p, dj.xc, x0)[0])
+        t, _ = gauss_legendre(dj.p)
+        th0 = np.arccos(t[k // (2 * dj.p)])
+        ph0 = np.pi * (k % (2 * dj.p)) / dj.p
+        return closest_point(dj.p, dj.xc, x0, th0, ph0)
+
+    def self_coefficients(self, j, dens, kind):
+        """The self-interaction of drop j at its own grid nodes (singular rule),
+        analysed to a degree-p expansion: the on-surface value anywhere."""
+        key = ("selfcoef", j, kind, hash(np.asarray(dens).tobytes()))
+        if key not in self._cache:
+            dj = self.drops[j]
+            v = singular(dj.p, dj.xc, dens, kind, None, self.opt.U_sing * dj.p)
+            self._cache[key] = np.stack([analyze(v[:, c], dj.p, dj.p) for c in range(3)])
+        return self._cache[key]
+
+    def nearest_value(self, j, dens, kind, x0):
+        """Layer potential of drop j at x0 in its nearest region (Sec. 2.3):
+        closest point x*, the exterior limit at x* from the self-interaction
+        expansion (the double layer jumps by -4 pi u(x*) from its on-surface
+        value to the exterior side), regular-rule values at x_l = x* + h sqrt(l) d
+        (d the unit vector from x* to x0), and Lagrange interpolation in the
+        distance along d."""
+        dj = self.drops[j]
+        th, ph, xs, _ = self.closest(j, x0)
+        dvec = np.asarray(x0) - xs
+        s0 = np.linalg.norm(dvec)
+        d = dvec / s0
+        sc = self.self_coefficients(j, dens, kind)
+        v0 = np.array([eval_point_d(dj.p, sc[c], th, ph) for c in range(3)])
+        if kind == 1:
+            u = np.asarray(dens).reshape(3, -1, 2)
+            v0 = v0 - 4.0 * np.pi * np.array([eval_point_d(dj.p, u[c], th, ph) for c in range(3)])
+        hj = self.h(j)
+        L = self.opt.near_L
+        sl = hj * np.sqrt(np.arange(1, L + 1))
+        xl = xs[None, :] + sl[:, None] * d[None, :]
+        dist = min_node_distance(dj.p, dj.xc, xl)
+        vals = np.zeros((L, 3))
+        far = dist > self.opt.A_tilde * hj
+        if far.any():
+            vals[far] = regular(dj.p, dj.p, dj.xc, dens, kind, xl[far])
+        if (~far).any():
+            vals[~far] = regular(dj.p, self.opt.U_tilde * dj.p, dj.xc, dens, kind, xl[~far])
+        return lagrange(np.concatenate([[0.0], sl]), np.vstack([v0[None, :], vals]), s0)
 
     def layer(self, i, dens_list, kind, targets=None, weights=None):
         """sum_j weights[j] * (int f.G or int u.T.n over drop j) at targets of drop i."""

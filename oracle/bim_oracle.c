@@ -773,3 +773,123 @@ void orc_min_node_distance(int ps, const double *xc, int nt, const double *x0, d
     }
     free(x);
 }
+
+/* ------------------------------------------------------------------------
+ * Nearest region (Sec. 2.3): closest point on a drop by Newton's method on
+ * the gradient of F = |x(theta, phi) - x0|^2 / 2, with the Levenberg-Marquardt
+ * shift mu I added to the Hessian when a step does not decrease F (the
+ * footnote of Sec. 2.3).
+ * ---------------------------------------------------------------------- */
+
+/* d^dt/dtheta^dt d^dp/dphi^dp of a real field at one point (dt <= 2). */
+double orc_eval_point_d(int p, const double *c, double theta, double phi, int dt, int dp)
+{
+    const int nc = ncoef(p);
+    double *P = malloc(sizeof(double) * 3 * nc);
+    double *D1 = P + nc, *D2 = P + 2 * nc;
+    orc_legendre(p, cos(theta), P);
+    orc_legendre_dtheta(p, cos(theta), P, D1, D2);
+    const double *L = dt == 0 ? P : (dt == 1 ? D1 : D2);
+    double v = 0.0;
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            /* (i m)^dp e^{i m phi} (re + i im), real part */
+            double cr = c[2 * tri(n, m)], ci = c[2 * tri(n, m) + 1];
+            double er = cos(m * phi), ei = sin(m * phi);
+            double zr = cr * er - ci * ei, zi = cr * ei + ci * er;
+            for (int k = 0; k < dp; ++k) {
+                double t = -m * zi;
+                zi = m * zr;
+                zr = t;
+            }
+            v += (m == 0 ? 1.0 : 2.0) * zr * L[tri(n, m)];
+        }
+    free(P);
+    return v;
+}
+
+static void surface_point(int p, const double *xc, double th, double ph, double out[6][3])
+{
+    const int nc2 = 2 * ncoef(p);
+    static const int DT[6] = {0, 1, 0, 2, 1, 0}, DP[6] = {0, 0, 1, 0, 1, 2};
+    for (int f = 0; f < 6; ++f)
+        for (int c = 0; c < 3; ++c) out[f][c] = orc_eval_point_d(p, xc + c * nc2, th, ph, DT[f], DP[f]);
+}
+
+/* Closest point of drop (p, xc) to x0 from the start (th0, ph0). Returns the
+ * number of iterations; res = {theta, phi, x*[3]}. */
+int orc_closest_point(int p, const double *xc, const double *x0, double th0, double ph0, double *res)
+{
+    double th = th0, ph = ph0, mu = 0.0;
+    double S[6][3];
+    surface_point(p, xc, th, ph, S);
+    double r[3] = {S[0][0] - x0[0], S[0][1] - x0[1], S[0][2] - x0[2]};
+    double F = 0.5 * dot3(r, r);
+    int it = 0, converged = 0;
+    for (; it < 100 && !converged; ++it) {
+        const double g0 = dot3(r, S[1]), g1 = dot3(r, S[2]);
+        const double H00 = dot3(S[1], S[1]) + dot3(r, S[3]);
+        const double H01 = dot3(S[1], S[2]) + dot3(r, S[4]);
+        const double H11 = dot3(S[2], S[2]) + dot3(r, S[5]);
+        const double scale = dot3(S[1], S[1]) + dot3(S[2], S[2]);
+        int accepted = 0;
+        for (int tries = 0; tries < 40 && !accepted; ++tries) {
+            const double a = H00 + mu * scale, b = H01, d = H11 + mu * scale;
+            const double det = a * d - b * b;
+            if (!(det > 0.0) || !(a > 0.0)) {  /* not a descent system: raise the shift */
+                mu = mu == 0.0 ? 1e-6 : 10.0 * mu;
+                continue;
+            }
+            const double s0 = -(d * g0 - b * g1) / det, s1 = -(a * g1 - b * g0) / det;
+            double Sn[6][3];
+            surface_point(p, xc, th + s0, ph + s1, Sn);
+            double rn[3] = {Sn[0][0] - x0[0], Sn[0][1] - x0[1], Sn[0][2] - x0[2]};
+            const double Fn = 0.5 * dot3(rn, rn);
+            /* near the minimum F changes by less than its rounding: take the
+             * small Newton steps without the decrease test */
+            const int local = mu == 0.0 && fabs(s0) + fabs(s1) < 1e-8;
+            if (Fn <= F || local) {
+                th += s0;
+                ph += s1;
+                memcpy(S, Sn, sizeof(S));
+                memcpy(r, rn, sizeof(r));
+                F = Fn;
+                mu = mu * 0.1 < 1e-12 ? 0.0 : mu * 0.1;
+                accepted = 1;
+                converged = fabs(s0) + fabs(s1) < 1e-15;
+            } else {
+                mu = mu == 0.0 ? 1e-6 : 10.0 * mu;
+            }
+        }
+        if (!accepted) break;  /* no decrease at any shift: at the minimum to rounding */
+    }
+    res[0] = th;
+    res[1] = ph;
+    res[2] = S[0][0];
+    res[3] = S[0][1];
+    res[4] = S[0][2];
+    return it;
+}
+
+/* Index of the nearest node of the degree-ps grid of a drop to each target. */
+void orc_nearest_node(int ps, const double *xc, int nt, const double *x0, int *idx)
+{
+    double *x = malloc(sizeof(double) * 3 * (ps + 1) * 2 * ps);
+    orc_geometry(ps, xc, ps, x, NULL, NULL, NULL);
+    const int nn = (ps + 1) * 2 * ps;
+#pragma omp parallel for schedule(static)
+    for (int it = 0; it < nt; ++it) {
+        double best = INFINITY;
+        int bi = 0;
+        for (int i = 0; i < nn; ++i) {
+            double h[3] = {x0[3 * it] - x[i], x0[3 * it + 1] - x[nn + i], x0[3 * it + 2] - x[2 * nn + i]};
+            double r = dot3(h, h);
+            if (r < best) {
+                best = r;
+                bi = i;
+            }
+        }
+        idx[it] = bi;
+    }
+    free(x);
+}

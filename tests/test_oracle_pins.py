@@ -526,3 +526,88 @@ def test_regions_two_spheres(orc):
     assert np.all(reg[dist > 5 * h] == 0) and np.all(reg[(dist <= 5 * h) & (dist > h)] == 1)
     assert np.all(reg[dist <= h] == 2)
     assert reg[np.argmax(x[:, 0])] != 0 and reg[np.argmin(x[:, 0])] == 0
+
+
+# --- nearest region (Sec. 2.3) ---------------------------------------------------
+
+def test_lagrange_interpolation_exact_for_polynomials(orc):
+    rng = np.random.default_rng(5)
+    s = np.concatenate([[0.0], 0.2 * np.sqrt(np.arange(1, 9))])
+    coef = rng.standard_normal(9)
+    vals = np.polyval(coef, s)
+    for x in (0.0, 0.013, 0.11, 0.5):
+        assert abs(orc.lagrange(s, vals[:, None], x)[0] - np.polyval(coef, x)) < 1e-12
+
+
+def test_closest_point_on_sphere_and_optimality_on_perturbed_drop(orc):
+    rng = np.random.default_rng(8)
+    p = 12
+    c = np.array([0.2, -0.1, 0.3])
+    sys_ = orc.System([orc.Drop(p, W.sphere(p, 1.3, c), 1.0)])
+    for _ in range(4):
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        th, ph, xs, it = sys_.closest(0, c + (1.3 + 0.04) * e)
+        assert np.abs(xs - (c + 1.3 * e)).max() < 1e-13
+    # perturbed drop: the gradient of |x - x0|^2 vanishes at x*, and x* is no
+    # farther than the nearest grid node
+    xc = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.1)
+    sys_ = orc.System([orc.Drop(p, xc, 1.0)])
+    x = sys_.nodes(0)
+    for k in (3, 77, 200):
+        n_out = x[k] / np.linalg.norm(x[k])
+        x0 = x[k] + 0.05 * n_out + 0.01 * rng.standard_normal(3)
+        th, ph, xs, it = sys_.closest(0, x0)
+        r = xs - x0
+        xt = np.array([orc.eval_point_d(p, xc[cc], th, ph, 1, 0) for cc in range(3)])
+        xp = np.array([orc.eval_point_d(p, xc[cc], th, ph, 0, 1) for cc in range(3)])
+        assert abs(r @ xt) < 1e-13 and abs(r @ xp) < 1e-13
+        assert np.linalg.norm(r) <= np.linalg.norm(x - x0, axis=1).min() + 1e-15
+
+
+def test_nearest_region_rule_on_sphere_closed_forms(orc):
+    """Constant density on a unit sphere at targets 0.05h and 0.3h outside:
+    the single layer matches the exterior closed form and the double layer
+    vanishes (which pins the -4 pi u jump to the exterior limit), to 1e-5;
+    the plain 4x-upsampled rule is far off at these distances."""
+    p = 16
+    xc = W.sphere(p)
+    s = orc.System([orc.Drop(p, xc, 1.0)], orc.Options(near_rule=1))
+    f = np.zeros((3, orc.ncoef(p), 2))
+    fv = np.array([0.3, -0.5, 0.8])
+    f[:, 0, 0] = fv * np.sqrt(4 * np.pi)
+    e = np.array([0.48, -0.6, 0.64])
+    h = s.h(0)
+    for frac in (0.05, 0.3):
+        x0 = (1.0 + frac * h) * e
+        r = np.linalg.norm(x0)
+        G = np.eye(3) / r + np.outer(x0, x0) / r ** 3
+        ex = (4 * np.pi * G + (4 * np.pi / 3) * (np.eye(3) / r ** 3 - 3 * np.outer(x0, x0) / r ** 5)) @ fv
+        v = s.nearest_value(0, f, 0, x0)
+        assert np.abs(v - ex).max() <= 1e-5 * np.abs(ex).max()
+        reg = orc.regular(p, 4 * p, xc, f, 0, x0[None, :])[0]
+        assert np.abs(reg - ex).max() > (100 if frac < 0.1 else 3) * np.abs(v - ex).max()
+        vd = s.nearest_value(0, f, 1, x0)
+        assert np.abs(vd).max() <= 1e-5
+
+
+def test_two_close_spheres_rigid_motion_with_nearest_region_rule(orc):
+    """Two unit spheres 0.05 apart (about h/5 at p = 12): a constant density
+    has exterior double layer 0, so the double layer at every grid target is
+    the on-surface value 4 pi e of its own sphere. With the nearest-region
+    rule the Omega_2 targets meet it to 1e-5; the Omega_1 rule misses by O(1)."""
+    p = 12
+    drops = [orc.Drop(p, W.sphere(p, 1.0, (0, 0, 0)), 2.0), orc.Drop(p, W.sphere(p, 1.0, (2.05, 0, 0)), 2.0)]
+    e = np.array([0.2, -0.7, 0.4])
+    u = np.zeros((3, orc.ncoef(p), 2))
+    u[:, 0, 0] = e * np.sqrt(4 * np.pi)
+    errs = {}
+    for rule in (0, 1):
+        s = orc.System(drops, orc.Options(near_rule=rule, A_tilde=5.0, U_tilde=4))
+        reg, _ = s.regions(0, 1)
+        tg = np.nonzero(reg == 2)[0]
+        assert len(tg) > 0
+        v = s.layer(0, [u, u], 1, targets=tg)
+        errs[rule] = np.abs(v - 4 * np.pi * e).max()
+    assert errs[1] <= 1e-5 * 4 * np.pi
+    assert errs[0] > 1e3 * errs[1]
