@@ -83,6 +83,13 @@ typedef struct {
                             1: rotation and quadrature on every application (no matrix);
                             2: one fused workgroup per target (stored matrix as in 0) */
     void *stream;        /* hipStream_t to run on; NULL = the context creates its own */
+    int near_rule;       /* targets in Omega_2 (nearest node of another drop within h, Sec. 2.3):
+                            0: the Omega_1 rule (upsampled regular quadrature);
+                            1: the special quadrature of Sec. 2.3 (closest point by damped Newton,
+                               on-surface value from the source drop's self-interaction expansion,
+                               exterior limit for the double layer, regular values at
+                               x* + h sqrt(l) d, l = 1..near_L, Lagrange interpolation) */
+    int near_L;          /* interpolation points of the special quadrature, 2..16 (paper: 8) */
 } bim_options;
 
 typedef struct {
@@ -90,7 +97,7 @@ typedef struct {
     double gmres_residual;    /* final relative residual */
     int n_targets;            /* grid targets over all drops */
     int n_omega1;             /* (target, source drop) pairs in Omega_1 */
-    int n_omega2;             /* pairs in Omega_2 (evaluated with the Omega_1 rule) */
+    int n_omega2;             /* pairs in Omega_2 (near_rule selects their quadrature) */
     int n_matvec;             /* operator applications in the solve */
     double ms_total;          /* wall time of the call */
 } bim_report;
@@ -101,7 +108,7 @@ int bim_version(void);
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
- * stream NULL. */
+ * stream NULL, near_rule 0, near_L 8. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */

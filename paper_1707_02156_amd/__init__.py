@@ -38,6 +38,8 @@ class bim_options(ctypes.Structure):
         ("gmres_maxit", ctypes.c_int),
         ("singular_path", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("near_rule", ctypes.c_int),
+        ("near_L", ctypes.c_int),
     ]
 
 

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbim.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["tables.cpp", "kernels.hip", "kernels_sing.hip", "kernels_pipe.hip", "kernels_xform.hip", "bim.hip"]
+SOURCES = ["tables.cpp", "kernels.hip", "kernels_sing.hip", "kernels_pipe.hip", "kernels_xform.hip", "kernels_near.hip",
+           "bim.hip"]
 ARCH = os.environ.get("BIM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -50,6 +50,9 @@ void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, co
 void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
                      const double *wsing, const double *cs, double *out, long ostride, double scale);
 int pair_sources_per_item();
+void launch_near_setup(hipStream_t st, const NearArgs &a);
+void launch_near_interp(hipStream_t st, const NearArgs &a, int kind, const double *selfc, const double *dens,
+                        const double *vacc, const double *wts, double *out);
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
                  long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride);
 struct SingArgs {
@@ -222,10 +225,20 @@ struct Ctx {
         DBuf d;
         int n = 0;
         double pairs = 0.0;  // target-source pairs per application
+        DBuf nw;             // weight of each nearest-region item
     };
     std::vector<std::unique_ptr<WList>> wlists;
     std::vector<int8_t> reg_h;
     int n_om1 = 0, n_om2 = 0;
+    // nearest-region items (near_rule 1) and their interpolation points
+    std::vector<NearItem> near_h;
+    std::vector<char> near_src;                 // drops that are the source of an item
+    DBuf near_items, near_par, near_vx, near_vreg, near_Pst, near_vacc, near_self, near_selfc;
+    DBuf near_dp, near_dcoff, near_dtoff, near_glt, near_gloff;
+    DBuf near_work, near_tl;
+    int near_nwork = 0;
+    long near_ldp = 0;
+    double near_pairs = 0.0;
     DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
     DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
@@ -606,6 +619,125 @@ static void build_force(Ctx &c)
 }
 
 // Regions and pair work lists (Sec. 2.3).
+// Nearest-region items: closest points, interpolation points and their grids
+// (one device pass), then the work list of the interpolation points against
+// the source drop of each item (standard or upsampled grid).
+static NearArgs near_args(Ctx &c)
+{
+    NearArgs a{};
+    a.items = c.near_items.as<NearItem>();
+    a.n = (int)c.near_h.size();
+    a.dp = c.near_dp.as<int>();
+    a.dcoff = c.near_dcoff.as<long>();
+    a.dtoff = c.near_dtoff.as<int>();
+    a.hj = c.hj.d();
+    a.xc = c.xc.d();
+    a.Ctot = c.Ctot;
+    a.tx = c.tx.d();
+    a.T = c.T;
+    a.gl_t = c.near_glt.d();
+    a.gl_off = c.near_gloff.as<int>();
+    a.L = c.opt.near_L;
+    a.A = c.opt.A_tilde;
+    a.par = c.near_par.d();
+    a.vx = c.near_vx.d();
+    a.V = (long)a.n * a.L;
+    a.vreg = c.near_vreg.as<int8_t>();
+    a.Pst = c.near_Pst.d();
+    a.ldp = c.near_ldp;
+    return a;
+}
+
+static void near_setup(Ctx &c)
+{
+    c.near_src.assign(c.nd, 0);
+    c.near_nwork = 0;
+    c.near_pairs = 0.0;
+    const int n = (int)c.near_h.size();
+    if (n == 0) return;
+    for (const NearItem &it : c.near_h) c.near_src[it.j] = 1;
+    const int L = c.opt.near_L;
+    const long V = (long)n * L;
+    int pmax = 0;
+    std::vector<int> dp(c.nd), dtoff(c.nd), gloff(c.nd);
+    std::vector<long> dcoff(c.nd);
+    std::vector<double> glt;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        dp[i] = d.p;
+        dtoff[i] = (int)d.toff;
+        dcoff[i] = d.coff;
+        gloff[i] = (int)glt.size();
+        GridTab &g = grid(c, d.p, d.p);
+        glt.insert(glt.end(), g.t.begin(), g.t.end());
+        pmax = std::max(pmax, d.p);
+    }
+    REQUIRE(pmax <= 63, BIM_EINVAL, "the nearest-region rule supports degrees up to 63");
+    c.near_ldp = ncoef(pmax);
+    c.near_items.ensure(n * sizeof(NearItem));
+    c.near_dp.ensure(c.nd * sizeof(int));
+    c.near_dtoff.ensure(c.nd * sizeof(int));
+    c.near_gloff.ensure(c.nd * sizeof(int));
+    c.near_dcoff.ensure(c.nd * sizeof(long));
+    c.near_glt.ensure(glt.size() * sizeof(double));
+    c.near_par.ensure((size_t)n * 4 * sizeof(double));
+    c.near_vx.ensure((size_t)3 * V * sizeof(double));
+    c.near_vreg.ensure((size_t)V);
+    c.near_Pst.ensure((size_t)n * c.near_ldp * sizeof(double));
+    c.near_vacc.ensure((size_t)3 * V * sizeof(double));
+    c.near_self.ensure((size_t)3 * c.T * sizeof(double));
+    c.near_selfc.ensure((size_t)3 * c.Ctot * sizeof(double));
+    HIPC(hipMemcpyAsync(c.near_items.ptr, c.near_h.data(), n * sizeof(NearItem), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(c.near_dp.ptr, dp.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(c.near_dtoff.ptr, dtoff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(c.near_gloff.ptr, gloff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(c.near_dcoff.ptr, dcoff.data(), c.nd * sizeof(long), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(c.near_glt.ptr, glt.data(), glt.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    launch_near_setup(c.stream, near_args(c));
+    std::vector<int8_t> vreg(V);
+    HIPC(hipMemcpyAsync(vreg.data(), c.near_vreg.ptr, V, hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    // work list: interpolation points grouped by (source drop, grid)
+    const int TILE = 64, CH = pair_sources_per_item();
+    std::vector<int> tl;
+    std::vector<PairWork> w;
+    for (int j = 0; j < c.nd; ++j) {
+        if (!c.near_src[j]) continue;
+        const Drop &dj = c.drops[j];
+        for (int g = 0; g < 2; ++g) {
+            const int start = (int)tl.size();
+            for (int it = 0; it < n; ++it) {
+                if (c.near_h[it].j != j) continue;
+                for (int l = 0; l < L; ++l)
+                    if (vreg[(long)it * L + l] == g) tl.push_back(it * L + l);
+            }
+            const int cnt = (int)tl.size() - start;
+            const long soff = g == 0 ? dj.toff : dj.uoff;
+            const int ns = g == 0 ? npts(dj.p) : npts(dj.qu);
+            for (int a = 0; a < cnt; a += TILE)
+                for (int b = 0; b < ns; b += CH) {
+                    PairWork pw;
+                    pw.tlist_off = start + a;
+                    pw.ntgt = std::min(TILE, cnt - a);
+                    pw.src_off = (int)(soff + b);
+                    pw.nsrc = std::min(CH, ns - b);
+                    pw.pair = j;
+                    pw.pad = g;
+                    pw.w = 1.0;
+                    w.push_back(pw);
+                    c.near_pairs += (double)pw.ntgt * pw.nsrc;
+                }
+        }
+    }
+    c.near_tl.ensure(std::max<size_t>(1, tl.size()) * sizeof(int));
+    c.near_work.ensure(std::max<size_t>(1, w.size()) * sizeof(PairWork));
+    if (!tl.empty())
+        HIPC(hipMemcpy(c.near_tl.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!w.empty())
+        HIPC(hipMemcpy(c.near_work.ptr, w.data(), w.size() * sizeof(PairWork), hipMemcpyHostToDevice));
+    c.near_nwork = (int)w.size();
+}
+
 static void build_regions(Ctx &c)
 {
     if (c.regions_ok) return;
@@ -650,6 +782,7 @@ static void build_regions(Ctx &c)
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
     std::vector<int> tl;
     std::vector<PairWork> w0, w1;
+    std::vector<NearItem> near;
     const int TILE = 64, CH = pair_sources_per_item();
     c.n_om1 = c.n_om2 = 0;
     for (int i = 0; i < c.nd; ++i) {
@@ -662,9 +795,11 @@ static void build_regions(Ctx &c)
                 const int start = (int)tl.size();
                 for (int t = 0; t < nti; ++t) {
                     const int8_t r = c.reg_h[(di.toff + t) * c.nd + j];
-                    if ((kind == 0) == (r == 0)) tl.push_back((int)(di.toff + t));
+                    const bool special = r == 2 && c.opt.near_rule == 1;
+                    if ((kind == 0) == (r == 0) && !special) tl.push_back((int)(di.toff + t));
                     if (kind == 1 && r == 1) ++c.n_om1;
                     if (kind == 1 && r == 2) ++c.n_om2;
+                    if (kind == 1 && special) near.push_back(NearItem{(int)(di.toff + t), i, j, 0});
                 }
                 const int cnt = (int)tl.size() - start;
                 const long soff = kind == 0 ? dj.toff : dj.uoff;
@@ -691,6 +826,8 @@ static void build_regions(Ctx &c)
     c.w0h = std::move(w0);
     c.w1h = std::move(w1);
     c.wlists.clear();
+    c.near_h = std::move(near);
+    near_setup(c);
     c.regions_ok = true;
 }
 
@@ -716,6 +853,12 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
     if (!keep.empty())
         HIPC(hipMemcpy(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice));
     e->n = (int)keep.size();
+    if (!c.near_h.empty()) {
+        std::vector<double> nw(c.near_h.size());
+        for (size_t it = 0; it < nw.size(); ++it) nw[it] = wt[(size_t)c.near_h[it].i * c.nd + c.near_h[it].j];
+        e->nw.ensure(nw.size() * sizeof(double));
+        HIPC(hipMemcpy(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     c.wlists.push_back(std::move(e));
     return *c.wlists.back();
 }
@@ -730,6 +873,31 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
     launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T);
+}
+
+// Nearest-region items (Sec. 2.3): the self-interaction grids of their source
+// drops (in near_self) analysed, the regular rule at the interpolation points,
+// then interpolation to the targets, weighted and added into acc.
+static void run_near(Ctx &c, int kind, const double *dens, const std::vector<double> &wt)
+{
+    if (c.near_h.empty()) return;
+    Ctx::WList &L = work_lists(c, wt);
+    std::vector<AnaJob> jobs;
+    for (int j = 0; j < c.nd; ++j) {
+        if (!c.near_src[j]) continue;
+        const Drop &d = c.drops[j];
+        jobs.push_back(ana_job(c, d.p, d.p, 3, c.near_self.d() + d.toff, c.T, c.near_selfc.d() + d.coff, c.Ctot));
+    }
+    ana_run(c, jobs);
+    const long V = (long)c.near_h.size() * c.opt.near_L;
+    HIPC(hipMemsetAsync(c.near_vacc.ptr, 0, 3 * V * sizeof(double), c.stream));
+    const double fpp = kind == 0 ? 29.0 : 30.0;
+    ProfScope ps(c, "near", c.near_pairs * fpp, 0.0);
+    const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
+    const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
+    launch_pair(c.stream, kind, c.near_nwork, c.near_work.as<PairWork>(), c.near_tl.as<int>(), c.near_vx.d(), V, g0,
+                g1, c.near_vacc.d(), V);
+    launch_near_interp(c.stream, near_args(c), kind, c.near_selfc.d(), dens, c.near_vacc.d(), L.nw.d(), c.acc.d());
 }
 
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
@@ -749,7 +917,7 @@ static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &n
 // Singular self-integral of drop i with density coefficients dens [3][Ctot]
 // (kind 0 SL, 1 DL), added into acc with the given scale: rotation of the
 // expansion per target, then the fused quadrature (per-application path).
-static void run_singular(Ctx &c, int i, int kind, const double *dens, double scale)
+static void run_singular(Ctx &c, int i, int kind, const double *dens, double scale, double *out = nullptr)
 {
     const Drop &d = c.drops[i];
     RotTab &r = rot(c, d.p);
@@ -765,7 +933,7 @@ static void run_singular(Ctx &c, int i, int kind, const double *dens, double sca
     {
         ProfScope ps(c, "sing_v1", 0.0, 0.0);
         launch_singular(c.stream, d.p, d.qs, kind, c.Rbuf.d(), gs.L.d(), (int)nc, gs.wsing.d(), gs.cs.d(),
-                        c.acc.d() + d.toff, c.T, scale);
+                        (out ? out : c.acc.d()) + d.toff, c.T, scale);
     }
 }
 
@@ -974,16 +1142,22 @@ static std::vector<double> dl_weights(const Ctx &c)
 static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<double> &wt)
 {
     build_regions(c);
-    std::vector<char> need(c.nd, 0);
+    std::vector<char> need(c.nd, 0), selfraw(c.nd, 0);
     for (int j = 0; j < c.nd; ++j)
         for (int i = 0; i < c.nd; ++i)
             if (wt[(size_t)i * c.nd + j] != 0.0) need[j] = 1;
+    for (const NearItem &it : c.near_h)
+        if (wt[(size_t)it.i * c.nd + it.j] != 0.0) selfraw[it.j] = 1;
     HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
+    if (!c.near_h.empty()) HIPC(hipMemsetAsync(c.near_self.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     density_nodes(c, ucoef, need);
     for (int i = 0; i < c.nd; ++i) {
         const double w = wt[(size_t)i * c.nd + i];
-        if (w == 0.0) continue;
+        if (w == 0.0 && !selfraw[i]) continue;
         const Drop &d = c.drops[i];
+        // the raw self-interaction goes to near_self when an item interpolates from it
+        double *dst = selfraw[i] ? c.near_self.d() : c.acc.d();
+        const double ws = selfraw[i] ? 1.0 : w;
         if (use_pipe(c, d) || use_fused(c, d, false, true)) {
             if (!dl_matrix_ready(c, i)) {
                 if (use_pipe(c, d)) run_pipe(c, i, false, true, nullptr);
@@ -992,14 +1166,19 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
             {
                 const double nt = npts(d.p), nc2 = 2.0 * ncoef(d.p);
                 ProfScope ps(c, "dl_apply", nt * 18.0 * nc2, nt * 6.0 * nc2 * 8.0 + 3.0 * nc2 * 8.0);
-                launch_dl_apply(c.stream, npts(d.p), 2 * ncoef(d.p), c.Mdl[i]->d(), ucoef + d.coff, c.Ctot, w,
-                                c.acc.d() + d.toff, c.T);
+                launch_dl_apply(c.stream, npts(d.p), 2 * ncoef(d.p), c.Mdl[i]->d(), ucoef + d.coff, c.Ctot, ws,
+                                dst + d.toff, c.T);
             }
         } else {
-            run_singular(c, i, 1, ucoef, w);
+            run_singular(c, i, 1, ucoef, ws, dst);
         }
+        if (selfraw[i] && w != 0.0)
+            for (int cc = 0; cc < 3; ++cc)
+                launch_scale_add(c.stream, npts(d.p), w, c.near_self.d() + cc * c.T + d.toff, 1.0,
+                                 c.acc.d() + cc * c.T + d.toff);
     }
     run_pairs(c, 1, wt);
+    run_near(c, 1, ucoef, wt);
 }
 
 // Single layer of fcoef at all targets into acc. with_dl[i] also builds the
@@ -1023,8 +1202,11 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
             run_singular(c, i, 0, fcoef, 1.0);
         }
     }
+    if (!c.near_h.empty())
+        HIPC(hipMemcpyAsync(c.near_self.ptr, c.acc.ptr, 3 * c.T * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
     std::vector<double> wt((size_t)c.nd * c.nd, 1.0);
     run_pairs(c, 0, wt);
+    run_near(c, 0, fcoef, wt);
 }
 
 // analysis of grid vectors [3][T] into coefficients [3][Ctot]
@@ -1260,6 +1442,8 @@ int bim_default_options(bim_options *o)
     o->gmres_maxit = 500;
     o->singular_path = 0;
     o->stream = nullptr;
+    o->near_rule = 0;
+    o->near_L = 8;
     return BIM_OK;
 }
 
@@ -1269,7 +1453,8 @@ int bim_create(const bim_options *opt, bim_ctx *out)
     *out = nullptr;
     if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
-        (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2))
+        (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
+        (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL)
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {

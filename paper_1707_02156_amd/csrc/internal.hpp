@@ -45,6 +45,36 @@ struct GivensArgs {
     double bnorm = 1.0;
 };
 
+// Nearest-region items: a grid target t (global index) of drop i whose
+// nearest node of source drop j is within h_j.
+struct NearItem {
+    int t, i, j, pad;
+};
+constexpr int kNearMaxL = 16;  // interpolation points per item, at most
+
+struct NearArgs {
+    const NearItem *items;
+    int n;                      // items
+    const int *dp;              // degree per drop
+    const long *dcoff;          // coefficient offset per drop (inside a component block)
+    const int *dtoff;           // first standard-grid node per drop
+    const double *hj;           // h per drop
+    const double *xc;           // drop coefficients [3][Ctot]
+    long Ctot;
+    const double *tx;           // standard-grid nodes (= grid targets) [3][T]
+    long T;
+    const double *gl_t;         // Gauss-Legendre nodes cos(theta_j) of each drop's grid
+    const int *gl_off;          // per drop: first entry in gl_t
+    int L;                      // interpolation points
+    double A;                   // Omega_1 threshold in units of h
+    double *par;                // per item: theta*, phi*, |x0 - x*|, nearest node
+    double *vx;                 // interpolation points [3][V], V = n L
+    long V;
+    int8_t *vreg;               // their grid: 0 standard, 1 upsampled
+    double *Pst;                // Ptilde_n^m(cos theta*) per item, stride ldp
+    long ldp;
+};
+
 // One source grid for the pair sums: component-major arrays [3][stride].
 struct PairSrc {
     const double *x, *wN, *wW, *d;
