@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 BOUND = {"sing_fused": "alu", "pair_sl": "alu", "pair_dl": "alu", "dl_apply": "hbm",
          "synthesis": "hbm", "analysis": "hbm", "sing_v1": "alu", "sing_rotate": "alu", "classify": "alu",
-         "pipe_rotate": "alu", "pipe_legendre": "hbm", "pipe_fourier": "alu", "pipe_adjrot": "alu"}
+         "pipe_rotate": "alu", "pipe_legendre": "hbm", "pipe_fourier": "alu", "pipe_adjrot": "alu", "near": "alu"}
 KERNELS = list(BOUND)
 
 

@@ -108,7 +108,7 @@ int bim_version(void);
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
- * stream NULL, near_rule 0, near_L 8. */
+ * stream NULL, near_rule 1, near_L 8. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */
@@ -190,7 +190,8 @@ int bim_synchronize(bim_ctx ctx);
  * "pipe_adjrot" (batched singular pipeline), "sing_fused" (fused singular
  * rule), "sing_rotate" and "sing_v1" (per-application singular path),
  * "dl_apply" (stored double layer times a density), "pair_sl", "pair_dl"
- * (pair sums), "synthesis", "analysis", "classify". Each timed launch adds an
+ * (pair sums), "near" (nearest-region interpolation points and
+ * interpolation), "synthesis", "analysis", "classify". Each timed launch adds an
  * event pair to the stream, which delays the next launch by a few
  * microseconds; bim_profile_select limits timing to chosen kernels. */
 int bim_profile(bim_ctx ctx, int enable);

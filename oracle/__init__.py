@@ -298,7 +298,7 @@ class Options:
     U0: tuple = (0.0, 0.0, 0.0)
     gradU: tuple = (0.0,) * 9
     lambda_rule: int = 0      # 0: source-drop lambda_j, 1: target-drop lambda_i
-    near_rule: int = 0        # Omega_2 targets: 0 the Omega_1 rule, 1 the special quadrature of Sec. 2.3
+    near_rule: int = 1        # Omega_2 targets: 0 the Omega_1 rule, 1 the special quadrature of Sec. 2.3
     near_L: int = 8           # interpolation points x_l = x* + h sqrt(l) d, l = 1..L (Sec. 5: L = 8)
     gmres_tol: float = 1e-10
     gmres_restart: int = 50

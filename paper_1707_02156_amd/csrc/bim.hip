@@ -1442,7 +1442,7 @@ int bim_default_options(bim_options *o)
     o->gmres_maxit = 500;
     o->singular_path = 0;
     o->stream = nullptr;
-    o->near_rule = 0;
+    o->near_rule = 1;
     o->near_L = 8;
     return BIM_OK;
 }

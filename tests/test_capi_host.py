@@ -37,7 +37,7 @@ def test_status_strings_and_defaults(B):
     o = B.bim_default_options()
     assert o.A_tilde == 5.0 and o.U_tilde == 4 and o.U_sing == 1 and o.U_geom == 2
     assert o.gmres_tol == 1e-10 and o.gmres_restart == 50 and o.precision == B.BIM_PREC_FP64
-    assert o.near_rule == 0 and o.near_L == 8
+    assert o.near_rule == 1 and o.near_L == 8
 
 
 def test_invalid_options_rejected_without_device(B):

@@ -71,21 +71,43 @@ def sphere(p: int, R: float = 1.0, c=(0.0, 0.0, 0.0)) -> np.ndarray:
     return xc
 
 
+def _draw_layout(p: int, lmin: int):
+    """Destinations of the normal draws of one component, in draw order:
+    for l = lmin..p: (l, 0) real, then (l, m) real and imaginary for m = 1..l."""
+    key = (p, lmin)
+    if key not in _LAYOUT:
+        idx, part, lv = [], [], []
+        for l in range(lmin, p + 1):
+            idx.append(idx_(l, 0)); part.append(0); lv.append(l)
+            for m in range(1, l + 1):
+                idx += [idx_(l, m), idx_(l, m)]; part += [0, 1]; lv += [l, l]
+        _LAYOUT[key] = (np.array(idx), np.array(part), np.array(lv, dtype=float))
+    return _LAYOUT[key]
+
+
+_LAYOUT = {}
+
+
+def idx_(n: int, m: int) -> int:
+    return n * (n + 1) // 2 + m
+
+
 def perturbation(rng: np.random.Generator, p: int, A: float, lmin: int = 2, power: float = 3.0) -> np.ndarray:
     """Random coefficients N(0,1) A l^-power for lmin <= l <= p on each Cartesian
     component; m = 0 real, m > 0 complex with Re and Im each of variance
     (A l^-power)^2 / 2; Im at m = p zero so the field is representable on the
-    degree-p grid."""
+    degree-p grid. Draw order: component, then l, then (m = 0), (m, Re, Im)."""
     d = np.zeros((3, ncoef(p), 2))
+    ii, pp, lv = _draw_layout(p, lmin)
+    if len(ii) == 0:
+        return d
+    scale = A * lv ** (-power)
+    half = ii != np.array([idx_(int(l), 0) for l in lv])
     for k in range(3):
-        for l in range(lmin, p + 1):
-            s = A * l ** (-power)
-            d[k, idx(l, 0), 0] = rng.standard_normal() * s
-            for m in range(1, l + 1):
-                d[k, idx(l, m), 0] = rng.standard_normal() * s / np.sqrt(2.0)
-                d[k, idx(l, m), 1] = rng.standard_normal() * s / np.sqrt(2.0)
-                if m == p:
-                    d[k, idx(l, m), 1] = 0.0
+        z = rng.standard_normal(len(ii)) * scale
+        z[half] = z[half] / np.sqrt(2.0)
+        d[k, ii, pp] = z
+    d[:, idx_(p, p), 1] = 0.0 if p >= lmin else d[:, idx_(p, p), 1]
     return d
 
 
@@ -102,12 +124,10 @@ def perturbation_bound(d: np.ndarray) -> float:
     (3, ncoef, 2): per component, the sum of coefficient moduli (doubled for
     m > 0) times the sup norm sqrt((2l+1)/4pi) of the basis function."""
     p = int(round((np.sqrt(8 * d.shape[1] + 1) - 3) / 2))
-    tot = np.zeros(3)
-    for k in range(3):
-        for l in range(0, p + 1):
-            sup = np.sqrt((2 * l + 1) / (4 * np.pi))
-            for m in range(0, l + 1):
-                tot[k] += (1.0 if m == 0 else 2.0) * np.hypot(*d[k, idx(l, m)]) * sup
+    n = np.concatenate([[l] * (l + 1) for l in range(p + 1)])
+    m = np.concatenate([np.arange(l + 1) for l in range(p + 1)])
+    w = np.where(m == 0, 1.0, 2.0) * np.sqrt((2 * n + 1) / (4 * np.pi))
+    tot = (np.hypot(d[..., 0], d[..., 1]) * w).sum(axis=1)
     return float(np.sqrt(np.sum(tot ** 2)))
 
 
@@ -288,3 +308,39 @@ def deformed_drops(npairs=8, p=48, eps=4.0 / 9.0, A=0.05, gap=0.1, spacing=8.0, 
     return Workload(name=f"deformed_drops_n{2 * npairs}_p{p}", drops=drops, eos=1, E=0.5, xs=0.6, A_tilde=5.0,
                     U_tilde=4, gmres_tol=1e-10,
                     notes="P2 spheroids eps 4/9 (D = 0.3), pairs 0.1 apart (noise-free), lambda 3")
+
+
+@dataclass
+class Request:
+    arrival: float          # seconds after the start of the stream (rate 1; scale by 1 / rate)
+    drops: list             # DropSpec list
+    p: int
+
+
+def serving_requests(n=2048, A=0.05, gap=0.2, seed=4):
+    """A stream of n independent drop systems with Poisson arrivals (unit rate:
+    exponential gaps of mean 1, to be divided by the target rate). Each has
+    N_d ~ U{1..8} drops of one degree p ~ U{8, 16, 24, 32}, unit radius, N(0,1)
+    0.05 l^-3 perturbations, lambda per drop ~ U{1, 2, 5}, centres by random
+    sequential addition in a cube of side 4 N_d^(1/3) + 2 with bounding-sphere
+    gap >= 0.2; uniform tension 1."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += rng.exponential(1.0)
+        nd = int(rng.integers(1, 9))
+        p = int(rng.choice([8, 16, 24, 32]))
+        perts = [perturbation(rng, p, A) for _ in range(nd)]
+        bounds = [1.0 + perturbation_bound(d) for d in perts]
+        side = 4.0 * nd ** (1.0 / 3.0) + 2.0
+        cs = random_centres(rng, bounds, [0.0] * nd, [side] * nd, gap)
+        lams = rng.choice([1.0, 2.0, 5.0], size=nd)
+        drops = []
+        for i in range(nd):
+            xc = sphere(p) + perts[i]
+            for k in range(3):
+                xc[k, 0, 0] += SQ4PI * cs[i, k]
+            drops.append(DropSpec(p, xc, float(lams[i]), None, cs[i], 1.0))
+        out.append(Request(t, drops, p))
+    return out
