@@ -109,6 +109,89 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"targets alternating drops) in {t_used:.1f} s"}
 
 
+def serve(args):
+    """Serving stream (2048 systems of 1-8 drops, p in {8, 16, 24, 32},
+    lambda in {1, 2, 5}, Poisson arrivals): one-at-a-time capacity of a plain
+    context, then the stream at rate_factor x that capacity through a 1-slot
+    server (one request at a time) and through the slotted server (continuous
+    admission, overlapping requests); p50/p99 arrival-to-finish latency and
+    throughput of each."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1707_02156_amd as B
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    reqs = W.serving_requests(n=args.requests)
+    ctx = B.Context()
+
+    def alone(r):
+        ctx.set_drops([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops])
+        ctx.set_tension(None, 0, sigma0=1.0)
+        return ctx.eval_velocity()[1]
+
+    for r in reqs[:8]:
+        alone(r)
+    sample = reqs[: min(len(reqs), args.capacity_sample)]
+    t0 = time.perf_counter()
+    for r in sample:
+        alone(r)
+    mean_s = (time.perf_counter() - t0) / len(sample)
+    ctx.close()
+    capacity = 1.0 / mean_s
+
+    def stream(slots, rate):
+        srv = B.Server(slots=slots)
+        for r in reqs[:8]:   # warm the contexts' tables
+            srv.wait(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
+        ids, lat, evals = [], [], [0]
+        done = threading.Event()
+
+        def collect():
+            k = 0
+            while k < len(reqs):
+                if k >= len(ids):
+                    time.sleep(0.0005)
+                    continue
+                res = srv.wait(ids[k])
+                u, rep, t = res
+                lat.append(t[2])
+                evals[0] += rep.n_targets * (1 + rep.n_matvec)
+                k += 1
+            done.set()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        for r in reqs:
+            delay = start + r.arrival / rate - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
+        done.wait()
+        th.join()
+        span = time.perf_counter() - start
+        srv.close()
+        lat = np.array(lat)
+        return {"slots": slots, "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "throughput_req_s": len(reqs) / span,
+                "evals_per_s": evals[0] / span}
+
+    rate = args.rate_factor * capacity
+    runs = [stream(1, rate), stream(args.slots, rate)]
+    for f in (1.5, 2.0):
+        runs.append(stream(args.slots, f * capacity))
+    res = {"metric": "p50/p99 solve latency and throughput of the serving stream", "requests": len(reqs),
+           "capacity_one_at_a_time_req_s": capacity, "mean_service_ms": mean_s * 1e3,
+           "rate_factor": args.rate_factor, "runs": runs, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "serving stream: 1-8 drops, p in {8,16,24,32}, lambda in {1,2,5}, gap >= 0.2, "
+                                  "Poisson arrivals"}}
+    print(json.dumps(res), flush=True)
+
+
 def kernel_frac(name, d):
     """Achieved fraction of the kernel's roofline (algorithmic work / event time)."""
     bound = BOUND[name]
@@ -132,11 +215,20 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the workload, copy a buffer of this size three times (a plain copy of known "
                          "size against which the HBM byte counters are scaled)")
+    ap.add_argument("--serve", action="store_true", help="run the serving stream instead of the step benchmark")
+    ap.add_argument("--requests", type=int, default=2048)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--rate-factor", type=float, default=0.8)
+    ap.add_argument("--capacity-sample", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve(args)
+        return
 
     import torch
 

@@ -53,7 +53,8 @@ enum {
     BIM_ENOMEM = -2,   /* device or host allocation failed */
     BIM_EDEVICE = -3,  /* HIP runtime error */
     BIM_ENOCONV = -4,  /* GMRES did not reach the tolerance; output holds the last iterate */
-    BIM_ESTATE = -5    /* call out of order (e.g. evaluation before bim_set_drops) */
+    BIM_ESTATE = -5,   /* call out of order (e.g. evaluation before bim_set_drops) */
+    BIM_EAGAIN = -6    /* server request not finished within the wait time */
 };
 
 enum { BIM_MEM_HOST = 0, BIM_MEM_DEVICE = 1 };
@@ -203,6 +204,46 @@ int bim_profile_select(bim_ctx ctx, const char *names);
  * flops and bytes of those launches. Unknown names give zeros. Synchronizes
  * the context stream. */
 int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, double *flops, double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Request server: independent drop systems (each a full velocity
+ * evaluation, bim_eval_velocity) submitted at any time and run concurrently.
+ * The server holds `slots` contexts, each with its own HIP stream (default
+ * priority) and host worker thread; the per-degree tables of a context stay
+ * resident between requests. A queued request is admitted, first come first
+ * served, when a slot is free and its estimated device memory
+ * (bim_server_footprint) fits in hbm_budget_gb next to the running requests;
+ * the device work of admitted requests overlaps.
+ * ---------------------------------------------------------------------- */
+typedef struct bim_server_s *bim_server;
+
+typedef struct {
+    int slots;              /* concurrent requests, 1..64 (default 4) */
+    double hbm_budget_gb;   /* admission budget, GB of estimated device memory (default 64) */
+    bim_options opt;        /* options of every context; opt.stream must be NULL */
+} bim_server_options;
+
+int bim_server_default_options(bim_server_options *opt);
+int bim_server_create(const bim_server_options *opt, bim_server *out);
+/* Finishes the running requests, drops the queued ones, frees everything. */
+int bim_server_destroy(bim_server srv);
+/* Queue one system: drops, surface coefficients, viscosity ratios and
+ * surfactant as for bim_set_drops / bim_set_tension (host pointers, copied
+ * before return; gamma_coef may be NULL for eos UNIFORM). out_kind 0: grid
+ * velocity, 1: coefficients (as bim_eval_velocity, host). *id names the
+ * request in bim_server_wait. */
+int bim_server_submit(bim_server srv, int n_drops, const int *p, const double *xcoef, const double *lambda,
+                      const double *gamma_coef, int eos, double E, double xs, double sigma0, int out_kind,
+                      uint64_t *id);
+/* Wait up to timeout_s seconds (< 0: no limit, 0: poll) for request id.
+ * Done: copies the velocity to out (may be NULL; size as bim_eval_velocity),
+ * the report to rep (may be NULL) and, if times_ms is not NULL, the queueing,
+ * service and total times in ms; releases the request and returns its status
+ * (BIM_OK, BIM_ENOCONV, ...). Not done: BIM_EAGAIN. Unknown id: BIM_EINVAL. */
+int bim_server_wait(bim_server srv, uint64_t id, double timeout_s, double *out, bim_report *rep,
+                    double *times_ms);
+/* Estimated device memory in bytes of one request with these degrees. */
+int bim_server_footprint(const bim_options *opt, int n_drops, const int *p, double *bytes);
 
 /* Host-side tables (no device needed; the same routines build the device
  * tables). Gauss-Legendre nodes t[0..q] (descending, theta ascending) and

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbim.so")
 
-BIM_OK, BIM_EINVAL, BIM_ENOMEM, BIM_EDEVICE, BIM_ENOCONV, BIM_ESTATE = 0, -1, -2, -3, -4, -5
+BIM_OK, BIM_EINVAL, BIM_ENOMEM, BIM_EDEVICE, BIM_ENOCONV, BIM_ESTATE, BIM_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 BIM_MEM_HOST, BIM_MEM_DEVICE = 0, 1
 BIM_EOS_UNIFORM, BIM_EOS_LINEAR, BIM_EOS_LANGMUIR = 0, 1, 2
 BIM_PREC_FP64, BIM_PREC_MIXED = 0, 1
@@ -40,6 +40,14 @@ class bim_options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("near_rule", ctypes.c_int),
         ("near_L", ctypes.c_int),
+    ]
+
+
+class bim_server_options(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int),
+        ("hbm_budget_gb", ctypes.c_double),
+        ("opt", bim_options),
     ]
 
 
@@ -86,6 +94,12 @@ EXPORTS = {
     "bim_host_gauss_legendre": ([_i, _vp, _vp], _i),
     "bim_host_legendre": ([_i, _d, _vp, _vp, _vp], _i),
     "bim_host_wigner_d": ([_i, _d, _vp], _i),
+    "bim_server_default_options": ([ctypes.POINTER(bim_server_options)], _i),
+    "bim_server_create": ([ctypes.POINTER(bim_server_options), ctypes.POINTER(_vp)], _i),
+    "bim_server_destroy": ([_vp], _i),
+    "bim_server_submit": ([_vp, _i, _vp, _vp, _vp, _vp, _i, _d, _d, _d, _i, ctypes.POINTER(ctypes.c_uint64)], _i),
+    "bim_server_wait": ([_vp, ctypes.c_uint64, _d, _vp, ctypes.POINTER(bim_report), _vp], _i),
+    "bim_server_footprint": ([ctypes.POINTER(bim_options), _i, _vp, ctypes.POINTER(_d)], _i),
 }
 
 _lib = None
@@ -377,3 +391,64 @@ class Context:
         rep = bim_eval_velocity(self.h, out, coefficients, allow_noconv)
         res = unpack_coefficients(out, self.ps) if coefficients else unpack_grid(out, self.ps)
         return res, rep
+
+
+class Server:
+    """Request server (bim_server_*): submit independent drop systems, wait
+    for their velocities. Options: slots, hbm_budget_gb, and any context
+    option by name."""
+
+    def __init__(self, slots=4, hbm_budget_gb=64.0, **opts):
+        so = bim_server_options()
+        _check(None, lib().bim_server_default_options(ctypes.byref(so)))
+        so.slots = slots
+        so.hbm_budget_gb = hbm_budget_gb
+        for k, v in opts.items():
+            setattr(so.opt, k, v)
+        h = ctypes.c_void_p()
+        _check(None, lib().bim_server_create(ctypes.byref(so), ctypes.byref(h)))
+        self.h = h
+        self._sizes = {}
+
+    def close(self):
+        if self.h:
+            lib().bim_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, ps, xcoefs, lams, gammas=None, eos=BIM_EOS_UNIFORM, E=0.0, xs=0.0, sigma0=1.0,
+               coefficients=False):
+        p = np.ascontiguousarray(ps, dtype=np.int32)
+        x = np.ascontiguousarray(pack_coefficients(xcoefs))
+        lam = np.ascontiguousarray(lams, dtype=np.float64)
+        g = np.ascontiguousarray(pack_scalar(gammas)) if gammas is not None else None
+        rid = ctypes.c_uint64()
+        _check(None, lib().bim_server_submit(self.h, len(p), p.ctypes.data, x.ctypes.data, lam.ctypes.data,
+                                             g.ctypes.data if g is not None else None, int(eos), float(E),
+                                             float(xs), float(sigma0), int(bool(coefficients)), ctypes.byref(rid)))
+        n = 3 * (sum(2 * ncoef(q) for q in p) if coefficients else sum(npts(q) for q in p))
+        self._sizes[rid.value] = (n, list(p), coefficients)
+        return rid.value
+
+    def wait(self, rid, timeout=-1.0, allow_noconv=False):
+        """(velocity per drop, report, (queue, service, total) ms), or None if
+        not finished within the timeout."""
+        n, ps, coef = self._sizes[rid]
+        out = np.zeros(n)
+        rep = bim_report()
+        t = np.zeros(3)
+        st = lib().bim_server_wait(self.h, ctypes.c_uint64(rid), float(timeout), out.ctypes.data, ctypes.byref(rep),
+                                   t.ctypes.data)
+        if st == BIM_EAGAIN:
+            return None
+        del self._sizes[rid]
+        if st != BIM_OK and not (allow_noconv and st == BIM_ENOCONV):
+            raise BimError(st, f"request {rid} failed with status {st}")
+        res = unpack_coefficients(out, ps) if coef else unpack_grid(out, ps)
+        return res, rep, tuple(t)
+

@@ -166,6 +166,9 @@ struct DBuf {
         if (b <= bytes && ptr) return;
         release();
         if (b == 0) b = 8;
+        // grow with slack: freeing device memory waits for the whole device,
+        // so a context reused for inputs of varying size should rarely regrow
+        if (bytes) b += b / 4;
         HIPC(hipMalloc(&ptr, b));
         bytes = b;
     }
@@ -393,7 +396,8 @@ static GridTab &grid(Ctx &c, int q, int nmax)
     }
     auto up = [&](DBuf &b, const std::vector<double> &v) {
         b.ensure(v.size() * sizeof(double));
-        HIPC(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     };
     up(g->L, L);
     up(g->wq, wq);
@@ -427,7 +431,8 @@ static RotTab &rot(Ctx &c, int p)
                 }
     auto up = [&](DBuf &b, const std::vector<double> &v) {
         b.ensure(v.size() * sizeof(double));
-        HIPC(hipMemcpy(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     };
     up(r->Ap, Ap);
     up(r->Am, Am);
@@ -732,9 +737,11 @@ static void near_setup(Ctx &c)
     c.near_tl.ensure(std::max<size_t>(1, tl.size()) * sizeof(int));
     c.near_work.ensure(std::max<size_t>(1, w.size()) * sizeof(PairWork));
     if (!tl.empty())
-        HIPC(hipMemcpy(c.near_tl.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(c.near_tl.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     if (!w.empty())
-        HIPC(hipMemcpy(c.near_work.ptr, w.data(), w.size() * sizeof(PairWork), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(c.near_work.ptr, w.data(), w.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     c.near_nwork = (int)w.size();
 }
 
@@ -851,13 +858,15 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
         }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
     if (!keep.empty())
-        HIPC(hipMemcpy(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     e->n = (int)keep.size();
     if (!c.near_h.empty()) {
         std::vector<double> nw(c.near_h.size());
         for (size_t it = 0; it < nw.size(); ++it) nw[it] = wt[(size_t)c.near_h[it].i * c.nd + c.near_h[it].j];
         e->nw.ensure(nw.size() * sizeof(double));
-        HIPC(hipMemcpy(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     }
     c.wlists.push_back(std::move(e));
     return *c.wlists.back();
@@ -974,7 +983,8 @@ static Ctx::PipeTab &pipe_tables(Ctx &c, int p, int qs)
     }
     auto up = [&](DBuf &b, const void *src, size_t bytes) {
         b.ensure(bytes);
-        HIPC(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+        HIPC(hipMemcpyAsync(b.ptr, src, bytes, hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     };
     up(t->syn, syn.data(), syn.size() * sizeof(double));
     up(t->ana, ana.data(), ana.size() * sizeof(double));
@@ -1422,6 +1432,7 @@ const char *bim_status_string(int s)
     case BIM_EDEVICE: return "device error";
     case BIM_ENOCONV: return "GMRES did not converge";
     case BIM_ESTATE: return "invalid call order";
+    case BIM_EAGAIN: return "request not finished";
     default: return "unknown status";
     }
 }
@@ -1477,7 +1488,9 @@ int bim_create(const bim_options *opt, bim_ctx *out)
     if (opt->stream) {
         c.stream = static_cast<hipStream_t>(opt->stream);
     } else {
-        if (hipStreamCreate(&c.stream) != hipSuccess) {
+        // non-blocking: no implicit ordering with the null stream, so that
+        // contexts on other threads never wait for each other
+        if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) {
             delete h;
             return BIM_EDEVICE;
         }
@@ -1532,10 +1545,12 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         }
         // validate coefficients on the host
         std::vector<double> hx((size_t)3 * coff);
-        if (mem_kind == BIM_MEM_DEVICE)
-            HIPC(hipMemcpy(hx.data(), xcoef, hx.size() * sizeof(double), hipMemcpyDeviceToHost));
-        else
+        if (mem_kind == BIM_MEM_DEVICE) {
+            HIPC(hipMemcpyAsync(hx.data(), xcoef, hx.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+        } else {
             std::memcpy(hx.data(), xcoef, hx.size() * sizeof(double));
+        }
         for (double v : hx) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surface coefficient");
         c.nd = n_drops;
         c.drops = ds;
@@ -1614,10 +1629,13 @@ int bim_set_tension(bim_ctx h, const double *gamma_coef, int eos, double E, doub
         c.sigma0 = sigma0;
         if (gamma_coef) {
             std::vector<double> hg((size_t)c.Ctot);
-            if (mem_kind == BIM_MEM_DEVICE)
-                HIPC(hipMemcpy(hg.data(), gamma_coef, hg.size() * sizeof(double), hipMemcpyDeviceToHost));
-            else
+            if (mem_kind == BIM_MEM_DEVICE) {
+                HIPC(hipMemcpyAsync(hg.data(), gamma_coef, hg.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                    c.stream));
+                HIPC(hipStreamSynchronize(c.stream));
+            } else {
                 std::memcpy(hg.data(), gamma_coef, hg.size() * sizeof(double));
+            }
             for (double v : hg) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surfactant coefficient");
             HIPC(hipMemcpyAsync(c.gc.ptr, hg.data(), hg.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
             HIPC(hipStreamSynchronize(c.stream));

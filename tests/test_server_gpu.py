@@ -1,0 +1,82 @@
+"""Request server: results in the mix equal results alone, admission by the
+memory budget, error paths.
+
+Requests are independent drop systems from the serving stream (1-8 drops of
+one degree in {8, 16, 24, 32}, lambda in {1, 2, 5}, uniform tension). Each
+result of a request run concurrently with others must equal the same request
+run alone on a plain context to 1e-12 relative per component (the only
+difference is the order of the atomic additions in the pair sums).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_02156_amd as B
+    return B
+
+
+def _requests(n, pmax=24):
+    return [r for r in W.serving_requests(n=4 * n) if r.p <= pmax][:n]
+
+
+def _alone(B, req):
+    c = B.Context()
+    c.set_drops([d.p for d in req.drops], [d.xc for d in req.drops], [d.lam for d in req.drops])
+    c.set_tension(None, 0, sigma0=1.0)
+    u, rep = c.eval_velocity()
+    c.close()
+    return u
+
+
+def test_results_in_the_mix_equal_results_alone(B):
+    print("server mix vs alone", flush=True)
+    reqs = _requests(10)
+    srv = B.Server(slots=4)
+    ids = [srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]) for r in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for r, (u, rep, t) in zip(reqs, got):
+        ref = _alone(B, r)
+        for a, b in zip(u, ref):
+            scale = np.abs(b).max(axis=0)
+            assert np.all(np.abs(a - b).max(axis=0) <= 1e-12 * scale)
+        assert t[2] >= t[1] > 0.0
+
+
+def test_budget_admits_one_request_at_a_time(B):
+    """A budget below any request's estimate runs them one at a time: the
+    service intervals (measured from the common submission instant) do not
+    overlap."""
+    print("server tiny budget", flush=True)
+    reqs = _requests(5, pmax=16)
+    srv = B.Server(slots=4, hbm_budget_gb=1e-9)
+    ids = [srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]) for r in reqs]
+    times = [srv.wait(i)[2] for i in ids]
+    srv.close()
+    iv = sorted((q, q + s) for q, s, _ in times)
+    for (a0, a1), (b0, b1) in zip(iv, iv[1:]):
+        assert b0 >= a1 - 1.0   # ms; submissions are within a millisecond of each other
+
+
+def test_server_error_paths(B):
+    srv = B.Server(slots=1)
+    r = _requests(1, pmax=32)[0]
+    with pytest.raises(B.BimError) as e:
+        srv.submit([1], [W.sphere(1)], [1.0])
+    assert e.value.status == B.BIM_EINVAL
+    rid = srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops])
+    res = srv.wait(rid, timeout=0.0)
+    if res is None:        # not finished at the poll: wait for it
+        res = srv.wait(rid)
+    assert res is not None
+    assert B.lib().bim_server_wait(srv.h, 987654321, 0.0, None, None, None) == B.BIM_EINVAL
+    srv.close()
