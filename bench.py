@@ -143,8 +143,8 @@ def serve(args):
     ctx.close()
     capacity = 1.0 / mean_s
 
-    def stream(slots, rate):
-        srv = B.Server(slots=slots)
+    def stream(slots, rate, batch=1):
+        srv = B.Server(slots=slots, max_batch=batch)
         for r in reqs[:8]:   # warm the contexts' tables
             srv.wait(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
         ids, lat, evals = [], [], [0]
@@ -176,14 +176,15 @@ def serve(args):
         span = time.perf_counter() - start
         srv.close()
         lat = np.array(lat)
-        return {"slots": slots, "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+        return {"slots": slots, "max_batch": batch, "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "throughput_req_s": len(reqs) / span,
                 "evals_per_s": evals[0] / span}
 
     rate = args.rate_factor * capacity
-    runs = [stream(1, rate), stream(args.slots, rate)]
-    for f in (1.5, 2.0):
+    runs = [stream(1, rate), stream(args.slots, rate), stream(args.slots, rate, args.max_batch)]
+    for f in (1.5, 2.0, 4.0):
         runs.append(stream(args.slots, f * capacity))
+        runs.append(stream(args.slots, f * capacity, args.max_batch))
     res = {"metric": "p50/p99 solve latency and throughput of the serving stream", "requests": len(reqs),
            "capacity_one_at_a_time_req_s": capacity, "mean_service_ms": mean_s * 1e3,
            "rate_factor": args.rate_factor, "runs": runs, "dtype": "f64", "data": "synthetic",
@@ -220,6 +221,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--rate-factor", type=float, default=0.8)
     ap.add_argument("--capacity-sample", type=int, default=128)
+    ap.add_argument("--max-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",

@@ -132,6 +132,14 @@ int bim_set_drops(bim_ctx ctx, int n_drops, const int *p, const double *xcoef,
 int bim_set_tension(bim_ctx ctx, const double *gamma_coef, int eos, double E, double xs,
                     double sigma0, int mem_kind);
 
+/* Independent systems in one context (batched evaluation): system_of_drop[d]
+ * >= 0 for each drop set by bim_set_drops (which resets all to 0). Drops of
+ * different systems do not interact (no pair sums; bim_regions reports -2);
+ * bim_eval_velocity solves all systems in one GMRES with the tolerance scaled
+ * by min_s ||b_s|| / ||b||, so that every system's own relative residual is at
+ * most gmres_tol; the report's gmres_residual is that per-system bound. */
+int bim_set_systems(bim_ctx ctx, const int *system_of_drop);
+
 /* Far field u_inf(x) = U0 + gradU x (gradU row-major 3x3). */
 int bim_set_farfield(bim_ctx ctx, const double U0[3], const double gradU[9]);
 
@@ -141,6 +149,7 @@ int bim_set_farfield(bim_ctx ctx, const double U0[3], const double gradU[9]);
 int bim_force(bim_ctx ctx, double *f_coef, int mem_kind);
 
 /* Region of every grid target w.r.t. every drop (Sec. 2.3): -1 own drop,
+ * -2 drop of another system (bim_set_systems),
  * 0 Omega_0 (dist > A_tilde h_j), 1 Omega_1 (h_j < dist <= A_tilde h_j),
  * 2 Omega_2 (dist <= h_j); dist = distance to the nearest node of drop j's
  * degree-p grid, h_j = R_j pi/(p_j+1), R_j the volume-equivalent radius.
@@ -213,14 +222,21 @@ int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, 
  * resident between requests. A queued request is admitted, first come first
  * served, when a slot is free and its estimated device memory
  * (bim_server_footprint) fits in hbm_budget_gb next to the running requests;
- * the device work of admitted requests overlaps.
+ * the device work of admitted requests overlaps. With max_batch > 1 a free
+ * slot also takes further queued requests of the same tension parameters and
+ * solves them together as independent systems (bim_set_systems): each
+ * result then meets gmres_tol on its own but differs from the result of the
+ * request alone at that level.
  * ---------------------------------------------------------------------- */
 typedef struct bim_server_s *bim_server;
 
 typedef struct {
-    int slots;              /* concurrent requests, 1..64 (default 4) */
+    int slots;              /* concurrent batches, 1..64 (default 4) */
     double hbm_budget_gb;   /* admission budget, GB of estimated device memory (default 64) */
     bim_options opt;        /* options of every context; opt.stream must be NULL */
+    int max_batch;          /* requests a free slot takes from the queue at once, run as independent
+                               systems of one context (bim_set_systems); 1 = one at a time (default) */
+    int max_batch_drops;    /* drops per batch at most (default 128) */
 } bim_server_options;
 
 int bim_server_default_options(bim_server_options *opt);

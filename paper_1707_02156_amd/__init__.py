@@ -48,6 +48,8 @@ class bim_server_options(ctypes.Structure):
         ("slots", ctypes.c_int),
         ("hbm_budget_gb", ctypes.c_double),
         ("opt", bim_options),
+        ("max_batch", ctypes.c_int),
+        ("max_batch_drops", ctypes.c_int),
     ]
 
 
@@ -79,6 +81,7 @@ EXPORTS = {
     "bim_last_error": ([_vp], ctypes.c_char_p),
     "bim_set_drops": ([_vp, _i, _vp, _vp, _vp, _i], _i),
     "bim_set_tension": ([_vp, _vp, _i, _d, _d, _d, _i], _i),
+    "bim_set_systems": ([_vp, _vp], _i),
     "bim_set_farfield": ([_vp, _vp, _vp], _i),
     "bim_force": ([_vp, _vp, _i], _i),
     "bim_regions": ([_vp, _vp, _vp, _i], _i),
@@ -347,6 +350,10 @@ class Context:
         self.ps = list(ps)
         bim_set_drops(self.h, ps, pack_coefficients(xcoefs), lams)
 
+    def set_systems(self, system_of_drop):
+        sy = np.ascontiguousarray(system_of_drop, dtype=np.int32)
+        _check(self.h, lib().bim_set_systems(self.h, sy.ctypes.data))
+
     def set_tension(self, gammas, eos, E=0.0, xs=0.0, sigma0=1.0):
         g = pack_scalar(gammas) if gammas is not None else None
         bim_set_tension(self.h, g, eos, E, xs, sigma0)
@@ -398,11 +405,13 @@ class Server:
     for their velocities. Options: slots, hbm_budget_gb, and any context
     option by name."""
 
-    def __init__(self, slots=4, hbm_budget_gb=64.0, **opts):
+    def __init__(self, slots=4, hbm_budget_gb=64.0, max_batch=1, max_batch_drops=128, **opts):
         so = bim_server_options()
         _check(None, lib().bim_server_default_options(ctypes.byref(so)))
         so.slots = slots
         so.hbm_budget_gb = hbm_budget_gb
+        so.max_batch = max_batch
+        so.max_batch_drops = max_batch_drops
         for k, v in opts.items():
             setattr(so.opt, k, v)
         h = ctypes.c_void_p()

@@ -40,8 +40,8 @@ void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, 
 void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
                         double *cb);
 void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
-                           const double *cb, const double *hj, double A, int exact, int8_t *reg, double *dist,
-                           int *list, int *count);
+                           const int *sys, const double *cb, const double *hj, double A, int exact, int8_t *reg,
+                           double *dist, int *list, int *count);
 void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,
                           const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
                           int8_t *reg, double *dist);
@@ -77,7 +77,8 @@ struct LegBatchH {
 };
 size_t rot_lds_bytes(int p);
 void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
-                 long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC);
+                 long xstride, const double *dc, long dstride, const PipeDrops &pd, int u0, int nunits,
+                 double *Bx, double *Bd, long NC);
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
                      double *out, long NC);
 int leg_mfma_max_rows();
@@ -85,10 +86,12 @@ int leg_mfma_max_depth();
 size_t fk_lds_bytes(int p, int qs, bool sl, int tg);
 void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
                const double *wsing, const double *X0, double *part, double *Fa, long NC12);
-void launch_sum_part(hipStream_t st, int nt, int Q1, const double *part, double scale, double *out, long ostride);
+void launch_sum_part(hipStream_t st, int nt, int Q1, int nk, int P1, const double *part, const PipeDrops &pd, int u0,
+                     double scale, double *out, long ostride);
 void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, double *X0);
 void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *Bt,
-                   long NC12, int j0, int nj, int tglobal0, double *M);
+                   long NC12, const PipeDrops &pd, int u0, int nunits);
+void launch_dl_apply_multi(hipStream_t st, const DlJob *jobs, int n, long ustride, long ostride);
 void pipe_set_lds_limits();
 struct SynJob {
     const double *coef;
@@ -219,6 +222,8 @@ struct Ctx {
     DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
     DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
     DBuf tdrop, vol, hj, noff, ncnt;
+    std::vector<int> sys_h;  // independent system of each drop (bim_set_systems)
+    DBuf sysd;
     DBuf reg, dist, cbnd, clist, ccount;
     bool regions_exact = false;  // distances of every pair computed (bim_regions with dist)
     DBuf tlist;
@@ -769,7 +774,8 @@ static void build_regions(Ctx &c)
         ProfScope ps(c, "classify", 0.0, 0.0);
         launch_drop_bounds(c.stream, c.nd, c.tx.d(), c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.cbnd.d());
         HIPC(hipMemsetAsync(c.ccount.ptr, 0, sizeof(int), c.stream));
-        launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.cbnd.d(), c.hj.d(),
+        launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.sysd.as<int>(),
+                              c.cbnd.d(), c.hj.d(),
                               c.opt.A_tilde, c.regions_exact ? 1 : 0, c.reg.as<int8_t>(), c.dist.d(),
                               c.clist.as<int>(), c.ccount.as<int>());
     }
@@ -796,7 +802,7 @@ static void build_regions(Ctx &c)
         const Drop &di = c.drops[i];
         const int nti = npts(di.p);
         for (int j = 0; j < c.nd; ++j) {
-            if (j == i) continue;
+            if (j == i || c.sys_h[i] != c.sys_h[j]) continue;
             const Drop &dj = c.drops[j];
             for (int kind = 0; kind < 2; ++kind) {
                 const int start = (int)tl.size();
@@ -1004,31 +1010,46 @@ static bool pipe_fits(int p, int qs)
            (qs + 1) <= leg_mfma_max_depth() && fk_lds_bytes(p, qs, true, 4) <= 163840 && rot_lds_bytes(p) <= 163840;
 }
 
-// Singular pass of drop i through the batched pipeline: single layer of dens
-// added into acc (sl) and/or the stored double-layer rows (dl).
-static void run_pipe(Ctx &c, int i, bool sl, bool dl, const double *dens)
+// Singular pass of a group of drops of one degree (and singular grid) through
+// the batched pipeline: single layer of dens added into acc (sl) and/or the
+// stored double-layer rows of each drop (dl). Chunks are sets of (drop,
+// latitude) units sized by a memory budget for the intermediates.
+static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl, const double *dens)
 {
-    const Drop &d = c.drops[i];
-    const int p = d.p, qs = d.qs, P1 = p + 1, Q1 = qs + 1, nk = 2 * p, nc = ncoef(p);
+    if (ids.empty()) return;
+    const Drop &d0 = c.drops[ids[0]];
+    const int p = d0.p, qs = d0.qs, P1 = p + 1, Q1 = qs + 1, nk = 2 * p, nc = ncoef(p);
     RotTab &r = rot(c, p);
     GridTab &gp = grid(c, p, p);
     GridTab &gs = grid(c, qs, p);
     Ctx::PipeTab &pt = pipe_tables(c, p, qs);
     pipe_set_lds_limits();
-    if (dl) {
-        if ((int)c.Mdl.size() < c.nd) {
-            c.Mdl.resize(c.nd);
-            c.Mok.resize(c.nd, 0);
+    REQUIRE((int)ids.size() <= kPipeMaxDrops, BIM_EINVAL, "too many drops in one pipeline pass");
+    PipeDrops pd{};
+    pd.n = (int)ids.size();
+    for (int q = 0; q < pd.n; ++q) {
+        const int i = ids[q];
+        const Drop &d = c.drops[i];
+        pd.coff[q] = d.coff;
+        pd.toff[q] = d.toff;
+        pd.M[q] = nullptr;
+        if (dl) {
+            if ((int)c.Mdl.size() < c.nd) {
+                c.Mdl.resize(c.nd);
+                c.Mok.resize(c.nd, 0);
+            }
+            if (!c.Mdl[i]) c.Mdl[i] = std::make_unique<DBuf>();
+            c.Mdl[i]->ensure((size_t)npts(p) * 6 * 2 * nc * sizeof(double));
+            pd.M[q] = c.Mdl[i]->d();
         }
-        if (!c.Mdl[i]) c.Mdl[i] = std::make_unique<DBuf>();
-        c.Mdl[i]->ensure((size_t)npts(p) * 6 * 2 * nc * sizeof(double));
     }
-    // latitudes per chunk from a memory budget for the intermediates
+    // units per chunk from a memory budget for the intermediates
     const double per_lat = (double)nk * 8.0 *
                            ((double)nc * 6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * 6 + (sl ? (double)P1 * Q1 * 6 : 0.0) +
                             (dl ? (double)P1 * Q1 * 12 + (double)nc * 12 : 0.0) + Q1 * 3 + 3);
     const double budget = 768.0 * 1024 * 1024;
-    int nj = std::max(1, std::min(P1, (int)(budget / per_lat)));
+    const int nu = pd.n * P1;
+    const int nj = std::max(1, std::min(nu, (int)(budget / per_lat)));
     const long NTc = (long)nj * nk;
     c.pBx.ensure((size_t)nc * NTc * 6 * 8);
     if (sl) c.pBd.ensure((size_t)nc * NTc * 6 * 8);
@@ -1041,13 +1062,13 @@ static void run_pipe(Ctx &c, int i, bool sl, bool dl, const double *dens)
         c.pBt.ensure((size_t)nc * NTc * 12 * 8);
     }
     const double rotlat = (double)rot_lat_size(p);
-    for (int j0 = 0; j0 < P1; j0 += nj) {
-        const int njc = std::min(nj, P1 - j0);
-        const long nt = (long)njc * nk, NC6 = nt * 6, NC12 = nt * 12;
+    for (int u0 = 0; u0 < nu; u0 += nj) {
+        const int nuc = std::min(nj, nu - u0);
+        const long nt = (long)nuc * nk, NC6 = nt * 6, NC12 = nt * 12;
         {
             ProfScope ps(c, "pipe_rotate", nt * (sl ? 6.0 : 3.0) * rotlat * 4.0, nt * (sl ? 2.0 : 1.0) * nc * 6 * 8.0);
-            launch_rot2(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d() + d.coff, c.Ctot,
-                        sl ? dens + d.coff : nullptr, c.Ctot, j0, njc, c.pBx.d(), sl ? c.pBd.d() : nullptr, NC6);
+            launch_rot2(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d(), c.Ctot, sl ? dens : nullptr, c.Ctot,
+                        pd, u0, nuc, c.pBx.d(), sl ? c.pBd.d() : nullptr, NC6);
             launch_pole(c.stream, p, (int)nt, c.pBx.d(), NC6, c.pX0.d());
         }
         {
@@ -1064,7 +1085,7 @@ static void run_pipe(Ctx &c, int i, bool sl, bool dl, const double *dens)
                          8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)));
             launch_fk(c.stream, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),
                       c.pX0.d(), c.pPart.d(), dl ? c.pFa.d() : nullptr, NC12);
-            if (sl) launch_sum_part(c.stream, (int)nt, Q1, c.pPart.d(), 1.0, c.acc.d() + d.toff + (long)j0 * nk, c.T);
+            if (sl) launch_sum_part(c.stream, (int)nt, Q1, nk, P1, c.pPart.d(), pd, u0, 1.0, c.acc.d(), c.T);
         }
         if (dl) {
             {
@@ -1073,13 +1094,26 @@ static void run_pipe(Ctx &c, int i, bool sl, bool dl, const double *dens)
             }
             {
                 ProfScope ps(c, "pipe_adjrot", nt * 6.0 * rotlat * 4.0, 8.0 * ((double)nc * NC12 + (double)nt * 6 * 2 * nc));
-                launch_adjrot(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.pBt.d(), NC12, j0, njc, j0 * nk,
-                              c.Mdl[i]->d());
+                launch_adjrot(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.pBt.d(), NC12, pd, u0, nuc);
             }
         }
     }
     HIPC(hipGetLastError());
-    if (dl) c.Mok[i] = 1;
+    if (dl)
+        for (int i : ids) c.Mok[i] = 1;
+}
+
+// Drops grouped by (degree, singular grid degree), in drop order.
+static std::vector<std::vector<int>> pipe_groups(const Ctx &c, const std::vector<int> &ids)
+{
+    std::map<std::pair<int, int>, std::vector<int>> g;
+    for (int i : ids) g[{c.drops[i].p, c.drops[i].qs}].push_back(i);
+    std::vector<std::vector<int>> out;
+    for (auto &kv : g)
+        for (size_t a = 0; a < kv.second.size(); a += kPipeMaxDrops)
+            out.emplace_back(kv.second.begin() + a,
+                             kv.second.begin() + std::min(kv.second.size(), a + (size_t)kPipeMaxDrops));
+    return out;
 }
 
 static bool use_fused(const Ctx &c, const Drop &d, bool sl, bool dl)
@@ -1161,6 +1195,16 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
     HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     if (!c.near_h.empty()) HIPC(hipMemsetAsync(c.near_self.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     density_nodes(c, ucoef, need);
+    // stored rows: build those missing (pipeline drops grouped by degree)
+    std::vector<int> build;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        if ((wt[(size_t)i * c.nd + i] != 0.0 || selfraw[i]) && use_pipe(c, d) && !dl_matrix_ready(c, i))
+            build.push_back(i);
+    }
+    for (auto &g : pipe_groups(c, build)) run_pipe_group(c, g, false, true, nullptr);
+    std::vector<DlJob> jobs;
+    double dfl = 0.0, dby = 0.0;
     for (int i = 0; i < c.nd; ++i) {
         const double w = wt[(size_t)i * c.nd + i];
         if (w == 0.0 && !selfraw[i]) continue;
@@ -1169,23 +1213,26 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
         double *dst = selfraw[i] ? c.near_self.d() : c.acc.d();
         const double ws = selfraw[i] ? 1.0 : w;
         if (use_pipe(c, d) || use_fused(c, d, false, true)) {
-            if (!dl_matrix_ready(c, i)) {
-                if (use_pipe(c, d)) run_pipe(c, i, false, true, nullptr);
-                else run_fused(c, i, false, true, nullptr);
-            }
-            {
-                const double nt = npts(d.p), nc2 = 2.0 * ncoef(d.p);
-                ProfScope ps(c, "dl_apply", nt * 18.0 * nc2, nt * 6.0 * nc2 * 8.0 + 3.0 * nc2 * 8.0);
-                launch_dl_apply(c.stream, npts(d.p), 2 * ncoef(d.p), c.Mdl[i]->d(), ucoef + d.coff, c.Ctot, ws,
-                                dst + d.toff, c.T);
-            }
+            if (!dl_matrix_ready(c, i)) run_fused(c, i, false, true, nullptr);
+            const double nt = npts(d.p), nc2 = 2.0 * ncoef(d.p);
+            dfl += nt * 18.0 * nc2;
+            dby += nt * 6.0 * nc2 * 8.0 + 3.0 * nc2 * 8.0;
+            jobs.push_back(DlJob{c.Mdl[i]->d(), ucoef + d.coff, dst + d.toff, ws, npts(d.p), 2 * ncoef(d.p)});
         } else {
             run_singular(c, i, 1, ucoef, ws, dst);
         }
-        if (selfraw[i] && w != 0.0)
-            for (int cc = 0; cc < 3; ++cc)
-                launch_scale_add(c.stream, npts(d.p), w, c.near_self.d() + cc * c.T + d.toff, 1.0,
-                                 c.acc.d() + cc * c.T + d.toff);
+    }
+    if (!jobs.empty()) {
+        ProfScope ps(c, "dl_apply", dfl, dby);
+        launch_dl_apply_multi(c.stream, jobs.data(), (int)jobs.size(), c.Ctot, c.T);
+    }
+    for (int i = 0; i < c.nd; ++i) {
+        const double w = wt[(size_t)i * c.nd + i];
+        if (!selfraw[i] || w == 0.0) continue;
+        const Drop &d = c.drops[i];
+        for (int cc = 0; cc < 3; ++cc)
+            launch_scale_add(c.stream, npts(d.p), w, c.near_self.d() + cc * c.T + d.toff, 1.0,
+                             c.acc.d() + cc * c.T + d.toff);
     }
     run_pairs(c, 1, wt);
     run_near(c, 1, ucoef, wt);
@@ -1199,11 +1246,20 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
     std::vector<char> need(c.nd, 1);
     HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
     density_nodes(c, fcoef, need);
+    // pipeline drops grouped by degree, separately with and without the rows
+    std::vector<int> with_rows, without_rows;
+    for (int i = 0; i < c.nd; ++i) {
+        if (!use_pipe(c, c.drops[i])) continue;
+        const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
+        (dl ? with_rows : without_rows).push_back(i);
+    }
+    for (auto &g : pipe_groups(c, with_rows)) run_pipe_group(c, g, true, true, fcoef);
+    for (auto &g : pipe_groups(c, without_rows)) run_pipe_group(c, g, true, false, fcoef);
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
         const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
         if (use_pipe(c, d)) {
-            run_pipe(c, i, true, dl, fcoef);
+            continue;
         } else if (use_fused(c, d, true, dl)) {
             run_fused(c, i, true, dl, fcoef);             // both in one pass
         } else if (use_fused(c, d, true, false)) {
@@ -1255,8 +1311,8 @@ static void apply_operator(Ctx &c, const double *x, double *y, const std::vector
 // step behind, through an event), so the device never waits for the host; a
 // step enqueued after convergence is discarded.
 // --------------------------------------------------------------------------
-static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, int &iters, double &relres,
-                 int &nmv)
+static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, double tol, int &iters,
+                 double &relres, int &nmv)
 {
     const long n = 3 * c.Ctot;
     const int m = std::max(1, std::min(c.opt.gmres_restart, gs_max_vectors() - 1));
@@ -1316,7 +1372,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         HIPC(hipStreamSynchronize(c.stream));
         const double beta = c.hhost[0];
         relres = beta / bn;
-        if (relres <= c.opt.gmres_tol) return BIM_OK;
+        if (relres <= tol) return BIM_OK;
         if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
         std::fill(gh, gh + m + 2, 0.0);
         gh[0] = beta;
@@ -1346,7 +1402,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
             ++nmv;
             kdone = k + 1;
             relres = r;
-            if (r <= c.opt.gmres_tol) {
+            if (r <= tol) {
                 conv = true;
                 break;
             }
@@ -1586,6 +1642,9 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
             noff[i] = (int)ds[i].toff;
             ncnt[i] = npts(ds[i].p);
         }
+        c.sys_h.assign(c.nd, 0);
+        c.sysd.ensure(c.nd * sizeof(int));
+        HIPC(hipMemcpyAsync(c.sysd.ptr, c.sys_h.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
         c.tdrop.ensure(c.T * sizeof(int));
         c.noff.ensure(c.nd * sizeof(int));
         c.ncnt.ensure(c.nd * sizeof(int));
@@ -1611,6 +1670,22 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
             rot(c, d.p);
         }
         HIPC(hipStreamSynchronize(c.stream));
+        return BIM_OK;
+    });
+}
+
+int bim_set_systems(bim_ctx h, const int *system_of_drop)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(system_of_drop, BIM_EINVAL, "null system array");
+        for (int i = 0; i < c.nd; ++i) REQUIRE(system_of_drop[i] >= 0, BIM_EINVAL, "negative system id");
+        c.sys_h.assign(system_of_drop, system_of_drop + c.nd);
+        HIPC(hipMemcpyAsync(c.sysd.ptr, c.sys_h.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        c.regions_ok = false;
+        c.regions_exact = false;
         return BIM_OK;
     });
 }
@@ -1764,7 +1839,34 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
         if (all_one) {
             launch_scale_add(c.stream, n, 0.5, c.bvec.d(), 0.0, c.xsol.d());
         } else {
-            rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), iters, relres, nmv);
+            // independent systems in one solve: a tolerance scaled by
+            // min_s ||b_s|| / ||b|| bounds every system's own relative
+            // residual by gmres_tol (||r_s|| <= ||r||)
+            double tol = c.opt.gmres_tol, bound = 1.0;
+            std::map<int, double> bs;
+            for (int i = 0; i < c.nd; ++i) bs[c.sys_h[i]] = 0.0;
+            if (bs.size() > 1) {
+                std::vector<double> hb(n);
+                HIPC(hipMemcpyAsync(hb.data(), c.bvec.ptr, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                HIPC(hipStreamSynchronize(c.stream));
+                double tot = 0.0;
+                for (int i = 0; i < c.nd; ++i)
+                    for (int comp = 0; comp < 3; ++comp)
+                        for (long e = 0; e < 2L * ncoef(c.drops[i].p); ++e) {
+                            const double v = hb[comp * c.Ctot + c.drops[i].coff + e];
+                            bs[c.sys_h[i]] += v * v;
+                            tot += v * v;
+                        }
+                double bmin = 0.0;
+                for (auto &kv : bs)
+                    if (kv.second > 0.0 && (bmin == 0.0 || kv.second < bmin)) bmin = kv.second;
+                if (bmin > 0.0 && tot > 0.0) {
+                    bound = std::sqrt(tot / bmin);
+                    tol /= bound;
+                }
+            }
+            rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), tol, iters, relres, nmv);
+            relres *= bound;
         }
         const bool dev = (out_kind & 2) != 0;
         if (out_kind & 1) {

@@ -45,6 +45,33 @@ struct GivensArgs {
     double bnorm = 1.0;
 };
 
+// Drops of one degree in a pass of the batched singular pipeline (kernel
+// argument). Latitude unit g = drop * (p+1) + j covers the 2p targets of
+// latitude j of that drop; a chunk of units starts at unit u0 and puts unit
+// u0 + y at columns y * 2p + k.
+constexpr int kPipeMaxDrops = 64;
+struct PipeDrops {
+    int n;
+    long coff[kPipeMaxDrops];   // coefficient offset (inside a component block)
+    long toff[kPipeMaxDrops];   // global index of the first target
+    double *M[kPipeMaxDrops];   // stored double-layer rows (or null)
+};
+
+// Stored double-layer rows of one drop applied to a density: out[c][t] +=
+// w sum_pairs M[t][pair] . u (k_dl_apply_multi takes several drops).
+struct DlJob {
+    const double *M;
+    const double *u;   // density coefficients of the drop, component stride ustride
+    double *out;       // first target of the drop, component stride ostride
+    double w;
+    int nt, nc2;
+};
+constexpr int kMaxDlJobs = 32;
+struct DlJobs {
+    int n;
+    DlJob j[kMaxDlJobs];
+};
+
 // Nearest-region items: a grid target t (global index) of drop i whose
 // nearest node of source drop j is within h_j.
 struct NearItem {

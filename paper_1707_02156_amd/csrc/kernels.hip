@@ -149,9 +149,10 @@ __global__ void k_nodes(int q, const double *__restrict__ syn, const double *__r
 // listed pair): the nearest-node distance and the region.
 // ----------------------------------------------------------------------------
 __global__ void k_classify_bound(int T, int nd, const double *__restrict__ tx, long tstride,
-                                 const int *__restrict__ tdrop, const double *__restrict__ cb /*[nd][4]*/,
-                                 const double *__restrict__ hj, double A, int exact, int8_t *__restrict__ reg,
-                                 double *__restrict__ dist, int *__restrict__ list, int *__restrict__ count)
+                                 const int *__restrict__ tdrop, const int *__restrict__ sys,
+                                 const double *__restrict__ cb /*[nd][4]*/, const double *__restrict__ hj, double A,
+                                 int exact, int8_t *__restrict__ reg, double *__restrict__ dist,
+                                 int *__restrict__ list, int *__restrict__ count)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)T * nd) return;
@@ -159,6 +160,11 @@ __global__ void k_classify_bound(int T, int nd, const double *__restrict__ tx, l
     const int t = idx / nd;
     if (tdrop[t] == j) {
         reg[idx] = -1;
+        if (dist) dist[idx] = 0.0;
+        return;
+    }
+    if (sys[tdrop[t]] != sys[j]) {  // drops of independent systems do not interact
+        reg[idx] = -2;
         if (dist) dist[idx] = 0.0;
         return;
     }
@@ -750,11 +756,11 @@ void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, 
 }
 
 void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
-                           const double *cb, const double *hj, double A, int exact, int8_t *reg, double *dist,
-                           int *list, int *count)
+                           const int *sys, const double *cb, const double *hj, double A, int exact, int8_t *reg,
+                           double *dist, int *list, int *count)
 {
-    hipLaunchKernelGGL(k_classify_bound, dim3(nblk((long)T * nd)), dim3(256), 0, st, T, nd, tx, tstride, tdrop, cb,
-                       hj, A, exact, reg, dist, list, count);
+    hipLaunchKernelGGL(k_classify_bound, dim3(nblk((long)T * nd)), dim3(256), 0, st, T, nd, tx, tstride, tdrop, sys,
+                       cb, hj, A, exact, reg, dist, list, count);
 }
 
 void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,

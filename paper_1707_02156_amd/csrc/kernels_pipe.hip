@@ -42,13 +42,16 @@ __host__ __device__ inline long koff(int mu, int P1) { return (long)mu * P1 - (l
 constexpr int kRotMaxPad = 64;  // degree p <= 63
 
 __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
-                                                  const double *__restrict__ csp, const double *__restrict__ xc,
-                                                  long xstride, const double *__restrict__ dc, long dstride,
-                                                  int j0, int tbase, double *__restrict__ Bx,
+                                                  const double *__restrict__ csp, const double *__restrict__ xc0,
+                                                  long xstride, const double *__restrict__ dc0, long dstride,
+                                                  PipeDrops pd, int u0, double *__restrict__ Bx,
                                                   double *__restrict__ Bd, long NC)
 {
     extern __shared__ double sm[];
-    const int n = blockIdx.x, j = j0 + blockIdx.y;
+    const int ug = u0 + blockIdx.y, dr = ug / (p + 1);
+    const int n = blockIdx.x, j = ug % (p + 1);
+    const double *xc = xc0 + pd.coff[dr];
+    const double *dc = dc0 ? dc0 + pd.coff[dr] : nullptr;
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
     const int nf = dc ? 6 : 3;
     const int MT = (N1 + 15) / 16, NP = MT * 16, NS = NP + 1, KS = (N1 + 3) / 4;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restric
                 }
         }
         if (!cok) continue;
-        const int t = tbase + blockIdx.y * nk + k;
+        const int t = blockIdx.y * nk + k;
         double *dst = (f < 3) ? Bx : Bd;
         const int ff = f < 3 ? f : f - 3;
 #pragma unroll
@@ -413,16 +416,18 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     }
 }
 
-// part[t][j'][3] summed over j' into out (scaled, added).
-__global__ void k_sum_part(int nt, int Q1, const double *__restrict__ part, double scale, double *__restrict__ out,
-                           long ostride)
+// part[t][j'][3] summed over j' into out (scaled, added); column t belongs to
+// unit u0 + t / nk of the pass.
+__global__ void k_sum_part(int nt, int Q1, int nk, int P1, const double *__restrict__ part, PipeDrops pd, int u0,
+                           double scale, double *__restrict__ out, long ostride)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt * 3) return;
     const int t = i / 3, c = i % 3;
     double s = 0.0;
     for (int j = 0; j < Q1; ++j) s += part[((long)t * Q1 + j) * 3 + c];
-    out[c * ostride + t] += scale * s;
+    const int ug = u0 + t / nk;
+    out[c * ostride + pd.toff[ug / P1] + (long)(ug % P1) * nk + t % nk] += scale * s;
 }
 
 // Pole values x0 of every target: sum_n Re x'^0_n sqrt((2n+1)/4pi) from the
@@ -447,11 +452,13 @@ __global__ void k_pole(int p, int nt, const double *__restrict__ Bx, long NC, do
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__restrict__ Ap,
                                                      const double *__restrict__ Am, const double *__restrict__ csp,
-                                                     const double *__restrict__ Bt, long NC12, int j0, int tbase,
-                                                     int tglobal0, double *__restrict__ M)
+                                                     const double *__restrict__ Bt, long NC12, PipeDrops pd,
+                                                     int u0)
 {
     extern __shared__ double sm[];
-    const int n = blockIdx.x, j = j0 + blockIdx.y;
+    const int ug = u0 + blockIdx.y, dr = ug / (p + 1);
+    const int n = blockIdx.x, j = ug % (p + 1);
+    double *__restrict__ M = pd.M[dr];
     const int N1 = n + 1, nk = 2 * p, P1 = p + 1;
     const int MT = (N1 + 15) / 16, NP = MT * 16, NS = NP + 1, KS = (N1 + 3) / 4;
     double *sAp = sm;                  // [nu][mu], NP x NP, zero padded, row stride NS
@@ -474,7 +481,7 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
         const int col = nt * 16 + r16;
         const bool cok = col < ncol;
         const int k = cok ? col / 6 : 0, pr = cok ? col % 6 : 0;
-        const long tcol = (long)(tbase + blockIdx.y * nk + k) * 12 + pr * 2;
+        const long tcol = (long)(blockIdx.y * nk + k) * 12 + pr * 2;
         d4_t al[4], be[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) al[m] = be[m] = (d4_t){0, 0, 0, 0};
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
                 }
         }
         if (!cok) continue;
-        const long tg = tglobal0 + (long)blockIdx.y * nk + k;  // target index within the drop
+        const long tg = (long)j * nk + k;  // target index within the drop
         double *Mt = M + (tg * 6 + pr) * nc2 + n * (n + 1);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -532,13 +539,14 @@ void pipe_set_lds_limits()
 }
 
 void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,
-                 long xstride, const double *dc, long dstride, int j0, int nj, double *Bx, double *Bd, long NC)
+                 long xstride, const double *dc, long dstride, const PipeDrops &pd, int u0, int nunits,
+                 double *Bx, double *Bd, long NC)
 {
     const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
     const int nf = dc ? 6 : 3;
     const size_t lds = (size_t)(2 * NP * (NP + 1) + nf * P1 * 2 + 2 * nk) * sizeof(double);
-    hipLaunchKernelGGL(k_rot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride, j0, 0,
-                       Bx, Bd, NC);
+    hipLaunchKernelGGL(k_rot_mfma, dim3(P1, nunits), dim3(256), lds, st, p, Ap, Am, csp, xc, xstride, dc, dstride,
+                       pd, u0, Bx, Bd, NC);
 }
 
 size_t rot_lds_bytes(int p)
@@ -588,9 +596,11 @@ void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const do
         hipLaunchKernelGGL((k_fk<false, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
 }
 
-void launch_sum_part(hipStream_t st, int nt, int Q1, const double *part, double scale, double *out, long ostride)
+void launch_sum_part(hipStream_t st, int nt, int Q1, int nk, int P1, const double *part, const PipeDrops &pd, int u0,
+                     double scale, double *out, long ostride)
 {
-    hipLaunchKernelGGL(k_sum_part, dim3(cdiv((long)nt * 3, 256)), dim3(256), 0, st, nt, Q1, part, scale, out, ostride);
+    hipLaunchKernelGGL(k_sum_part, dim3(cdiv((long)nt * 3, 256)), dim3(256), 0, st, nt, Q1, nk, P1, part, pd, u0, scale,
+                       out, ostride);
 }
 
 void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, double *X0)
@@ -599,11 +609,11 @@ void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, doubl
 }
 
 void launch_adjrot(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *Bt,
-                   long NC12, int j0, int nj, int tglobal0, double *M)
+                   long NC12, const PipeDrops &pd, int u0, int nunits)
 {
     const int P1 = p + 1, nk = 2 * p, NP = (P1 + 15) / 16 * 16;
     const size_t lds = (size_t)(2 * NP * (NP + 1) + 2 * nk) * sizeof(double);
-    hipLaunchKernelGGL(k_adjrot_mfma, dim3(P1, nj), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, j0, 0, tglobal0, M);
+    hipLaunchKernelGGL(k_adjrot_mfma, dim3(P1, nunits), dim3(256), lds, st, p, Ap, Am, csp, Bt, NC12, pd, u0);
 }
 
 }  // namespace bim

@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace bim {
 
 static constexpr double kInvSqrt4Pi_s = 0.28209479177387814347;
@@ -502,6 +504,52 @@ bool sing_fused_fits(int p, int qs, bool sl, bool dl)
     if (!lds_ok) return false;
     if (!dl) return true;
     return dl_entries(p, 512) <= (sl ? 11 : 17);
+}
+
+// Stored rows of several drops in one launch: block (target group, job).
+__global__ __launch_bounds__(256) void k_dl_apply_multi(DlJobs jobs, long ustride, long ostride)
+{
+    const DlJob &J = jobs.j[blockIdx.y];
+    const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wv >= J.nt) return;
+    const int nc2 = J.nc2;
+    const double *Mt = J.M + (long)wv * 6 * nc2;
+    const double *u0 = J.u, *u1 = J.u + ustride, *u2 = J.u + 2 * ustride;
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    for (int e = lane; e < nc2; e += 64) {
+        const double a = u0[e], b = u1[e], c = u2[e];
+        const double m00 = Mt[e], m01 = Mt[nc2 + e], m02 = Mt[2 * nc2 + e];
+        const double m11 = Mt[3 * nc2 + e], m12 = Mt[4 * nc2 + e], m22 = Mt[5 * nc2 + e];
+        o0 = fma(m00, a, fma(m01, b, fma(m02, c, o0)));
+        o1 = fma(m01, a, fma(m11, b, fma(m12, c, o1)));
+        o2 = fma(m02, a, fma(m12, b, fma(m22, c, o2)));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        o0 += __shfl_down(o0, o, 64);
+        o1 += __shfl_down(o1, o, 64);
+        o2 += __shfl_down(o2, o, 64);
+    }
+    if (lane == 0) {
+        J.out[wv] += J.w * o0;
+        J.out[ostride + wv] += J.w * o1;
+        J.out[2 * ostride + wv] += J.w * o2;
+    }
+}
+
+void launch_dl_apply_multi(hipStream_t st, const DlJob *jobs, int n, long ustride, long ostride)
+{
+    for (int o = 0; o < n; o += kMaxDlJobs) {
+        DlJobs b{};
+        b.n = std::min(kMaxDlJobs, n - o);
+        int maxnt = 0;
+        for (int i = 0; i < b.n; ++i) {
+            b.j[i] = jobs[o + i];
+            maxnt = std::max(maxnt, jobs[o + i].nt);
+        }
+        hipLaunchKernelGGL(k_dl_apply_multi, dim3((unsigned)(((long)maxnt * 64 + 255) / 256), b.n), dim3(256), 0, st,
+                           b, ustride, ostride);
+    }
 }
 
 void launch_dl_apply(hipStream_t st, int nt, int nc2, const double *M, const double *u, long ustride, double w,

@@ -1,12 +1,15 @@
 // Request server over the velocity evaluation: continuous admission of
 // independent drop systems into a fixed set of slots, each slot a context
 // with its own HIP stream and a host worker thread, so that the device work
-// of requests admitted at different times overlaps. A request is admitted
-// when a slot is free and its estimated device memory fits in the budget
-// next to the requests already running (first come, first served). The
-// per-degree tables of a context stay resident between requests.
+// of requests admitted at different times overlaps. A free slot takes the
+// head of the queue (first come, first served) when its estimated device
+// memory fits in the budget next to the running requests, together with
+// further queued requests of the same tension up to the batch limits: a
+// batch runs as independent systems of one context (one launch sequence for
+// all of them). The per-degree tables of a context stay resident.
 #include "../../include/bim.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -77,27 +80,105 @@ void run_request(bim_ctx ctx, Request &r)
     if (st != BIM_OK) r.err = bim_last_error(ctx);
 }
 
+bool same_tension(const Request &a, const Request &b)
+{
+    return a.eos == b.eos && a.E == b.E && a.xs == b.xs && a.sigma0 == b.sigma0 && a.out_kind == b.out_kind &&
+           a.gamma.empty() == b.gamma.empty();
+}
+
+// Several requests as independent systems of one context: one evaluation,
+// outputs split back per request.
+void run_batch(bim_ctx ctx, std::vector<Request *> &batch)
+{
+    if (batch.size() == 1) {
+        run_request(ctx, *batch[0]);
+        return;
+    }
+    std::vector<int> p, sys;
+    std::vector<double> lam, gamma;
+    std::vector<long> coff, toff;  // per request: offsets inside one component block
+    long ctot = 0, T = 0;
+    for (size_t q = 0; q < batch.size(); ++q) {
+        const Request &r = *batch[q];
+        coff.push_back(ctot);
+        toff.push_back(T);
+        for (int d = 0; d < r.nd; ++d) {
+            p.push_back(r.p[d]);
+            sys.push_back((int)q);
+            lam.push_back(r.lam[d]);
+            ctot += 2 * ncoef_s(r.p[d]);
+            T += npts_s(r.p[d]);
+        }
+        gamma.insert(gamma.end(), r.gamma.begin(), r.gamma.end());
+    }
+    std::vector<double> xc((size_t)3 * ctot);
+    for (size_t q = 0; q < batch.size(); ++q) {
+        const Request &r = *batch[q];
+        const long n = (long)r.xc.size() / 3;
+        for (int c = 0; c < 3; ++c) std::memcpy(&xc[c * ctot + coff[q]], &r.xc[c * n], n * sizeof(double));
+    }
+    const Request &r0 = *batch[0];
+    const bool coef = (r0.out_kind & 1) != 0;
+    const long per = coef ? ctot : T;
+    std::vector<double> out((size_t)3 * per);
+    bim_report rep{};
+    int st = bim_set_drops(ctx, (int)p.size(), p.data(), xc.data(), lam.data(), BIM_MEM_HOST);
+    if (st == BIM_OK) st = bim_set_systems(ctx, sys.data());
+    if (st == BIM_OK)
+        st = bim_set_tension(ctx, gamma.empty() ? nullptr : gamma.data(), r0.eos, r0.E, r0.xs, r0.sigma0,
+                             BIM_MEM_HOST);
+    if (st == BIM_OK) st = bim_eval_velocity(ctx, out.data(), coef ? 1 : 0, &rep);
+    const std::string err = st != BIM_OK ? bim_last_error(ctx) : std::string();
+    for (size_t q = 0; q < batch.size(); ++q) {
+        Request &r = *batch[q];
+        const long n = (long)r.out.size() / 3, o = coef ? coff[q] : toff[q];
+        for (int c = 0; c < 3; ++c) std::memcpy(&r.out[c * n], &out[c * per + o], n * sizeof(double));
+        r.rep = rep;
+        long tq = 0;
+        for (int d = 0; d < r.nd; ++d) tq += npts_s(r.p[d]);
+        r.rep.n_targets = (int)tq;
+        r.status = st;
+        r.err = err;
+    }
+}
+
 void worker(bim_server_s *s, int k)
 {
     for (;;) {
-        Request *r = nullptr;
+        std::vector<Request *> batch;
+        double fp = 0.0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stop || admissible(*s); });
             if (s->stop) return;
-            r = s->queue.front();
-            s->queue.pop_front();
-            s->inflight += r->footprint;
-            r->t_start = Clock::now();
+            // the head, then further queued requests of the same tension while
+            // they fit the batch limits and the memory budget
+            const double budget = s->opt.hbm_budget_gb * 1e9;
+            int drops = 0;
+            while (!s->queue.empty() && (int)batch.size() < std::max(1, s->opt.max_batch)) {
+                Request *r = s->queue.front();
+                if (!batch.empty() && (!same_tension(*r, *batch[0]) || drops + r->nd > s->opt.max_batch_drops ||
+                                       s->inflight + fp + r->footprint > budget))
+                    break;
+                s->queue.pop_front();
+                batch.push_back(r);
+                fp += r->footprint;
+                drops += r->nd;
+                r->t_start = Clock::now();
+            }
+            s->inflight += fp;
         }
         s->cv_work.notify_all();  // the next request may fit too
-        run_request(s->ctx[k], *r);
+        run_batch(s->ctx[k], batch);
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->inflight -= r->footprint;
+            s->inflight -= fp;
             if (s->inflight < 0.5) s->inflight = 0.0;
-            r->t_end = Clock::now();
-            r->done = true;
+            const auto t = Clock::now();
+            for (Request *r : batch) {
+                r->t_end = t;
+                r->done = true;
+            }
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();
@@ -141,6 +222,8 @@ int bim_server_default_options(bim_server_options *o)
     std::memset(o, 0, sizeof(*o));
     o->slots = 4;
     o->hbm_budget_gb = 64.0;
+    o->max_batch = 1;
+    o->max_batch_drops = 128;
     return bim_default_options(&o->opt);
 }
 
@@ -148,7 +231,9 @@ int bim_server_create(const bim_server_options *opt, bim_server *out)
 {
     if (!opt || !out) return BIM_EINVAL;
     *out = nullptr;
-    if (opt->slots < 1 || opt->slots > 64 || !(opt->hbm_budget_gb > 0.0) || opt->opt.stream) return BIM_EINVAL;
+    if (opt->slots < 1 || opt->slots > 64 || !(opt->hbm_budget_gb > 0.0) || opt->opt.stream || opt->max_batch < 1 ||
+        opt->max_batch_drops < 1)
+        return BIM_EINVAL;
     std::unique_ptr<bim_server_s> s;
     try {
         s = std::make_unique<bim_server_s>();

@@ -80,3 +80,41 @@ def test_server_error_paths(B):
     assert res is not None
     assert B.lib().bim_server_wait(srv.h, 987654321, 0.0, None, None, None) == B.BIM_EINVAL
     srv.close()
+
+
+def test_independent_systems_in_one_context(B):
+    """Two systems occupying the same region of space, set as independent
+    systems of one context: each gets the result it has alone (no
+    interaction leaks across systems), to the GMRES tolerance."""
+    print("independent systems", flush=True)
+    r1, r2 = _requests(2, pmax=16)
+    a1, a2 = _alone(B, r1), _alone(B, r2)
+    drops = r1.drops + r2.drops
+    c = B.Context(gmres_tol=1e-12)
+    c.set_drops([d.p for d in drops], [d.xc for d in drops], [d.lam for d in drops])
+    c.set_systems([0] * len(r1.drops) + [1] * len(r2.drops))
+    c.set_tension(None, 0, sigma0=1.0)
+    reg, _ = c.regions()
+    n1 = sum(B.npts(d.p) for d in r1.drops)
+    assert np.all(reg[:n1, len(r1.drops):] == -2) and np.all(reg[n1:, :len(r1.drops)] == -2)
+    u, rep = c.eval_velocity()
+    c.close()
+    for got, ref in zip(u, a1 + a2):
+        assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_batched_server_results_match_alone(B):
+    """max_batch 8: queued requests run together as independent systems;
+    every result matches the request alone to 1e-8 (both meet the GMRES
+    tolerance 1e-10 on their own system)."""
+    print("batched server", flush=True)
+    reqs = _requests(12)
+    srv = B.Server(slots=2, max_batch=8)
+    ids = [srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]) for r in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for r, (u, rep, t) in zip(reqs, got):
+        assert rep.gmres_residual <= 1e-10
+        ref = _alone(B, r)
+        for a, b in zip(u, ref):
+            assert np.abs(a - b).max() <= 1e-8 * np.abs(b).max()
