@@ -85,7 +85,7 @@ int leg_mfma_max_rows();
 int leg_mfma_max_depth();
 size_t fk_lds_bytes(int p, int qs, bool sl, int tg);
 void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
-               const double *wsing, const double *X0, double *part, double *Fa, long NC12);
+               const double *wsing, const double *cs, const double *X0, double *part, double *Fa, long NC12);
 void launch_sum_part(hipStream_t st, int nt, int Q1, int nk, int P1, const double *part, const PipeDrops &pd, int u0,
                      double scale, double *out, long ostride);
 void launch_pole(hipStream_t st, int p, int nt, const double *Bx, long NC, double *X0);
@@ -1084,7 +1084,7 @@ static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl
             ProfScope ps(c, "pipe_fourier", nt * fl,
                          8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)));
             launch_fk(c.stream, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),
-                      c.pX0.d(), c.pPart.d(), dl ? c.pFa.d() : nullptr, NC12);
+                      gs.cs.d(), c.pX0.d(), c.pPart.d(), dl ? c.pFa.d() : nullptr, NC12);
             if (sl) launch_sum_part(c.stream, (int)nt, Q1, nk, P1, c.pPart.d(), pd, u0, 1.0, c.acc.d(), c.T);
         }
         if (dl) {

@@ -190,11 +190,21 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
 // lanes reading consecutive points hit distinct LDS banks
 constexpr int kVS = 13;
 
+// 1/sqrt(x) to full double precision: hardware estimate plus one third-order
+// correction (relative error of the estimate e -> O(e^3))
+__device__ inline double rsq_full(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
 template <bool SL, bool DL, int TG>
 __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double *__restrict__ Gx,
                                             const double *__restrict__ Gd, long NC6,
-                                            const double *__restrict__ wsing, const double *__restrict__ X0,
-                                            double *__restrict__ part, double *__restrict__ Fa, long NC12)
+                                            const double *__restrict__ wsing, const double *__restrict__ cs,
+                                            const double *__restrict__ X0, double *__restrict__ part,
+                                            double *__restrict__ Fa, long NC12)
 {
     extern __shared__ double sm[];
     const int P1 = p + 1, Q1 = qs + 1, nk = 2 * qs;
@@ -209,7 +219,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     double *red = V + (long)TG * nk * kVS;   // [tg][3]
     double *sCS = red + TG * 3;              // cos, sin of pi e / qs, e < 2 qs
     for (int i = threadIdx.x; i < TG * 3; i += 256) red[i] = 0.0;
-    for (int e = threadIdx.x; e < nk; e += 256) sincos(3.14159265358979323846 * e / qs, &sCS[nk + e], &sCS[e]);
+    for (int e = threadIdx.x; e < 2 * nk; e += 256) sCS[e] = cs[e];
     // ---- load G (weights w_mu applied; x_phi built from x)
     for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
         const int e = i % 6;           // c*2 + re/im
@@ -238,58 +248,97 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     const bool even = (qs & 1) == 0;
     const int nkk = even ? qs / 2 + 1 : qs;
     // ---- F: point values. cos/sin(mu phi) by the three-term recurrence
-    // c_{mu+1} = 2 cos(phi) c_mu - c_{mu-1} (same for sin), error O(p^2 eps)
-    for (int it = threadIdx.x; it < ntg * nkk * 3; it += 256) {
+    // c_{mu+1} = 2 cos(phi) c_mu - c_{mu-1} (same for sin), error O(p^2 eps).
+    // A thread takes the points kk and kk + H of one (target, component): each
+    // G value read from LDS feeds both.
+    const int H = (nkk + 1) / 2;
+    for (int it = threadIdx.x; it < ntg * H * 3; it += 256) {
         const int c = it % 3;
         const int r = it / 3;
-        const int kk = r % nkk, tg = r / nkk;
+        const int kp = r % H, tg = r / H;
+        const int kq[2] = {kp, kp + H};
+        const bool two = kp + H < nkk;
         const double *g = sG + (long)tg * P1 * NTY * 6 + 2 * c;
-        const double c1 = sCS[kk], s1 = sCS[nk + kk], tc = 2.0 * c1;
-        double c0 = 1.0, s0 = 0.0, cm1 = c1, sm1 = -s1;  // orders mu and mu - 1
-        double CE[NTY], CO[NTY], SE[NTY], SO[NTY];
+        double tc[2], c0[2], s0[2], cm1[2], sm1[2];
+        double CE[2][NTY], CO[2][NTY], SE[2][NTY], SO[2][NTY];
 #pragma unroll
-        for (int q = 0; q < NTY; ++q) { CE[q] = 0; CO[q] = 0; SE[q] = 0; SO[q] = 0; }
+        for (int b = 0; b < 2; ++b) {
+            const int kb = min(kq[b], nkk - 1);
+            const double c1 = sCS[kb], s1 = sCS[nk + kb];
+            tc[b] = 2.0 * c1;
+            c0[b] = 1.0;
+            s0[b] = 0.0;
+            cm1[b] = c1;  // orders mu and mu - 1
+            sm1[b] = -s1;
+#pragma unroll
+            for (int q = 0; q < NTY; ++q) { CE[b][q] = 0; CO[b][q] = 0; SE[b][q] = 0; SO[b][q] = 0; }
+        }
         int mu = 0;
         for (; mu + 1 <= p; mu += 2) {
             const double *ge = g + (long)mu * NTY * 6, *go = ge + NTY * 6;
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CE[q] = fma(ge[6 * q], c0, CE[q]);
-                SE[q] = fma(ge[6 * q + 1], s0, SE[q]);
+                const double gc = ge[6 * q], gs = ge[6 * q + 1];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    CE[b][q] = fma(gc, c0[b], CE[b][q]);
+                    SE[b][q] = fma(gs, s0[b], SE[b][q]);
+                }
             }
-            const double c1n = fma(tc, c0, -cm1), s1n = fma(tc, s0, -sm1);
+            double c1n[2], s1n[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                c1n[b] = fma(tc[b], c0[b], -cm1[b]);
+                s1n[b] = fma(tc[b], s0[b], -sm1[b]);
+            }
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CO[q] = fma(go[6 * q], c1n, CO[q]);
-                SO[q] = fma(go[6 * q + 1], s1n, SO[q]);
+                const double gc = go[6 * q], gs = go[6 * q + 1];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    CO[b][q] = fma(gc, c1n[b], CO[b][q]);
+                    SO[b][q] = fma(gs, s1n[b], SO[b][q]);
+                }
             }
-            cm1 = c1n;
-            sm1 = s1n;
-            c0 = fma(tc, c1n, -c0);
-            s0 = fma(tc, s1n, -s0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cm1[b] = c1n[b];
+                sm1[b] = s1n[b];
+                c0[b] = fma(tc[b], c1n[b], -c0[b]);
+                s0[b] = fma(tc[b], s1n[b], -s0[b]);
+            }
         }
         if (mu <= p) {  // last order (even)
             const double *ge = g + (long)mu * NTY * 6;
 #pragma unroll
             for (int q = 0; q < NTY; ++q) {
-                CE[q] = fma(ge[6 * q], c0, CE[q]);
-                SE[q] = fma(ge[6 * q + 1], s0, SE[q]);
+                const double gc = ge[6 * q], gs = ge[6 * q + 1];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    CE[b][q] = fma(gc, c0[b], CE[b][q]);
+                    SE[b][q] = fma(gs, s0[b], SE[b][q]);
+                }
             }
         }
         double *Vb = V + (long)tg * nk * kVS;
         // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
-        auto put = [&](int kp, double f1, double f2) {
-            double *v = Vb + (long)kp * kVS;
-            v[c] = (CE[0] - f1 * SE[0]) + f2 * (CO[0] - f1 * SO[0]);
-            v[3 + c] = (CE[1] - f1 * SE[1]) + f2 * (CO[1] - f1 * SO[1]);
-            v[6 + c] = (CE[2] - f1 * SE[2]) + f2 * (CO[2] - f1 * SO[2]);
-            if (SL) v[9 + c] = (CE[3] - f1 * SE[3]) + f2 * (CO[3] - f1 * SO[3]);
-        };
-        put(kk, 1.0, 1.0);
-        put(kk + qs, 1.0, -1.0);
-        if (even && kk != 0 && kk != qs / 2) {
-            put(nk - kk, -1.0, 1.0);
-            put(qs - kk, -1.0, -1.0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (b == 1 && !two) break;
+            const int kk = kq[b];
+            auto put = [&](int kpt, double f1, double f2) {
+                double *v = Vb + (long)kpt * kVS;
+                v[c] = (CE[b][0] - f1 * SE[b][0]) + f2 * (CO[b][0] - f1 * SO[b][0]);
+                v[3 + c] = (CE[b][1] - f1 * SE[b][1]) + f2 * (CO[b][1] - f1 * SO[b][1]);
+                v[6 + c] = (CE[b][2] - f1 * SE[b][2]) + f2 * (CO[b][2] - f1 * SO[b][2]);
+                if (SL) v[9 + c] = (CE[b][3] - f1 * SE[b][3]) + f2 * (CO[b][3] - f1 * SO[b][3]);
+            };
+            put(kk, 1.0, 1.0);
+            put(kk + qs, 1.0, -1.0);
+            if (even && kk != 0 && kk != qs / 2) {
+                put(nk - kk, -1.0, 1.0);
+                put(qs - kk, -1.0, -1.0);
+            }
         }
     }
     __syncthreads();
@@ -309,11 +358,12 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
             const double N2 = xt0 * xp1 - xt1 * xp0;
             const double h0 = X0[3 * t] - v[0], h1 = X0[3 * t + 1] - v[1], h2 = X0[3 * t + 2] - v[2];
             const double r2 = h0 * h0 + h1 * h1 + h2 * h2;
-            const double ri = rsqrt(r2);
+            const double ri = rsq_full(r2);
             if (SL) {
                 const double f0 = v[9], f1 = v[10], f2 = v[11];
                 const double hf = h0 * f0 + h1 * f1 + h2 * f2;
-                const double Wr = om * sqrt(N0 * N0 + N1 * N1 + N2 * N2) * ri;
+                const double n2 = N0 * N0 + N1 * N1 + N2 * N2;
+                const double Wr = om * (n2 * rsq_full(n2)) * ri;
                 const double q = hf * ri * ri;
                 e0 = Wr * fma(h0, q, f0);
                 e1 = Wr * fma(h1, q, f1);
@@ -583,17 +633,17 @@ size_t fk_lds_bytes(int p, int qs, bool sl, int tg)
 }
 
 void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const double *Gx, const double *Gd, long NC6,
-               const double *wsing, const double *X0, double *part, double *Fa, long NC12)
+               const double *wsing, const double *cs, const double *X0, double *part, double *Fa, long NC12)
 {
     constexpr int TG = 4;
     const dim3 grid(cdiv(nt, TG), qs + 1);
     const size_t lds = fk_lds_bytes(p, qs, sl, TG);
     if (sl && dl)
-        hipLaunchKernelGGL((k_fk<true, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+        hipLaunchKernelGGL((k_fk<true, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
     else if (sl)
-        hipLaunchKernelGGL((k_fk<true, false, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+        hipLaunchKernelGGL((k_fk<true, false, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
     else
-        hipLaunchKernelGGL((k_fk<false, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, X0, part, Fa, NC12);
+        hipLaunchKernelGGL((k_fk<false, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
 }
 
 void launch_sum_part(hipStream_t st, int nt, int Q1, int nk, int P1, const double *part, const PipeDrops &pd, int u0,
