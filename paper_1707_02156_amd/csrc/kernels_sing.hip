@@ -406,6 +406,36 @@ __global__ __launch_bounds__(DL ? 512 : 1024) void k_sing_fused(SingArgs a)
 }
 
 // out_c[t] += w * sum_{c'} sum_e M[t][pair(c,c')][e] u_{c'}[e], one wavefront per target.
+// One target row: (o0, o1, o2) = M_t (u0, u1, u2) over the six symmetric pair
+// rows of length nc2 (even; rows and densities 16-byte aligned), read as
+// double2 by one wavefront, two iterations of loads in flight per lane.
+__device__ inline void dl_row(const double *__restrict__ Mt, const double *__restrict__ u, long ustride, int nc2,
+                              int lane, double &o0, double &o1, double &o2)
+{
+    const int h = nc2 >> 1;
+    const double2 *M0 = reinterpret_cast<const double2 *>(Mt), *M1 = M0 + h, *M2 = M1 + h, *M3 = M2 + h,
+                  *M4 = M3 + h, *M5 = M4 + h;
+    const double2 *U0 = reinterpret_cast<const double2 *>(u), *U1 = reinterpret_cast<const double2 *>(u + ustride),
+                  *U2 = reinterpret_cast<const double2 *>(u + 2 * ustride);
+    o0 = o1 = o2 = 0.0;
+#pragma unroll 2
+    for (int e = lane; e < h; e += 64) {
+        const double2 a = U0[e], b = U1[e], c = U2[e];
+        const double2 m00 = M0[e], m01 = M1[e], m02 = M2[e], m11 = M3[e], m12 = M4[e], m22 = M5[e];
+        o0 = fma(m00.x, a.x, fma(m01.x, b.x, fma(m02.x, c.x, o0)));
+        o1 = fma(m01.x, a.x, fma(m11.x, b.x, fma(m12.x, c.x, o1)));
+        o2 = fma(m02.x, a.x, fma(m12.x, b.x, fma(m22.x, c.x, o2)));
+        o0 = fma(m00.y, a.y, fma(m01.y, b.y, fma(m02.y, c.y, o0)));
+        o1 = fma(m01.y, a.y, fma(m11.y, b.y, fma(m12.y, c.y, o1)));
+        o2 = fma(m02.y, a.y, fma(m12.y, b.y, fma(m22.y, c.y, o2)));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        o0 += __shfl_down(o0, o, 64);
+        o1 += __shfl_down(o1, o, 64);
+        o2 += __shfl_down(o2, o, 64);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_dl_apply(int nt, int nc2, const double *__restrict__ M,
                                                   const double *__restrict__ u, long ustride, double w,
                                                   double *__restrict__ out, long ostride)
@@ -413,22 +443,8 @@ __global__ __launch_bounds__(256) void k_dl_apply(int nt, int nc2, const double 
     const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wv >= nt) return;
-    const double *Mt = M + (long)wv * 6 * nc2;
-    const double *u0 = u, *u1 = u + ustride, *u2 = u + 2 * ustride;
-    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-    for (int e = lane; e < nc2; e += 64) {
-        const double a = u0[e], b = u1[e], c = u2[e];
-        const double m00 = Mt[e], m01 = Mt[nc2 + e], m02 = Mt[2 * nc2 + e];
-        const double m11 = Mt[3 * nc2 + e], m12 = Mt[4 * nc2 + e], m22 = Mt[5 * nc2 + e];
-        o0 = fma(m00, a, fma(m01, b, fma(m02, c, o0)));
-        o1 = fma(m01, a, fma(m11, b, fma(m12, c, o1)));
-        o2 = fma(m02, a, fma(m12, b, fma(m22, c, o2)));
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        o0 += __shfl_down(o0, o, 64);
-        o1 += __shfl_down(o1, o, 64);
-        o2 += __shfl_down(o2, o, 64);
-    }
+    double o0, o1, o2;
+    dl_row(M + (long)wv * 6 * nc2, u, ustride, nc2, lane, o0, o1, o2);
     if (lane == 0) {
         out[wv] += w * o0;
         out[ostride + wv] += w * o1;
@@ -513,23 +529,8 @@ __global__ __launch_bounds__(256) void k_dl_apply_multi(DlJobs jobs, long ustrid
     const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wv >= J.nt) return;
-    const int nc2 = J.nc2;
-    const double *Mt = J.M + (long)wv * 6 * nc2;
-    const double *u0 = J.u, *u1 = J.u + ustride, *u2 = J.u + 2 * ustride;
-    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-    for (int e = lane; e < nc2; e += 64) {
-        const double a = u0[e], b = u1[e], c = u2[e];
-        const double m00 = Mt[e], m01 = Mt[nc2 + e], m02 = Mt[2 * nc2 + e];
-        const double m11 = Mt[3 * nc2 + e], m12 = Mt[4 * nc2 + e], m22 = Mt[5 * nc2 + e];
-        o0 = fma(m00, a, fma(m01, b, fma(m02, c, o0)));
-        o1 = fma(m01, a, fma(m11, b, fma(m12, c, o1)));
-        o2 = fma(m02, a, fma(m12, b, fma(m22, c, o2)));
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        o0 += __shfl_down(o0, o, 64);
-        o1 += __shfl_down(o1, o, 64);
-        o2 += __shfl_down(o2, o, 64);
-    }
+    double o0, o1, o2;
+    dl_row(J.M + (long)wv * 6 * J.nc2, J.u, ustride, J.nc2, lane, o0, o1, o2);
     if (lane == 0) {
         J.out[wv] += J.w * o0;
         J.out[ostride + wv] += J.w * o1;
