@@ -100,14 +100,6 @@ struct SynJob {
     long cstride, ostride, fstride;
     int p, q, ldn, ncomp, mask;
 };
-struct AnaJob {
-    const double *v;
-    const double *L;
-    const double *wq;
-    double *coef;
-    long vstride, cstride;
-    int p, q, ldn, ncomp;
-};
 void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n);
 void launch_anal_batch(hipStream_t st, const AnaJob *jobs, int n);
 size_t anal_batch_lds(int p, int q);
@@ -125,7 +117,8 @@ void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, do
 void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long ld, const double *h1, double *w,
                            double *part, unsigned *cnt, double *h2);
 void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
-                           double *part, unsigned *cnt, double *h, const GivensArgs &ga = GivensArgs{});
+                           double *part, unsigned *cnt, double *h, const GivensArgs &ga = GivensArgs{},
+                           double *vout = nullptr);
 void launch_backsub(hipStream_t st, int k, const double *H, long ldH, const double *g, double *y);
 void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
@@ -254,6 +247,7 @@ struct Ctx {
     DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt, givbuf;
     hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
+    double *hres = nullptr;        // pinned, coherent: GMRES residual estimates written by the device
 
     bool nodes_ok = false, force_ok = false, regions_ok = false;
 
@@ -290,6 +284,7 @@ struct Ctx {
         grids.clear();
         rots.clear();
         if (hhost) (void)hipHostFree(hhost);
+        if (hres) (void)hipHostFree(hres);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -517,6 +512,8 @@ static AnaJob ana_job(Ctx &c, int q, int p, int ncomp, const double *v, long vst
     j.q = q;
     j.ldn = ncoef(p);
     j.ncomp = ncomp;
+    j.cx = nullptr;
+    j.csc = 0.0;
     return j;
 }
 
@@ -1300,8 +1297,24 @@ static void synth_grid_all(Ctx &c, const double *coef, double *grid_vals)
 static void apply_operator(Ctx &c, const double *x, double *y, const std::vector<double> &wt)
 {
     double_layer_grid(c, x, wt);
-    project(c, c.acc.d(), y);
-    launch_op_combine(c.stream, 3 * c.Ctot, c.scl.d(), x, y);
+    // y = (lambda + 1) x - P[acc]: the combine rides on the batched analysis
+    // when every drop's grid fits it
+    std::vector<AnaJob> jobs;
+    bool fused = true;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        AnaJob j = ana_job(c, d.p, d.p, 3, c.acc.d() + d.toff, c.T, y + d.coff, c.Ctot);
+        j.cx = x + d.coff;
+        j.csc = d.lam + 1.0;
+        fused = fused && anal_batch_lds(d.p, d.p) <= 163840;
+        jobs.push_back(j);
+    }
+    if (fused) {
+        ana_run(c, jobs);
+    } else {
+        project(c, c.acc.d(), y);
+        launch_op_combine(c.stream, 3 * c.Ctot, c.scl.d(), x, y);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1323,7 +1336,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
     c.wvec.ensure((size_t)n * sizeof(double));
     c.rvec.ensure((size_t)n * sizeof(double));
     c.gspart.ensure((size_t)gs_blocks(n) * (m + 2) * sizeof(double));
-    c.givbuf.ensure((size_t)(ldH * m + 3 * (m + 2) + 2) * sizeof(double));
+    c.givbuf.ensure((size_t)(ldH * m + 3 * (m + 2)) * sizeof(double));
     if (!c.gscnt.ptr) {
         c.gscnt.ensure(sizeof(unsigned));
         HIPC(hipMemsetAsync(c.gscnt.ptr, 0, sizeof(unsigned), c.stream));
@@ -1341,7 +1354,11 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
     ga.cs = ga.H + ldH * m;
     ga.sn = ga.cs + (m + 2);
     ga.g = ga.sn + (m + 2);
-    double *resd = ga.g + (m + 2);  // residual estimates of the two latest steps
+    // residual estimates of the two latest steps: coherent pinned host memory
+    // that the Givens step writes directly (read after the step's event)
+    if (!c.hres) HIPC(hipHostMalloc((void **)&c.hres, 2 * sizeof(double), hipHostMallocCoherent));
+    double *resdev = nullptr;
+    HIPC(hipHostGetDevicePointer((void **)&resdev, c.hres, 0));
     HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
     // ||b||
     launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, const_cast<double *>(b), part, cnt, h);
@@ -1354,7 +1371,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
     relres = 0.0;
     if (bn == 0.0) return BIM_OK;
     double *gh = c.hhost + 256;  // host image of g at a restart
-    volatile double *resh = c.hhost + 2;
+    volatile double *resh = c.hres;
     bool first = true;
     while (true) {
         // r = b - A x
@@ -1366,8 +1383,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
             launch_scale_add(c.stream, n, 1.0, b, -1.0, c.rvec.d());
         }
         first = false;
-        launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, c.rvec.d(), part, cnt, h);
-        launch_gs_scale(c.stream, n, c.rvec.d(), h, V);
+        launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, c.rvec.d(), part, cnt, h, GivensArgs{}, V);
         HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
         const double beta = c.hhost[0];
@@ -1384,13 +1400,10 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         auto step = [&](int k) {
             apply_operator(c, V + (long)k * n, w, wt);
             GivensArgs gk = ga;
-            gk.res = resd + (k & 1);
+            gk.res = resdev + (k & 1);  // written by the device into pinned host memory
             launch_gs_dots(c.stream, n, k + 1, V, n, w, part, cnt, h);
             launch_gs_update_dots(c.stream, n, k + 1, V, n, h, w, part, cnt, h2);
-            launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h, gk);
-            launch_gs_scale(c.stream, n, w, h + k + 1, V + (long)(k + 1) * n);
-            HIPC(hipMemcpyAsync((void *)(resh + (k & 1)), resd + (k & 1), sizeof(double), hipMemcpyDeviceToHost,
-                                c.stream));
+            launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h, gk, V + (long)(k + 1) * n);
             HIPC(hipEventRecord(c.ev[k & 1], c.stream));
         };
         step(0);

@@ -59,6 +59,20 @@ struct PipeDrops {
 
 // Stored double-layer rows of one drop applied to a density: out[c][t] +=
 // w sum_pairs M[t][pair] . u (k_dl_apply_multi takes several drops).
+// One analysis job of the batched kernel: grid values -> coefficients of
+// degree p for ncomp components; with cx set the output is csc * cx - P[v]
+// (the Galerkin combine of the second-kind operator) instead of P[v].
+struct AnaJob {
+    const double *v;      // component c grid at v + c * vstride
+    const double *L;      // Legendre tables [3][q+1][ldn] (kind 0 used)
+    const double *wq;     // (pi/q) w_j
+    double *coef;         // component c at coef + c * cstride
+    long vstride, cstride;
+    int p, q, ldn, ncomp;
+    const double *cx;     // optional: coefficients combined into the output (same layout as coef)
+    double csc;
+};
+
 struct DlJob {
     const double *M;
     const double *u;   // density coefficients of the drop, component stride ustride

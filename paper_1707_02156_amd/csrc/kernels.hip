@@ -582,7 +582,7 @@ template <bool UPD, bool NRM>
 __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__restrict__ V, long ld,
                                             const double *__restrict__ hin, double *__restrict__ w,
                                             double *__restrict__ part, unsigned *__restrict__ cnt,
-                                            double *__restrict__ hout, GivensArgs ga)
+                                            double *__restrict__ hout, GivensArgs ga, double *__restrict__ vout)
 {
     __shared__ double sacc[4][kGsChunk];
     __shared__ bool last;
@@ -642,21 +642,42 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
     __syncthreads();
     if (!last) return;
     __threadfence();
+    // Sum i of nsum: G threads add its block partials in a fixed strided
+    // order, then a butterfly inside the group (G divides the wavefront)
     const int nsum = NRM ? 1 : kv;
-    for (int i = threadIdx.x; i < nsum; i += 256) {
-        const double *pi = part + (long)i * nb;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int q = 0;
-        for (; q + 4 <= nb; q += 4) {
-            s0 += __hip_atomic_load(pi + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s1 += __hip_atomic_load(pi + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s2 += __hip_atomic_load(pi + q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s3 += __hip_atomic_load(pi + q + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ double snrm;
+    {
+        int G = 64;
+        while (G > 1 && G * nsum > 256) G >>= 1;
+        const int i = threadIdx.x / G, g = threadIdx.x % G;
+        double s = 0.0;
+        if (i < nsum) {
+            const double *pi = part + (long)i * nb;
+            for (int q = g; q < nb; q += G) s += __hip_atomic_load(pi + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        for (; q < nb; ++q) s0 += __hip_atomic_load(pi + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double s = (s0 + s1) + (s2 + s3);
-        if (NRM) hout[kv] = sqrt(s);
-        else hout[i] = s;
+        for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (i < nsum && g == 0) {
+            if (NRM) {
+                hout[kv] = sqrt(s);
+                snrm = sqrt(s);
+            } else {
+                hout[i] = s;
+            }
+        }
+    }
+    if (NRM && vout) {
+        // v = w / ||w|| (zero norm: v = 0). The acquire fence above invalidated
+        // this unit's L1, so plain loads see the other blocks' w.
+        __syncthreads();
+        const double t = snrm, ti = t > 0.0 ? 1.0 / t : 0.0;
+        // n is even and both vectors 16-byte aligned; 16 loads in flight per thread
+        const double2 *w2 = reinterpret_cast<const double2 *>(w);
+        double2 *v2 = reinterpret_cast<double2 *>(vout);
+#pragma unroll 16
+        for (long e = threadIdx.x; e < n / 2; e += 256) {
+            const double2 a = w2[e];
+            v2[e] = make_double2(a.x * ti, a.y * ti);
+        }
     }
     if (NRM && UPD)
         for (int i = threadIdx.x; i < kv; i += 256) hout[i] += hin[i];
@@ -684,7 +705,8 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
             const double gk = ga.g[kc];
             ga.g[kc + 1] = -sr * gk;
             ga.g[kc] = cr * gk;
-            ga.res[0] = fabs(ga.g[kc + 1]) / ga.bnorm;
+            ga.res[0] = fabs(ga.g[kc + 1]) / ga.bnorm;  // host-visible memory
+            __threadfence_system();
         }
     }
     if (threadIdx.x == 0) atomicExch(cnt, 0u);
@@ -825,13 +847,14 @@ void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x
 
 long gs_blocks(long n) { return (n + kGsChunk - 1) / kGsChunk; }
 int gs_max_vectors() { return 256; }
+constexpr long kGsFuseScale = 64;  // blocks up to which the last block also writes the scaled vector
 
 // pass 1 of classical Gram-Schmidt: h[i] = V_i . w, i < kv
 void launch_gs_dots(hipStream_t st, long n, int kv, const double *V, long ld, double *w, double *part,
                     unsigned *cnt, double *h)
 {
     hipLaunchKernelGGL((k_gs<false, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, nullptr, w, part,
-                       cnt, h, GivensArgs{});
+                       cnt, h, GivensArgs{}, nullptr);
 }
 
 // w -= V h1, then h2[i] = V_i . w
@@ -839,20 +862,24 @@ void launch_gs_update_dots(hipStream_t st, long n, int kv, const double *V, long
                            double *part, unsigned *cnt, double *h2)
 {
     hipLaunchKernelGGL((k_gs<true, false>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h1, w, part, cnt,
-                       h2, GivensArgs{});
+                       h2, GivensArgs{}, nullptr);
 }
 
 // w -= V h2, h[i] += h2[i], h[kv] = ||w||; with kv = 0 just h[0] = ||w||.
 // With ga.H set (kv > 0) the last block also applies the Givens update.
+// vout (if set) receives w / ||w||.
 void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long ld, const double *h2, double *w,
-                           double *part, unsigned *cnt, double *h, const GivensArgs &ga)
+                           double *part, unsigned *cnt, double *h, const GivensArgs &ga, double *vout)
 {
+    const long nb = gs_blocks(n);
+    const bool al = n % 2 == 0 && (((uintptr_t)w | (uintptr_t)vout) & 15) == 0;
+    double *vk = nb <= kGsFuseScale && al ? vout : nullptr;
     if (kv > 0)
-        hipLaunchKernelGGL((k_gs<true, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, kv, V, ld, h2, w, part, cnt,
-                           h, ga);
+        hipLaunchKernelGGL((k_gs<true, true>), dim3(nb), dim3(256), 0, st, n, kv, V, ld, h2, w, part, cnt, h, ga, vk);
     else
-        hipLaunchKernelGGL((k_gs<false, true>), dim3(gs_blocks(n)), dim3(256), 0, st, n, 0, V, ld, nullptr, w, part,
-                           cnt, h, GivensArgs{});
+        hipLaunchKernelGGL((k_gs<false, true>), dim3(nb), dim3(256), 0, st, n, 0, V, ld, nullptr, w, part, cnt, h,
+                           GivensArgs{}, vk);
+    if (vout && !vk) hipLaunchKernelGGL(k_gs_scale, dim3(nblk(n)), dim3(256), 0, st, n, w, h + kv, vout);
 }
 
 void launch_backsub(hipStream_t st, int k, const double *H, long ldH, const double *g, double *y)

@@ -106,15 +106,6 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
     }
 }
 
-struct AnaJob {
-    const double *v;      // component c grid at v + c * vstride
-    const double *L;      // Legendre tables [3][q+1][ldn] (kind 0 used)
-    const double *wq;     // (pi/q) w_j
-    double *coef;         // component c at coef + c * cstride
-    long vstride, cstride;
-    int p, q, ldn, ncomp;
-};
-
 constexpr int kMaxAnaJobs = 24;
 struct AnaJobs {
     int n;
@@ -171,8 +162,14 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
             sr = fma(w, F[2 * (j * kAnaMC + mm)], sr);
             si = fma(w, F[2 * (j * kAnaMC + mm) + 1], si);
         }
-        out[2 * e] = sr;
-        out[2 * e + 1] = si;
+        if (J.cx) {  // Galerkin combine: csc x - P[...]
+            const double *x = J.cx + c * J.cstride;
+            out[2 * e] = fma(J.csc, x[2 * e], -sr);
+            out[2 * e + 1] = fma(J.csc, x[2 * e + 1], -si);
+        } else {
+            out[2 * e] = sr;
+            out[2 * e + 1] = si;
+        }
     }
 }
 
