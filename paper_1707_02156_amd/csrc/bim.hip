@@ -100,7 +100,8 @@ struct SynJob {
     long cstride, ostride, fstride;
     int p, q, ldn, ncomp, mask;
 };
-void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n);
+void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n, double *z0 = nullptr, long nz0 = 0,
+                        double *z1 = nullptr, long nz1 = 0);
 void launch_anal_batch(hipStream_t st, const AnaJob *jobs, int n);
 size_t anal_batch_lds(int p, int q);
 bool sing_fused_fits(int p, int qs, bool sl, bool dl);
@@ -469,9 +470,16 @@ static SynJob syn_job(Ctx &c, int p, int q, int ncomp, const double *coef, long 
     return j;
 }
 
-static void syn_run(Ctx &c, const std::vector<SynJob> &jobs)
+// Batched synthesis; the optional ranges z0[nz0], z1[nz1] are cleared by the
+// same launch (stream-ordered before everything enqueued after it).
+static void syn_run(Ctx &c, const std::vector<SynJob> &jobs, double *z0 = nullptr, long nz0 = 0,
+                    double *z1 = nullptr, long nz1 = 0)
 {
-    if (jobs.empty()) return;
+    if (jobs.empty()) {
+        if (nz0 > 0) HIPC(hipMemsetAsync(z0, 0, nz0 * sizeof(double), c.stream));
+        if (nz1 > 0) HIPC(hipMemsetAsync(z1, 0, nz1 * sizeof(double), c.stream));
+        return;
+    }
     double fl = 0.0, by = 0.0;
     for (auto &j : jobs) {
         const int nout = __builtin_popcount(j.mask);
@@ -479,7 +487,7 @@ static void syn_run(Ctx &c, const std::vector<SynJob> &jobs)
         by += (double)j.ncomp * (2.0 * ncoef(j.p) + nout * npts(j.q)) * 8.0;
     }
     ProfScope ps(c, "synthesis", fl, by);
-    launch_synth_batch(c.stream, jobs.data(), (int)jobs.size());
+    launch_synth_batch(c.stream, jobs.data(), (int)jobs.size(), z0, nz0, z1, nz1);
 }
 
 static void synth(Ctx &c, int p, int q, int nf, const double *coef, long cstride, int dt, int dp, double *out,
@@ -914,7 +922,8 @@ static void run_near(Ctx &c, int kind, const double *dens, const std::vector<dou
 
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
 // and upsampled nodes of the drops whose flag is set.
-static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need)
+static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need, double *z0 = nullptr,
+                          long nz0 = 0, double *z1 = nullptr, long nz1 = 0)
 {
     std::vector<SynJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
@@ -923,7 +932,7 @@ static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &n
         jobs.push_back(syn_job(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0x1, c.s0d.d() + d.toff, c.T, 0));
         jobs.push_back(syn_job(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0x1, c.s1d.d() + d.uoff, c.S1, 0));
     }
-    syn_run(c, jobs);
+    syn_run(c, jobs, z0, nz0, z1, nz1);
 }
 
 // Singular self-integral of drop i with density coefficients dens [3][Ctot]
@@ -1189,9 +1198,9 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
             if (wt[(size_t)i * c.nd + j] != 0.0) need[j] = 1;
     for (const NearItem &it : c.near_h)
         if (wt[(size_t)it.i * c.nd + it.j] != 0.0) selfraw[it.j] = 1;
-    HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
-    if (!c.near_h.empty()) HIPC(hipMemsetAsync(c.near_self.ptr, 0, 3 * c.T * sizeof(double), c.stream));
-    density_nodes(c, ucoef, need);
+    // acc (and near_self) cleared by the density synthesis launch
+    density_nodes(c, ucoef, need, c.acc.d(), 3 * c.T, c.near_h.empty() ? nullptr : c.near_self.d(),
+                  c.near_h.empty() ? 0 : 3 * c.T);
     // stored rows: build those missing (pipeline drops grouped by degree)
     std::vector<int> build;
     for (int i = 0; i < c.nd; ++i) {
@@ -1241,8 +1250,7 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
 {
     build_regions(c);
     std::vector<char> need(c.nd, 1);
-    HIPC(hipMemsetAsync(c.acc.ptr, 0, 3 * c.T * sizeof(double), c.stream));
-    density_nodes(c, fcoef, need);
+    density_nodes(c, fcoef, need, c.acc.d(), 3 * c.T);  // acc cleared by the same launch
     // pipeline drops grouped by degree, separately with and without the rows
     std::vector<int> with_rows, without_rows;
     for (int i = 0; i < c.nd; ++i) {

@@ -32,6 +32,8 @@ struct SynJob {
 constexpr int kMaxSynJobs = 20;
 struct SynJobs {
     int n;
+    double *zero[2];  // optional ranges cleared by the launch (accumulators of the pass that follows)
+    long nzero[2];
     SynJob j[kMaxSynJobs];
 };
 
@@ -40,6 +42,13 @@ constexpr int kSynK = 64;  // longitudes k (and k + q) per synthesis block
 __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
 {
     __shared__ double G[3 * 3 * 65 * 2];  // [c][kind][m][re,im]
+    {
+        const long nb = (long)gridDim.x * gridDim.y * gridDim.z;
+        const long bid = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        for (int z = 0; z < 2; ++z)
+            if (jobs.zero[z])
+                for (long i = bid * 256 + threadIdx.x; i < jobs.nzero[z]; i += nb * 256) jobs.zero[z][i] = 0.0;
+    }
     const SynJob &J = jobs.j[blockIdx.y];
     const int j = blockIdx.x;
     const int k0 = blockIdx.z * kSynK;
@@ -176,11 +185,17 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
 // ----------------------------------------------------------------------------
 // host side: job collectors that flush full batches
 // ----------------------------------------------------------------------------
-void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n)
+void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n, double *z0, long nz0, double *z1, long nz1)
 {
     for (int o = 0; o < n; o += kMaxSynJobs) {
         SynJobs b{};
         b.n = std::min(kMaxSynJobs, n - o);
+        if (o == 0) {
+            b.zero[0] = nz0 > 0 ? z0 : nullptr;
+            b.nzero[0] = nz0;
+            b.zero[1] = nz1 > 0 ? z1 : nullptr;
+            b.nzero[1] = nz1;
+        }
         int maxq = 0;
         for (int i = 0; i < b.n; ++i) {
             b.j[i] = jobs[o + i];
