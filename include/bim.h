@@ -181,6 +181,45 @@ int bim_apply_double_layer(bim_ctx ctx, const double *u_coef, double *out, int m
  * stops at gmres_maxit above the tolerance. */
 int bim_eval_velocity(bim_ctx ctx, double *u_out, int out_kind, bim_report *rep);
 
+/* One coupled step of the drops and their insoluble surfactant (Sec. 3,
+ * Algorithm 1): explicit midpoint rule for the drop coefficients and the
+ * second-order IMEX scheme of Sec. 3.2 for the surfactant coefficients set by
+ * bim_set_tension (without them only the drops move):
+ *   u0 = velocity(t); x_h = x + dt/2 u0;
+ *   (I - dt/(2 Pe) L) Gamma_h = Gamma + dt/2 fE(x, u0, Gamma) by GMRES with the
+ *   sphere's diagonal 1 + dt/(2 Pe) n(n+1)/R^2 as right preconditioner
+ *   (R the drop's volume-equivalent radius at x_h, Sec. 3.2.1);
+ *   u_h = velocity(t + dt/2); x' = x + dt u_h;
+ *   Gamma' = Gamma + dt (fE(x_h, u_h, Gamma_h) + L Gamma_h / Pe),
+ * with L the Laplace-Beltrami operator and fE = -Gamma div_s u (the rate at
+ * nodes that move with the velocity; it conserves surfactant mass), both
+ * evaluated on the degree U_geom p grid and projected to degree p.
+ * Error estimates: drop = ||x'_midpoint - x'_Euler|| / ||x'|| (2-norm of all
+ * position coefficients); surfactant = max over drops of the relative change
+ * of int Gamma dS (conservation error). The step is accepted when
+ * max(err) < tol, or always when tol <= 0; the context then holds the new
+ * state, otherwise it keeps the state at t. dt_next = dt (0.9 tol/err)^(1/2)
+ * (dt when tol <= 0 or err = 0). Pe > 0; Pe = +infinity switches diffusion
+ * off. Errors: BIM_EINVAL (dt <= 0 or not finite, Pe <= 0 or NaN, tol not
+ * finite), BIM_ESTATE (no drops), BIM_ENOCONV (a GMRES solve did not
+ * converge; the state at t is kept). rep may be NULL. */
+typedef struct {
+    double dt_next;
+    double err_drop;
+    double err_surf;
+    double mass0, mass1;   /* total surfactant over all drops at t and at t + dt */
+    int accepted;
+    int gmres_velocity[2]; /* GMRES iterations of the velocity solves at t and t + dt/2 */
+    int gmres_imex;        /* GMRES iterations of the IMEX stage solve (0 without diffusion) */
+    double ms_total;
+} bim_step_report;
+int bim_time_step(bim_ctx ctx, double dt, double Pe, double tol, bim_step_report *rep);
+
+/* Current drop coefficients ([3][sum (p+1)(p+2)], component-major) and
+ * surfactant coefficients ([sum (p+1)(p+2)]); either pointer may be NULL.
+ * BIM_ESTATE when gamma_coef is requested and no surfactant was set. */
+int bim_get_state(bim_ctx ctx, double *xcoef, double *gamma_coef, int mem_kind);
+
 /* Stand-alone transforms on the context's device and stream (Sec. 1.1, 2.1).
  * Synthesis: nf scalar fields of degree p (each (p+1)(p+2) doubles,
  * consecutive) to grid values on the degree-q grid (q >= p), derivative

@@ -68,6 +68,26 @@ class bim_report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class bim_step_report(ctypes.Structure):
+    _fields_ = [
+        ("dt_next", ctypes.c_double),
+        ("err_drop", ctypes.c_double),
+        ("err_surf", ctypes.c_double),
+        ("mass0", ctypes.c_double),
+        ("mass1", ctypes.c_double),
+        ("accepted", ctypes.c_int),
+        ("gmres_velocity", ctypes.c_int * 2),
+        ("gmres_imex", ctypes.c_int),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["gmres_velocity"] = list(self.gmres_velocity)
+        d["accepted"] = bool(self.accepted)
+        return d
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -88,6 +108,8 @@ EXPORTS = {
     "bim_single_layer": ([_vp, _vp, _vp, _i], _i),
     "bim_apply_double_layer": ([_vp, _vp, _vp, _i, _i], _i),
     "bim_eval_velocity": ([_vp, _vp, _i, ctypes.POINTER(bim_report)], _i),
+    "bim_time_step": ([_vp, _d, _d, _d, ctypes.POINTER(bim_step_report)], _i),
+    "bim_get_state": ([_vp, _vp, _vp, _i], _i),
     "bim_sh_synthesize": ([_vp, _i, _i, _i, _vp, _i, _i, _vp, _i], _i),
     "bim_sh_analyze": ([_vp, _i, _i, _i, _vp, _vp, _i], _i),
     "bim_synchronize": ([_vp], _i),
@@ -398,6 +420,29 @@ class Context:
         rep = bim_eval_velocity(self.h, out, coefficients, allow_noconv)
         res = unpack_coefficients(out, self.ps) if coefficients else unpack_grid(out, self.ps)
         return res, rep
+
+    def time_step(self, dt, Pe=float("inf"), tol=0.0):
+        """One coupled drop / surfactant step (bim_time_step); returns the report
+        as a dict (dt_next, err_drop, err_surf, mass0, mass1, accepted, ...)."""
+        rep = bim_step_report()
+        _check(self.h, lib().bim_time_step(self.h, float(dt), float(Pe), float(tol), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def state(self, surfactant=True):
+        """(per-drop position coefficients, per-drop surfactant coefficients or None)."""
+        nc = self.ncoef_total()
+        x = np.zeros(3 * nc)
+        g = np.zeros(nc) if surfactant else None
+        _check(self.h, lib().bim_get_state(self.h, x.ctypes.data, g.ctypes.data if surfactant else None, 0))
+        xs = unpack_coefficients(x, self.ps)
+        if not surfactant:
+            return xs, None
+        gs, o = [], 0
+        for p in self.ps:
+            n = 2 * ncoef(p)
+            gs.append(g[o:o + n].reshape(ncoef(p), 2).copy())
+            o += n
+        return xs, gs
 
 
 class Server:

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -122,6 +123,9 @@ void launch_gs_update_norm(hipStream_t st, long n, int kv, const double *V, long
                            double *vout = nullptr);
 void launch_backsub(hipStream_t st, int k, const double *H, long ldH, const double *g, double *y);
 void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm, double *v);
+void launch_surf_terms(hipStream_t st, const SurfJob *jobs, int n);
+void launch_mul(hipStream_t st, long n, const double *d, const double *x, double *y);
+void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, const double *y, double *out);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 
 static const double kPi = 3.14159265358979323846;
@@ -246,6 +250,9 @@ struct Ctx {
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
     DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt, givbuf;
+    // time step: states, stage velocities and surfactant terms, surface fields and outputs
+    DBuf ts_x0, ts_g0, ts_u0, ts_uh, ts_xh, ts_gh, ts_fe, ts_ki, ts_ke, ts_sinv, ts_w, ts_lw, ts_z, ts_syn, ts_grid,
+        ts_acc;
     hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
     double *hres = nullptr;        // pinned, coherent: GMRES residual estimates written by the device
@@ -1332,10 +1339,11 @@ static void apply_operator(Ctx &c, const double *x, double *y, const std::vector
 // step behind, through an event), so the device never waits for the host; a
 // step enqueued after convergence is discarded.
 // --------------------------------------------------------------------------
-static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, double tol, int &iters,
-                 double &relres, int &nmv)
+using OpFn = std::function<void(const double *, double *)>;
+
+static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *x, double tol, int &iters,
+                    double &relres, int &nmv)
 {
-    const long n = 3 * c.Ctot;
     const int m = std::max(1, std::min(c.opt.gmres_restart, gs_max_vectors() - 1));
     const long ldH = m + 2;
     c.V.ensure((size_t)(m + 1) * n * sizeof(double));
@@ -1386,7 +1394,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         if (first) {
             HIPC(hipMemcpyAsync(c.rvec.ptr, b, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
         } else {
-            apply_operator(c, x, c.rvec.d(), wt);
+            apply(x, c.rvec.d());
             ++nmv;
             launch_scale_add(c.stream, n, 1.0, b, -1.0, c.rvec.d());
         }
@@ -1406,7 +1414,7 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         bool conv = false;
         // step k: Arnoldi vector k + 1, column k of R, residual estimate -> resh[k & 1]
         auto step = [&](int k) {
-            apply_operator(c, V + (long)k * n, w, wt);
+            apply(V + (long)k * n, w);
             GivensArgs gk = ga;
             gk.res = resdev + (k & 1);  // written by the device into pinned host memory
             launch_gs_dots(c.stream, n, k + 1, V, n, w, part, cnt, h);
@@ -1435,6 +1443,15 @@ static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &
         if (conv) return BIM_OK;
         if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
     }
+}
+
+// GMRES on the second-kind operator of the velocity (coefficients [3][Ctot])
+static int gmres(Ctx &c, const double *b, double *x, const std::vector<double> &wt, double tol, int &iters,
+                 double &relres, int &nmv)
+{
+    return gmres_op(
+        c, 3 * c.Ctot, [&](const double *u, double *y) { apply_operator(c, u, y, wt); }, b, x, tol, iters, relres,
+        nmv);
 }
 
 // --------------------------------------------------------------------------
@@ -1807,6 +1824,258 @@ int bim_single_layer(bim_ctx h, const double *f_coef, double *out, int mem_kind)
     });
 }
 
+// --------------------------------------------------------------------------
+// Drop and surfactant time step (Sec. 3, Algorithm 1): explicit midpoint rule
+// for the drops, second-order IMEX for the surfactant, conservation error.
+// --------------------------------------------------------------------------
+// per-drop offsets into the surface-field buffer (33 fields on the degree
+// U_geom p grid) and into the grid outputs (2 fields)
+static void surf_layout(Ctx &c, std::vector<long> &so, std::vector<long> &go, long &stot, long &gtot)
+{
+    so.resize(c.nd);
+    go.resize(c.nd);
+    stot = gtot = 0;
+    for (int i = 0; i < c.nd; ++i) {
+        const long np = npts(c.drops[i].qg);
+        so[i] = stot;
+        go[i] = gtot;
+        stot += 33 * np;
+        gtot += 2 * np;
+    }
+}
+
+// synthesis on the degree U_geom p grid of each drop: x (6 derivative fields
+// x 3 components), Gamma (6 fields), u (3 fields x 3 components); a null
+// argument leaves those fields as they are
+static void surf_synth(Ctx &c, const double *x, const double *g, const double *u)
+{
+    std::vector<long> so, go;
+    long stot, gtot;
+    surf_layout(c, so, go, stot, gtot);
+    c.ts_syn.ensure((size_t)stot * sizeof(double));
+    std::vector<SynJob> jobs;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        const long np = npts(d.qg);
+        double *s = c.ts_syn.d() + so[i];
+        if (x) jobs.push_back(syn_job(c, d.p, d.qg, 3, x + d.coff, c.Ctot, 0x3f, s, np, 3 * np));
+        if (g) jobs.push_back(syn_job(c, d.p, d.qg, 1, g + d.coff, 0, 0x3f, s + 18 * np, 0, np));
+        if (u) jobs.push_back(syn_job(c, d.p, d.qg, 3, u + d.coff, c.Ctot, 0x7, s + 24 * np, np, 3 * np));
+    }
+    syn_run(c, jobs);
+}
+
+// surface terms from the fields in ts_syn: -Gamma div_s u into fEc and the
+// Laplace-Beltrami of Gamma into lgc (coefficients to degree p, layout
+// [Ctot]); int Gamma dS into mass[nd] and the enclosed volume into vol[nd]
+static void surf_terms(Ctx &c, bool gam, double *fEc, double *lgc, double *mass, double *vol)
+{
+    std::vector<long> so, go;
+    long stot, gtot;
+    surf_layout(c, so, go, stot, gtot);
+    c.ts_grid.ensure((size_t)gtot * sizeof(double));
+    if (mass) HIPC(hipMemsetAsync(mass, 0, c.nd * sizeof(double), c.stream));
+    if (vol) HIPC(hipMemsetAsync(vol, 0, c.nd * sizeof(double), c.stream));
+    std::vector<SurfJob> jobs;
+    std::vector<AnaJob> ajobs;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        const long np = npts(d.qg);
+        SurfJob j{};
+        j.syn = c.ts_syn.d() + so[i];
+        j.wreg = grid(c, d.qg, d.p).wreg.d();
+        j.fE = fEc ? c.ts_grid.d() + go[i] : nullptr;
+        j.lg = lgc ? c.ts_grid.d() + go[i] + np : nullptr;
+        j.mass = mass ? mass + i : nullptr;
+        j.vol = vol ? vol + i : nullptr;
+        j.np = np;
+        j.q = d.qg;
+        j.gam = gam ? 1 : 0;
+        jobs.push_back(j);
+        if (fEc) ajobs.push_back(ana_job(c, d.qg, d.p, 1, j.fE, 0, fEc + d.coff, 0));
+        if (lgc) ajobs.push_back(ana_job(c, d.qg, d.p, 1, j.lg, 0, lgc + d.coff, 0));
+    }
+    {
+        ProfScope ps(c, "surface_terms", 0.0, 0.0);
+        launch_surf_terms(c.stream, jobs.data(), (int)jobs.size());
+    }
+    if (!ajobs.empty()) ana_run(c, ajobs);
+}
+
+static void dcopy(Ctx &c, double *dst, const double *src, long n)
+{
+    HIPC(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+}
+
+static std::vector<double> dget(Ctx &c, const double *src, long n)
+{
+    std::vector<double> h(n);
+    HIPC(hipMemcpyAsync(h.data(), src, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    return h;
+}
+
+static int solve_velocity(Ctx &c, int &iters, double &relres, int &nmv);
+
+// One step from the context's state. On return the context holds the state
+// at t + dt when accepted, else the state at t.
+static int time_step(Ctx &c, double dt, double Pe, double tol, bim_step_report &r)
+{
+    const long n3 = 3 * c.Ctot, n1 = c.Ctot;
+    const bool surf = c.have_gamma;
+    const bool diff = surf && std::isfinite(Pe);
+    for (DBuf *b : {&c.ts_x0, &c.ts_u0, &c.ts_uh, &c.ts_xh}) b->ensure((size_t)n3 * sizeof(double));
+    for (DBuf *b : {&c.ts_g0, &c.ts_gh, &c.ts_fe, &c.ts_ki, &c.ts_ke, &c.ts_sinv, &c.ts_w, &c.ts_lw, &c.ts_z})
+        b->ensure((size_t)n1 * sizeof(double));
+    c.ts_acc.ensure((size_t)3 * c.nd * sizeof(double));
+    double *m0 = c.ts_acc.d(), *m1 = m0 + c.nd, *vol = m1 + c.nd;
+    double *x0 = c.ts_x0.d(), *g0 = c.ts_g0.d(), *u0 = c.ts_u0.d(), *uh = c.ts_uh.d(), *xh = c.ts_xh.d(),
+           *gh = c.ts_gh.d(), *fe = c.ts_fe.d(), *ki = c.ts_ki.d(), *ke = c.ts_ke.d();
+    dcopy(c, x0, c.xc.d(), n3);
+    if (surf) dcopy(c, g0, c.gc.d(), n1);
+    auto restore = [&]() {
+        dcopy(c, c.xc.d(), x0, n3);
+        if (surf) dcopy(c, c.gc.d(), g0, n1);
+        invalidate(c);
+        HIPC(hipStreamSynchronize(c.stream));
+    };
+    // velocity at t
+    int it = 0, nmv = 0;
+    double rr = 0.0;
+    int rc = solve_velocity(c, it, rr, nmv);
+    r.gmres_velocity[0] = it;
+    if (rc != BIM_OK) {
+        restore();
+        return rc;
+    }
+    dcopy(c, u0, c.xsol.d(), n3);
+    if (surf) {
+        surf_synth(c, x0, g0, u0);
+        surf_terms(c, true, fe, nullptr, m0, nullptr);
+    }
+    // half step: x + dt/2 u; (I - dt/(2 Pe) L) Gamma_h = Gamma + dt/2 fE
+    launch_axpby(c.stream, n3, 1.0, x0, 0.5 * dt, u0, xh);
+    r.gmres_imex = 0;
+    if (surf) {
+        launch_axpby(c.stream, n1, 1.0, g0, 0.5 * dt, fe, gh);  // right-hand side, then the stage value
+        if (diff) {
+            const double cf = 0.5 * dt / Pe;
+            surf_synth(c, xh, nullptr, nullptr);
+            surf_terms(c, false, nullptr, nullptr, nullptr, vol);
+            // right preconditioner: the operator's diagonal on the sphere of each
+            // drop's volume-equivalent radius, 1 + cf n (n + 1) / R^2 (Sec. 3.2.1)
+            const std::vector<double> hv = dget(c, vol, c.nd);
+            std::vector<double> sinv(n1);
+            for (int i = 0; i < c.nd; ++i) {
+                const Drop &d = c.drops[i];
+                const double R = std::cbrt(3.0 * hv[i] / (4.0 * kPi));
+                for (int n = 0; n <= d.p; ++n)
+                    for (int m = 0; m <= n; ++m) {
+                        const long e = d.coff + 2L * (n * (n + 1) / 2 + m);
+                        sinv[e] = sinv[e + 1] = 1.0 / (1.0 + cf * n * (n + 1) / (R * R));
+                    }
+            }
+            HIPC(hipMemcpyAsync(c.ts_sinv.ptr, sinv.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+            double *si = c.ts_sinv.d(), *w = c.ts_w.d(), *lw = c.ts_lw.d(), *z = c.ts_z.d();
+            auto op = [&](const double *zin, double *y) {  // y = (I - cf L) S^-1 zin
+                launch_mul(c.stream, n1, si, zin, w);
+                surf_synth(c, nullptr, w, nullptr);
+                surf_terms(c, true, nullptr, lw, nullptr, nullptr);
+                launch_axpby(c.stream, n1, 1.0, w, -cf, lw, y);
+            };
+            int nm2 = 0;
+            rc = gmres_op(c, n1, op, gh, z, c.opt.gmres_tol, it, rr, nm2);
+            r.gmres_imex = it;
+            if (rc != BIM_OK) {
+                restore();
+                return rc;
+            }
+            launch_mul(c.stream, n1, si, z, gh);
+            // L Gamma_h (the implicit stage slope times Pe)
+            surf_synth(c, nullptr, gh, nullptr);
+            surf_terms(c, true, nullptr, ki, nullptr, nullptr);
+        }
+    }
+    // velocity at t + dt/2
+    dcopy(c, c.xc.d(), xh, n3);
+    if (surf) dcopy(c, c.gc.d(), gh, n1);
+    rc = solve_velocity(c, it, rr, nmv);
+    r.gmres_velocity[1] = it;
+    if (rc != BIM_OK) {
+        restore();
+        return rc;
+    }
+    dcopy(c, uh, c.xsol.d(), n3);
+    // full step: x0 + dt u_h; Gamma0 + dt (fE_h + L Gamma_h / Pe)
+    launch_axpby(c.stream, n3, 1.0, x0, dt, uh, c.xc.d());
+    double mass0 = 0.0, mass1 = 0.0, esurf = 0.0;
+    if (surf) {
+        surf_synth(c, xh, gh, uh);
+        surf_terms(c, true, ke, nullptr, nullptr, nullptr);
+        if (diff) launch_axpby(c.stream, n1, 1.0, ke, 1.0 / Pe, ki, ke);
+        launch_axpby(c.stream, n1, 1.0, g0, dt, ke, c.gc.d());
+        surf_synth(c, c.xc.d(), c.gc.d(), nullptr);
+        surf_terms(c, true, nullptr, nullptr, m1, nullptr);
+        const std::vector<double> hm = dget(c, m0, 2 * c.nd);
+        for (int i = 0; i < c.nd; ++i) {
+            mass0 += hm[i];
+            mass1 += hm[c.nd + i];
+            esurf = std::max(esurf, std::fabs(hm[c.nd + i] - hm[i]) / std::fabs(hm[i]));
+        }
+    }
+    // drop error: midpoint against the explicit Euler row, ||x1 - x_E|| = dt ||u_h - u_0||
+    const std::vector<double> hu0 = dget(c, u0, n3), huh = dget(c, uh, n3), hx1 = dget(c, c.xc.d(), n3);
+    double sd = 0.0, sx = 0.0;
+    for (long e = 0; e < n3; ++e) {
+        const double d = dt * (huh[e] - hu0[e]);
+        sd += d * d;
+        sx += hx1[e] * hx1[e];
+    }
+    r.err_drop = std::sqrt(sd / sx);
+    r.err_surf = esurf;
+    r.mass0 = mass0;
+    r.mass1 = mass1;
+    const double err = std::max(r.err_drop, r.err_surf);
+    r.accepted = (tol <= 0.0 || err < tol) ? 1 : 0;
+    r.dt_next = (tol > 0.0 && err > 0.0) ? dt * std::sqrt(0.9 * tol / err) : dt;
+    if (!r.accepted) restore();
+    invalidate(c);
+    HIPC(hipStreamSynchronize(c.stream));
+    return BIM_OK;
+}
+
+int bim_time_step(bim_ctx h, double dt, double Pe, double tol, bim_step_report *rep)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(std::isfinite(dt) && dt > 0.0, BIM_EINVAL, "dt must be finite and > 0");
+        REQUIRE(Pe > 0.0 && !std::isnan(Pe), BIM_EINVAL, "Pe must be > 0 (infinity: no diffusion)");
+        REQUIRE(std::isfinite(tol), BIM_EINVAL, "tol must be finite");
+        auto t0 = std::chrono::steady_clock::now();
+        bim_step_report r{};
+        const int rc = time_step(c, dt, Pe, tol, r);
+        r.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = r;
+        return rc;
+    });
+}
+
+int bim_get_state(bim_ctx h, double *xcoef, double *gamma_coef, int mem_kind)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(mem_kind == BIM_MEM_HOST || mem_kind == BIM_MEM_DEVICE, BIM_EINVAL, "bad mem_kind");
+        REQUIRE(!gamma_coef || c.have_gamma, BIM_ESTATE, "no surfactant set (bim_set_tension with gamma_coef)");
+        if (xcoef) copy_out(c, xcoef, c.xc.ptr, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+        if (gamma_coef) copy_out(c, gamma_coef, c.gc.ptr, (size_t)c.Ctot * sizeof(double), mem_kind);
+        HIPC(hipStreamSynchronize(c.stream));
+        return BIM_OK;
+    });
+}
+
 int bim_apply_double_layer(bim_ctx h, const double *u_coef, double *out, int mode, int mem_kind)
 {
     return guarded(h ? &h->c : nullptr, [&]() {
@@ -1829,6 +2098,69 @@ int bim_apply_double_layer(bim_ctx h, const double *u_coef, double *out, int mod
     });
 }
 
+// Velocity solve at the current drop and surfactant state: geometry, force,
+// single layer, right-hand side and GMRES on the second-kind operator; the
+// velocity coefficients are left in c.xsol [3][Ctot].
+static int solve_velocity(Ctx &c, int &iters, double &relres, int &nmv)
+{
+    // a velocity evaluation always recomputes the geometry, the force and
+    // the regions from the drop coefficients
+    invalidate(c);
+    build_force(c);
+    bool all_one = true;
+    for (auto &d : c.drops) all_one = all_one && d.lam == 1.0;
+    std::vector<char> with_dl(c.nd, 0);
+    if (!all_one) {
+        const std::vector<double> wt = dl_weights(c);
+        for (int i = 0; i < c.nd; ++i) with_dl[i] = wt[(size_t)i * c.nd + i] != 0.0;
+    }
+    single_layer_grid(c, c.fc.d(), &with_dl);
+    // b = 2 u_inf - S / (4 pi) on the grid, then Galerkin projection
+    c.tmp.ensure((size_t)3 * std::max<long>(c.Ctot, c.T) * sizeof(double));
+    launch_rhs(c.stream, (int)c.T, c.tx.d(), c.T, c.acc.d(), -1.0 / (4.0 * kPi), c.U0, c.gU.d(), c.tmp.d());
+    c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+    project(c, c.tmp.d(), c.bvec.d());
+    int rc = BIM_OK;
+    iters = 0;
+    nmv = 0;
+    relres = 0.0;
+    const long n = 3 * c.Ctot;
+    c.xsol.ensure((size_t)n * sizeof(double));
+    if (all_one) {
+        launch_scale_add(c.stream, n, 0.5, c.bvec.d(), 0.0, c.xsol.d());
+    } else {
+        // independent systems in one solve: a tolerance scaled by
+        // min_s ||b_s|| / ||b|| bounds every system's own relative
+        // residual by gmres_tol (||r_s|| <= ||r||)
+        double tol = c.opt.gmres_tol, bound = 1.0;
+        std::map<int, double> bs;
+        for (int i = 0; i < c.nd; ++i) bs[c.sys_h[i]] = 0.0;
+        if (bs.size() > 1) {
+            std::vector<double> hb(n);
+            HIPC(hipMemcpyAsync(hb.data(), c.bvec.ptr, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            HIPC(hipStreamSynchronize(c.stream));
+            double tot = 0.0;
+            for (int i = 0; i < c.nd; ++i)
+                for (int comp = 0; comp < 3; ++comp)
+                    for (long e = 0; e < 2L * ncoef(c.drops[i].p); ++e) {
+                        const double v = hb[comp * c.Ctot + c.drops[i].coff + e];
+                        bs[c.sys_h[i]] += v * v;
+                        tot += v * v;
+                    }
+            double bmin = 0.0;
+            for (auto &kv : bs)
+                if (kv.second > 0.0 && (bmin == 0.0 || kv.second < bmin)) bmin = kv.second;
+            if (bmin > 0.0 && tot > 0.0) {
+                bound = std::sqrt(tot / bmin);
+                tol /= bound;
+            }
+        }
+        rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), tol, iters, relres, nmv);
+        relres *= bound;
+    }
+    return rc;
+}
+
 int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
 {
     return guarded(h ? &h->c : nullptr, [&]() {
@@ -1837,58 +2169,10 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
         REQUIRE(u_out, BIM_EINVAL, "null output");
         REQUIRE(out_kind >= 0 && out_kind <= 3, BIM_EINVAL, "bad out_kind");
         auto t0 = std::chrono::steady_clock::now();
-        // a velocity evaluation always recomputes the geometry, the force and
-        // the regions from the drop coefficients
-        invalidate(c);
-        build_force(c);
-        bool all_one = true;
-        for (auto &d : c.drops) all_one = all_one && d.lam == 1.0;
-        std::vector<char> with_dl(c.nd, 0);
-        if (!all_one) {
-            const std::vector<double> wt = dl_weights(c);
-            for (int i = 0; i < c.nd; ++i) with_dl[i] = wt[(size_t)i * c.nd + i] != 0.0;
-        }
-        single_layer_grid(c, c.fc.d(), &with_dl);
-        // b = 2 u_inf - S / (4 pi) on the grid, then Galerkin projection
-        c.tmp.ensure((size_t)3 * std::max<long>(c.Ctot, c.T) * sizeof(double));
-        launch_rhs(c.stream, (int)c.T, c.tx.d(), c.T, c.acc.d(), -1.0 / (4.0 * kPi), c.U0, c.gU.d(), c.tmp.d());
-        c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
-        project(c, c.tmp.d(), c.bvec.d());
-        int rc = BIM_OK, iters = 0, nmv = 0;
+        int iters = 0, nmv = 0;
         double relres = 0.0;
+        const int rc = solve_velocity(c, iters, relres, nmv);
         const long n = 3 * c.Ctot;
-        if (all_one) {
-            launch_scale_add(c.stream, n, 0.5, c.bvec.d(), 0.0, c.xsol.d());
-        } else {
-            // independent systems in one solve: a tolerance scaled by
-            // min_s ||b_s|| / ||b|| bounds every system's own relative
-            // residual by gmres_tol (||r_s|| <= ||r||)
-            double tol = c.opt.gmres_tol, bound = 1.0;
-            std::map<int, double> bs;
-            for (int i = 0; i < c.nd; ++i) bs[c.sys_h[i]] = 0.0;
-            if (bs.size() > 1) {
-                std::vector<double> hb(n);
-                HIPC(hipMemcpyAsync(hb.data(), c.bvec.ptr, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-                HIPC(hipStreamSynchronize(c.stream));
-                double tot = 0.0;
-                for (int i = 0; i < c.nd; ++i)
-                    for (int comp = 0; comp < 3; ++comp)
-                        for (long e = 0; e < 2L * ncoef(c.drops[i].p); ++e) {
-                            const double v = hb[comp * c.Ctot + c.drops[i].coff + e];
-                            bs[c.sys_h[i]] += v * v;
-                            tot += v * v;
-                        }
-                double bmin = 0.0;
-                for (auto &kv : bs)
-                    if (kv.second > 0.0 && (bmin == 0.0 || kv.second < bmin)) bmin = kv.second;
-                if (bmin > 0.0 && tot > 0.0) {
-                    bound = std::sqrt(tot / bmin);
-                    tol /= bound;
-                }
-            }
-            rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), tol, iters, relres, nmv);
-            relres *= bound;
-        }
         const bool dev = (out_kind & 2) != 0;
         if (out_kind & 1) {
             copy_out(c, u_out, c.xsol.ptr, (size_t)n * sizeof(double), dev ? BIM_MEM_DEVICE : BIM_MEM_HOST);

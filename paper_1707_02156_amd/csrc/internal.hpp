@@ -73,6 +73,25 @@ struct AnaJob {
     double csc;
 };
 
+// One drop of the surface-operator kernel (kernels_surf.hip). syn holds, per
+// grid point (np of them): x fields f = 0..5 (value, d_theta, d_phi,
+// d_theta^2, d_theta d_phi, d_phi^2) x 3 components at (3 f + c) np; Gamma
+// fields f = 0..5 at (18 + f) np (when gam); u fields f = 0..2 x 3
+// components at (24 + 3 f + c) np (when fE is set).
+struct SurfJob {
+    const double *syn;
+    const double *wreg;   // regular-rule weight per latitude (pi/q) w_j / sin theta_j
+    double *fE, *lg;      // grid outputs: -Gamma div_s u, Laplace-Beltrami of Gamma (optional)
+    double *mass, *vol;   // accumulated int Gamma dS and enclosed volume (optional)
+    long np;
+    int q, gam;           // grid degree; Gamma fields present
+};
+constexpr int kMaxSurfJobs = 32;
+struct SurfJobs {
+    int n;
+    SurfJob j[kMaxSurfJobs];
+};
+
 struct DlJob {
     const double *M;
     const double *u;   // density coefficients of the drop, component stride ustride
