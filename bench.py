@@ -203,6 +203,72 @@ def kernel_frac(name, d):
     return d["flops"] / sec / 1e12 / peak
 
 
+def time_loop(args):
+    """Coupled drop / surfactant time stepping (bim_time_step) of the two-drop
+    p=32 workload in a shear flow with its surfactant: adaptive steps from
+    dt0; reports time steps per second, target-point evaluations per second
+    (both velocity solves of every step), acceptance, dt, and the drift of the
+    total surfactant and of the volumes over the run."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1707_02156_amd as B
+
+    torch.cuda.set_device(0)
+    wl = workload("two_drops")
+    shear = np.zeros((3, 3))
+    shear[0, 1] = args.shear
+    ctx = B.Context(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom,
+                    gmres_tol=wl.gmres_tol)
+    ctx.set_drops([d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops])
+    ctx.set_tension([d.gc for d in wl.drops], wl.eos, wl.E, wl.xs)
+    B.bim_set_farfield(ctx.h, np.zeros(3), shear)
+    vol0 = [oracle.volume(d.p, d.xc) for d in wl.drops]
+    dt = args.dt0
+    for _ in range(args.warmup):                  # warm-up: steps with tol <= 0 are always accepted
+        ctx.time_step(dt, Pe=args.pe, tol=0.0)
+    T = ctx.ntargets()
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ctx.time_step(dt, Pe=args.pe, tol=args.tol)
+        reps.append(r)
+        dt = min(r["dt_next"], args.dt_max)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xs, _ = ctx.state()
+    vol1 = [oracle.volume(d.p, x) for d, x in zip(wl.drops, xs)]
+    ctx.close()
+    ms = (t1 - t0) * 1e3 / args.steps
+    evals = sum(T * (2 + r["gmres_velocity"][0] + r["gmres_velocity"][1]) for r in reps) / args.steps
+    acc = [r for r in reps if r["accepted"]]
+    res = {
+        "metric": "coupled drop/surfactant time steps/s",
+        "value": 1e3 / ms,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["two_drops"] + f"; shear rate {args.shear}, Pe {args.pe}, "
+                   f"adaptive dt (tol {args.tol}, dt0 {args.dt0}, dt_max {args.dt_max})", "targets": T},
+        "evals_per_s": evals / (ms * 1e-3),
+        "accepted": len(acc),
+        "dt_last": dt,
+        "gmres_velocity_mean": float(np.mean([sum(r["gmres_velocity"]) / 2 for r in reps])),
+        "gmres_imex_mean": float(np.mean([r["gmres_imex"] for r in reps])),
+        "err_surf_max_accepted": max((r["err_surf"] for r in acc), default=0.0),
+        "mass_drift": (acc[-1]["mass1"] / acc[0]["mass0"] - 1.0) if acc else 0.0,
+        "volume_drift": [v1 / v0 - 1.0 for v0, v1 in zip(vol0, vol1)],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +288,12 @@ def main():
     ap.add_argument("--rate-factor", type=float, default=0.8)
     ap.add_argument("--capacity-sample", type=int, default=128)
     ap.add_argument("--max-batch", type=int, default=16)
+    ap.add_argument("--time-loop", action="store_true", help="run the coupled drop / surfactant time stepping")
+    ap.add_argument("--pe", type=float, default=200.0)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--dt0", type=float, default=0.05)
+    ap.add_argument("--dt-max", type=float, default=0.2)
+    ap.add_argument("--shear", type=float, default=0.2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",
@@ -230,6 +302,9 @@ def main():
 
     if args.serve:
         serve(args)
+        return
+    if args.time_loop:
+        time_loop(args)
         return
 
     import torch
