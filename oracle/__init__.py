@@ -59,6 +59,7 @@ def lib():
         L.orc_analyze.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
         L.orc_eval_point.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double]
         L.orc_eval_point.restype = ctypes.c_double
+        L.orc_eval_points_d.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.orc_wigner_d.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
         L.orc_rotate.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_geometry.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
@@ -236,6 +237,15 @@ def regular(ps: int, q: int, xc, dc, kind: int, x0):
 def eval_point_d(p: int, c, theta: float, phi: float, dt: int = 0, dp: int = 0) -> float:
     """d^dt/dtheta^dt d^dp/dphi^dp of a real degree-p expansion at one point."""
     return lib().orc_eval_point_d(p, _p(_c(c)), float(theta), float(phi), int(dt), int(dp))
+
+
+def eval_points_d(p: int, c, theta, phi, dt: int = 0, dp: int = 0):
+    """eval_point_d at arrays of angles (vectorised over points in C)."""
+    th = _c(theta)
+    ph = _c(phi)
+    out = np.zeros(len(th))
+    lib().orc_eval_points_d(p, _p(_c(c)), len(th), _p(th), _p(ph), int(dt), int(dp), _p(out))
+    return out
 
 
 def closest_point(p: int, xc, x0, theta0: float, phi0: float):

@@ -808,6 +808,14 @@ double orc_eval_point_d(int p, const double *c, double theta, double phi, int dt
     return v;
 }
 
+/* The same at n points (theta[i], phi[i]) into out[i]. */
+void orc_eval_points_d(int p, const double *c, int n, const double *theta, const double *phi, int dt, int dp,
+                       double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) out[i] = orc_eval_point_d(p, c, theta[i], phi[i], dt, dp);
+}
+
 static void surface_point(int p, const double *xc, double th, double ph, double out[6][3])
 {
     const int nc2 = 2 * ncoef(p);
