@@ -220,6 +220,30 @@ int bim_time_step(bim_ctx ctx, double dt, double Pe, double tol, bim_step_report
  * BIM_ESTATE when gamma_coef is requested and no surfactant was set. */
 int bim_get_state(bim_ctx ctx, double *xcoef, double *gamma_coef, int mem_kind);
 
+/* Angle reparametrization of every drop (Sec. 4, Algorithm 2). The surface
+ * keeps its expansion (zero-padded to degree q = U_rep p); only the parameter
+ * angles of the degree-q grid nodes move: each pseudo-time step solves, per
+ * node, [x_t.x_t x_t.x_p; x_t.x_p x_p.x_p] alpha = (w.x_t, w.x_p) with
+ * w = -(I - n n) grad E and grad E = sum_{n >= n_cut} x~_n^m Y_n^m (perfect
+ * low-pass filter, x~ the current coefficients, n_cut the smallest l >= 2
+ * whose coefficient-magnitude tail sum_{n>=l} sum_m |x~_n^m| is below P_cut
+ * times that of l = 1), then (theta, phi) += dtau alpha. It stops when the
+ * largest |g| = |(I - n n) grad E| over the nodes is below eps or after
+ * imax - 1 steps. The drop coefficients, and the surfactant coefficients when
+ * set, become the analysis of the initial expansions at the final angles,
+ * truncated to degree p (the surfactant stays the same function of the
+ * surface points). The paper's values are U_rep = 2, dtau = 1, imax = 30.
+ * Errors: BIM_EINVAL (U_rep < 1, U_rep p > 64, P_cut outside (0, 1], eps
+ * < 0 or not finite, imax < 1, dtau <= 0 or not finite), BIM_ESTATE (no
+ * drops). rep may be NULL. */
+typedef struct {
+    int moves;      /* pseudo-time steps taken (largest over the drops) */
+    int ncut_min;   /* smallest final n_cut over the drops */
+    double gnorm;   /* largest final max |g| over the drops */
+    double ms_total;
+} bim_rep_report;
+int bim_reparametrize(bim_ctx ctx, int U_rep, double P_cut, double eps, int imax, double dtau, bim_rep_report *rep);
+
 /* Stand-alone transforms on the context's device and stream (Sec. 1.1, 2.1).
  * Synthesis: nf scalar fields of degree p (each (p+1)(p+2) doubles,
  * consecutive) to grid values on the degree-q grid (q >= p), derivative

@@ -88,6 +88,18 @@ class bim_step_report(ctypes.Structure):
         return d
 
 
+class bim_rep_report(ctypes.Structure):
+    _fields_ = [
+        ("moves", ctypes.c_int),
+        ("ncut_min", ctypes.c_int),
+        ("gnorm", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -110,6 +122,7 @@ EXPORTS = {
     "bim_eval_velocity": ([_vp, _vp, _i, ctypes.POINTER(bim_report)], _i),
     "bim_time_step": ([_vp, _d, _d, _d, ctypes.POINTER(bim_step_report)], _i),
     "bim_get_state": ([_vp, _vp, _vp, _i], _i),
+    "bim_reparametrize": ([_vp, _i, _d, _d, _i, _d, ctypes.POINTER(bim_rep_report)], _i),
     "bim_sh_synthesize": ([_vp, _i, _i, _i, _vp, _i, _i, _vp, _i], _i),
     "bim_sh_analyze": ([_vp, _i, _i, _i, _vp, _vp, _i], _i),
     "bim_synchronize": ([_vp], _i),
@@ -426,6 +439,13 @@ class Context:
         as a dict (dt_next, err_drop, err_surf, mass0, mass1, accepted, ...)."""
         rep = bim_step_report()
         _check(self.h, lib().bim_time_step(self.h, float(dt), float(Pe), float(tol), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def reparametrize(self, U_rep=2, P_cut=1e-3, eps=1e-10, imax=30, dtau=1.0):
+        """Angle reparametrization of every drop (bim_reparametrize); returns the report."""
+        rep = bim_rep_report()
+        _check(self.h, lib().bim_reparametrize(self.h, int(U_rep), float(P_cut), float(eps), int(imax),
+                                               float(dtau), ctypes.byref(rep)))
         return rep.as_dict()
 
     def state(self, surfactant=True):

@@ -126,6 +126,10 @@ void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm,
 void launch_surf_terms(hipStream_t st, const SurfJob *jobs, int n);
 void launch_mul(hipStream_t st, long n, const double *d, const double *x, double *y);
 void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, const double *y, double *out);
+void launch_rep_eval(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *th,
+                     const double *ph, long N, double *out);
+void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax);
+void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 
 static const double kPi = 3.14159265358979323846;
@@ -253,6 +257,8 @@ struct Ctx {
     // time step: states, stage velocities and surfactant terms, surface fields and outputs
     DBuf ts_x0, ts_g0, ts_u0, ts_uh, ts_xh, ts_gh, ts_fe, ts_ki, ts_ke, ts_sinv, ts_w, ts_lw, ts_z, ts_syn, ts_grid,
         ts_acc;
+    // reparametrization: initial expansions, current coefficients, node angles, evaluations
+    DBuf rp_x0, rp_g0, rp_xt, rp_hp, rp_ang, rp_E, rp_gE, rp_g, rp_gmax;
     hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
     double *hres = nullptr;        // pinned, coherent: GMRES residual estimates written by the device
@@ -2072,6 +2078,132 @@ int bim_get_state(bim_ctx h, double *xcoef, double *gamma_coef, int mem_kind)
         if (xcoef) copy_out(c, xcoef, c.xc.ptr, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
         if (gamma_coef) copy_out(c, gamma_coef, c.gc.ptr, (size_t)c.Ctot * sizeof(double), mem_kind);
         HIPC(hipStreamSynchronize(c.stream));
+        return BIM_OK;
+    });
+}
+
+// --------------------------------------------------------------------------
+// Angle reparametrization (Sec. 4, Algorithm 2)
+// --------------------------------------------------------------------------
+// Adaptive cutoff: the smallest l in 2..q with N2(l) < P_cut N1,
+// N2(l) = sum_{n >= l} sum_{|m| <= n} |x_n^m| (Euclidean norm of the 3-vector
+// coefficient; m > 0 counted twice), N1 = N2(1); q + 1 when there is none.
+static int rep_ncut(const std::vector<double> &xt, int q, long cs, double P_cut)
+{
+    std::vector<double> mag(q + 1, 0.0);
+    for (int n = 0; n <= q; ++n)
+        for (int m = 0; m <= n; ++m) {
+            const long e = (long)n * (n + 1) / 2 + m;
+            double v = 0.0;
+            for (int c = 0; c < 3; ++c) v += xt[c * cs + 2 * e] * xt[c * cs + 2 * e] + xt[c * cs + 2 * e + 1] * xt[c * cs + 2 * e + 1];
+            mag[n] += (m ? 2.0 : 1.0) * std::sqrt(v);
+        }
+    double N1 = 0.0;
+    for (int n = 1; n <= q; ++n) N1 += mag[n];
+    for (int l = 2; l <= q; ++l) {
+        double tail = 0.0;
+        for (int n = l; n <= q; ++n) tail += mag[n];
+        if (tail < P_cut * N1) return l;
+    }
+    return q + 1;
+}
+
+struct RepOut {
+    int moves = 0, ncut = 0;
+    double gnorm = 0.0;
+};
+
+// Algorithm 2 on drop i: the initial expansions (degree p, zero-padded to
+// q = U p) stay fixed; the angles of the degree-q grid nodes move by forward
+// Euler steps of the parameter velocity of w = -(I - n n) grad E, grad E the
+// field of the coefficients of degree >= n_cut. The drop's position (and
+// surfactant) coefficients are replaced by the analysis of the initial
+// expansions at the final angles, truncated to degree p.
+static RepOut reparam_drop(Ctx &c, int i, int U, double P_cut, double eps, int imax, double dtau)
+{
+    const Drop &d = c.drops[i];
+    const int p = d.p, q = U * p;
+    const long N = npts(q), nq2 = 2L * ncoef(q), np2 = 2L * ncoef(p);
+    GridTab &gq = grid(c, q, q);
+    c.rp_x0.ensure((size_t)3 * nq2 * sizeof(double));
+    c.rp_g0.ensure((size_t)nq2 * sizeof(double));
+    c.rp_xt.ensure((size_t)3 * nq2 * sizeof(double));
+    c.rp_hp.ensure((size_t)3 * nq2 * sizeof(double));
+    c.rp_ang.ensure((size_t)2 * N * sizeof(double));
+    c.rp_E.ensure((size_t)9 * N * sizeof(double));
+    c.rp_gE.ensure((size_t)3 * N * sizeof(double));
+    c.rp_g.ensure((size_t)3 * N * sizeof(double));
+    c.rp_gmax.ensure(sizeof(double));
+    double *x0 = c.rp_x0.d(), *g0 = c.rp_g0.d(), *xt = c.rp_xt.d(), *hp = c.rp_hp.d(), *th = c.rp_ang.d(),
+           *ph = th + N, *E = c.rp_E.d(), *gE = c.rp_gE.d(), *g = c.rp_g.d();
+    auto *gmax = (unsigned long long *)c.rp_gmax.ptr;
+    HIPC(hipMemsetAsync(x0, 0, (size_t)3 * nq2 * sizeof(double), c.stream));
+    for (int comp = 0; comp < 3; ++comp) dcopy(c, x0 + comp * nq2, c.xc.d() + comp * c.Ctot + d.coff, np2);
+    if (c.have_gamma) {
+        HIPC(hipMemsetAsync(g0, 0, (size_t)nq2 * sizeof(double), c.stream));
+        dcopy(c, g0, c.gc.d() + d.coff, np2);
+    }
+    std::vector<double> ang(2 * N);
+    for (int j = 0; j <= q; ++j)
+        for (int k = 0; k < 2 * q; ++k) {
+            ang[(long)j * 2 * q + k] = gq.th[j];
+            ang[N + (long)j * 2 * q + k] = kPi * k / q;
+        }
+    HIPC(hipMemcpyAsync(th, ang.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    RepOut r;
+    // x~ at the current angles, the cutoff, grad E and g with its largest norm
+    auto evaluate = [&]() {
+        launch_rep_eval(c.stream, q, 3, x0, nq2, th, ph, N, E);
+        ana_run(c, {ana_job(c, q, q, 3, E, 3 * N, xt, nq2)});
+        r.ncut = rep_ncut(dget(c, xt, 3 * nq2), q, nq2, P_cut);
+        dcopy(c, hp, xt, 3 * nq2);
+        for (int comp = 0; comp < 3; ++comp)
+            HIPC(hipMemsetAsync(hp + comp * nq2, 0, (size_t)2 * ncoef(r.ncut - 1) * sizeof(double), c.stream));
+        syn_run(c, {syn_job(c, q, q, 3, hp, nq2, 0x1, gE, N, 0)});
+        HIPC(hipMemsetAsync(gmax, 0, sizeof(double), c.stream));
+        launch_rep_grad(c.stream, N, E, gE, g, gmax);
+        r.gnorm = dget(c, (const double *)gmax, 1)[0];
+    };
+    evaluate();
+    for (int it = 1; it < imax; ++it) {
+        launch_rep_move(c.stream, N, E, g, dtau, th, ph);
+        ++r.moves;
+        evaluate();
+        if (r.gnorm < eps) break;
+    }
+    for (int comp = 0; comp < 3; ++comp) dcopy(c, c.xc.d() + comp * c.Ctot + d.coff, xt + comp * nq2, np2);
+    if (c.have_gamma) {
+        launch_rep_eval(c.stream, q, 1, g0, nq2, th, ph, N, E);
+        ana_run(c, {ana_job(c, q, q, 1, E, 0, hp, 0)});
+        dcopy(c, c.gc.d() + d.coff, hp, np2);
+    }
+    HIPC(hipStreamSynchronize(c.stream));
+    return r;
+}
+
+int bim_reparametrize(bim_ctx h, int U_rep, double P_cut, double eps, int imax, double dtau, bim_rep_report *rep)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(U_rep >= 1, BIM_EINVAL, "U_rep must be >= 1");
+        for (auto &d : c.drops) REQUIRE(U_rep * d.p <= 64, BIM_EINVAL, "U_rep * p must be <= 64");
+        REQUIRE(P_cut > 0.0 && P_cut <= 1.0, BIM_EINVAL, "P_cut must be in (0, 1]");
+        REQUIRE(std::isfinite(eps) && eps >= 0.0, BIM_EINVAL, "eps must be finite and >= 0");
+        REQUIRE(imax >= 1, BIM_EINVAL, "imax must be >= 1");
+        REQUIRE(std::isfinite(dtau) && dtau > 0.0, BIM_EINVAL, "dtau must be finite and > 0");
+        auto t0 = std::chrono::steady_clock::now();
+        bim_rep_report r{};
+        r.ncut_min = 1 << 30;
+        for (int i = 0; i < c.nd; ++i) {
+            const RepOut o = reparam_drop(c, i, U_rep, P_cut, eps, imax, dtau);
+            r.moves = std::max(r.moves, o.moves);
+            r.gnorm = std::max(r.gnorm, o.gnorm);
+            r.ncut_min = std::min(r.ncut_min, o.ncut);
+        }
+        invalidate(c);
+        r.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = r;
         return BIM_OK;
     });
 }

@@ -124,4 +124,163 @@ void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, c
     hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, out);
 }
 
+// ----------------------------------------------------------------------------
+// Angle reparametrization (Sec. 4, Algorithm 2)
+// ----------------------------------------------------------------------------
+constexpr int kRepMaxF = 3;
+constexpr double kPiS = 3.14159265358979323846;
+
+__device__ inline double wave_add(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Values and angle derivatives of nf <= 3 real expansions of degree q
+// (component f at coef + f * cstride) at nodes (theta_i, phi_i), theta in
+// [0, pi]. One wavefront per node; lanes take the orders m = lane, lane + 64,
+// ...; each runs the orthonormal associated-Legendre recursion in n (Sec. 1.1)
+// and the theta derivative from the same order,
+//   dP_n^m/dtheta = (n cos(theta) P_n^m - sqrt((2n+1)(n^2-m^2)/(2n-1)) P_{n-1}^m) / sin(theta);
+// the order sums are wavefront sums. out[(3 f + d) N + i]: d = 0 value,
+// 1 d/dtheta, 2 d/dphi.
+__global__ __launch_bounds__(256) void k_rep_eval(int q, int nf, const double *__restrict__ coef, long cstride,
+                                                  const double *__restrict__ th, const double *__restrict__ ph,
+                                                  long N, double *__restrict__ out)
+{
+    const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // node (one per wavefront)
+    const int lane = threadIdx.x & 63;
+    if (i >= N) return;                                                 // the whole wavefront
+    const double t = cos(th[i]), s = sin(th[i]), phi = ph[i];
+    double acc[kRepMaxF][3] = {};
+    for (int m0 = 0; m0 <= q; m0 += 64) {
+        const int m = m0 + lane;
+        if (m > q) continue;
+        double pmm = 1.0 / sqrt(4.0 * kPiS);
+        for (int k = 1; k <= m; ++k) pmm *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+        double G[kRepMaxF][2][2] = {};  // [field][value, d_theta][re, im]
+        double Pm1 = 0.0, Pm2 = 0.0;
+        for (int n = m; n <= q; ++n) {
+            double P;
+            if (n == m) {
+                P = pmm;
+            } else if (n == m + 1) {
+                P = sqrt(2.0 * m + 3.0) * t * pmm;
+            } else {
+                const double an = sqrt((2.0 * n + 1.0) * (2.0 * n - 1.0) / ((double)(n - m) * (n + m)));
+                const double bn = sqrt((2.0 * n + 1.0) * (double)(n + m - 1) * (n - m - 1) /
+                                       ((2.0 * n - 3.0) * (double)(n - m) * (n + m)));
+                P = an * t * Pm1 - bn * Pm2;
+            }
+            const double D =
+                (n * t * P - (n > m ? sqrt((2.0 * n + 1.0) * (double)(n - m) * (n + m) / (2.0 * n - 1.0)) * Pm1
+                                    : 0.0)) / s;
+            Pm2 = Pm1;
+            Pm1 = P;
+            const long e = (long)n * (n + 1) / 2 + m;
+            for (int f = 0; f < nf; ++f) {
+                const double cr = coef[f * cstride + 2 * e], ci = coef[f * cstride + 2 * e + 1];
+                G[f][0][0] = fma(cr, P, G[f][0][0]);
+                G[f][0][1] = fma(ci, P, G[f][0][1]);
+                G[f][1][0] = fma(cr, D, G[f][1][0]);
+                G[f][1][1] = fma(ci, D, G[f][1][1]);
+            }
+        }
+        double sm, cm;
+        sincos(m * phi, &sm, &cm);
+        const double w = m ? 2.0 : 1.0;
+        for (int f = 0; f < nf; ++f) {
+            // Re(g e^{i m phi}) and Re(i m g e^{i m phi})
+            acc[f][0] += w * (G[f][0][0] * cm - G[f][0][1] * sm);
+            acc[f][1] += w * (G[f][1][0] * cm - G[f][1][1] * sm);
+            acc[f][2] += -w * m * (G[f][0][0] * sm + G[f][0][1] * cm);
+        }
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int d = 0; d < 3; ++d) {
+            const double v = wave_add(acc[f][d]);
+            if (lane == 0) out[(3L * f + d) * N + i] = v;
+        }
+}
+
+// g = (I - n n) grad E at every node, n = X_t x X_p / |X_t x X_p|; gmax holds
+// the largest |g| as the bits of a non-negative double (ordered like unsigned
+// integers). E: k_rep_eval output for the 3 position components; gE [3][N].
+__global__ void k_rep_grad(long N, const double *__restrict__ E, const double *__restrict__ gE,
+                           double *__restrict__ g, unsigned long long *gmax)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double mag = 0.0;
+    if (i < N) {
+        double xt[3], xp[3], v[3];
+        for (int c = 0; c < 3; ++c) {
+            xt[c] = E[(3L * c + 1) * N + i];
+            xp[c] = E[(3L * c + 2) * N + i];
+            v[c] = gE[c * N + i];
+        }
+        double n[3] = {xt[1] * xp[2] - xt[2] * xp[1], xt[2] * xp[0] - xt[0] * xp[2], xt[0] * xp[1] - xt[1] * xp[0]};
+        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int c = 0; c < 3; ++c) n[c] /= nn;
+        const double vn = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
+        for (int c = 0; c < 3; ++c) {
+            const double gc = v[c] - vn * n[c];
+            g[c * N + i] = gc;
+            mag = fma(gc, gc, mag);
+        }
+        mag = sqrt(mag);
+    }
+    for (int o = 32; o > 0; o >>= 1) mag = fmax(mag, __shfl_xor(mag, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(gmax, (unsigned long long)__double_as_longlong(mag));
+}
+
+// One forward-Euler step of the angles: w = -g, A alpha = (w.X_t, w.X_p) with
+// A the metric of the initial expansion at the node; theta, phi += dtau alpha,
+// taken back into theta in [0, pi] across the pole (phi + pi) and phi mod 2 pi.
+__global__ void k_rep_move(long N, const double *__restrict__ E, const double *__restrict__ g, double dtau,
+                           double *__restrict__ th, double *__restrict__ ph)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double a00 = 0.0, a01 = 0.0, a11 = 0.0, b0 = 0.0, b1 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double xt = E[(3L * c + 1) * N + i], xp = E[(3L * c + 2) * N + i], w = -g[c * N + i];
+        a00 = fma(xt, xt, a00);
+        a01 = fma(xt, xp, a01);
+        a11 = fma(xp, xp, a11);
+        b0 = fma(w, xt, b0);
+        b1 = fma(w, xp, b1);
+    }
+    const double det = a00 * a11 - a01 * a01;
+    double t = th[i] + dtau * (a11 * b0 - a01 * b1) / det;
+    double p = ph[i] + dtau * (a00 * b1 - a01 * b0) / det;
+    if (t < 0.0) {
+        t = -t;
+        p += kPiS;
+    } else if (t > kPiS) {
+        t = 2.0 * kPiS - t;
+        p += kPiS;
+    }
+    p = fmod(p, 2.0 * kPiS);
+    if (p < 0.0) p += 2.0 * kPiS;
+    th[i] = t;
+    ph[i] = p;
+}
+
+void launch_rep_eval(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *th,
+                     const double *ph, long N, double *out)
+{
+    hipLaunchKernelGGL(k_rep_eval, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, q, nf, coef, cstride, th, ph, N,
+                       out);
+}
+
+void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax)
+{
+    hipLaunchKernelGGL(k_rep_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, gE, g, gmax);
+}
+
+void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph)
+{
+    hipLaunchKernelGGL(k_rep_move, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, g, dtau, th, ph);
+}
+
 }  // namespace bim
