@@ -232,9 +232,12 @@ def time_loop(args):
     reps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    rreps = []
     for _ in range(args.steps):
         r = ctx.time_step(dt, Pe=args.pe, tol=args.tol)
         reps.append(r)
+        if r["accepted"] and args.rep_imax > 0:   # Algorithm 1: reparametrize after an accepted step
+            rreps.append(ctx.reparametrize(U_rep=2, P_cut=args.rep_pcut, eps=args.rep_eps, imax=args.rep_imax))
         dt = min(r["dt_next"], args.dt_max)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -266,6 +269,11 @@ def time_loop(args):
         "mass_drift": (acc[-1]["mass1"] / acc[0]["mass0"] - 1.0) if acc else 0.0,
         "volume_drift": [v1 / v0 - 1.0 for v0, v1 in zip(vol0, vol1)],
     }
+    if rreps:
+        res["reparametrization"] = {"calls": len(rreps), "ms_mean": float(np.mean([r["ms_total"] for r in rreps])),
+                                    "moves_mean": float(np.mean([r["moves"] for r in rreps])),
+                                    "U_rep": 2, "P_cut": args.rep_pcut, "eps": args.rep_eps, "imax": args.rep_imax}
+        res["config"]["workload"] += f"; reparametrization after accepted steps (imax {args.rep_imax})"
     print(json.dumps(res), flush=True)
 
 
@@ -294,6 +302,9 @@ def main():
     ap.add_argument("--dt0", type=float, default=0.05)
     ap.add_argument("--dt-max", type=float, default=0.2)
     ap.add_argument("--shear", type=float, default=0.2)
+    ap.add_argument("--rep-imax", type=int, default=0, help="time loop: reparametrize after accepted steps (0: off)")
+    ap.add_argument("--rep-pcut", type=float, default=1e-3)
+    ap.add_argument("--rep-eps", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it (use --gpus 1)",

@@ -126,10 +126,14 @@ void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm,
 void launch_surf_terms(hipStream_t st, const SurfJob *jobs, int n);
 void launch_mul(hipStream_t st, long n, const double *d, const double *x, double *y);
 void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, const double *y, double *out);
-void launch_rep_eval(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *th,
+void launch_rep_pack(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *hdr, double *rec);
+void launch_rep_eval(hipStream_t st, int q, int nf, const double *rec, const double *cm, const double *th,
                      const double *ph, long N, double *out);
 void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax);
-void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph);
+void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph,
+                     const unsigned long long *gmax, double eps, int check, int *moves);
+void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
+                    unsigned long long *gmax);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 
 static const double kPi = 3.14159265358979323846;
@@ -258,7 +262,8 @@ struct Ctx {
     DBuf ts_x0, ts_g0, ts_u0, ts_uh, ts_xh, ts_gh, ts_fe, ts_ki, ts_ke, ts_sinv, ts_w, ts_lw, ts_z, ts_syn, ts_grid,
         ts_acc;
     // reparametrization: initial expansions, current coefficients, node angles, evaluations
-    DBuf rp_x0, rp_g0, rp_xt, rp_hp, rp_ang, rp_E, rp_gE, rp_g, rp_gmax;
+    DBuf rp_x0, rp_g0, rp_xt, rp_hp, rp_ang, rp_E, rp_gE, rp_g, rp_gmax, rp_rec;
+    std::map<int, std::unique_ptr<DBuf>> rp_tab;  // Legendre recursion coefficients per degree
     hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
     double *hres = nullptr;        // pinned, coherent: GMRES residual estimates written by the device
@@ -2085,27 +2090,51 @@ int bim_get_state(bim_ctx h, double *xcoef, double *gamma_coef, int mem_kind)
 // --------------------------------------------------------------------------
 // Angle reparametrization (Sec. 4, Algorithm 2)
 // --------------------------------------------------------------------------
-// Adaptive cutoff: the smallest l in 2..q with N2(l) < P_cut N1,
-// N2(l) = sum_{n >= l} sum_{|m| <= n} |x_n^m| (Euclidean norm of the 3-vector
-// coefficient; m > 0 counted twice), N1 = N2(1); q + 1 when there is none.
-static int rep_ncut(const std::vector<double> &xt, int q, long cs, double P_cut)
+// Recursion coefficients of the orthonormal associated Legendre functions of
+// degree <= q at tri(n, m): a_nm = sqrt((2n+1)(2n-1)/((n-m)(n+m))),
+// b_nm = sqrt((2n+1)(n+m-1)(n-m-1)/((2n-3)(n-m)(n+m))) (n >= m + 2),
+// d_nm = sqrt((2n+1)(n^2-m^2)/(2n-1)); then c_m = (4 pi)^(-1/2) prod_{k<=m} -sqrt((2k+1)/(2k)).
+// Recursion records of the degree-q point evaluation, order-major: for
+// m = 0..q, n = m..q the 4 doubles {a, b, d, n} of
+//   P_n^m = a cos(theta) P_{n-1}^m - b P_{n-2}^m,
+//   sin(theta) dP_n^m/dtheta = n cos(theta) P_n^m - d P_{n-1}^m,
+// with (a, b) = (0, -1) at n = m (the start value c_m sin^m(theta) enters as
+// P_{m-2}) and (sqrt(2m+3), 0) at n = m + 1; then c_m for m = 0..q.
+static const double *rep_table(Ctx &c, int q)
 {
-    std::vector<double> mag(q + 1, 0.0);
-    for (int n = 0; n <= q; ++n)
-        for (int m = 0; m <= n; ++m) {
-            const long e = (long)n * (n + 1) / 2 + m;
-            double v = 0.0;
-            for (int c = 0; c < 3; ++c) v += xt[c * cs + 2 * e] * xt[c * cs + 2 * e] + xt[c * cs + 2 * e + 1] * xt[c * cs + 2 * e + 1];
-            mag[n] += (m ? 2.0 : 1.0) * std::sqrt(v);
+    auto it = c.rp_tab.find(q);
+    if (it != c.rp_tab.end()) return it->second->d();
+    const long R = (long)(q + 1) * (q + 2) / 2;
+    std::vector<double> t(4 * R + q + 1, 0.0);
+    long j = 0;
+    for (int m = 0; m <= q; ++m)
+        for (int n = m; n <= q; ++n, ++j) {
+            double *h = &t[4 * j];
+            if (n == m) {
+                h[0] = 0.0;
+                h[1] = -1.0;
+            } else if (n == m + 1) {
+                h[0] = std::sqrt(2.0 * m + 3.0);
+            } else {
+                h[0] = std::sqrt((2.0 * n + 1.0) * (2.0 * n - 1.0) / ((double)(n - m) * (n + m)));
+                h[1] = std::sqrt((2.0 * n + 1.0) * (double)(n + m - 1) * (n - m - 1) /
+                                 ((2.0 * n - 3.0) * (double)(n - m) * (n + m)));
+            }
+            if (n > m) h[2] = std::sqrt((2.0 * n + 1.0) * (double)(n - m) * (n + m) / (2.0 * n - 1.0));
+            h[3] = n;
         }
-    double N1 = 0.0;
-    for (int n = 1; n <= q; ++n) N1 += mag[n];
-    for (int l = 2; l <= q; ++l) {
-        double tail = 0.0;
-        for (int n = l; n <= q; ++n) tail += mag[n];
-        if (tail < P_cut * N1) return l;
+    double cm = 1.0 / std::sqrt(4.0 * kPi);
+    for (int m = 0; m <= q; ++m) {
+        if (m > 0) cm *= -std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+        t[4 * R + m] = cm;
     }
-    return q + 1;
+    auto buf = std::make_unique<DBuf>();
+    buf->ensure(t.size() * sizeof(double));
+    HIPC(hipMemcpyAsync(buf->ptr, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    const double *d = buf->d();
+    c.rp_tab[q] = std::move(buf);
+    return d;
 }
 
 struct RepOut {
@@ -2125,6 +2154,9 @@ static RepOut reparam_drop(Ctx &c, int i, int U, double P_cut, double eps, int i
     const int p = d.p, q = U * p;
     const long N = npts(q), nq2 = 2L * ncoef(q), np2 = 2L * ncoef(p);
     GridTab &gq = grid(c, q, q);
+    const long R = ncoef(q);
+    const double *hdr = rep_table(c, q), *cmt = hdr + 4 * R;
+    c.rp_rec.ensure((size_t)10 * R * sizeof(double));
     c.rp_x0.ensure((size_t)3 * nq2 * sizeof(double));
     c.rp_g0.ensure((size_t)nq2 * sizeof(double));
     c.rp_xt.ensure((size_t)3 * nq2 * sizeof(double));
@@ -2133,7 +2165,7 @@ static RepOut reparam_drop(Ctx &c, int i, int U, double P_cut, double eps, int i
     c.rp_E.ensure((size_t)9 * N * sizeof(double));
     c.rp_gE.ensure((size_t)3 * N * sizeof(double));
     c.rp_g.ensure((size_t)3 * N * sizeof(double));
-    c.rp_gmax.ensure(sizeof(double));
+    c.rp_gmax.ensure(4 * sizeof(double));  // residual bits, cutoff, move count
     double *x0 = c.rp_x0.d(), *g0 = c.rp_g0.d(), *xt = c.rp_xt.d(), *hp = c.rp_hp.d(), *th = c.rp_ang.d(),
            *ph = th + N, *E = c.rp_E.d(), *gE = c.rp_gE.d(), *g = c.rp_g.d();
     auto *gmax = (unsigned long long *)c.rp_gmax.ptr;
@@ -2150,30 +2182,41 @@ static RepOut reparam_drop(Ctx &c, int i, int U, double P_cut, double eps, int i
             ang[N + (long)j * 2 * q + k] = kPi * k / q;
         }
     HIPC(hipMemcpyAsync(th, ang.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    RepOut r;
-    // x~ at the current angles, the cutoff, grad E and g with its largest norm
+    int *dnc = (int *)((char *)c.rp_gmax.ptr + sizeof(double));
+    int *dmoves = dnc + 1;
+    HIPC(hipMemsetAsync(dmoves, 0, sizeof(int), c.stream));
+    double *rec = c.rp_rec.d();
+    launch_rep_pack(c.stream, q, 3, x0, nq2, hdr, rec);
+    // x~ at the current angles, the cutoff and filter, grad E, g and its largest norm
     auto evaluate = [&]() {
-        launch_rep_eval(c.stream, q, 3, x0, nq2, th, ph, N, E);
+        launch_rep_eval(c.stream, q, 3, rec, cmt, th, ph, N, E);
         ana_run(c, {ana_job(c, q, q, 3, E, 3 * N, xt, nq2)});
-        r.ncut = rep_ncut(dget(c, xt, 3 * nq2), q, nq2, P_cut);
-        dcopy(c, hp, xt, 3 * nq2);
-        for (int comp = 0; comp < 3; ++comp)
-            HIPC(hipMemsetAsync(hp + comp * nq2, 0, (size_t)2 * ncoef(r.ncut - 1) * sizeof(double), c.stream));
+        launch_rep_cut(c.stream, q, xt, nq2, P_cut, hp, dnc, gmax);
         syn_run(c, {syn_job(c, q, q, 3, hp, nq2, 0x1, gE, N, 0)});
-        HIPC(hipMemsetAsync(gmax, 0, sizeof(double), c.stream));
         launch_rep_grad(c.stream, N, E, gE, g, gmax);
-        r.gnorm = dget(c, (const double *)gmax, 1)[0];
     };
+    // all iterations are enqueued at once: once max |g| < eps the moves are
+    // skipped on the device and the evaluations repeat the final state
     evaluate();
     for (int it = 1; it < imax; ++it) {
-        launch_rep_move(c.stream, N, E, g, dtau, th, ph);
-        ++r.moves;
+        launch_rep_move(c.stream, N, E, g, dtau, th, ph, gmax, eps, it > 1, dmoves);
         evaluate();
-        if (r.gnorm < eps) break;
+    }
+    RepOut r;
+    {
+        std::vector<char> hs(2 * sizeof(double));
+        HIPC(hipMemcpyAsync(hs.data(), c.rp_gmax.ptr, hs.size(), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        double gn;
+        std::memcpy(&gn, hs.data(), sizeof(double));
+        std::memcpy(&r.ncut, hs.data() + sizeof(double), sizeof(int));
+        std::memcpy(&r.moves, hs.data() + sizeof(double) + sizeof(int), sizeof(int));
+        r.gnorm = gn;
     }
     for (int comp = 0; comp < 3; ++comp) dcopy(c, c.xc.d() + comp * c.Ctot + d.coff, xt + comp * nq2, np2);
     if (c.have_gamma) {
-        launch_rep_eval(c.stream, q, 1, g0, nq2, th, ph, N, E);
+        launch_rep_pack(c.stream, q, 1, g0, nq2, hdr, rec);
+        launch_rep_eval(c.stream, q, 1, rec, cmt, th, ph, N, E);
         ana_run(c, {ana_job(c, q, q, 1, E, 0, hp, 0)});
         dcopy(c, c.gc.d() + d.coff, hp, np2);
     }

@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace bim {
 
 __global__ __launch_bounds__(256) void k_surf_terms(SurfJobs jobs)
@@ -127,80 +129,142 @@ void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, c
 // ----------------------------------------------------------------------------
 // Angle reparametrization (Sec. 4, Algorithm 2)
 // ----------------------------------------------------------------------------
-constexpr int kRepMaxF = 3;
+constexpr int kRepMaxDeg = 64;  // degree bound of the reparametrization grid (U_rep p)
 constexpr double kPiS = 3.14159265358979323846;
 
-__device__ inline double wave_add(double v)
+// Values and angle derivatives of NF (1 or 3) real expansions of degree q
+// at nodes (theta_i, phi_i), theta in [0, pi], from the orthonormal
+// associated-Legendre recursion in n at fixed order m (Sec. 1.1),
+//   P_m^m = c_m sin^m(theta),  P_{m+1}^m = sqrt(2m+3) cos(theta) P_m^m,
+//   P_n^m = a_nm cos(theta) P_{n-1}^m - b_nm P_{n-2}^m,
+// and the theta derivative from the same order,
+//   dP_n^m/dtheta = (n cos(theta) P_n^m - d_nm P_{n-1}^m) / sin(theta),
+//   d_nm = sqrt((2n+1)(n^2-m^2)/(2n-1))  (d_mm = 0).
+// The expansions are first packed (k_rep_pack) into order-major records
+// rec[(off(m) + n - m) RS], off(m) = m(q+1) - m(m-1)/2, RS = 4 + 2 NF:
+//   {a, b, d, n, re_0, im_0, ..., re_{NF-1}, im_{NF-1}},
+// with (a, b) = (0, -1) at n = m and (sqrt(2m+3), 0) at n = m + 1, so that
+// one recursion P = a t P_{n-1} - b P_{n-2} started from (P_{m-1}, P_{m-2})
+// = (0, c_m sin^m) covers every n. The expansions are fixed while the nodes
+// move, so the packing is done once per set of expansions.
+template <int NF>
+__global__ void k_rep_pack(int q, const double *__restrict__ coef, long cstride, const double *__restrict__ hdr,
+                           double *__restrict__ rec)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    constexpr int RS = 4 + 2 * NF;
+    const long nc = (long)(q + 1) * (q + 2) / 2;
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nc) return;
+    int m = 0;
+    long off = 0;
+    while (off + (q + 1 - m) <= j) off += q + 1 - m++;
+    const int n = m + (int)(j - off);
+    const long e = (long)n * (n + 1) / 2 + m;
+    double *r = rec + j * RS;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = hdr[4 * j + k];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        r[4 + 2 * f] = coef[f * cstride + 2 * e];
+        r[5 + 2 * f] = coef[f * cstride + 2 * e + 1];
+    }
 }
 
-// Values and angle derivatives of nf <= 3 real expansions of degree q
-// (component f at coef + f * cstride) at nodes (theta_i, phi_i), theta in
-// [0, pi]. One wavefront per node; lanes take the orders m = lane, lane + 64,
-// ...; each runs the orthonormal associated-Legendre recursion in n (Sec. 1.1)
-// and the theta derivative from the same order,
-//   dP_n^m/dtheta = (n cos(theta) P_n^m - sqrt((2n+1)(n^2-m^2)/(2n-1)) P_{n-1}^m) / sin(theta);
-// the order sums are wavefront sums. out[(3 f + d) N + i]: d = 0 value,
-// 1 d/dtheta, 2 d/dphi.
-__global__ __launch_bounds__(256) void k_rep_eval(int q, int nf, const double *__restrict__ coef, long cstride,
-                                                  const double *__restrict__ th, const double *__restrict__ ph,
-                                                  long N, double *__restrict__ out)
+// Evaluation: lanes take nodes (64 per block); the orders are split into
+// kRepWaves runs of whole orders with about equal record counts (order m
+// goes to run floor(off(m) kRepWaves / R), R = (q+1)(q+2)/2), one per
+// wavefront of the block. The records of a wavefront's orders are
+// wavefront-uniform, read through scalar loads. The order sums of the runs
+// are added in LDS in a fixed order, within the block (a split of the orders
+// over several blocks needs device-scope fences for the cross-block sum,
+// which cost more than the added parallelism gains).
+// out[(3 f + d) N + i]: d = 0 value, 1 d/dtheta, 2 d/dphi.
+constexpr int kRepWaves = 16;
+static_assert(kRepWaves % 2 == 0, "two-phase block sum");
+
+template <int NF>
+__global__ __launch_bounds__(64 * kRepWaves) void k_rep_eval(int q, const double *__restrict__ rec,
+                                                             const double *__restrict__ cmt,
+                                                             const double *__restrict__ th,
+                                                             const double *__restrict__ ph, long N,
+                                                             double *__restrict__ out)
 {
-    const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // node (one per wavefront)
+    constexpr int RS = 4 + 2 * NF, NO = 3 * NF;
+    __shared__ double red[kRepWaves / 2][NO][64];
     const int lane = threadIdx.x & 63;
-    if (i >= N) return;                                                 // the whole wavefront
-    const double t = cos(th[i]), s = sin(th[i]), phi = ph[i];
-    double acc[kRepMaxF][3] = {};
-    for (int m0 = 0; m0 <= q; m0 += 64) {
-        const int m = m0 + lane;
-        if (m > q) continue;
-        double pmm = 1.0 / sqrt(4.0 * kPiS);
-        for (int k = 1; k <= m; ++k) pmm *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-        double G[kRepMaxF][2][2] = {};  // [field][value, d_theta][re, im]
-        double Pm1 = 0.0, Pm2 = 0.0;
-        for (int n = m; n <= q; ++n) {
-            double P;
-            if (n == m) {
-                P = pmm;
-            } else if (n == m + 1) {
-                P = sqrt(2.0 * m + 3.0) * t * pmm;
-            } else {
-                const double an = sqrt((2.0 * n + 1.0) * (2.0 * n - 1.0) / ((double)(n - m) * (n + m)));
-                const double bn = sqrt((2.0 * n + 1.0) * (double)(n + m - 1) * (n - m - 1) /
-                                       ((2.0 * n - 3.0) * (double)(n - m) * (n + m)));
-                P = an * t * Pm1 - bn * Pm2;
-            }
-            const double D =
-                (n * t * P - (n > m ? sqrt((2.0 * n + 1.0) * (double)(n - m) * (n + m) / (2.0 * n - 1.0)) * Pm1
-                                    : 0.0)) / s;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long grp = blockIdx.x;
+    const long i = grp * 64 + lane, ic = i < N ? i : N - 1;  // lanes past N evaluate node N - 1, store nothing
+    const double t = cos(th[ic]), s = sin(th[ic]), is = 1.0 / s, phi = ph[ic];
+    const long R = (long)(q + 1) * (q + 2) / 2;
+    double acc[NF][3] = {};
+    bool first = true;
+    double spow = 1.0, cm = 1.0, sm = 0.0, c1 = 1.0, s1 = 0.0;  // sin^m, e^{i m phi}, e^{i phi}
+    long off = 0;
+    for (int m = 0; m <= q; off += q + 1 - m, ++m) {
+        if ((off * kRepWaves) / R != w) continue;
+        if (first) {  // the run's first order: sin^m by binary powers, e^{i m phi} directly
+            double b = s;
+            for (int k = m; k; k >>= 1, b *= b)
+                if (k & 1) spow *= b;
+            sincos(m * phi, &sm, &cm);
+            sincos(phi, &s1, &c1);
+            first = false;
+        } else {  // the next order of the run
+            spow *= s;
+            const double c = cm * c1 - sm * s1;
+            sm = sm * c1 + cm * s1;
+            cm = c;
+        }
+        const double *r = rec + off * RS;
+        double Pm1 = 0.0, Pm2 = cmt[m] * spow;
+        double G[NF][2][2] = {};  // [field][value, d_theta * sin][re, im]
+#pragma unroll 2
+        for (int n = m; n <= q; ++n, r += RS) {
+            const double P = fma(r[0] * t, Pm1, -r[1] * Pm2);
+            const double Dp = fma(r[3] * t, P, -r[2] * Pm1);
             Pm2 = Pm1;
             Pm1 = P;
-            const long e = (long)n * (n + 1) / 2 + m;
-            for (int f = 0; f < nf; ++f) {
-                const double cr = coef[f * cstride + 2 * e], ci = coef[f * cstride + 2 * e + 1];
-                G[f][0][0] = fma(cr, P, G[f][0][0]);
-                G[f][0][1] = fma(ci, P, G[f][0][1]);
-                G[f][1][0] = fma(cr, D, G[f][1][0]);
-                G[f][1][1] = fma(ci, D, G[f][1][1]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                G[f][0][0] = fma(r[4 + 2 * f], P, G[f][0][0]);
+                G[f][0][1] = fma(r[5 + 2 * f], P, G[f][0][1]);
+                G[f][1][0] = fma(r[4 + 2 * f], Dp, G[f][1][0]);
+                G[f][1][1] = fma(r[5 + 2 * f], Dp, G[f][1][1]);
             }
         }
-        double sm, cm;
-        sincos(m * phi, &sm, &cm);
-        const double w = m ? 2.0 : 1.0;
-        for (int f = 0; f < nf; ++f) {
+        const double wt = m ? 2.0 : 1.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
             // Re(g e^{i m phi}) and Re(i m g e^{i m phi})
-            acc[f][0] += w * (G[f][0][0] * cm - G[f][0][1] * sm);
-            acc[f][1] += w * (G[f][1][0] * cm - G[f][1][1] * sm);
-            acc[f][2] += -w * m * (G[f][0][0] * sm + G[f][0][1] * cm);
+            acc[f][0] += wt * (G[f][0][0] * cm - G[f][0][1] * sm);
+            acc[f][1] += wt * is * (G[f][1][0] * cm - G[f][1][1] * sm);
+            acc[f][2] += -wt * m * (G[f][0][0] * sm + G[f][0][1] * cm);
         }
     }
-    for (int f = 0; f < nf; ++f)
-        for (int d = 0; d < 3; ++d) {
-            const double v = wave_add(acc[f][d]);
-            if (lane == 0) out[(3L * f + d) * N + i] = v;
-        }
+    // block sum: the upper half of the wavefronts stores, the lower half adds
+    constexpr int H = kRepWaves / 2;
+    if (w >= H) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) red[w - H][3 * f + d][lane] = acc[f][d];
+    }
+    __syncthreads();
+    if (w < H) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) red[w][3 * f + d][lane] += acc[f][d];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NO * 64; idx += blockDim.x) {
+        const int k = idx >> 6, l = idx & 63;
+        double v = 0.0;
+        for (int u = 0; u < H; ++u) v += red[u][k][l];
+        const long node = grp * 64 + l;
+        if (node < N) out[k * N + node] = v;
+    }
 }
 
 // g = (I - n n) grad E at every node, n = X_t x X_p / |X_t x X_p|; gmax holds
@@ -236,10 +300,15 @@ __global__ void k_rep_grad(long N, const double *__restrict__ E, const double *_
 // One forward-Euler step of the angles: w = -g, A alpha = (w.X_t, w.X_p) with
 // A the metric of the initial expansion at the node; theta, phi += dtau alpha,
 // taken back into theta in [0, pi] across the pole (phi + pi) and phi mod 2 pi.
+// With check set the step is skipped once the previous residual max |g|
+// (gmax) is below eps (the iteration has stopped); moves counts the steps taken.
 __global__ void k_rep_move(long N, const double *__restrict__ E, const double *__restrict__ g, double dtau,
-                           double *__restrict__ th, double *__restrict__ ph)
+                           double *__restrict__ th, double *__restrict__ ph, const unsigned long long *gmax,
+                           double eps, int check, int *moves)
 {
+    if (check && __longlong_as_double((long long)gmax[0]) < eps) return;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) moves[0] += 1;
     if (i >= N) return;
     double a00 = 0.0, a01 = 0.0, a11 = 0.0, b0 = 0.0, b1 = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -266,11 +335,24 @@ __global__ void k_rep_move(long N, const double *__restrict__ E, const double *_
     ph[i] = p;
 }
 
-void launch_rep_eval(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *th,
+void launch_rep_pack(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *hdr, double *rec)
+{
+    const long nc = (long)(q + 1) * (q + 2) / 2;
+    const unsigned blocks = (unsigned)((nc + 255) / 256);
+    if (nf == 3)
+        hipLaunchKernelGGL(k_rep_pack<3>, dim3(blocks), dim3(256), 0, st, q, coef, cstride, hdr, rec);
+    else
+        hipLaunchKernelGGL(k_rep_pack<1>, dim3(blocks), dim3(256), 0, st, q, coef, cstride, hdr, rec);
+}
+
+void launch_rep_eval(hipStream_t st, int q, int nf, const double *rec, const double *cm, const double *th,
                      const double *ph, long N, double *out)
 {
-    hipLaunchKernelGGL(k_rep_eval, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, q, nf, coef, cstride, th, ph, N,
-                       out);
+    const unsigned blocks = (unsigned)((N + 63) / 64);
+    if (nf == 3)
+        hipLaunchKernelGGL(k_rep_eval<3>, dim3(blocks), dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, N, out);
+    else
+        hipLaunchKernelGGL(k_rep_eval<1>, dim3(blocks), dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, N, out);
 }
 
 void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax)
@@ -278,9 +360,88 @@ void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, 
     hipLaunchKernelGGL(k_rep_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, gE, g, gmax);
 }
 
-void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph)
+void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph,
+                     const unsigned long long *gmax, double eps, int check, int *moves)
 {
-    hipLaunchKernelGGL(k_rep_move, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, g, dtau, th, ph);
+    hipLaunchKernelGGL(k_rep_move, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, g, dtau, th, ph, gmax,
+                       eps, check, moves);
+}
+
+// Adaptive cutoff and filter in one block: mag_n = sum_{|m| <= n} |x_n^m|
+// (3-vector norm, m > 0 twice), n_cut = the smallest l in 2..q whose tail
+// sum_{n >= l} mag_n is below P_cut sum_{n >= 1} mag_n (q + 1 when none);
+// hp = xt with the degrees n < n_cut zeroed; clears gmax for the gradient.
+// Each thread holds up to kRepCutPer coefficients (3 components) in
+// registers from one coalesced pass; the per-degree sums, their tails and
+// the search run from LDS in a fixed order (no atomics on the sums).
+constexpr int kRepCutThreads = 1024, kRepCutPer = 3;  // tri(kRepMaxDeg + 1) <= 3072
+static_assert((kRepMaxDeg + 1) * (kRepMaxDeg + 2) / 2 <= kRepCutThreads * kRepCutPer, "cutoff kernel size");
+
+__global__ __launch_bounds__(kRepCutThreads) void k_rep_cut(int q, const double *__restrict__ xt, long cs,
+                                                            double P_cut, double *__restrict__ hp, int *ncut,
+                                                            unsigned long long *gmax)
+{
+    __shared__ double v[kRepCutThreads * kRepCutPer];
+    __shared__ double mag[kRepMaxDeg + 1], tail[kRepMaxDeg + 2];
+    __shared__ int snc;
+    const int tid = threadIdx.x;
+    const int nc = (q + 1) * (q + 2) / 2;
+    double2 x[kRepCutPer][3];
+    int deg[kRepCutPer];
+#pragma unroll
+    for (int k = 0; k < kRepCutPer; ++k) {
+        const int e = tid + k * kRepCutThreads;
+        deg[k] = -1;
+        if (e < nc) {
+            int n = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while (n * (n + 1) / 2 > e) --n;
+            while ((n + 1) * (n + 2) / 2 <= e) ++n;
+            deg[k] = n;
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x[k][c] = *reinterpret_cast<const double2 *>(xt + c * cs + 2L * e);
+                s += x[k][c].x * x[k][c].x + x[k][c].y * x[k][c].y;
+            }
+            v[e] = (e == n * (n + 1) / 2 ? 1.0 : 2.0) * sqrt(s);
+        }
+    }
+    if (tid == 0) snc = q + 1;
+    __syncthreads();
+    if (tid <= q) {
+        double a = 0.0;
+        for (int m = 0; m <= tid; ++m) a += v[tid * (tid + 1) / 2 + m];
+        mag[tid] = a;
+    }
+    __syncthreads();
+    if (tid >= 1 && tid <= q) {
+        double t = 0.0;
+        for (int n = tid; n <= q; ++n) t += mag[n];
+        tail[tid] = t;
+    }
+    __syncthreads();
+    if (tid >= 2 && tid <= q && tail[tid] < P_cut * tail[1]) atomicMin(&snc, tid);
+    __syncthreads();
+    const int l = snc;
+    if (tid == 0) {
+        ncut[0] = l;
+        gmax[0] = 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < kRepCutPer; ++k) {
+        if (deg[k] < 0) continue;
+        const long e = tid + k * kRepCutThreads;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            *reinterpret_cast<double2 *>(hp + c * cs + 2 * e) = deg[k] >= l ? x[k][c] : double2{0.0, 0.0};
+    }
+}
+
+void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
+                    unsigned long long *gmax)
+{
+    if (q < 1 || q > kRepMaxDeg || (cs & 1)) return;  // the host validates q = U_rep p <= 64, cs = (q+1)(q+2)
+    hipLaunchKernelGGL(k_rep_cut, dim3(1), dim3(kRepCutThreads), 0, st, q, xt, cs, P_cut, hp, ncut, gmax);
 }
 
 }  // namespace bim
