@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 PEAK = {"alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 BOUND = {"sing_fused": "alu", "pair_sl": "alu", "pair_dl": "alu", "dl_apply": "hbm",
          "synthesis": "hbm", "analysis": "hbm", "sing_v1": "alu", "sing_rotate": "alu", "classify": "alu",
-         "pipe_rotate": "alu", "pipe_legendre": "hbm", "pipe_fourier": "alu", "pipe_adjrot": "alu", "near": "alu"}
+         "pipe_rotate": "alu", "pipe_legendre": "hbm", "pipe_fourier": "alu", "pipe_adjrot": "alu", "near": "alu",
+         "fmm": "alu"}
 KERNELS = list(BOUND)
 
 
@@ -303,6 +304,9 @@ def main():
     ap.add_argument("--dt-max", type=float, default=0.2)
     ap.add_argument("--shear", type=float, default=0.2)
     ap.add_argument("--rep-imax", type=int, default=0, help="time loop: reparametrize after accepted steps (0: off)")
+    ap.add_argument("--fmm-order", type=int, default=0,
+                    help="fast summation of far drop pairs: multipole order P (0: every pair summed directly)")
+    ap.add_argument("--fmm-eps", type=float, default=1e-10, help="truncation bound rho^(P+1) of a far pair")
     ap.add_argument("--rep-pcut", type=float, default=1e-3)
     ap.add_argument("--rep-eps", type=float, default=1e-6)
     args = ap.parse_args()
@@ -335,7 +339,8 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx = B.Context(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom,
-                        gmres_tol=wl.gmres_tol, singular_path=args.singular_path, stream=stream.cuda_stream)
+                        gmres_tol=wl.gmres_tol, singular_path=args.singular_path, stream=stream.cuda_stream,
+                        fmm_order=args.fmm_order, fmm_eps=args.fmm_eps)
         ctx.set_drops([d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops])
         if wl.eos != 0:
             ctx.set_tension([d.gc for d in wl.drops], wl.eos, wl.E, wl.xs)
@@ -399,6 +404,9 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms"] / nprof, 4) for k, v in brk.items() if v["launches"]},
         "kernels_roofline_frac": {k: round(kernel_frac(k, v), 4) for k, v in brk.items() if v["ms"] > 0},
     }
+    if args.fmm_order > 0:
+        res["config"]["fast_summation"] = {"order": args.fmm_order, "eps": args.fmm_eps,
+                                           "far_pairs": reps[-1].n_fmm_pairs}
     ctx.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)

@@ -91,6 +91,17 @@ typedef struct {
                                exterior limit for the double layer, regular values at
                                x* + h sqrt(l) d, l = 1..near_L, Lagrange interpolation) */
     int near_L;          /* interpolation points of the special quadrature, 2..16 (paper: 8) */
+    int fmm_order;       /* fast summation of far drop pairs (the O(N^2) pair sums of Sec. 2.1 and
+                            2.3, which the paper proposes to replace by fast summation, Sec. 6):
+                            0 = off (every pair summed directly); P in 2..30 = multipole order of a
+                            drop-level fast multipole method on four harmonic potentials (Laplace
+                            multipoles of each source drop, translated to local expansions of each
+                            target drop, evaluated at its nodes). A drop pair (i, j) takes it when
+                            all targets of i are in the same region of j (0 or 1, no Omega_2) and
+                            rho^(P+1) <= fmm_eps, rho = (a_i + a_j) / |c_i - c_j| (bounding radii
+                            and centres of i's nodes and of j's source grid); the others are
+                            summed directly */
+    double fmm_eps;      /* truncation bound of a far pair, in (0, 1) */
 } bim_options;
 
 typedef struct {
@@ -101,6 +112,7 @@ typedef struct {
     int n_omega2;             /* pairs in Omega_2 (near_rule selects their quadrature) */
     int n_matvec;             /* operator applications in the solve */
     double ms_total;          /* wall time of the call */
+    int n_fmm_pairs;          /* drop pairs taken by the fast summation (fmm_order > 0) */
 } bim_report;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -109,7 +121,7 @@ int bim_version(void);
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
- * stream NULL, near_rule 1, near_L 8. */
+ * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */

@@ -40,6 +40,8 @@ class bim_options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("near_rule", ctypes.c_int),
         ("near_L", ctypes.c_int),
+        ("fmm_order", ctypes.c_int),
+        ("fmm_eps", ctypes.c_double),
     ]
 
 
@@ -62,6 +64,7 @@ class bim_report(ctypes.Structure):
         ("n_omega2", ctypes.c_int),
         ("n_matvec", ctypes.c_int),
         ("ms_total", ctypes.c_double),
+        ("n_fmm_pairs", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libbim.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["tables.cpp", "kernels.hip", "kernels_sing.hip", "kernels_pipe.hip", "kernels_xform.hip", "kernels_near.hip",
-           "kernels_surf.hip", "bim.hip", "server.cpp"]
+           "kernels_surf.hip", "kernels_fmm.hip", "bim.hip", "server.cpp"]
 ARCH = os.environ.get("BIM_OFFLOAD_ARCH", "gfx950")
 
 

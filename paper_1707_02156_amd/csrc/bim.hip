@@ -135,6 +135,13 @@ void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, d
 void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
                     unsigned long long *gmax);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
+void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, double2 *Y);
+void launch_fmm_p2m(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int kind, int P, const double *cen,
+                    const double2 *Y, double *W, double2 *part, double2 *M);
+void launch_fmm_m2l(hipStream_t st, int npairs, const FmmPair *pairs, int P, const double *cen_s, const double *cen_t,
+                    const double2 *M, double2 *Lp, int nt, const int *poff, double2 *L);
+void launch_fmm_l2p(hipStream_t st, int njobs, const FmmTgtJob *jobs, int maxn, int P, const double *cen_t,
+                    const double2 *L, const double *tx, long tstride, double *out, long ostride);
 
 static const double kPi = 3.14159265358979323846;
 
@@ -228,6 +235,7 @@ struct Ctx {
     DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
     DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
     DBuf tdrop, vol, hj, noff, ncnt;
+    DBuf unoff, uncnt, cbnd1;  // upsampled grids: node offsets, counts, centres and radii
     std::vector<int> sys_h;  // independent system of each drop (bim_set_systems)
     DBuf sysd;
     DBuf reg, dist, cbnd, clist, ccount;
@@ -240,10 +248,37 @@ struct Ctx {
         int n = 0;
         double pairs = 0.0;  // target-source pairs per application
         DBuf nw;             // weight of each nearest-region item
+        DBuf fp;             // far pairs of the fast summation with their weights
     };
     std::vector<std::unique_ptr<WList>> wlists;
     std::vector<int8_t> reg_h;
     int n_om1 = 0, n_om2 = 0;
+    // fast summation of far drop pairs (opt.fmm_order > 0): multipole slots
+    // (drop, source grid), target slots (drops), pairs grouped by target slot
+    struct Fmm {
+        int P = 0;
+        std::vector<FmmSrcJob> src;
+        std::vector<FmmTgtJob> tgt;
+        std::vector<FmmPair> pairs;  // weights set per weight table
+        std::vector<int> pair_ij;    // i * nd + j of each pair
+        std::vector<int> poff;       // pairs of target slot t: [poff[t], poff[t+1])
+        int maxns = 0, maxnt = 0;
+        long nsrc = 0, ntgt = 0, nchunks = 0;
+        double m2l_flops = 0.0;  // algorithmic flops of the translations of one application
+        DBuf dsrc, dtgt, dpoff, cen_s, cen_t, Y, W, part, M, Lp, L;
+        void reset(int order)  // a new plan (device buffers kept for reuse)
+        {
+            P = order;
+            src.clear();
+            tgt.clear();
+            pairs.clear();
+            pair_ij.clear();
+            poff.clear();
+            maxns = maxnt = 0;
+            nsrc = ntgt = nchunks = 0;
+            m2l_flops = 0.0;
+        }
+    } fmm;
     // nearest-region items (near_rule 1) and their interpolation points
     std::vector<NearItem> near_h;
     std::vector<char> near_src;                 // drops that are the source of an item
@@ -773,6 +808,54 @@ static void near_setup(Ctx &c)
     c.near_nwork = (int)w.size();
 }
 
+// Device side of the fast-summation plan built by build_regions: job and
+// centre arrays, work buffers, and the regular harmonics of every source
+// grid's nodes about its centre (fixed while the geometry is).
+static void fmm_setup(Ctx &c, const std::vector<double> &cb0, const std::vector<double> &cb1)
+{
+    Ctx::Fmm &F = c.fmm;
+    const int P = F.P, ntri = (P + 1) * (P + 2) / 2;
+    std::vector<double> cs(4 * F.src.size()), ct(4 * F.tgt.size());
+    for (auto &sj : F.src) {
+        const bool up = sj.x == c.s1x.d();
+        for (int k = 0; k < 4; ++k) cs[4 * sj.slot + k] = (up ? cb1 : cb0)[4 * sj.drop + k];
+        sj.yoff = F.nsrc * ntri;
+        sj.woff = F.nsrc * 12;
+        sj.pbase = (int)F.nchunks;
+        F.nsrc += sj.ns;
+        F.nchunks += (sj.ns + kFmmChunk - 1) / kFmmChunk;
+        F.maxns = std::max(F.maxns, sj.ns);
+    }
+    for (auto &tj : F.tgt) {
+        int i = 0;
+        while (c.drops[i].toff != tj.off) ++i;
+        for (int k = 0; k < 4; ++k) ct[4 * tj.slot + k] = cb0[4 * i + k];
+        F.ntgt += tj.n;
+        F.maxnt = std::max(F.maxnt, tj.n);
+    }
+    F.poff.push_back((int)F.pairs.size());
+    const size_t cb = (size_t)4 * ntri * sizeof(double2);
+    F.dsrc.ensure(F.src.size() * sizeof(FmmSrcJob));
+    F.dtgt.ensure(F.tgt.size() * sizeof(FmmTgtJob));
+    F.dpoff.ensure(F.poff.size() * sizeof(int));
+    F.cen_s.ensure(cs.size() * sizeof(double));
+    F.cen_t.ensure(ct.size() * sizeof(double));
+    F.Y.ensure((size_t)F.nsrc * ntri * sizeof(double2));
+    F.W.ensure((size_t)F.nsrc * 12 * sizeof(double));
+    F.part.ensure((size_t)F.nchunks * cb);
+    F.M.ensure(F.src.size() * 4 * (P + 1) * (P + 1) * sizeof(double2));
+    F.Lp.ensure(F.pairs.size() * cb);
+    F.L.ensure(F.tgt.size() * cb);
+    HIPC(hipMemcpyAsync(F.dsrc.ptr, F.src.data(), F.src.size() * sizeof(FmmSrcJob), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(F.dtgt.ptr, F.tgt.data(), F.tgt.size() * sizeof(FmmTgtJob), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(F.dpoff.ptr, F.poff.data(), F.poff.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(F.cen_s.ptr, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemcpyAsync(F.cen_t.ptr, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    launch_fmm_ytab(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, P, F.cen_s.d(),
+                    (double2 *)F.Y.ptr);
+    HIPC(hipStreamSynchronize(c.stream));
+}
+
 static void build_regions(Ctx &c)
 {
     if (c.regions_ok) return;
@@ -796,6 +879,10 @@ static void build_regions(Ctx &c)
     {
         ProfScope ps(c, "classify", 0.0, 0.0);
         launch_drop_bounds(c.stream, c.nd, c.tx.d(), c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.cbnd.d());
+        if (c.opt.fmm_order > 0) {
+            c.cbnd1.ensure(4 * c.nd * sizeof(double));
+            launch_drop_bounds(c.stream, c.nd, c.s1x.d(), c.S1, c.unoff.as<int>(), c.uncnt.as<int>(), c.cbnd1.d());
+        }
         HIPC(hipMemsetAsync(c.ccount.ptr, 0, sizeof(int), c.stream));
         launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.sysd.as<int>(),
                               c.cbnd.d(), c.hj.d(),
@@ -814,6 +901,41 @@ static void build_regions(Ctx &c)
     c.reg_h.resize(nreg);
     HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
+    // far drop pairs for the fast summation: every target of i in the same
+    // region (0 or 1) with respect to j, and the truncation bound
+    // rho^(P+1) <= eps, rho = (a_i + a_j) / |c_i - c_j| (bounding radii of the
+    // target nodes and of the source grid the region selects)
+    std::vector<double> cb0, cb1;
+    const int P = c.opt.fmm_order;
+    if (P > 0) {
+        cb0.resize(4 * c.nd);
+        cb1.resize(4 * c.nd);
+        HIPC(hipMemcpyAsync(cb0.data(), c.cbnd.ptr, cb0.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipMemcpyAsync(cb1.data(), c.cbnd1.ptr, cb1.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+    }
+    // grid of a far pair (-1: summed directly); order: the smallest degree
+    // Q <= P with rho^(Q+1) <= eps, used by that pair's translation
+    auto far_grid = [&](int i, int j, int &order) -> int {
+        if (P <= 0) return -1;
+        const Drop &di = c.drops[i];
+        const int8_t r0 = c.reg_h[di.toff * c.nd + j];
+        if (r0 != 0 && r0 != 1) return -1;
+        for (int t = 1; t < npts(di.p); ++t)
+            if (c.reg_h[(di.toff + t) * c.nd + j] != r0) return -1;
+        const double *cs = (r0 == 0 ? cb0.data() : cb1.data()) + 4 * j, *ct = cb0.data() + 4 * i;
+        const double D = std::sqrt((ct[0] - cs[0]) * (ct[0] - cs[0]) + (ct[1] - cs[1]) * (ct[1] - cs[1]) +
+                                   (ct[2] - cs[2]) * (ct[2] - cs[2]));
+        const double rho = (cs[3] + ct[3]) / D;
+        if (!(rho < 1.0 && std::pow(rho, P + 1) <= c.opt.fmm_eps)) return -1;
+        order = 2;
+        while (order < P && std::pow(rho, order + 1) > c.opt.fmm_eps) ++order;
+        return r0;
+    };
+    Ctx::Fmm &F = c.fmm;
+    F.reset(P);
+    std::map<std::pair<int, int>, int> sslot;
+    std::map<int, int> tslot;
     // work lists: for each (target drop i, source drop j != i): Omega_0 targets
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
     std::vector<int> tl;
@@ -827,6 +949,38 @@ static void build_regions(Ctx &c)
         for (int j = 0; j < c.nd; ++j) {
             if (j == i || c.sys_h[i] != c.sys_h[j]) continue;
             const Drop &dj = c.drops[j];
+            int forder = 0;
+            const int fg = far_grid(i, j, forder);
+            if (fg >= 0) {
+                if (fg == 1) c.n_om1 += nti;
+                const auto ks = std::make_pair(j, fg);
+                if (!sslot.count(ks)) {
+                    const int sl = (int)F.src.size();
+                    sslot[ks] = sl;
+                    FmmSrcJob sj{};
+                    sj.x = fg == 0 ? c.tx.d() : c.s1x.d();
+                    sj.d = fg == 0 ? c.s0d.d() : c.s1d.d();
+                    sj.wW = fg == 0 ? c.s0W.d() : c.s1W.d();
+                    sj.wN = fg == 0 ? c.s0N.d() : c.s1N.d();
+                    sj.stride = fg == 0 ? c.T : c.S1;
+                    sj.off = fg == 0 ? dj.toff : dj.uoff;
+                    sj.ns = fg == 0 ? npts(dj.p) : npts(dj.qu);
+                    sj.slot = sl;
+                    sj.drop = j;
+                    F.src.push_back(sj);
+                }
+                if (!tslot.count(i)) {
+                    const int sl = (int)F.tgt.size();
+                    tslot[i] = sl;
+                    F.tgt.push_back(FmmTgtJob{di.toff, nti, sl});
+                    F.poff.push_back((int)F.pairs.size());
+                }
+                F.pairs.push_back(FmmPair{sslot[ks], tslot[i], forder, 0, 0.0});
+                const double nt = (forder + 1) * (forder + 2) / 2;
+                F.m2l_flops += nt * (forder + 1) * (forder + 1) * 32.0;
+                F.pair_ij.push_back(i * c.nd + j);
+                continue;
+            }
             for (int kind = 0; kind < 2; ++kind) {
                 const int start = (int)tl.size();
                 for (int t = 0; t < nti; ++t) {
@@ -859,6 +1013,7 @@ static void build_regions(Ctx &c)
     if (!tl.empty())
         HIPC(hipMemcpyAsync(c.tlist.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
+    if (!F.pairs.empty()) fmm_setup(c, cb0, cb1);
     c.w0h = std::move(w0);
     c.w1h = std::move(w1);
     c.wlists.clear();
@@ -897,8 +1052,39 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
         HIPC(hipMemcpyAsync(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
     }
+    if (!c.fmm.pairs.empty()) {
+        std::vector<FmmPair> fp = c.fmm.pairs;
+        for (size_t k = 0; k < fp.size(); ++k) fp[k].w = wt[c.fmm.pair_ij[k]];
+        e->fp.ensure(fp.size() * sizeof(FmmPair));
+        HIPC(hipMemcpyAsync(e->fp.ptr, fp.data(), fp.size() * sizeof(FmmPair), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+    }
     c.wlists.push_back(std::move(e));
     return *c.wlists.back();
+}
+
+// Far drop pairs by the fast summation (plan of build_regions), added into
+// acc: per-source weights and multipoles of every source grid, one
+// translation per pair with its weight, the local expansions summed per
+// target drop, then evaluated at its nodes.
+static void run_fmm(Ctx &c, int kind, Ctx::WList &L)
+{
+    Ctx::Fmm &F = c.fmm;
+    if (F.pairs.empty()) return;
+    const int P = F.P;
+    const double ntri = (P + 1) * (P + 2) / 2;
+    // algorithmic flops: P2M 8 (SL) or 48 (DL) per source and coefficient;
+    // M2L 32 per coefficient pair at the pair's order (4 channels, complex);
+    // L2P 60 per target and coefficient
+    const double fl = (double)F.nsrc * ntri * (kind == 0 ? 8.0 : 48.0) + F.m2l_flops + (double)F.ntgt * ntri * 60.0;
+    ProfScope ps(c, "fmm", fl, 0.0);
+    launch_fmm_p2m(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, kind, P, F.cen_s.d(),
+                   (const double2 *)F.Y.ptr, F.W.d(), (double2 *)F.part.ptr, (double2 *)F.M.ptr);
+    launch_fmm_m2l(c.stream, (int)F.pairs.size(), L.fp.as<FmmPair>(), P, F.cen_s.d(), F.cen_t.d(),
+                   (const double2 *)F.M.ptr, (double2 *)F.Lp.ptr, (int)F.tgt.size(), F.dpoff.as<int>(),
+                   (double2 *)F.L.ptr);
+    launch_fmm_l2p(c.stream, (int)F.tgt.size(), F.dtgt.as<FmmTgtJob>(), F.maxnt, P, F.cen_t.d(),
+                   (const double2 *)F.L.ptr, c.tx.d(), c.T, c.acc.d(), c.T);
 }
 
 // Pair sums with weight table wt, added into acc: one launch over the items
@@ -911,6 +1097,7 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
     launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T);
+    run_fmm(c, kind, L);
 }
 
 // Nearest-region items (Sec. 2.3): the self-interaction grids of their source
@@ -1560,6 +1747,8 @@ int bim_default_options(bim_options *o)
     o->stream = nullptr;
     o->near_rule = 1;
     o->near_L = 8;
+    o->fmm_order = 0;
+    o->fmm_eps = 1e-10;
     return BIM_OK;
 }
 
@@ -1570,7 +1759,9 @@ int bim_create(const bim_options *opt, bim_ctx *out)
     if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
         (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
-        (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL)
+        (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL ||
+        (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder)) ||
+        !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0))
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {
@@ -1685,11 +1876,13 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         c.tmp.ensure((size_t)3 * c.T * sizeof(double));
         c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
         c.xsol.ensure((size_t)3 * c.Ctot * sizeof(double));
-        std::vector<int> tdrop(c.T), noff(c.nd), ncnt(c.nd);
+        std::vector<int> tdrop(c.T), noff(c.nd), ncnt(c.nd), unoff(c.nd), uncnt(c.nd);
         for (int i = 0; i < c.nd; ++i) {
             for (int t = 0; t < npts(ds[i].p); ++t) tdrop[ds[i].toff + t] = i;
             noff[i] = (int)ds[i].toff;
             ncnt[i] = npts(ds[i].p);
+            unoff[i] = (int)ds[i].uoff;
+            uncnt[i] = npts(ds[i].qu);
         }
         c.sys_h.assign(c.nd, 0);
         c.sysd.ensure(c.nd * sizeof(int));
@@ -1700,6 +1893,10 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         HIPC(hipMemcpyAsync(c.tdrop.ptr, tdrop.data(), c.T * sizeof(int), hipMemcpyHostToDevice, c.stream));
         HIPC(hipMemcpyAsync(c.noff.ptr, noff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
         HIPC(hipMemcpyAsync(c.ncnt.ptr, ncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        c.unoff.ensure(c.nd * sizeof(int));
+        c.uncnt.ensure(c.nd * sizeof(int));
+        HIPC(hipMemcpyAsync(c.unoff.ptr, unoff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipMemcpyAsync(c.uncnt.ptr, uncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
         // Galerkin operator diagonal (lambda_i + 1)
         std::vector<double> scl((size_t)3 * c.Ctot);
         for (int comp = 0; comp < 3; ++comp)
@@ -2362,6 +2559,7 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
             rep->n_targets = (int)c.T;
             rep->n_omega1 = c.n_om1;
             rep->n_omega2 = c.n_om2;
+            rep->n_fmm_pairs = (int)c.fmm.pairs.size();
             rep->n_matvec = nmv;
             rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }

@@ -141,4 +141,34 @@ struct PairSrc {
     long stride;
 };
 
+// Fast summation of far drop pairs (kernels_fmm.hip). Expansion order P <=
+// kFmmMaxOrder; 4 channels; local expansions and partial multipoles keep
+// m >= 0 ((P+1)(P+2)/2 complex per channel), the multipoles used by the
+// translation all orders ((P+1)^2 complex per channel).
+constexpr int kFmmMaxOrder = 30, kFmmThreads = 512, kFmmChunk = 256;
+static_assert((kFmmMaxOrder + 1) * (kFmmMaxOrder + 2) / 2 <= kFmmThreads, "one thread per coefficient");
+
+// One source grid of one drop (a multipole slot): nodes [off, off + ns) of
+// component-major arrays with the given stride; regular-harmonic table at
+// Y + yoff (ns x ntri), per-source weights at W + woff (ns x 4 or 12),
+// partial multipoles from chunk pbase on.
+struct FmmSrcJob {
+    const double *x, *d, *wW, *wN;
+    long stride, off, yoff, woff;
+    int ns, slot, pbase, drop;
+};
+
+// A far pair: multipole slot src translated to target slot tgt with weight
+// w, truncated at degree order (<= P) in both expansions.
+struct FmmPair {
+    int src, tgt, order, pad;
+    double w;
+};
+
+// Target nodes [off, off + n) (global target indices) of target slot.
+struct FmmTgtJob {
+    long off;
+    int n, slot;
+};
+
 }  // namespace bim

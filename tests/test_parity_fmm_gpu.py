@@ -1,0 +1,150 @@
+"""Fast summation of far drop pairs (option fmm_order) against the direct
+pair sums of the oracle and of the GPU path.
+
+The fast summation approximates the pair sums of the far drop pairs; its
+truncation error for a pair is bounded by a constant times rho^(P+1) of
+that pair's contribution, and a pair takes it only when rho^(P+1) <= fmm_eps.
+Bars:
+- against the oracle's direct sums on sampled targets (far pairs from the
+  standard grid, A_tilde = 5): 1e-10 of the largest sampled value, with
+  fmm_eps = 1e-12 (the FP64 bar of the direct path);
+- against the direct GPU path on every target of the 64-drop workload
+  (far pairs from the 2x grid): 1e-10 with fmm_eps = 1e-12;
+- the error falls with the order P at a fixed set of far pairs (a wrong sign
+  or index in a translation term would not converge);
+- a full velocity solve agrees with the direct solve to 1e-9.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_parity_gpu import ctx_for, osys, random_coef
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_02156_amd as B
+    return B
+
+
+def _density(rng, p):
+    c = random_coef(rng, p, 3)
+    for n in range(p + 1):
+        c[:, n * (n + 1) // 2:(n + 1) * (n + 2) // 2] *= (1.0 + n) ** -2
+    return c
+
+
+def _rel(got, ref):
+    return np.abs(np.asarray(got) - np.asarray(ref)).max() / np.abs(ref).max()
+
+
+def _layers(c, dens):
+    return np.concatenate([np.ravel(u) for u in c.single_layer()]), \
+        np.concatenate([np.ravel(u) for u in c.double_layer(dens, mode=0)])
+
+
+def _fmm_pairs(c):
+    _, rep = c.eval_velocity(coefficients=True)
+    return rep.n_fmm_pairs
+
+
+def test_fmm_against_oracle_sampled(B, orc):
+    """12 drops of degree 10 in a cube of side 16 (A_tilde = 5: far targets
+    are in Omega_0 and the far pairs use the standard grid)."""
+    print("fmm: 12 drops p=10 vs oracle", flush=True)
+    wl = W.many_drops(nd=12, p=10, box=16.0, gap=0.5, seed=41)
+    rng = np.random.default_rng(42)
+    c = ctx_for(B, wl, A_tilde=5.0, fmm_order=24, fmm_eps=1e-12)
+    s = osys(orc, wl, A_tilde=5.0)
+    nd = len(wl.drops)
+    dens = [_density(rng, 10) for _ in range(nd)]
+    u = c.single_layer()
+    D = c.double_layer(dens, mode=0)
+    assert _fmm_pairs(c) > 0
+    forces = [s.force(j) for j in range(nd)]
+    for i in (0, 5, 11):
+        tg = np.sort(rng.choice(B.npts(10), 10, replace=False))
+        su = -s.layer(i, forces, 0, targets=tg) / (8 * np.pi)
+        sd = s.layer(i, dens, 1, targets=tg) / (4 * np.pi)
+        assert _rel(u[i][tg], su) <= 1e-10
+        assert _rel(D[i][tg], sd) <= 1e-10
+    c.close()
+
+
+def test_fmm_matches_direct_many_drops(B):
+    """The 64-drop workload (p = 16, every pair on the 2x grid): every target,
+    single and double layer, fast summation against direct sums."""
+    print("fmm: 64 drops vs direct", flush=True)
+    wl = W.many_drops()
+    rng = np.random.default_rng(43)
+    dens = [_density(rng, 16) for _ in range(len(wl.drops))]
+    cd = ctx_for(B, wl)
+    sd, dd = _layers(cd, dens)
+    cd.close()
+    cf = ctx_for(B, wl, fmm_order=24, fmm_eps=1e-12)
+    sf, df = _layers(cf, dens)
+    nf = _fmm_pairs(cf)
+    cf.close()
+    print("far pairs", nf, "of", 64 * 63, flush=True)
+    assert nf > 0
+    assert _rel(sf, sd) <= 1e-10
+    assert _rel(df, dd) <= 1e-10
+
+
+def test_fmm_error_falls_with_order(B):
+    """Eight drops, every pair with rho < 0.6 taken (fmm_eps = 0.6^(P+1) at
+    each order P; each pair translated at its own order Q <= P, the smallest
+    with rho^(Q+1) <= fmm_eps): the error against the direct sums falls from
+    P = 4 to 8 to 16 and stays within 10 fmm_eps of the largest value (the
+    truncation bound of one pair, times 1/(1 - rho)^2 <= 6.25)."""
+    print("fmm: convergence in P", flush=True)
+    wl = W.many_drops(nd=8, p=8, box=14.0, gap=1.0, seed=44)
+    rng = np.random.default_rng(45)
+    dens = [_density(rng, 8) for _ in range(len(wl.drops))]
+    cd = ctx_for(B, wl, A_tilde=5.0)
+    sd, dd = _layers(cd, dens)
+    cd.close()
+    errs, npairs = [], []
+    for P in (4, 8, 16):
+        c = ctx_for(B, wl, A_tilde=5.0, fmm_order=P, fmm_eps=0.6 ** (P + 1))
+        sf, df = _layers(c, dens)
+        npairs.append(_fmm_pairs(c))
+        errs.append((_rel(sf, sd), _rel(df, dd)))
+        c.close()
+    print("pairs", npairs, "errors", errs, flush=True)
+    assert npairs[0] == npairs[1] == npairs[2] > 0
+    for k in range(2):
+        assert errs[0][k] > errs[1][k] > errs[2][k]
+    for P, e in zip((4, 8, 16), errs):
+        assert max(e) <= 10 * 0.6 ** (P + 1)
+
+
+def test_fmm_velocity_solve(B):
+    """A full velocity solve (single layer, right-hand side, GMRES on the
+    double-layer operator) with the fast summation against the direct solve."""
+    print("fmm: velocity solve", flush=True)
+    wl = W.many_drops(nd=16, p=12, box=14.0, gap=0.4, seed=46)
+    cd = ctx_for(B, wl)
+    ud, rd = cd.eval_velocity(coefficients=True)
+    cd.close()
+    cf = ctx_for(B, wl, fmm_order=24, fmm_eps=1e-12)
+    uf, rf = cf.eval_velocity(coefficients=True)
+    cf.close()
+    assert rf.n_fmm_pairs > 0 and rd.n_fmm_pairs == 0
+    a = np.concatenate([np.ravel(x) for x in ud])
+    b = np.concatenate([np.ravel(x) for x in uf])
+    assert _rel(b, a) <= 1e-9
+    assert abs(rf.gmres_iterations - rd.gmres_iterations) <= 1
+
+
+def test_fmm_option_errors(B):
+    for kw in [dict(fmm_order=1), dict(fmm_order=31), dict(fmm_order=8, fmm_eps=0.0),
+               dict(fmm_order=8, fmm_eps=1.0), dict(fmm_order=-2)]:
+        with pytest.raises(B.BimError) as e:
+            B.Context(**kw)
+        assert e.value.status == B.BIM_EINVAL
