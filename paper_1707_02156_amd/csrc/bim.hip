@@ -141,7 +141,7 @@ void launch_fmm_p2m(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns,
 void launch_fmm_m2l(hipStream_t st, int npairs, const FmmPair *pairs, int P, const double *cen_s, const double *cen_t,
                     const double2 *M, double2 *Lp, int nt, const int *poff, double2 *L);
 void launch_fmm_l2p(hipStream_t st, int njobs, const FmmTgtJob *jobs, int maxn, int P, const double *cen_t,
-                    const double2 *L, const double *tx, long tstride, double *out, long ostride);
+                    const double2 *L, double2 *C, const double *tx, long tstride, double *out, long ostride);
 
 static const double kPi = 3.14159265358979323846;
 
@@ -265,7 +265,7 @@ struct Ctx {
         int maxns = 0, maxnt = 0;
         long nsrc = 0, ntgt = 0, nchunks = 0;
         double m2l_flops = 0.0;  // algorithmic flops of the translations of one application
-        DBuf dsrc, dtgt, dpoff, cen_s, cen_t, Y, W, part, M, Lp, L;
+        DBuf dsrc, dtgt, dpoff, cen_s, cen_t, Y, W, part, M, Lp, L, C;
         void reset(int order)  // a new plan (device buffers kept for reuse)
         {
             P = order;
@@ -846,6 +846,7 @@ static void fmm_setup(Ctx &c, const std::vector<double> &cb0, const std::vector<
     F.M.ensure(F.src.size() * 4 * (P + 1) * (P + 1) * sizeof(double2));
     F.Lp.ensure(F.pairs.size() * cb);
     F.L.ensure(F.tgt.size() * cb);
+    F.C.ensure(F.tgt.size() * ntri * 15 * sizeof(double2));
     HIPC(hipMemcpyAsync(F.dsrc.ptr, F.src.data(), F.src.size() * sizeof(FmmSrcJob), hipMemcpyHostToDevice, c.stream));
     HIPC(hipMemcpyAsync(F.dtgt.ptr, F.tgt.data(), F.tgt.size() * sizeof(FmmTgtJob), hipMemcpyHostToDevice, c.stream));
     HIPC(hipMemcpyAsync(F.dpoff.ptr, F.poff.data(), F.poff.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
@@ -1084,7 +1085,7 @@ static void run_fmm(Ctx &c, int kind, Ctx::WList &L)
                    (const double2 *)F.M.ptr, (double2 *)F.Lp.ptr, (int)F.tgt.size(), F.dpoff.as<int>(),
                    (double2 *)F.L.ptr);
     launch_fmm_l2p(c.stream, (int)F.tgt.size(), F.dtgt.as<FmmTgtJob>(), F.maxnt, P, F.cen_t.d(),
-                   (const double2 *)F.L.ptr, c.tx.d(), c.T, c.acc.d(), c.T);
+                   (const double2 *)F.L.ptr, (double2 *)F.C.ptr, c.tx.d(), c.T, c.acc.d(), c.T);
 }
 
 // Pair sums with weight table wt, added into acc: one launch over the items

@@ -317,86 +317,124 @@ __global__ void k_fmm_lsum(int nt, int P, const int *__restrict__ poff, const do
 }
 
 // ---- L2P: velocity at the target nodes ---------------------------------------
-// Thread = target node of a target drop; the local coefficients are
-// wavefront-uniform (scalar loads). With xi = x - c_t and U = U_k^l(xi):
-//   H_c      = sum L_c[k][l] conj(U),
-//   d_z H_c  = sum L_c[k+1][l] conj(U),
-//   d_x H_c  = sum (L_c[k+1][l-1] - L_c[k+1][l+1]) / 2 conj(U),
-//   d_y H_c  = sum i (L_c[k+1][l-1] + L_c[k+1][l+1]) / 2 conj(U),
-// each real field summed over l >= 0 as the l = 0 term plus twice the real
-// part of the l > 0 terms; out[i][t] += H_i - xi_j d_i H_j + d_i H_3.
-__global__ __launch_bounds__(256) void k_fmm_l2p(const FmmTgtJob *__restrict__ jobs, int P,
-                                                 const double *__restrict__ cen_t, const double2 *__restrict__ L,
-                                                 const double *__restrict__ tx, long tstride, double *__restrict__ out,
-                                                 long ostride)
+// Coefficients of the 15 real fields evaluated at the targets, per target
+// slot and tri(k,l): f = 0..2 H_c, 3..6 d_x H_c, 7..10 d_y H_c, 11..14 d_z H_c,
+// with U = U_k^l(xi), xi = x - c_t, each field = sum_{k, l >= 0} Re(C_f conj(U)):
+//   H_c:     L_c[k][l]
+//   d_z H_c: L_c[k+1][l]
+//   d_x H_c: (L_c[k+1][l-1] - L_c[k+1][l+1]) / 2
+//   d_y H_c: i (L_c[k+1][l-1] + L_c[k+1][l+1]) / 2
+// (L[k+1][-1] = -conj(L[k+1][1])), times 2 for l > 0 (the l < 0 terms of a
+// real field are the conjugates of the l > 0 terms).
+constexpr int kFmmFields = 15, kL2pWaves = 8;
+
+__global__ void k_fmm_lderiv(int nt, int P, const double2 *__restrict__ L, double2 *__restrict__ C)
 {
+    const int t = blockIdx.y;
+    const int ntri = (P + 1) * (P + 2) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt || e >= ntri) return;
+    int k = 0;
+    while ((k + 1) * (k + 2) / 2 <= e) ++k;
+    const int l = e - k * (k + 1) / 2;
+    const double wl = l ? 2.0 : 1.0;
+    const double2 *Lt = L + (long)t * 4 * ntri;
+    double2 *o = C + ((long)t * ntri + e) * kFmmFields;
+    for (int ch = 0; ch < 3; ++ch) {
+        const double2 v = Lt[ch * ntri + e];
+        o[ch] = make_double2(wl * v.x, wl * v.y);
+    }
+    for (int ch = 0; ch < 4; ++ch) {
+        double2 gx = make_double2(0.0, 0.0), gy = gx, gz = gx;
+        if (k < P) {
+            const double2 Z = Lt[ch * ntri + ftri(k + 1, l)], B = Lt[ch * ntri + ftri(k + 1, l + 1)];
+            double2 A = Lt[ch * ntri + ftri(k + 1, l > 0 ? l - 1 : 1)];
+            if (l == 0) A.x = -A.x;
+            gx = make_double2(0.5 * wl * (A.x - B.x), 0.5 * wl * (A.y - B.y));
+            gy = make_double2(-0.5 * wl * (A.y + B.y), 0.5 * wl * (A.x + B.x));
+            gz = make_double2(wl * Z.x, wl * Z.y);
+        }
+        o[3 + ch] = gx;
+        o[7 + ch] = gy;
+        o[11 + ch] = gz;
+    }
+}
+
+// Block: 64 targets of one target slot (lane = target), its kL2pWaves
+// wavefronts taking runs of whole columns l with about equal term counts
+// (column l goes to wavefront floor(off(l) kL2pWaves / ntri), off(l) = terms of
+// the columns before it); the coefficients are wavefront-uniform (scalar
+// loads); the fields are summed over the wavefronts in LDS in a fixed order;
+// out[i][t] += H_i - xi_j d_i H_j + d_i H_3.
+__global__ __launch_bounds__(64 * kL2pWaves) void k_fmm_l2p(const FmmTgtJob *__restrict__ jobs, int P,
+                                                            const double *__restrict__ cen_t,
+                                                            const double2 *__restrict__ C,
+                                                            const double *__restrict__ tx, long tstride,
+                                                            double *__restrict__ out, long ostride)
+{
+    constexpr int H = kL2pWaves / 2;
+    __shared__ double red[H][kFmmFields][64];
     const FmmTgtJob jb = jobs[blockIdx.y];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x * blockDim.x >= jb.n) return;
-    const int ii = i < jb.n ? i : jb.n - 1;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i0 = blockIdx.x * 64;
+    if (i0 >= jb.n) return;
+    const int i = i0 + lane, ii = i < jb.n ? i : jb.n - 1;
     const long t = jb.off + ii;
     const double *c = cen_t + 4 * jb.slot;
     const double x = tx[t] - c[0], y = tx[tstride + t] - c[1], z = tx[2 * tstride + t] - c[2];
     const double r2 = x * x + y * y + z * z;
     const int ntri = (P + 1) * (P + 2) / 2;
-    const double2 *Lt = L + (long)jb.slot * 4 * ntri;
-    double hv[3] = {0, 0, 0}, gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
-    double dre = 1.0, dim = 0.0;
-    for (int l = 0; l <= P; ++l) {
+    const double2 *Ct = C + (long)jb.slot * ntri * kFmmFields;
+    double f[kFmmFields];
+#pragma unroll
+    for (int q = 0; q < kFmmFields; ++q) f[q] = 0.0;
+    double dre = 1.0, dim = 0.0;  // U_l^l
+    int off = 0;
+    for (int l = 0; l <= P; off += P + 1 - l, ++l) {
         if (l) {
-            const double f = -0.5 / l, ar = f * x, ai = f * y;
+            const double g = -0.5 / l, ar = g * x, ai = g * y;
             const double tt = dre * ar - dim * ai;
             dim = dre * ai + dim * ar;
             dre = tt;
         }
-        const double wl = l ? 2.0 : 1.0;
-        double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+        if ((off * kL2pWaves) / ntri != w) continue;
+        double p1r = dre, p1i = dim, p2r = 0.0, p2i = 0.0;
         for (int k = l; k <= P; ++k) {
-            double ur, ui;
-            if (k == l) {
-                ur = dre;
-                ui = dim;
-            } else {
+            double ur = p1r, ui = p1i;
+            if (k > l) {
                 const double inv = 1.0 / ((double)(k + l) * (k - l)), a = (2 * k - 1) * z;
                 ur = (a * p1r - r2 * p2r) * inv;
                 ui = (a * p1i - r2 * p2i) * inv;
+                p2r = p1r;
+                p2i = p1i;
+                p1r = ur;
+                p1i = ui;
             }
-            p2r = p1r;
-            p2i = p1i;
-            p1r = ur;
-            p1i = ui;
-            // Re(C conj(U)) = C.x ur + C.y ui
-            const double wr = wl * ur, wi = wl * ui;
-            const int e = ftri(k, l);
+            const double2 *cr = Ct + (long)ftri(k, l) * kFmmFields;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const double2 cv = Lt[ch * ntri + e];
-                hv[ch] = fma(cv.x, wr, fma(cv.y, wi, hv[ch]));
-            }
-            if (k < P) {
-                const int ez = ftri(k + 1, l), ep = ftri(k + 1, l + 1), em = ftri(k + 1, l > 0 ? l - 1 : 1);
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    const double2 Z = Lt[ch * ntri + ez], B = Lt[ch * ntri + ep];
-                    double2 A = Lt[ch * ntri + em];
-                    if (l == 0) {  // L[k+1][-1] = -conj(L[k+1][1])
-                        A.x = -A.x;
-                    }
-                    gz[ch] = fma(Z.x, wr, fma(Z.y, wi, gz[ch]));
-                    const double xr = 0.5 * (A.x - B.x), xi = 0.5 * (A.y - B.y);
-                    gx[ch] = fma(xr, wr, fma(xi, wi, gx[ch]));
-                    // i (A + B) / 2 = (-(A.y + B.y), A.x + B.x) / 2
-                    const double yr = -0.5 * (A.y + B.y), yi = 0.5 * (A.x + B.x);
-                    gy[ch] = fma(yr, wr, fma(yi, wi, gy[ch]));
-                }
-            }
+            for (int q = 0; q < kFmmFields; ++q) f[q] = fma(cr[q].x, ur, fma(cr[q].y, ui, f[q]));
         }
     }
-    if (i >= jb.n) return;
+    if (w >= H)
+#pragma unroll
+        for (int q = 0; q < kFmmFields; ++q) red[w - H][q][lane] = f[q];
+    __syncthreads();
+    if (w < H)
+#pragma unroll
+        for (int q = 0; q < kFmmFields; ++q) red[w][q][lane] += f[q];
+    __syncthreads();
+    if (w != 0 || i >= jb.n) return;
+#pragma unroll
+    for (int q = 0; q < kFmmFields; ++q) {
+        double v = 0.0;
+        for (int u = 0; u < H; ++u) v += red[u][q][lane];
+        f[q] = v;
+    }
     const double xi[3] = {x, y, z};
-    const double *g[3] = {gx, gy, gz};
     for (int d = 0; d < 3; ++d) {
-        const double v = hv[d] - (xi[0] * g[d][0] + xi[1] * g[d][1] + xi[2] * g[d][2]) + g[d][3];
+        const double *g = f + 3 + 4 * d;  // d_d H_0..3
+        const double v = f[d] - (xi[0] * g[0] + xi[1] * g[1] + xi[2] * g[2]) + g[3];
         out[d * ostride + t] += v;
     }
 }
@@ -434,11 +472,13 @@ void launch_fmm_m2l(hipStream_t st, int npairs, const FmmPair *pairs, int P, con
 }
 
 void launch_fmm_l2p(hipStream_t st, int njobs, const FmmTgtJob *jobs, int maxn, int P, const double *cen_t,
-                    const double2 *L, const double *tx, long tstride, double *out, long ostride)
+                    const double2 *L, double2 *C, const double *tx, long tstride, double *out, long ostride)
 {
     if (!njobs || !maxn) return;
-    hipLaunchKernelGGL(k_fmm_l2p, dim3((maxn + 255) / 256, njobs), dim3(256), 0, st, jobs, P, cen_t, L, tx, tstride,
-                       out, ostride);
+    const int ntri = (P + 1) * (P + 2) / 2;
+    hipLaunchKernelGGL(k_fmm_lderiv, dim3((ntri + 255) / 256, njobs), dim3(256), 0, st, njobs, P, L, C);
+    hipLaunchKernelGGL(k_fmm_l2p, dim3((maxn + 63) / 64, njobs), dim3(64 * kL2pWaves), 0, st, jobs, P, cen_t, C, tx,
+                       tstride, out, ostride);
 }
 
 }  // namespace bim
