@@ -144,8 +144,8 @@ struct PairSrc {
 // Fast summation of far drop pairs (kernels_fmm.hip). Expansion order P <=
 // kFmmMaxOrder; 4 channels; local expansions and partial multipoles keep
 // m >= 0 ((P+1)(P+2)/2 complex per channel), the multipoles used by the
-// translation all orders ((P+1)^2 complex per channel).
-constexpr int kFmmMaxOrder = 30, kFmmThreads = 512, kFmmChunk = 256;
+// translation all orders, channel fastest ((P+1)^2 x 4 complex).
+constexpr int kFmmMaxOrder = 30, kFmmThreads = 512, kFmmChunk = 128;
 static_assert((kFmmMaxOrder + 1) * (kFmmMaxOrder + 2) / 2 <= kFmmThreads, "one thread per coefficient");
 
 // One source grid of one drop (a multipole slot): nodes [off, off + ns) of

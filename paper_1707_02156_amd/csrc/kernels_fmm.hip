@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kFmmThreads) void k_fmm_p2m(const FmmSrcJob *__rest
     for (int ch = 0; ch < 4; ++ch) o[ch * ntri + e] = make_double2(ar[ch], ai[ch]);
 }
 
-// Multipoles of every order: Mf[slot][c][n^2 + n + m], |m| <= n, from the
+// Multipoles of every order: Mf[slot][n^2 + n + m][c], |m| <= n, from the
 // sum of the job's partial chunks (in order) and M_n^{-m} = (-1)^m conj(M_n^m).
 __global__ void k_fmm_msum(const FmmSrcJob *__restrict__ jobs, int P, const double2 *__restrict__ part,
                            double2 *__restrict__ Mf)
@@ -192,7 +192,7 @@ __global__ void k_fmm_msum(const FmmSrcJob *__restrict__ jobs, int P, const doub
     const int ntri = (P + 1) * (P + 2) / 2, nsq = (P + 1) * (P + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * nsq) return;
-    const int ch = i / nsq, f = i % nsq;
+    const int ch = i & 3, f = i >> 2;
     int n = 0;
     while ((n + 1) * (n + 1) <= f) ++n;
     const int m = f - n * n - n, ma = m < 0 ? -m : m;
@@ -279,12 +279,12 @@ __global__ __launch_bounds__(kFmmThreads) void k_fmm_m2l(const FmmPair *__restri
     for (int n = 0; n <= Q; ++n) {
         const int N = n + k;
         const double2 *trow = th + (N * N + N + l);  // T_N^{m+l} at trow[m]
-        const double2 *mrow = Ms + (n * n + n);      // M_n^m at mrow[m]
+        const double2 *mrow = Ms + 4 * (n * n + n);  // M_n^m, 4 channels, at mrow[4 m]
         for (int m = -n; m <= n; ++m) {
             const double2 t = trow[m];
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
-                const double2 mv = mrow[ch * nsq + m];
+                const double2 mv = mrow[4 * m + ch];
                 ar[ch] = fma(mv.x, t.x, fma(-mv.y, t.y, ar[ch]));
                 ai[ch] = fma(mv.x, t.y, fma(mv.y, t.x, ai[ch]));
             }
