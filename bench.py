@@ -307,6 +307,8 @@ def main():
     ap.add_argument("--fmm-order", type=int, default=0,
                     help="fast summation of far drop pairs: multipole order P (0: every pair summed directly)")
     ap.add_argument("--fmm-eps", type=float, default=1e-10, help="truncation bound rho^(P+1) of a far pair")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: the direct pair sums in FP32 arithmetic, the rest in FP64")
     ap.add_argument("--rep-pcut", type=float, default=1e-3)
     ap.add_argument("--rep-eps", type=float, default=1e-6)
     args = ap.parse_args()
@@ -340,7 +342,8 @@ def main():
     with torch.cuda.stream(stream):
         ctx = B.Context(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom,
                         gmres_tol=wl.gmres_tol, singular_path=args.singular_path, stream=stream.cuda_stream,
-                        fmm_order=args.fmm_order, fmm_eps=args.fmm_eps)
+                        fmm_order=args.fmm_order, fmm_eps=args.fmm_eps,
+                        precision=B.BIM_PREC_MIXED if args.precision == "mixed" else B.BIM_PREC_FP64)
         ctx.set_drops([d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops])
         if wl.eos != 0:
             ctx.set_tension([d.gc for d in wl.drops], wl.eos, wl.E, wl.xs)
@@ -392,7 +395,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64 (pair sums f32)",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "targets": T, "gmres_iterations": reps[-1].gmres_iterations,

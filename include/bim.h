@@ -67,7 +67,13 @@ typedef struct bim_ctx_s *bim_ctx;
 
 typedef struct {
     int device;          /* HIP device ordinal */
-    int precision;       /* BIM_PREC_FP64 (only FP64 is implemented; MIXED is rejected) */
+    int precision;       /* BIM_PREC_FP64: every step in FP64.
+                            BIM_PREC_MIXED: the direct pair sums (regular rule on the standard and
+                            upsampled grids of the other drops, Sec. 2.1, 2.3) in FP32 arithmetic,
+                            coordinates taken relative to the source drop's centre, runs of 16
+                            sources summed in FP32 and accumulated in FP64; the singular
+                            self-integrals, transforms, nearest-region quadrature, fast summation
+                            and GMRES stay in FP64 (relative error of the velocity about 1e-6) */
     double A_tilde;      /* Omega_1 threshold in units of h (Sec. 2.3; paper uses 5) */
     int U_tilde;         /* Omega_1 grid degree factor: sources on the degree U_tilde*p grid */
     int U_sing;          /* singular rule grid degree factor (q = U_sing*p; 1 = paper) */

@@ -55,7 +55,8 @@ void launch_near_setup(hipStream_t st, const NearArgs &a);
 void launch_near_interp(hipStream_t st, const NearArgs &a, int kind, const double *selfc, const double *dens,
                         const double *vacc, const double *wts, double *out);
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride);
+                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride,
+                 const double *cb32 = nullptr, int nd = 0);
 struct SingArgs {
     int p, qs, nt;
     const double *Ap, *Am, *ApT, *AmT;
@@ -1097,7 +1098,9 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
     ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
-    launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T);
+    const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+    launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T,
+                f32 ? c.cbnd.d() : nullptr, c.nd);
     run_fmm(c, kind, L);
 }
 
@@ -1757,7 +1760,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
 {
     if (!opt || !out) return BIM_EINVAL;
     *out = nullptr;
-    if (opt->precision != BIM_PREC_FP64 || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
+    if ((opt->precision != BIM_PREC_FP64 && opt->precision != BIM_PREC_MIXED) || opt->U_tilde < 1 || opt->U_sing < 1 || opt->U_geom < 1 ||
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
         (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
         (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL ||

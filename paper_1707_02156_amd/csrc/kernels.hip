@@ -534,6 +534,104 @@ __global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work,
     }
 }
 
+// The same pair sums in FP32 arithmetic (precision BIM_PREC_MIXED): sources
+// and targets are taken relative to the source drop's centre (mean node, cb)
+// in FP64 and rounded to FP32, so the differences h keep FP32 relative
+// accuracy for every distance; 1/r from the single-precision reciprocal
+// square root (about 1 ulp); each wavefront's sum over its quarter of the
+// tile runs in FP32 over runs of kPairRun sources, flushed into FP64
+// accumulators, and the wavefronts combine in FP64.
+constexpr int kPairRun = 16;
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_pair32(const PairWork *__restrict__ work, const int *__restrict__ tlist,
+                                                const double *__restrict__ tx, long tstride, PairSrc g0, PairSrc g1,
+                                                const double *__restrict__ cb, int nd, double *__restrict__ out,
+                                                long ostride)
+{
+    // DL (x,y,z,u0)(u1,u2,-6 wN0,-6 wN1)(-6 wN2)   SL (x,y,z,wW f0)(wW f1,wW f2)
+    constexpr int NP = KIND == 0 ? 2 : 3;
+    __shared__ float4 sh[kPairSrc][NP];
+    __shared__ double red[3][3][64];
+    const PairWork w = work[blockIdx.x];
+    const PairSrc &G = w.pad ? g1 : g0;
+    const double *c = cb + 4 * (w.pair % nd);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool active = lane < w.ntgt;
+    const int t = active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off];
+    const float x0 = (float)(tx[t] - c[0]), y0 = (float)(tx[tstride + t] - c[1]),
+                z0 = (float)(tx[2 * tstride + t] - c[2]);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int s0 = 0; s0 < w.nsrc; s0 += kPairSrc) {
+        const int ns = min(kPairSrc, w.nsrc - s0);
+        if (s0) __syncthreads();
+        for (int i = threadIdx.x; i < ns; i += 256) {
+            const long s = (long)w.src_off + s0 + i;
+            const long st = G.stride;
+            const float px = (float)(G.x[s] - c[0]), py = (float)(G.x[st + s] - c[1]),
+                        pz = (float)(G.x[2 * st + s] - c[2]);
+            if (KIND == 0) {
+                const double ww = G.wW[s];
+                sh[i][0] = make_float4(px, py, pz, (float)(ww * G.d[s]));
+                sh[i][1] = make_float4((float)(ww * G.d[st + s]), (float)(ww * G.d[2 * st + s]), 0.f, 0.f);
+            } else {
+                sh[i][0] = make_float4(px, py, pz, (float)G.d[s]);
+                sh[i][1] = make_float4((float)G.d[st + s], (float)G.d[2 * st + s], (float)(-6.0 * G.wN[s]),
+                                       (float)(-6.0 * G.wN[st + s]));
+                sh[i][2] = make_float4((float)(-6.0 * G.wN[2 * st + s]), 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        const int u1 = min(ns, (wv + 1) * 64);
+        for (int r0 = wv * 64; r0 < u1; r0 += kPairRun) {
+            const int r1 = min(u1, r0 + kPairRun);
+            float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+#pragma unroll 4
+            for (int u = r0; u < r1; ++u) {
+                const float4 p0 = sh[u][0], p1 = sh[u][1];
+                const float hx = x0 - p0.x, hy = y0 - p0.y, hz = z0 - p0.z;
+                const float r2 = fmaf(hz, hz, fmaf(hy, hy, hx * hx));
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                if (KIND == 0) {
+                    // wW G f = wW (f / r + h (h.f) / r^3)
+                    const float hd = fmaf(hz, p1.y, fmaf(hy, p1.x, hx * p0.w));
+                    const float q = hd * ri * ri;
+                    b0 = fmaf(ri, fmaf(hx, q, p0.w), b0);
+                    b1 = fmaf(ri, fmaf(hy, q, p1.x), b1);
+                    b2 = fmaf(ri, fmaf(hz, q, p1.y), b2);
+                } else {
+                    // -6 h (h.u)(h.wN) / r^5
+                    const float4 p2 = sh[u][2];
+                    const float hd = fmaf(hz, p1.y, fmaf(hy, p1.x, hx * p0.w));
+                    const float hn = fmaf(hz, p2.x, fmaf(hy, p1.w, hx * p1.z));
+                    const float r2i = ri * ri;
+                    const float sc = (hd * hn) * (r2i * r2i * ri);
+                    b0 = fmaf(sc, hx, b0);
+                    b1 = fmaf(sc, hy, b1);
+                    b2 = fmaf(sc, hz, b2);
+                }
+            }
+            a0 += (double)b0;
+            a1 += (double)b1;
+            a2 += (double)b2;
+        }
+    }
+    if (wv > 0) {
+        red[wv - 1][0][lane] = a0;
+        red[wv - 1][1][lane] = a1;
+        red[wv - 1][2][lane] = a2;
+    }
+    __syncthreads();
+    if (wv == 0 && active) {
+        a0 += (red[0][0][lane] + red[1][0][lane]) + red[2][0][lane];
+        a1 += (red[0][1][lane] + red[1][1][lane]) + red[2][1][lane];
+        a2 += (red[0][2][lane] + red[1][2][lane]) + red[2][2][lane];
+        atomicAdd(&out[t], w.w * a0);
+        atomicAdd(&out[ostride + t], w.w * a1);
+        atomicAdd(&out[2 * ostride + t], w.w * a2);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Pointwise combinations and GMRES vector kernels (FP64).
 // ----------------------------------------------------------------------------
@@ -820,9 +918,19 @@ void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, c
 int pair_sources_per_item() { return kPairItem; }
 
 void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride)
+                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride, const double *cb32,
+                 int nd)
 {
     if (nwork <= 0) return;
+    if (cb32) {  // FP32 arithmetic
+        if (kind == 0)
+            hipLaunchKernelGGL(k_pair32<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, cb32, nd,
+                               out, ostride);
+        else
+            hipLaunchKernelGGL(k_pair32<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, cb32, nd,
+                               out, ostride);
+        return;
+    }
     if (kind == 0)
         hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, out, ostride);
     else

@@ -37,17 +37,18 @@ def test_status_strings_and_defaults(B):
     o = B.bim_default_options()
     assert o.A_tilde == 5.0 and o.U_tilde == 4 and o.U_sing == 1 and o.U_geom == 2
     assert o.gmres_tol == 1e-10 and o.gmres_restart == 50 and o.precision == B.BIM_PREC_FP64
-    assert o.near_rule == 1 and o.near_L == 8
+    assert o.near_rule == 1 and o.near_L == 8 and o.fmm_order == 0 and o.fmm_eps == 1e-10
 
 
 def test_invalid_options_rejected_without_device(B):
     import ctypes
-    o = B.bim_default_options(precision=B.BIM_PREC_MIXED)
+    o = B.bim_default_options(precision=2)
     h = ctypes.c_void_p()
     assert B.lib().bim_create(ctypes.byref(o), ctypes.byref(h)) == B.BIM_EINVAL
     o = B.bim_default_options(U_tilde=0)
     assert B.lib().bim_create(ctypes.byref(o), ctypes.byref(h)) == B.BIM_EINVAL
-    for bad in (dict(near_rule=2), dict(near_L=1), dict(near_L=17)):
+    for bad in (dict(near_rule=2), dict(near_L=1), dict(near_L=17), dict(fmm_order=1), dict(fmm_order=31),
+                dict(fmm_order=8, fmm_eps=0.0), dict(fmm_order=8, fmm_eps=1.0)):
         o = B.bim_default_options(**bad)
         assert B.lib().bim_create(ctypes.byref(o), ctypes.byref(h)) == B.BIM_EINVAL
     assert B.lib().bim_destroy(None) == B.BIM_EINVAL
