@@ -37,7 +37,7 @@ struct SynJobs {
     SynJob j[kMaxSynJobs];
 };
 
-constexpr int kSynK = 64;  // longitudes k (and k + q) per synthesis block
+constexpr int kSynK = 64;  // longitudes k <= q/2 (and their images k + q, -k, q - k) per synthesis block
 
 __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
 {
@@ -52,8 +52,9 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
     const SynJob &J = jobs.j[blockIdx.y];
     const int j = blockIdx.x;
     const int k0 = blockIdx.z * kSynK;
-    if (j > J.q || k0 >= J.q) return;
-    const int kn = min(kSynK, J.q - k0);
+    const int H = J.q / 2 + 1;  // longitudes k <= q/2; the others by symmetry
+    if (j > J.q || k0 >= H) return;
+    const int kn = min(kSynK, H - k0);
     const int p = J.p, P1 = p + 1, q = J.q, nk = 2 * q;
     int kinds = 0;  // bit 0: Ptilde, 1: d/dtheta, 2: d2/dtheta2
     for (int b = 0; b < 6; ++b)
@@ -91,7 +92,9 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
         const double *g = G + 2 * ((c * 3 + dt) * P1);
         double sn, cs;
         sincos(dphi * k, &sn, &cs);
-        double cm = 1.0, sm = 0.0, ev = 0.0, od = 0.0;
+        // cosine and sine sums kept apart (C - S at phi, C + S at -phi) and
+        // split by the parity of m (the odd orders flip at phi + pi)
+        double cm = 1.0, sm = 0.0, ce = 0.0, co = 0.0, se = 0.0, so = 0.0;
         for (int m = 0; m <= p; ++m) {
             double ar = g[2 * m], ai = g[2 * m + 1];
             if (dp == 1) {
@@ -102,16 +105,26 @@ __global__ __launch_bounds__(256) void k_synth_batch(SynJobs jobs)
                 ar *= -(double)m * m;
                 ai *= -(double)m * m;
             }
-            const double v = (m ? 2.0 : 1.0) * (ar * cm - ai * sm);
-            if (m & 1) od += v;
-            else ev += v;
+            const double w = m ? 2.0 : 1.0;
+            const double vc = w * ar * cm, vs = w * ai * sm;
+            if (m & 1) {
+                co += vc;
+                so += vs;
+            } else {
+                ce += vc;
+                se += vs;
+            }
             const double c2 = cm * cs - sm * sn;
             sm = fma(sm, cs, cm * sn);
             cm = c2;
         }
         double *o = J.out + fo * J.fstride + c * J.ostride + (long)j * nk;
-        o[k] = ev + od;
-        o[k + q] = ev - od;
+        o[k] = (ce - se) + (co - so);      // phi_k
+        o[k + q] = (ce - se) - (co - so);  // phi_k + pi
+        if (k > 0 && 2 * k != q) {
+            o[nk - k] = (ce + se) + (co + so);  // -phi_k
+            o[q - k] = (ce + se) - (co + so);   // pi - phi_k
+        }
     }
 }
 
@@ -201,7 +214,7 @@ void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n, double *z0, l
             b.j[i] = jobs[o + i];
             maxq = std::max(maxq, jobs[o + i].q);
         }
-        hipLaunchKernelGGL(k_synth_batch, dim3(maxq + 1, b.n, (maxq + kSynK - 1) / kSynK), dim3(256), 0, st, b);
+        hipLaunchKernelGGL(k_synth_batch, dim3(maxq + 1, b.n, (maxq / 2 + 1 + kSynK - 1) / kSynK), dim3(256), 0, st, b);
     }
 }
 
