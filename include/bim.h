@@ -71,9 +71,11 @@ typedef struct {
                             BIM_PREC_MIXED: the direct pair sums (regular rule on the standard and
                             upsampled grids of the other drops, Sec. 2.1, 2.3) in FP32 arithmetic,
                             coordinates taken relative to the source drop's centre, runs of 16
-                            sources summed in FP32 and accumulated in FP64; the singular
-                            self-integrals, transforms, nearest-region quadrature, fast summation
-                            and GMRES stay in FP64 (relative error of the velocity about 1e-6) */
+                            sources summed in FP32 and accumulated in FP64; the fast summation
+                            keeps its stored source harmonics in FP32 (multipoles accumulated in
+                            FP64); the singular self-integrals, transforms, nearest-region
+                            quadrature and GMRES stay in FP64 (relative error of the velocity
+                            about 1e-6) */
     double A_tilde;      /* Omega_1 threshold in units of h (Sec. 2.3; paper uses 5) */
     int U_tilde;         /* Omega_1 grid degree factor: sources on the degree U_tilde*p grid */
     int U_sing;          /* singular rule grid degree factor (q = U_sing*p; 1 = paper) */

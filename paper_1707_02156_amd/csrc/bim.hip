@@ -136,9 +136,10 @@ void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, d
 void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
                     unsigned long long *gmax);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
-void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, double2 *Y);
+void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, void *Y,
+                     bool f32);
 void launch_fmm_p2m(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int kind, int P, const double *cen,
-                    const double2 *Y, double *W, double2 *part, double2 *M);
+                    const void *Y, bool f32, double *W, double2 *part, double2 *M);
 void launch_fmm_m2l(hipStream_t st, int npairs, const FmmPair *pairs, int P, const double *cen_s, const double *cen_t,
                     const double2 *M, double2 *Lp, int nt, const int *poff, double2 *L);
 void launch_fmm_l2p(hipStream_t st, int njobs, const FmmTgtJob *jobs, int maxn, int P, const double *cen_t,
@@ -841,7 +842,8 @@ static void fmm_setup(Ctx &c, const std::vector<double> &cb0, const std::vector<
     F.dpoff.ensure(F.poff.size() * sizeof(int));
     F.cen_s.ensure(cs.size() * sizeof(double));
     F.cen_t.ensure(ct.size() * sizeof(double));
-    F.Y.ensure((size_t)F.nsrc * ntri * sizeof(double2));
+    const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+    F.Y.ensure((size_t)F.nsrc * ntri * (f32 ? sizeof(float2) : sizeof(double2)));
     F.W.ensure((size_t)F.nsrc * 12 * sizeof(double));
     F.part.ensure((size_t)F.nchunks * cb);
     F.M.ensure(F.src.size() * 4 * (P + 1) * (P + 1) * sizeof(double2));
@@ -853,8 +855,7 @@ static void fmm_setup(Ctx &c, const std::vector<double> &cb0, const std::vector<
     HIPC(hipMemcpyAsync(F.dpoff.ptr, F.poff.data(), F.poff.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
     HIPC(hipMemcpyAsync(F.cen_s.ptr, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
     HIPC(hipMemcpyAsync(F.cen_t.ptr, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    launch_fmm_ytab(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, P, F.cen_s.d(),
-                    (double2 *)F.Y.ptr);
+    launch_fmm_ytab(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, P, F.cen_s.d(), F.Y.ptr, f32);
     HIPC(hipStreamSynchronize(c.stream));
 }
 
@@ -1080,8 +1081,8 @@ static void run_fmm(Ctx &c, int kind, Ctx::WList &L)
     // L2P 60 per target and coefficient
     const double fl = (double)F.nsrc * ntri * (kind == 0 ? 8.0 : 48.0) + F.m2l_flops + (double)F.ntgt * ntri * 60.0;
     ProfScope ps(c, "fmm", fl, 0.0);
-    launch_fmm_p2m(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, kind, P, F.cen_s.d(),
-                   (const double2 *)F.Y.ptr, F.W.d(), (double2 *)F.part.ptr, (double2 *)F.M.ptr);
+    launch_fmm_p2m(c.stream, F.dsrc.as<FmmSrcJob>(), (int)F.src.size(), F.maxns, kind, P, F.cen_s.d(), F.Y.ptr,
+                   c.opt.precision == BIM_PREC_MIXED, F.W.d(), (double2 *)F.part.ptr, (double2 *)F.M.ptr);
     launch_fmm_m2l(c.stream, (int)F.pairs.size(), L.fp.as<FmmPair>(), P, F.cen_s.d(), F.cen_t.d(),
                    (const double2 *)F.M.ptr, (double2 *)F.Lp.ptr, (int)F.tgt.size(), F.dpoff.as<int>(),
                    (double2 *)F.L.ptr);

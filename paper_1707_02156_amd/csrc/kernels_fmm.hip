@@ -37,9 +37,12 @@ namespace bim {
 __device__ inline int ftri(int n, int m) { return n * (n + 1) / 2 + m; }
 
 // ---- regular harmonics of the source nodes, stored once per geometry -------
-// Y[(s) * ntri + tri(n,m)] = U_n^m(y_s - c) for the ns nodes of a source grid.
+// Y[(s) * ntri + tri(n,m)] = U_n^m(y_s - c) for the ns nodes of a source grid,
+// as double2, or float2 in the mixed-precision form (the multipoles are still
+// accumulated in FP64).
+template <class YT>
 __global__ void k_fmm_ytab(const FmmSrcJob *__restrict__ jobs, int P, const double *__restrict__ cen,
-                           double2 *__restrict__ Y)
+                           YT *__restrict__ Y)
 {
     const FmmSrcJob j = jobs[blockIdx.y];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,7 +52,7 @@ __global__ void k_fmm_ytab(const FmmSrcJob *__restrict__ jobs, int P, const doub
     const long g = j.off + s;
     const double x = j.x[g] - c[0], y = j.x[j.stride + g] - c[1], z = j.x[2 * j.stride + g] - c[2];
     const double r2 = x * x + y * y + z * z;
-    double2 *out = Y + (j.yoff + (long)s * ntri);
+    YT *out = Y + (j.yoff + (long)s * ntri);
     double dre = 1.0, dim = 0.0;  // U_m^m
     for (int m = 0; m <= P; ++m) {
         if (m) {
@@ -59,11 +62,11 @@ __global__ void k_fmm_ytab(const FmmSrcJob *__restrict__ jobs, int P, const doub
             dre = t;
         }
         double p1r = dre, p1i = dim, p2r = 0.0, p2i = 0.0;
-        out[ftri(m, m)] = make_double2(dre, dim);
+        out[ftri(m, m)] = YT{(decltype(YT::x))dre, (decltype(YT::x))dim};
         for (int n = m + 1; n <= P; ++n) {
             const double inv = 1.0 / ((double)(n + m) * (n - m)), a = (2 * n - 1) * z;
             const double ur = (a * p1r - r2 * p2r) * inv, ui = (a * p1i - r2 * p2i) * inv;
-            out[ftri(n, m)] = make_double2(ur, ui);
+            out[ftri(n, m)] = YT{(decltype(YT::x))ur, (decltype(YT::x))ui};
             p2r = p1r;
             p2i = p1i;
             p1r = ur;
@@ -111,9 +114,9 @@ __global__ void k_fmm_srcw(const FmmSrcJob *__restrict__ jobs, int kind, const d
 // ---- P2M: partial multipoles of source chunks ------------------------------
 // Block (chunk, job): thread = coefficient tri(n,m); sums over the chunk's
 // kFmmChunk sources; part[(job chunk base + chunk)][c][tri].
-template <int KIND>
+template <int KIND, class YT>
 __global__ __launch_bounds__(kFmmThreads) void k_fmm_p2m(const FmmSrcJob *__restrict__ jobs, int P,
-                                                         const double2 *__restrict__ Y, const double *__restrict__ W,
+                                                         const YT *__restrict__ Y, const double *__restrict__ W,
                                                          double2 *__restrict__ part)
 {
     const FmmSrcJob j = jobs[blockIdx.y];
@@ -128,12 +131,13 @@ __global__ __launch_bounds__(kFmmThreads) void k_fmm_p2m(const FmmSrcJob *__rest
     while ((n + 1) * (n + 2) / 2 <= e) ++n;
     const int m = e - n * (n + 1) / 2;
     double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    const double2 *Yc = Y + j.yoff;
+    const YT *Yc = Y + j.yoff;
     constexpr int NW = KIND == 0 ? 4 : 12;
     const double *Wc = W + j.woff;
     if (KIND == 0) {
         for (int s = s0; s < s1; ++s) {
-            const double2 u = Yc[(long)s * ntri + e];
+            const YT uy = Yc[(long)s * ntri + e];
+            const double2 u = make_double2(uy.x, uy.y);
             const double *w = Wc + (long)s * NW;
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {  // q conj(U)
@@ -147,17 +151,15 @@ __global__ __launch_bounds__(kFmmThreads) void k_fmm_p2m(const FmmSrcJob *__rest
         const int e0 = ftri(n - 1, min(m, n - 1)), ep = ftri(n - 1, min(m + 1, n - 1)),
                   em = ftri(n - 1, m > 0 ? m - 1 : 1 <= n - 1 ? 1 : 0);
         for (int s = s0; s < s1; ++s) {
-            const double2 *yr = Yc + (long)s * ntri;
-            const double2 u0 = hm ? yr[e0] : make_double2(0.0, 0.0);
-            const double2 up = hp ? yr[ep] : make_double2(0.0, 0.0);
+            const YT *yr = Yc + (long)s * ntri;
+            const YT y0 = yr[e0], yp = yr[ep], ym = yr[em];
+            const double2 u0 = hm ? make_double2(y0.x, y0.y) : make_double2(0.0, 0.0);
+            const double2 up = hp ? make_double2(yp.x, yp.y) : make_double2(0.0, 0.0);
             double2 um;  // conj(U_{n-1}^{m-1}); at m = 0 conj(U^{-1}) = -U^{1}
             if (m > 0) {
-                um = yr[em];
-                um.y = -um.y;
+                um = make_double2(ym.x, -ym.y);
             } else if (n - 1 >= 1) {
-                um = yr[em];
-                um.x = -um.x;
-                um.y = -um.y;
+                um = make_double2(-ym.x, -ym.y);
             } else {
                 um = make_double2(0.0, 0.0);
             }
@@ -440,22 +442,38 @@ __global__ __launch_bounds__(64 * kL2pWaves) void k_fmm_l2p(const FmmTgtJob *__r
 }
 
 // ---- launchers ------------------------------------------------------------------
-void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, double2 *Y)
+void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, void *Y,
+                     bool f32)
 {
     if (!njobs || !maxns) return;
-    hipLaunchKernelGGL(k_fmm_ytab, dim3((maxns + 127) / 128, njobs), dim3(128), 0, st, jobs, P, cen, Y);
+    if (f32)
+        hipLaunchKernelGGL(k_fmm_ytab<float2>, dim3((maxns + 127) / 128, njobs), dim3(128), 0, st, jobs, P, cen,
+                           (float2 *)Y);
+    else
+        hipLaunchKernelGGL(k_fmm_ytab<double2>, dim3((maxns + 127) / 128, njobs), dim3(128), 0, st, jobs, P, cen,
+                           (double2 *)Y);
 }
 
 void launch_fmm_p2m(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int kind, int P, const double *cen,
-                    const double2 *Y, double *W, double2 *part, double2 *M)
+                    const void *Y, bool f32, double *W, double2 *part, double2 *M)
 {
     if (!njobs || !maxns) return;
     hipLaunchKernelGGL(k_fmm_srcw, dim3((maxns + 255) / 256, njobs), dim3(256), 0, st, jobs, kind, cen, W);
     const int nch = (maxns + kFmmChunk - 1) / kFmmChunk;
-    if (kind == 0)
-        hipLaunchKernelGGL(k_fmm_p2m<0>, dim3(nch, njobs), dim3(kFmmThreads), 0, st, jobs, P, Y, W, part);
-    else
-        hipLaunchKernelGGL(k_fmm_p2m<1>, dim3(nch, njobs), dim3(kFmmThreads), 0, st, jobs, P, Y, W, part);
+    const dim3 g(nch, njobs), b(kFmmThreads);
+    if (f32) {
+        const float2 *Yf = (const float2 *)Y;
+        if (kind == 0)
+            hipLaunchKernelGGL((k_fmm_p2m<0, float2>), g, b, 0, st, jobs, P, Yf, W, part);
+        else
+            hipLaunchKernelGGL((k_fmm_p2m<1, float2>), g, b, 0, st, jobs, P, Yf, W, part);
+    } else {
+        const double2 *Yd = (const double2 *)Y;
+        if (kind == 0)
+            hipLaunchKernelGGL((k_fmm_p2m<0, double2>), g, b, 0, st, jobs, P, Yd, W, part);
+        else
+            hipLaunchKernelGGL((k_fmm_p2m<1, double2>), g, b, 0, st, jobs, P, Yd, W, part);
+    }
     const int nsq = (P + 1) * (P + 1);
     hipLaunchKernelGGL(k_fmm_msum, dim3((4 * nsq + 255) / 256, njobs), dim3(256), 0, st, jobs, P, part, M);
 }
