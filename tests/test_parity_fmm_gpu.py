@@ -148,3 +148,47 @@ def test_fmm_option_errors(B):
         with pytest.raises(B.BimError) as e:
             B.Context(**kw)
         assert e.value.status == B.BIM_EINVAL
+
+
+def test_fmm_independent_systems(B):
+    """Two copies of a spread system set as independent systems of one
+    context (occupying the same region of space): the far pairs are taken
+    only inside each system, and each system gets the result it has alone."""
+    print("fmm: independent systems", flush=True)
+    wl = W.many_drops(nd=8, p=10, box=14.0, gap=0.5, seed=47)
+    opts = dict(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, gmres_tol=1e-12, fmm_order=20, fmm_eps=1e-12)
+    ps, xs, ls = [d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops]
+    c = B.Context(**opts)
+    c.set_drops(ps, xs, ls)
+    c.set_tension(None, 0)
+    alone, ra = c.eval_velocity()
+    c.close()
+    c = B.Context(**opts)
+    c.set_drops(ps + ps, xs + xs, ls + ls)
+    c.set_systems([0] * 8 + [1] * 8)
+    c.set_tension(None, 0)
+    both, rb = c.eval_velocity()
+    c.close()
+    assert ra.n_fmm_pairs > 0 and rb.n_fmm_pairs == 2 * ra.n_fmm_pairs
+    for k in range(16):
+        ref = alone[k % 8]
+        assert np.abs(both[k] - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_fmm_time_step(B):
+    """One coupled time step (drops only, extensional flow) with the fast
+    summation against the same step with direct sums."""
+    print("fmm: time step", flush=True)
+    wl = W.many_drops(nd=8, p=8, box=14.0, gap=0.8, seed=48)
+    grad = 0.3 * np.diag([1.0, -0.5, -0.5])
+    res = []
+    for kw in (dict(), dict(fmm_order=20, fmm_eps=1e-12)):
+        c = ctx_for(B, wl, gmres_tol=1e-12, **kw)
+        B.bim_set_farfield(c.h, np.zeros(3), grad)
+        rep = c.time_step(0.05, tol=1e-2)
+        xs, _ = c.state(surfactant=False)
+        res.append((np.concatenate([np.ravel(x) for x in xs]), rep))
+        c.close()
+    assert _rel(res[1][0], res[0][0]) <= 1e-9
+    assert res[1][1]["accepted"] == res[0][1]["accepted"]
+    assert res[1][1]["dt_next"] == pytest.approx(res[0][1]["dt_next"], rel=1e-6)
