@@ -94,16 +94,20 @@ def test_mixed_velocity_solve(B):
     assert abs(out[B.BIM_PREC_MIXED][1] - out[B.BIM_PREC_FP64][1]) <= 1
 
 
-def test_mixed_with_fast_summation(B):
+@pytest.mark.parametrize("eps", [1e-12, 1e-8])
+def test_mixed_with_fast_summation(B, eps):
     """Mixed precision and the fast summation together (the far pairs by the
-    FP64 multipole method, the near pairs in FP32)."""
-    print("mixed + fast summation", flush=True)
+    multipole method, the near pairs in FP32), with the truncation bound at
+    the FP64 level and at 1e-8 (below the mixed form's 1e-5 bar)."""
+    print("mixed + fast summation, eps", eps, flush=True)
     wl = W.many_drops(nd=16, p=12, box=14.0, gap=0.4, seed=46)
     cd = ctx_for(B, wl)
     ud, _ = cd.eval_velocity(coefficients=True)
     cd.close()
-    cm = ctx_for(B, wl, precision=B.BIM_PREC_MIXED, fmm_order=24, fmm_eps=1e-12)
+    cm = ctx_for(B, wl, precision=B.BIM_PREC_MIXED, fmm_order=24, fmm_eps=eps)
     um, rm = cm.eval_velocity(coefficients=True)
     cm.close()
     assert rm.n_fmm_pairs > 0
-    assert _rel(_flat(um), _flat(ud)) <= TOL32
+    e = _rel(_flat(um), _flat(ud))
+    print("rel err", e, flush=True)
+    assert e <= TOL32
