@@ -406,9 +406,10 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms"] / nprof, 4) for k, v in brk.items() if v["launches"]},
         "kernels_roofline_frac": {k: round(kernel_frac(k, v), 4) for k, v in brk.items() if v["ms"] > 0},
     }
-    if args.fmm_order > 0:
-        res["config"]["fast_summation"] = {"order": args.fmm_order, "eps": args.fmm_eps,
-                                           "far_pairs": reps[-1].n_fmm_pairs}
+    if args.fmm_order != 0:
+        res["config"]["fast_summation"] = {"order": reps[-1].fmm_order, "eps": args.fmm_eps,
+                                           "far_pairs": reps[-1].n_fmm_pairs,
+                                           "chosen_by_timing": args.fmm_order < 0}
     ctx.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)

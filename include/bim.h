@@ -101,7 +101,10 @@ typedef struct {
     int near_L;          /* interpolation points of the special quadrature, 2..16 (paper: 8) */
     int fmm_order;       /* fast summation of far drop pairs (the O(N^2) pair sums of Sec. 2.1 and
                             2.3, which the paper proposes to replace by fast summation, Sec. 6):
-                            0 = off (every pair summed directly); P in 2..30 = multipole order of a
+                            0 = off (every pair summed directly); -1 = order chosen by timing at
+                            the first velocity evaluation after bim_set_drops (0, 8, 12, 16, 20, 24
+                            or 30: for a given fmm_eps only the cost depends on the order);
+                            P in 2..30 = multipole order of a
                             drop-level fast multipole method on four harmonic potentials (Laplace
                             multipoles of each source drop, translated to local expansions of each
                             target drop, evaluated at its nodes). A drop pair (i, j) takes it when
@@ -120,7 +123,8 @@ typedef struct {
     int n_omega2;             /* pairs in Omega_2 (near_rule selects their quadrature) */
     int n_matvec;             /* operator applications in the solve */
     double ms_total;          /* wall time of the call */
-    int n_fmm_pairs;          /* drop pairs taken by the fast summation (fmm_order > 0) */
+    int n_fmm_pairs;          /* drop pairs taken by the fast summation (fmm_order != 0) */
+    int fmm_order;            /* multipole order in use (0: every pair summed directly) */
 } bim_report;
 
 /* Library version (major*10000 + minor*100 + patch). */

@@ -65,6 +65,7 @@ class bim_report(ctypes.Structure):
         ("n_matvec", ctypes.c_int),
         ("ms_total", ctypes.c_double),
         ("n_fmm_pairs", ctypes.c_int),
+        ("fmm_order", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -255,7 +255,7 @@ struct Ctx {
     std::vector<std::unique_ptr<WList>> wlists;
     std::vector<int8_t> reg_h;
     int n_om1 = 0, n_om2 = 0;
-    // fast summation of far drop pairs (opt.fmm_order > 0): multipole slots
+    // fast summation of far drop pairs (opt.fmm_order != 0): multipole slots
     // (drop, source grid), target slots (drops), pairs grouped by target slot
     struct Fmm {
         int P = 0;
@@ -281,6 +281,7 @@ struct Ctx {
             m2l_flops = 0.0;
         }
     } fmm;
+    int fmm_tuned = -1;  // order chosen by tune_fmm (fmm_order = -1), -1 before tuning
     // nearest-region items (near_rule 1) and their interpolation points
     std::vector<NearItem> near_h;
     std::vector<char> near_src;                 // drops that are the source of an item
@@ -859,64 +860,16 @@ static void fmm_setup(Ctx &c, const std::vector<double> &cb0, const std::vector<
     HIPC(hipStreamSynchronize(c.stream));
 }
 
-static void build_regions(Ctx &c)
+// Work lists of the pair sums for fast-summation order P (0: every pair
+// summed directly): the direct items of both grids, the nearest-region items
+// and the fast-summation plan. cb0, cb1: centres and bounding radii of the
+// standard and upsampled nodes of every drop (read when P > 0).
+static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std::vector<double> &cb1)
 {
-    if (c.regions_ok) return;
-    build_nodes(c);
-    std::vector<double> vol(c.nd), h(c.nd);
-    HIPC(hipMemcpyAsync(vol.data(), c.vol.ptr, c.nd * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
-    for (int i = 0; i < c.nd; ++i) {
-        REQUIRE(vol[i] > 0.0 && std::isfinite(vol[i]), BIM_EINVAL, "drop " + std::to_string(i) + " has non-positive volume");
-        const double R = std::cbrt(3.0 * vol[i] / (4.0 * kPi));
-        h[i] = R * kPi / (c.drops[i].p + 1);
-    }
-    c.hj.ensure(c.nd * sizeof(double));
-    HIPC(hipMemcpyAsync(c.hj.ptr, h.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    const long nreg = c.T * c.nd;
-    c.reg.ensure(nreg);
-    c.dist.ensure(nreg * sizeof(double));
-    c.cbnd.ensure(4 * c.nd * sizeof(double));
-    c.clist.ensure(std::max<long>(1, nreg) * sizeof(int));
-    c.ccount.ensure(sizeof(int));
-    {
-        ProfScope ps(c, "classify", 0.0, 0.0);
-        launch_drop_bounds(c.stream, c.nd, c.tx.d(), c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.cbnd.d());
-        if (c.opt.fmm_order > 0) {
-            c.cbnd1.ensure(4 * c.nd * sizeof(double));
-            launch_drop_bounds(c.stream, c.nd, c.s1x.d(), c.S1, c.unoff.as<int>(), c.uncnt.as<int>(), c.cbnd1.d());
-        }
-        HIPC(hipMemsetAsync(c.ccount.ptr, 0, sizeof(int), c.stream));
-        launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.sysd.as<int>(),
-                              c.cbnd.d(), c.hj.d(),
-                              c.opt.A_tilde, c.regions_exact ? 1 : 0, c.reg.as<int8_t>(), c.dist.d(),
-                              c.clist.as<int>(), c.ccount.as<int>());
-    }
-    int nscan = 0;
-    HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
-    {
-        ProfScope ps(c, "classify", 0.0, 0.0);
-        launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
-                             c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
-                             c.dist.d());
-    }
-    c.reg_h.resize(nreg);
-    HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
     // far drop pairs for the fast summation: every target of i in the same
     // region (0 or 1) with respect to j, and the truncation bound
     // rho^(P+1) <= eps, rho = (a_i + a_j) / |c_i - c_j| (bounding radii of the
     // target nodes and of the source grid the region selects)
-    std::vector<double> cb0, cb1;
-    const int P = c.opt.fmm_order;
-    if (P > 0) {
-        cb0.resize(4 * c.nd);
-        cb1.resize(4 * c.nd);
-        HIPC(hipMemcpyAsync(cb0.data(), c.cbnd.ptr, cb0.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-        HIPC(hipMemcpyAsync(cb1.data(), c.cbnd1.ptr, cb1.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
-    }
     // grid of a far pair (-1: summed directly); order: the smallest degree
     // Q <= P with rho^(Q+1) <= eps, used by that pair's translation
     auto far_grid = [&](int i, int j, int &order) -> int {
@@ -1021,6 +974,105 @@ static void build_regions(Ctx &c)
     c.w1h = std::move(w1);
     c.wlists.clear();
     c.near_h = std::move(near);
+}
+
+static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt);
+
+// Order of the fast summation chosen by timing (fmm_order = -1): the
+// double-layer pair pass (direct items plus fast summation, unit weights)
+// is timed with events at each candidate order and with every pair direct;
+// the fastest wins. For a given fmm_eps every far pair meets the same
+// truncation bound at any order, so the choice changes the cost, not the
+// accuracy. The accumulator is cleared afterwards.
+static int tune_fmm(Ctx &c, const std::vector<double> &cb0, const std::vector<double> &cb1)
+{
+    static const int cand[] = {0, 8, 12, 16, 20, 24, 30};
+    const std::vector<double> ones((size_t)c.nd * c.nd, 1.0);
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    int best = 0;
+    float tbest = 0.0f;
+    for (int P : cand) {
+        build_lists(c, P, cb0, cb1);
+        if (P > 0 && c.fmm.pairs.empty()) continue;  // no far pair at this order: the same as direct
+        run_pairs(c, 1, ones);  // warm-up
+        HIPC(hipEventRecord(e0, c.stream));
+        run_pairs(c, 1, ones);
+        HIPC(hipEventRecord(e1, c.stream));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        if (P == 0 || ms < tbest) {
+            tbest = ms;
+            best = P;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(hipMemsetAsync(c.acc.ptr, 0, (size_t)3 * c.T * sizeof(double), c.stream));
+    return best;
+}
+
+static void build_regions(Ctx &c)
+{
+    if (c.regions_ok) return;
+    build_nodes(c);
+    std::vector<double> vol(c.nd), h(c.nd);
+    HIPC(hipMemcpyAsync(vol.data(), c.vol.ptr, c.nd * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < c.nd; ++i) {
+        REQUIRE(vol[i] > 0.0 && std::isfinite(vol[i]), BIM_EINVAL, "drop " + std::to_string(i) + " has non-positive volume");
+        const double R = std::cbrt(3.0 * vol[i] / (4.0 * kPi));
+        h[i] = R * kPi / (c.drops[i].p + 1);
+    }
+    c.hj.ensure(c.nd * sizeof(double));
+    HIPC(hipMemcpyAsync(c.hj.ptr, h.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    const long nreg = c.T * c.nd;
+    c.reg.ensure(nreg);
+    c.dist.ensure(nreg * sizeof(double));
+    c.cbnd.ensure(4 * c.nd * sizeof(double));
+    c.clist.ensure(std::max<long>(1, nreg) * sizeof(int));
+    c.ccount.ensure(sizeof(int));
+    {
+        ProfScope ps(c, "classify", 0.0, 0.0);
+        launch_drop_bounds(c.stream, c.nd, c.tx.d(), c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.cbnd.d());
+        if (c.opt.fmm_order != 0) {
+            c.cbnd1.ensure(4 * c.nd * sizeof(double));
+            launch_drop_bounds(c.stream, c.nd, c.s1x.d(), c.S1, c.unoff.as<int>(), c.uncnt.as<int>(), c.cbnd1.d());
+        }
+        HIPC(hipMemsetAsync(c.ccount.ptr, 0, sizeof(int), c.stream));
+        launch_classify_bound(c.stream, (int)c.T, c.nd, c.tx.d(), c.T, c.tdrop.as<int>(), c.sysd.as<int>(),
+                              c.cbnd.d(), c.hj.d(),
+                              c.opt.A_tilde, c.regions_exact ? 1 : 0, c.reg.as<int8_t>(), c.dist.d(),
+                              c.clist.as<int>(), c.ccount.as<int>());
+    }
+    int nscan = 0;
+    HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    {
+        ProfScope ps(c, "classify", 0.0, 0.0);
+        launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
+                             c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
+                             c.dist.d());
+    }
+    c.reg_h.resize(nreg);
+    HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
+    HIPC(hipStreamSynchronize(c.stream));
+    std::vector<double> cb0, cb1;
+    if (c.opt.fmm_order != 0) {
+        cb0.resize(4 * c.nd);
+        cb1.resize(4 * c.nd);
+        HIPC(hipMemcpyAsync(cb0.data(), c.cbnd.ptr, cb0.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipMemcpyAsync(cb1.data(), c.cbnd1.ptr, cb1.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+    }
+    int P = c.opt.fmm_order;
+    if (P < 0) {
+        if (c.fmm_tuned < 0) c.fmm_tuned = tune_fmm(c, cb0, cb1);
+        P = c.fmm_tuned;
+    }
+    build_lists(c, P, cb0, cb1);
     near_setup(c);
     c.regions_ok = true;
 }
@@ -1765,7 +1817,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
         !(opt->A_tilde >= 0.0) || !(opt->gmres_tol > 0.0) || opt->gmres_restart < 1 || opt->gmres_maxit < 0 ||
         (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
         (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL ||
-        (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder)) ||
+        (opt->fmm_order != 0 && opt->fmm_order != -1 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder)) ||
         !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0))
         return BIM_EINVAL;
     bim_ctx h = nullptr;
@@ -1826,6 +1878,7 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         Ctx &c = h->c;
         REQUIRE(n_drops >= 1 && p && xcoef && lambda, BIM_EINVAL, "bim_set_drops: null argument or no drops");
         REQUIRE(mem_kind == BIM_MEM_HOST || mem_kind == BIM_MEM_DEVICE, BIM_EINVAL, "bad mem_kind");
+        c.fmm_tuned = -1;  // a new system: choose the fast-summation order again
         std::vector<Drop> ds(n_drops);
         long coff = 0, toff = 0, uoff = 0;
         for (int i = 0; i < n_drops; ++i) {
@@ -2565,6 +2618,7 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
             rep->n_omega1 = c.n_om1;
             rep->n_omega2 = c.n_om2;
             rep->n_fmm_pairs = (int)c.fmm.pairs.size();
+            rep->fmm_order = c.fmm.P;
             rep->n_matvec = nmv;
             rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }

@@ -142,6 +142,28 @@ def test_fmm_velocity_solve(B):
     assert abs(rf.gmres_iterations - rd.gmres_iterations) <= 1
 
 
+def test_fmm_order_chosen_by_timing(B):
+    """fmm_order = -1 on the 64-drop workload: an order from the candidate
+    list is chosen, reported, kept for the next evaluation, and the result
+    meets the same bar against the direct sums."""
+    print("fmm: tuned order", flush=True)
+    wl = W.many_drops()
+    rng = np.random.default_rng(49)
+    dens = [_density(rng, 16) for _ in range(len(wl.drops))]
+    cd = ctx_for(B, wl)
+    dd = np.concatenate([np.ravel(u) for u in cd.double_layer(dens, mode=0)])
+    cd.close()
+    c = ctx_for(B, wl, fmm_order=-1, fmm_eps=1e-12)
+    df = np.concatenate([np.ravel(u) for u in c.double_layer(dens, mode=0)])
+    _, r1 = c.eval_velocity(coefficients=True)
+    _, r2 = c.eval_velocity(coefficients=True)
+    c.close()
+    print("chosen order", r1.fmm_order, "far pairs", r1.n_fmm_pairs, flush=True)
+    assert r1.fmm_order in (0, 8, 12, 16, 20, 24, 30) and r2.fmm_order == r1.fmm_order
+    assert (r1.fmm_order == 0) == (r1.n_fmm_pairs == 0)
+    assert _rel(df, dd) <= 1e-10
+
+
 def test_fmm_option_errors(B):
     for kw in [dict(fmm_order=1), dict(fmm_order=31), dict(fmm_order=8, fmm_eps=0.0),
                dict(fmm_order=8, fmm_eps=1.0), dict(fmm_order=-2)]:
