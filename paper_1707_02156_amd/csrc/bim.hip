@@ -1990,6 +1990,7 @@ int bim_set_systems(bim_ctx h, const int *system_of_drop)
         HIPC(hipStreamSynchronize(c.stream));
         c.regions_ok = false;
         c.regions_exact = false;
+        c.fmm_tuned = -1;  // other drop pairs: choose the fast-summation order again
         return BIM_OK;
     });
 }
