@@ -1047,27 +1047,41 @@ static void build_regions(Ctx &c)
                               c.opt.A_tilde, c.regions_exact ? 1 : 0, c.reg.as<int8_t>(), c.dist.d(),
                               c.clist.as<int>(), c.ccount.as<int>());
     }
-    int nscan = 0;
-    HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
-    {
-        ProfScope ps(c, "classify", 0.0, 0.0);
-        launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
-                             c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
-                             c.dist.d());
+    // drops that interact (two drops of one system); without any, the bound
+    // kernel has already written every region (own drop -1, other system -2)
+    // and there is nothing to scan or to list
+    bool pairs = false;
+    for (int i = 0; i < c.nd && !pairs; ++i)
+        for (int j = i + 1; j < c.nd; ++j)
+            if (c.sys_h[i] == c.sys_h[j]) {
+                pairs = true;
+                break;
+            }
+    if (pairs) {
+        int nscan = 0;
+        HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        {
+            ProfScope ps(c, "classify", 0.0, 0.0);
+            launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
+                                 c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
+                                 c.dist.d());
+        }
+        c.reg_h.resize(nreg);
+        HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+    } else {
+        c.reg_h.assign(nreg, -1);  // not read without pairs
     }
-    c.reg_h.resize(nreg);
-    HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
     std::vector<double> cb0, cb1;
-    if (c.opt.fmm_order != 0) {
+    if (c.opt.fmm_order != 0 && pairs) {
         cb0.resize(4 * c.nd);
         cb1.resize(4 * c.nd);
         HIPC(hipMemcpyAsync(cb0.data(), c.cbnd.ptr, cb0.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipMemcpyAsync(cb1.data(), c.cbnd1.ptr, cb1.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
     }
-    int P = c.opt.fmm_order;
+    int P = pairs ? c.opt.fmm_order : 0;
     if (P < 0) {
         if (c.fmm_tuned < 0) c.fmm_tuned = tune_fmm(c, cb0, cb1);
         P = c.fmm_tuned;
