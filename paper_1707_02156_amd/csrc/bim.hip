@@ -872,13 +872,26 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     // target nodes and of the source grid the region selects)
     // grid of a far pair (-1: summed directly); order: the smallest degree
     // Q <= P with rho^(Q+1) <= eps, used by that pair's translation
+    // uni[i * nd + j]: the region shared by all targets of i with respect to
+    // j, or -4 (one sweep over the regions in memory order)
+    std::vector<int8_t> uni;
+    if (P > 0) {
+        uni.resize((size_t)c.nd * c.nd);
+        for (int i = 0; i < c.nd; ++i) {
+            const Drop &di = c.drops[i];
+            int8_t *u = &uni[(size_t)i * c.nd];
+            const int8_t *row = &c.reg_h[di.toff * c.nd];
+            for (int j = 0; j < c.nd; ++j) u[j] = row[j];
+            for (int t = 1; t < npts(di.p); ++t) {
+                row = &c.reg_h[(di.toff + t) * c.nd];
+                for (int j = 0; j < c.nd; ++j) u[j] = row[j] == u[j] ? u[j] : (int8_t)-4;
+            }
+        }
+    }
     auto far_grid = [&](int i, int j, int &order) -> int {
         if (P <= 0) return -1;
-        const Drop &di = c.drops[i];
-        const int8_t r0 = c.reg_h[di.toff * c.nd + j];
+        const int8_t r0 = uni[(size_t)i * c.nd + j];
         if (r0 != 0 && r0 != 1) return -1;
-        for (int t = 1; t < npts(di.p); ++t)
-            if (c.reg_h[(di.toff + t) * c.nd + j] != r0) return -1;
         const double *cs = (r0 == 0 ? cb0.data() : cb1.data()) + 4 * j, *ct = cb0.data() + 4 * i;
         const double D = std::sqrt((ct[0] - cs[0]) * (ct[0] - cs[0]) + (ct[1] - cs[1]) * (ct[1] - cs[1]) +
                                    (ct[2] - cs[2]) * (ct[2] - cs[2]));
