@@ -907,7 +907,7 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     std::map<int, int> tslot;
     // work lists: for each (target drop i, source drop j != i): Omega_0 targets
     // against j's standard grid, Omega_1/2 targets against j's upsampled grid
-    std::vector<int> tl;
+    std::vector<int> tl, k0, k1;
     std::vector<PairWork> w0, w1;
     std::vector<NearItem> near;
     const int TILE = 64, CH = pair_sources_per_item();
@@ -950,17 +950,30 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
                 F.pair_ij.push_back(i * c.nd + j);
                 continue;
             }
+            // one pass over i's targets: region 0 to the standard grid, 1 (and 2 by
+            // the Omega_1 rule) to the upsampled grid, 2 by the special rule to the
+            // nearest-region items
+            k0.clear();
+            k1.clear();
+            for (int t = 0; t < nti; ++t) {
+                const int8_t r = c.reg_h[(di.toff + t) * c.nd + j];
+                const int tg = (int)(di.toff + t);
+                if (r == 0) {
+                    k0.push_back(tg);
+                    continue;
+                }
+                if (r == 1) ++c.n_om1;
+                if (r == 2) ++c.n_om2;
+                if (r == 2 && c.opt.near_rule == 1)
+                    near.push_back(NearItem{tg, i, j, 0});
+                else
+                    k1.push_back(tg);
+            }
             for (int kind = 0; kind < 2; ++kind) {
                 const int start = (int)tl.size();
-                for (int t = 0; t < nti; ++t) {
-                    const int8_t r = c.reg_h[(di.toff + t) * c.nd + j];
-                    const bool special = r == 2 && c.opt.near_rule == 1;
-                    if ((kind == 0) == (r == 0) && !special) tl.push_back((int)(di.toff + t));
-                    if (kind == 1 && r == 1) ++c.n_om1;
-                    if (kind == 1 && r == 2) ++c.n_om2;
-                    if (kind == 1 && special) near.push_back(NearItem{(int)(di.toff + t), i, j, 0});
-                }
-                const int cnt = (int)tl.size() - start;
+                const std::vector<int> &kl = kind == 0 ? k0 : k1;
+                tl.insert(tl.end(), kl.begin(), kl.end());
+                const int cnt = (int)kl.size();
                 const long soff = kind == 0 ? dj.toff : dj.uoff;
                 const int ns = kind == 0 ? npts(dj.p) : npts(dj.qu);
                 for (int a = 0; a < cnt; a += TILE)
