@@ -875,7 +875,7 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     // uni[i * nd + j]: the region shared by all targets of i with respect to
     // j, or -4 (one sweep over the regions in memory order)
     std::vector<int8_t> uni;
-    if (P > 0) {
+    {
         uni.resize((size_t)c.nd * c.nd);
         for (int i = 0; i < c.nd; ++i) {
             const Drop &di = c.drops[i];
@@ -948,6 +948,27 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
                 const double nt = (forder + 1) * (forder + 2) / 2;
                 F.m2l_flops += nt * (forder + 1) * (forder + 1) * 32.0;
                 F.pair_ij.push_back(i * c.nd + j);
+                continue;
+            }
+            const int8_t ru = uni[(size_t)i * c.nd + j];
+            if (ru == 0 || ru == 1) {
+                // every target of i in one region: items over the contiguous
+                // target range, no index list
+                if (ru == 1) c.n_om1 += nti;
+                const long soff = ru == 0 ? dj.toff : dj.uoff;
+                const int ns = ru == 0 ? npts(dj.p) : npts(dj.qu);
+                for (int a = 0; a < nti; a += TILE)
+                    for (int b = 0; b < ns; b += CH) {
+                        PairWork pw;
+                        pw.tlist_off = (int)(di.toff + a);
+                        pw.ntgt = std::min(TILE, nti - a);
+                        pw.src_off = (int)(soff + b);
+                        pw.nsrc = std::min(CH, ns - b);
+                        pw.pair = i * c.nd + j;
+                        pw.pad = ru | kPairContig;
+                        pw.w = 0.0;
+                        (ru == 0 ? w0 : w1).push_back(pw);
+                    }
                 continue;
             }
             // one pass over i's targets: region 0 to the standard grid, 1 (and 2 by

@@ -26,14 +26,16 @@ double legendre_sum(int q, double t);
 
 // ---- device-side work descriptors ----
 struct PairWork {
-    int tlist_off;  // first entry in the target index list
+    int tlist_off;  // first entry in the target index list, or the first target (kPairContig)
     int ntgt;       // targets in this item (<= 64)
     int src_off;    // first source node in the source arrays
     int nsrc;       // source nodes in this item
     int pair;       // target drop * n_drops + source drop
-    int pad;        // source grid: 0 standard, 1 upsampled
+    int pad;        // bit 0: source grid (0 standard, 1 upsampled); kPairContig: targets
+                    // tlist_off .. tlist_off + ntgt - 1, no index list
     double w;       // weight applied to the sum
 };
+constexpr int kPairContig = 2;
 
 // Device state of the GMRES least-squares problem (Givens rotations applied
 // on the device): R by columns, rotations, right-hand side g, and the

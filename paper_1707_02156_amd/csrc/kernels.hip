@@ -461,10 +461,11 @@ __global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work,
     __shared__ double2 sh[kPairSrc][NP];
     __shared__ double red[3][3][64];
     const PairWork w = work[blockIdx.x];
-    const PairSrc &G = w.pad ? g1 : g0;
+    const PairSrc &G = (w.pad & 1) ? g1 : g0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool active = lane < w.ntgt;
-    const int t = active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off];
+    const int t = (w.pad & kPairContig) ? w.tlist_off + (active ? lane : 0)
+                                        : (active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off]);
     const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int s0 = 0; s0 < w.nsrc; s0 += kPairSrc) {
@@ -554,11 +555,12 @@ __global__ __launch_bounds__(256) void k_pair32(const PairWork *__restrict__ wor
     __shared__ float4 sh[kPairSrc][NP];
     __shared__ double red[3][3][64];
     const PairWork w = work[blockIdx.x];
-    const PairSrc &G = w.pad ? g1 : g0;
+    const PairSrc &G = (w.pad & 1) ? g1 : g0;
     const double *c = cb + 4 * (w.pair % nd);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool active = lane < w.ntgt;
-    const int t = active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off];
+    const int t = (w.pad & kPairContig) ? w.tlist_off + (active ? lane : 0)
+                                        : (active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off]);
     const float x0 = (float)(tx[t] - c[0]), y0 = (float)(tx[tstride + t] - c[1]),
                 z0 = (float)(tx[2 * tstride + t] - c[2]);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
