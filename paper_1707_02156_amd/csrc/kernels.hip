@@ -13,7 +13,6 @@
 
 namespace bim {
 
-static constexpr double kPi = 3.14159265358979323846;
 static constexpr double kInvSqrt4Pi = 0.28209479177387814347;
 
 // ----------------------------------------------------------------------------
