@@ -13,7 +13,6 @@ Fixed by the method, not by retyping it:
 - the filtered residual max |g| decreases under the iteration.
 """
 import numpy as np
-import pytest
 
 import oracle as O
 import workloads as W
