@@ -127,13 +127,15 @@ void launch_gs_scale(hipStream_t st, long n, const double *w, const double *nrm,
 void launch_surf_terms(hipStream_t st, const SurfJob *jobs, int n);
 void launch_mul(hipStream_t st, long n, const double *d, const double *x, double *y);
 void launch_axpby(hipStream_t st, long n, double a, const double *x, double b, const double *y, double *out);
-void launch_rep_pack(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *hdr, double *rec);
-void launch_rep_eval(hipStream_t st, int q, int nf, const double *rec, const double *cm, const double *th,
-                     const double *ph, long N, double *out);
-void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax);
-void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph,
-                     const unsigned long long *gmax, double eps, int check, int *moves);
-void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
+void launch_rep_pack(hipStream_t st, int q, int nf, int nb, const double *coef, long cstride, const double *hdr,
+                     double *rec);
+void launch_rep_eval(hipStream_t st, int q, int nf, int nb, const double *rec, const double *cm, const double *th,
+                     const double *ph, long ang_bs, long N, double *out);
+void launch_rep_grad(hipStream_t st, int nb, long N, const double *E, const double *gE, double *g,
+                     unsigned long long *gmax);
+void launch_rep_move(hipStream_t st, int nb, long N, const double *E, const double *g, double dtau, double *th,
+                     double *ph, long ang_bs, const unsigned long long *gmax, double eps, int check, int *moves);
+void launch_rep_cut(hipStream_t st, int q, int nb, const double *xt, long cs, double P_cut, double *hp, int *ncut,
                     unsigned long long *gmax);
 void launch_lincomb(hipStream_t st, long n, int k, const double *V, long ld, const double *y, double *x);
 void launch_fmm_ytab(hipStream_t st, const FmmSrcJob *jobs, int njobs, int maxns, int P, const double *cen, void *Y,
@@ -2459,83 +2461,105 @@ struct RepOut {
     double gnorm = 0.0;
 };
 
-// Algorithm 2 on drop i: the initial expansions (degree p, zero-padded to
-// q = U p) stay fixed; the angles of the degree-q grid nodes move by forward
-// Euler steps of the parameter velocity of w = -(I - n n) grad E, grad E the
-// field of the coefficients of degree >= n_cut. The drop's position (and
-// surfactant) coefficients are replaced by the analysis of the initial
-// expansions at the final angles, truncated to degree p.
-static RepOut reparam_drop(Ctx &c, int i, int U, double P_cut, double eps, int imax, double dtau)
+// Algorithm 2 on the drops `ids`, all of degree p, as one batch: the
+// initial expansions (degree p, zero-padded to q = U p) stay fixed; the
+// angles of the degree-q grid nodes move by forward Euler steps of the
+// parameter velocity of w = -(I - n n) grad E, grad E the field of the
+// coefficients of degree >= n_cut. Each drop keeps its own cutoff, residual
+// and stopping test. The drops' position (and surfactant) coefficients are
+// replaced by the analysis of the initial expansions at the final angles,
+// truncated to degree p.
+static RepOut reparam_group(Ctx &c, const std::vector<int> &ids, int U, double P_cut, double eps, int imax,
+                            double dtau)
 {
-    const Drop &d = c.drops[i];
-    const int p = d.p, q = U * p;
+    const int nb = (int)ids.size();
+    const int p = c.drops[ids[0]].p, q = U * p;
     const long N = npts(q), nq2 = 2L * ncoef(q), np2 = 2L * ncoef(p);
     GridTab &gq = grid(c, q, q);
     const long R = ncoef(q);
     const double *hdr = rep_table(c, q), *cmt = hdr + 4 * R;
-    c.rp_rec.ensure((size_t)10 * R * sizeof(double));
-    c.rp_x0.ensure((size_t)3 * nq2 * sizeof(double));
-    c.rp_g0.ensure((size_t)nq2 * sizeof(double));
-    c.rp_xt.ensure((size_t)3 * nq2 * sizeof(double));
-    c.rp_hp.ensure((size_t)3 * nq2 * sizeof(double));
-    c.rp_ang.ensure((size_t)2 * N * sizeof(double));
-    c.rp_E.ensure((size_t)9 * N * sizeof(double));
-    c.rp_gE.ensure((size_t)3 * N * sizeof(double));
-    c.rp_g.ensure((size_t)3 * N * sizeof(double));
-    c.rp_gmax.ensure(4 * sizeof(double));  // residual bits, cutoff, move count
+    c.rp_rec.ensure((size_t)nb * 10 * R * sizeof(double));
+    c.rp_x0.ensure((size_t)nb * 3 * nq2 * sizeof(double));
+    c.rp_g0.ensure((size_t)nb * nq2 * sizeof(double));
+    c.rp_xt.ensure((size_t)nb * 3 * nq2 * sizeof(double));
+    c.rp_hp.ensure((size_t)nb * 3 * nq2 * sizeof(double));
+    c.rp_ang.ensure((size_t)nb * 2 * N * sizeof(double));
+    c.rp_E.ensure((size_t)nb * 9 * N * sizeof(double));
+    c.rp_gE.ensure((size_t)nb * 3 * N * sizeof(double));
+    c.rp_g.ensure((size_t)nb * 3 * N * sizeof(double));
+    c.rp_gmax.ensure((size_t)nb * 2 * sizeof(double));  // residual bits [nb], then cutoff [nb] and moves [nb]
     double *x0 = c.rp_x0.d(), *g0 = c.rp_g0.d(), *xt = c.rp_xt.d(), *hp = c.rp_hp.d(), *th = c.rp_ang.d(),
            *ph = th + N, *E = c.rp_E.d(), *gE = c.rp_gE.d(), *g = c.rp_g.d();
     auto *gmax = (unsigned long long *)c.rp_gmax.ptr;
-    HIPC(hipMemsetAsync(x0, 0, (size_t)3 * nq2 * sizeof(double), c.stream));
-    for (int comp = 0; comp < 3; ++comp) dcopy(c, x0 + comp * nq2, c.xc.d() + comp * c.Ctot + d.coff, np2);
+    int *dnc = (int *)(gmax + nb), *dmoves = dnc + nb;
+    const long A = 2 * N;  // angle stride between drops: th then ph
+    HIPC(hipMemsetAsync(x0, 0, (size_t)nb * 3 * nq2 * sizeof(double), c.stream));
+    for (int b = 0; b < nb; ++b)
+        HIPC(hipMemcpy2DAsync(x0 + 3L * b * nq2, nq2 * sizeof(double), c.xc.d() + c.drops[ids[b]].coff,
+                              c.Ctot * sizeof(double), np2 * sizeof(double), 3, hipMemcpyDeviceToDevice, c.stream));
     if (c.have_gamma) {
-        HIPC(hipMemsetAsync(g0, 0, (size_t)nq2 * sizeof(double), c.stream));
-        dcopy(c, g0, c.gc.d() + d.coff, np2);
+        HIPC(hipMemsetAsync(g0, 0, (size_t)nb * nq2 * sizeof(double), c.stream));
+        for (int b = 0; b < nb; ++b) dcopy(c, g0 + b * nq2, c.gc.d() + c.drops[ids[b]].coff, np2);
     }
-    std::vector<double> ang(2 * N);
+    std::vector<double> ang((size_t)nb * A);
     for (int j = 0; j <= q; ++j)
         for (int k = 0; k < 2 * q; ++k) {
             ang[(long)j * 2 * q + k] = gq.th[j];
             ang[N + (long)j * 2 * q + k] = kPi * k / q;
         }
-    HIPC(hipMemcpyAsync(th, ang.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    int *dnc = (int *)((char *)c.rp_gmax.ptr + sizeof(double));
-    int *dmoves = dnc + 1;
-    HIPC(hipMemsetAsync(dmoves, 0, sizeof(int), c.stream));
+    for (int b = 1; b < nb; ++b) std::copy(ang.begin(), ang.begin() + A, ang.begin() + (long)b * A);
+    HIPC(hipMemcpyAsync(th, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPC(hipMemsetAsync(dmoves, 0, nb * sizeof(int), c.stream));
     double *rec = c.rp_rec.d();
-    launch_rep_pack(c.stream, q, 3, x0, nq2, hdr, rec);
+    launch_rep_pack(c.stream, q, 3, nb, x0, nq2, hdr, rec);
+    std::vector<AnaJob> ajobs;
+    std::vector<SynJob> sjobs;
+    for (int b = 0; b < nb; ++b) {
+        ajobs.push_back(ana_job(c, q, q, 3, E + 9 * N * b, 3 * N, xt + 3 * nq2 * b, nq2));
+        sjobs.push_back(syn_job(c, q, q, 3, hp + 3 * nq2 * b, nq2, 0x1, gE + 3 * N * b, N, 0));
+    }
     // x~ at the current angles, the cutoff and filter, grad E, g and its largest norm
     auto evaluate = [&]() {
-        launch_rep_eval(c.stream, q, 3, rec, cmt, th, ph, N, E);
-        ana_run(c, {ana_job(c, q, q, 3, E, 3 * N, xt, nq2)});
-        launch_rep_cut(c.stream, q, xt, nq2, P_cut, hp, dnc, gmax);
-        syn_run(c, {syn_job(c, q, q, 3, hp, nq2, 0x1, gE, N, 0)});
-        launch_rep_grad(c.stream, N, E, gE, g, gmax);
+        launch_rep_eval(c.stream, q, 3, nb, rec, cmt, th, ph, A, N, E);
+        ana_run(c, ajobs);
+        launch_rep_cut(c.stream, q, nb, xt, nq2, P_cut, hp, dnc, gmax);
+        syn_run(c, sjobs);
+        launch_rep_grad(c.stream, nb, N, E, gE, g, gmax);
     };
-    // all iterations are enqueued at once: once max |g| < eps the moves are
-    // skipped on the device and the evaluations repeat the final state
+    // all iterations are enqueued at once: once a drop's max |g| < eps its
+    // moves are skipped on the device and its evaluations repeat the final state
     evaluate();
     for (int it = 1; it < imax; ++it) {
-        launch_rep_move(c.stream, N, E, g, dtau, th, ph, gmax, eps, it > 1, dmoves);
+        launch_rep_move(c.stream, nb, N, E, g, dtau, th, ph, A, gmax, eps, it > 1, dmoves);
         evaluate();
     }
     RepOut r;
+    r.ncut = 1 << 30;
     {
-        std::vector<char> hs(2 * sizeof(double));
+        std::vector<char> hs((size_t)nb * 2 * sizeof(double));
         HIPC(hipMemcpyAsync(hs.data(), c.rp_gmax.ptr, hs.size(), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
-        double gn;
-        std::memcpy(&gn, hs.data(), sizeof(double));
-        std::memcpy(&r.ncut, hs.data() + sizeof(double), sizeof(int));
-        std::memcpy(&r.moves, hs.data() + sizeof(double) + sizeof(int), sizeof(int));
-        r.gnorm = gn;
+        for (int b = 0; b < nb; ++b) {
+            double gn;
+            int nc, mv;
+            std::memcpy(&gn, hs.data() + b * sizeof(double), sizeof(double));
+            std::memcpy(&nc, hs.data() + nb * sizeof(double) + b * sizeof(int), sizeof(int));
+            std::memcpy(&mv, hs.data() + nb * sizeof(double) + (nb + b) * sizeof(int), sizeof(int));
+            r.gnorm = std::max(r.gnorm, gn);
+            r.ncut = std::min(r.ncut, nc);
+            r.moves = std::max(r.moves, mv);
+        }
     }
-    for (int comp = 0; comp < 3; ++comp) dcopy(c, c.xc.d() + comp * c.Ctot + d.coff, xt + comp * nq2, np2);
+    for (int b = 0; b < nb; ++b)
+        HIPC(hipMemcpy2DAsync(c.xc.d() + c.drops[ids[b]].coff, c.Ctot * sizeof(double), xt + 3L * b * nq2,
+                              nq2 * sizeof(double), np2 * sizeof(double), 3, hipMemcpyDeviceToDevice, c.stream));
     if (c.have_gamma) {
-        launch_rep_pack(c.stream, q, 1, g0, nq2, hdr, rec);
-        launch_rep_eval(c.stream, q, 1, rec, cmt, th, ph, N, E);
-        ana_run(c, {ana_job(c, q, q, 1, E, 0, hp, 0)});
-        dcopy(c, c.gc.d() + d.coff, hp, np2);
+        launch_rep_pack(c.stream, q, 1, nb, g0, nq2, hdr, rec);
+        launch_rep_eval(c.stream, q, 1, nb, rec, cmt, th, ph, A, N, E);
+        std::vector<AnaJob> gjobs;
+        for (int b = 0; b < nb; ++b) gjobs.push_back(ana_job(c, q, q, 1, E + 3 * N * b, 0, hp + nq2 * b, 0));
+        ana_run(c, gjobs);
+        for (int b = 0; b < nb; ++b) dcopy(c, c.gc.d() + c.drops[ids[b]].coff, hp + nq2 * b, np2);
     }
     HIPC(hipStreamSynchronize(c.stream));
     return r;
@@ -2555,8 +2579,10 @@ int bim_reparametrize(bim_ctx h, int U_rep, double P_cut, double eps, int imax, 
         auto t0 = std::chrono::steady_clock::now();
         bim_rep_report r{};
         r.ncut_min = 1 << 30;
-        for (int i = 0; i < c.nd; ++i) {
-            const RepOut o = reparam_drop(c, i, U_rep, P_cut, eps, imax, dtau);
+        std::map<int, std::vector<int>> by_degree;  // one batch per drop degree
+        for (int i = 0; i < c.nd; ++i) by_degree[c.drops[i].p].push_back(i);
+        for (const auto &grp : by_degree) {
+            const RepOut o = reparam_group(c, grp.second, U_rep, P_cut, eps, imax, dtau);
             r.moves = std::max(r.moves, o.moves);
             r.gnorm = std::max(r.gnorm, o.gnorm);
             r.ncut_min = std::min(r.ncut_min, o.ncut);

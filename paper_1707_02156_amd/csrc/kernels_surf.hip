@@ -147,6 +147,11 @@ constexpr double kPiS = 3.14159265358979323846;
 // one recursion P = a t P_{n-1} - b P_{n-2} started from (P_{m-1}, P_{m-2})
 // = (0, c_m sin^m) covers every n. The expansions are fixed while the nodes
 // move, so the packing is done once per set of expansions.
+// Batched over drops of one degree (blockIdx.y = drop b of the batch): the
+// expansions of drop b start at coef + b NF cstride, its records at
+// rec + b R RS. The evaluation, gradient and move kernels take the same
+// batch index, with the nodes of drop b at th/ph + b ang_bs and its
+// outputs at the per-drop strides given below.
 template <int NF>
 __global__ void k_rep_pack(int q, const double *__restrict__ coef, long cstride, const double *__restrict__ hdr,
                            double *__restrict__ rec)
@@ -155,6 +160,8 @@ __global__ void k_rep_pack(int q, const double *__restrict__ coef, long cstride,
     const long nc = (long)(q + 1) * (q + 2) / 2;
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nc) return;
+    coef += (long)blockIdx.y * NF * cstride;
+    rec += (long)blockIdx.y * nc * RS;
     int m = 0;
     long off = 0;
     while (off + (q + 1 - m) <= j) off += q + 1 - m++;
@@ -178,7 +185,8 @@ __global__ void k_rep_pack(int q, const double *__restrict__ coef, long cstride,
 // are added in LDS in a fixed order, within the block (a split of the orders
 // over several blocks needs device-scope fences for the cross-block sum,
 // which cost more than the added parallelism gains).
-// out[(3 f + d) N + i]: d = 0 value, 1 d/dtheta, 2 d/dphi.
+// out[(3 f + d) N + i] (+ b 3 NF N for drop b): d = 0 value, 1 d/dtheta,
+// 2 d/dphi.
 constexpr int kRepWaves = 16;
 static_assert(kRepWaves % 2 == 0, "two-phase block sum");
 
@@ -186,7 +194,7 @@ template <int NF>
 __global__ __launch_bounds__(64 * kRepWaves) void k_rep_eval(int q, const double *__restrict__ rec,
                                                              const double *__restrict__ cmt,
                                                              const double *__restrict__ th,
-                                                             const double *__restrict__ ph, long N,
+                                                             const double *__restrict__ ph, long ang_bs, long N,
                                                              double *__restrict__ out)
 {
     constexpr int RS = 4 + 2 * NF, NO = 3 * NF;
@@ -194,9 +202,13 @@ __global__ __launch_bounds__(64 * kRepWaves) void k_rep_eval(int q, const double
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long grp = blockIdx.x;
+    const long R = (long)(q + 1) * (q + 2) / 2;
+    rec += (long)blockIdx.y * R * RS;
+    th += (long)blockIdx.y * ang_bs;
+    ph += (long)blockIdx.y * ang_bs;
+    out += (long)blockIdx.y * NO * N;
     const long i = grp * 64 + lane, ic = i < N ? i : N - 1;  // lanes past N evaluate node N - 1, store nothing
     const double t = cos(th[ic]), s = sin(th[ic]), is = 1.0 / s, phi = ph[ic];
-    const long R = (long)(q + 1) * (q + 2) / 2;
     double acc[NF][3] = {};
     bool first = true;
     double spow = 1.0, cm = 1.0, sm = 0.0, c1 = 1.0, s1 = 0.0;  // sin^m, e^{i m phi}, e^{i phi}
@@ -270,10 +282,15 @@ __global__ __launch_bounds__(64 * kRepWaves) void k_rep_eval(int q, const double
 // g = (I - n n) grad E at every node, n = X_t x X_p / |X_t x X_p|; gmax holds
 // the largest |g| as the bits of a non-negative double (ordered like unsigned
 // integers). E: k_rep_eval output for the 3 position components; gE [3][N].
+// Drop b of a batch: E + 9 N b, gE and g + 3 N b, gmax + b.
 __global__ void k_rep_grad(long N, const double *__restrict__ E, const double *__restrict__ gE,
                            double *__restrict__ g, unsigned long long *gmax)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    E += 9 * N * blockIdx.y;
+    gE += 3 * N * blockIdx.y;
+    g += 3 * N * blockIdx.y;
+    gmax += blockIdx.y;
     double mag = 0.0;
     if (i < N) {
         double xt[3], xp[3], v[3];
@@ -302,12 +319,19 @@ __global__ void k_rep_grad(long N, const double *__restrict__ E, const double *_
 // taken back into theta in [0, pi] across the pole (phi + pi) and phi mod 2 pi.
 // With check set the step is skipped once the previous residual max |g|
 // (gmax) is below eps (the iteration has stopped); moves counts the steps taken.
+// Drop b of a batch: E + 9 N b, g + 3 N b, th/ph + ang_bs b, gmax and moves + b.
 __global__ void k_rep_move(long N, const double *__restrict__ E, const double *__restrict__ g, double dtau,
-                           double *__restrict__ th, double *__restrict__ ph, const unsigned long long *gmax,
-                           double eps, int check, int *moves)
+                           double *__restrict__ th, double *__restrict__ ph, long ang_bs,
+                           const unsigned long long *gmax, double eps, int check, int *moves)
 {
+    gmax += blockIdx.y;
     if (check && __longlong_as_double((long long)gmax[0]) < eps) return;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    E += 9 * N * blockIdx.y;
+    g += 3 * N * blockIdx.y;
+    th += ang_bs * blockIdx.y;
+    ph += ang_bs * blockIdx.y;
+    moves += blockIdx.y;
     if (i == 0) moves[0] += 1;
     if (i >= N) return;
     double a00 = 0.0, a01 = 0.0, a11 = 0.0, b0 = 0.0, b1 = 0.0;
@@ -335,36 +359,39 @@ __global__ void k_rep_move(long N, const double *__restrict__ E, const double *_
     ph[i] = p;
 }
 
-void launch_rep_pack(hipStream_t st, int q, int nf, const double *coef, long cstride, const double *hdr, double *rec)
+void launch_rep_pack(hipStream_t st, int q, int nf, int nb, const double *coef, long cstride, const double *hdr,
+                     double *rec)
 {
     const long nc = (long)(q + 1) * (q + 2) / 2;
-    const unsigned blocks = (unsigned)((nc + 255) / 256);
+    const dim3 grid((unsigned)((nc + 255) / 256), (unsigned)nb);
     if (nf == 3)
-        hipLaunchKernelGGL(k_rep_pack<3>, dim3(blocks), dim3(256), 0, st, q, coef, cstride, hdr, rec);
+        hipLaunchKernelGGL(k_rep_pack<3>, grid, dim3(256), 0, st, q, coef, cstride, hdr, rec);
     else
-        hipLaunchKernelGGL(k_rep_pack<1>, dim3(blocks), dim3(256), 0, st, q, coef, cstride, hdr, rec);
+        hipLaunchKernelGGL(k_rep_pack<1>, grid, dim3(256), 0, st, q, coef, cstride, hdr, rec);
 }
 
-void launch_rep_eval(hipStream_t st, int q, int nf, const double *rec, const double *cm, const double *th,
-                     const double *ph, long N, double *out)
+void launch_rep_eval(hipStream_t st, int q, int nf, int nb, const double *rec, const double *cm, const double *th,
+                     const double *ph, long ang_bs, long N, double *out)
 {
-    const unsigned blocks = (unsigned)((N + 63) / 64);
+    const dim3 grid((unsigned)((N + 63) / 64), (unsigned)nb);
     if (nf == 3)
-        hipLaunchKernelGGL(k_rep_eval<3>, dim3(blocks), dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, N, out);
+        hipLaunchKernelGGL(k_rep_eval<3>, grid, dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, ang_bs, N, out);
     else
-        hipLaunchKernelGGL(k_rep_eval<1>, dim3(blocks), dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, N, out);
+        hipLaunchKernelGGL(k_rep_eval<1>, grid, dim3(64 * kRepWaves), 0, st, q, rec, cm, th, ph, ang_bs, N, out);
 }
 
-void launch_rep_grad(hipStream_t st, long N, const double *E, const double *gE, double *g, unsigned long long *gmax)
+void launch_rep_grad(hipStream_t st, int nb, long N, const double *E, const double *gE, double *g,
+                     unsigned long long *gmax)
 {
-    hipLaunchKernelGGL(k_rep_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, gE, g, gmax);
+    hipLaunchKernelGGL(k_rep_grad, dim3((unsigned)((N + 255) / 256), (unsigned)nb), dim3(256), 0, st, N, E, gE, g,
+                       gmax);
 }
 
-void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, double dtau, double *th, double *ph,
-                     const unsigned long long *gmax, double eps, int check, int *moves)
+void launch_rep_move(hipStream_t st, int nb, long N, const double *E, const double *g, double dtau, double *th,
+                     double *ph, long ang_bs, const unsigned long long *gmax, double eps, int check, int *moves)
 {
-    hipLaunchKernelGGL(k_rep_move, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, E, g, dtau, th, ph, gmax,
-                       eps, check, moves);
+    hipLaunchKernelGGL(k_rep_move, dim3((unsigned)((N + 255) / 256), (unsigned)nb), dim3(256), 0, st, N, E, g, dtau,
+                       th, ph, ang_bs, gmax, eps, check, moves);
 }
 
 // Adaptive cutoff and filter in one block: mag_n = sum_{|m| <= n} |x_n^m|
@@ -374,6 +401,8 @@ void launch_rep_move(hipStream_t st, long N, const double *E, const double *g, d
 // Each thread holds up to kRepCutPer coefficients (3 components) in
 // registers from one coalesced pass; the per-degree sums, their tails and
 // the search run from LDS in a fixed order (no atomics on the sums).
+// One block per drop of a batch: drop b at xt and hp + 3 cs b, ncut and
+// gmax + b.
 constexpr int kRepCutThreads = 1024, kRepCutPer = 3;  // tri(kRepMaxDeg + 1) <= 3072
 static_assert((kRepMaxDeg + 1) * (kRepMaxDeg + 2) / 2 <= kRepCutThreads * kRepCutPer, "cutoff kernel size");
 
@@ -386,6 +415,10 @@ __global__ __launch_bounds__(kRepCutThreads) void k_rep_cut(int q, const double 
     __shared__ int snc;
     const int tid = threadIdx.x;
     const int nc = (q + 1) * (q + 2) / 2;
+    xt += 3 * cs * blockIdx.x;
+    hp += 3 * cs * blockIdx.x;
+    ncut += blockIdx.x;
+    gmax += blockIdx.x;
     double2 x[kRepCutPer][3];
     int deg[kRepCutPer];
 #pragma unroll
@@ -437,11 +470,11 @@ __global__ __launch_bounds__(kRepCutThreads) void k_rep_cut(int q, const double 
     }
 }
 
-void launch_rep_cut(hipStream_t st, int q, const double *xt, long cs, double P_cut, double *hp, int *ncut,
+void launch_rep_cut(hipStream_t st, int q, int nb, const double *xt, long cs, double P_cut, double *hp, int *ncut,
                     unsigned long long *gmax)
 {
     if (q < 1 || q > kRepMaxDeg || (cs & 1)) return;  // the host validates q = U_rep p <= 64, cs = (q+1)(q+2)
-    hipLaunchKernelGGL(k_rep_cut, dim3(1), dim3(kRepCutThreads), 0, st, q, xt, cs, P_cut, hp, ncut, gmax);
+    hipLaunchKernelGGL(k_rep_cut, dim3((unsigned)nb), dim3(kRepCutThreads), 0, st, q, xt, cs, P_cut, hp, ncut, gmax);
 }
 
 }  // namespace bim

@@ -129,3 +129,25 @@ def test_reparametrize_error_paths(B):
             c.reparametrize(**kw)
         assert e.value.status == B.BIM_EINVAL
     c.close()
+
+
+def test_batch_of_one_degree_each_as_alone(B, orc):
+    """Three drops of one degree run as one batch: a twisted sphere, a
+    perturbed drop and a standard sphere (which stops after its first move
+    while the others go on). Each drop must get what the oracle gives it
+    alone, surfactant included."""
+    print("reparam: batch of three p=10 drops", flush=True)
+    O, RP = orc
+    rng = np.random.default_rng(33)
+    p = 10
+    xs_in = [twisted_sphere(O, RP, p, 0.35, 0.12, 1.0, (0.0, 0.0, 0.0)),
+             W.perturbed_sphere(rng, p, 0.9, (3.0, 0.0, 0.0), 0.06),
+             W.sphere(p, 1.1, (0.0, 3.0, 0.0))]
+    gs_in = [W.scalar_field(rng, p, 0.2, 1.0, 1.0) for _ in range(3)]
+    kw = dict(U_rep=2, P_cut=1e-3, eps=1e-10, imax=10, dtau=1.0)
+    xs, gs, rep = _run(B, [(p, x) for x in xs_in], gs_in, **kw)
+    oreps = [_check(O, RP, p, xs_in[k], gs_in[k], xs[k], gs[k], rep, **kw) for k in range(3)]
+    assert oreps[2]["moves"] == 1 and oreps[0]["moves"] > 1
+    assert rep["moves"] == max(o["moves"] for o in oreps)
+    assert rep["ncut_min"] == min(o["ncut"] for o in oreps)
+    assert np.abs(xs[2] - xs_in[2]).max() <= 1e-13
