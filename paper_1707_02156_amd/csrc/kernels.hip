@@ -676,6 +676,8 @@ __global__ void k_op_combine(long n, const double *__restrict__ sc, const double
 //   NRM:  hacc[i] += hin[i] for i < kv (UPD only) and hacc[kv] = ||w||
 // ----------------------------------------------------------------------------
 constexpr int kGsR = 4, kGsChunk = 64 * kGsR;
+constexpr int kGsMaxVectors = 256;  // Krylov vectors; the Givens staging below needs 3 (kv - 1) + 2 doubles of sacc
+static_assert(3 * (kGsMaxVectors - 1) + 2 <= 4 * kGsChunk, "Givens staging exceeds the LDS buffer");
 
 template <bool UPD, bool NRM>
 __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__restrict__ V, long ld,
@@ -778,35 +780,57 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
             v2[e] = make_double2(a.x * ti, a.y * ti);
         }
     }
-    if (NRM && UPD)
+    if (NRM && UPD && !ga.H)
         for (int i = threadIdx.x; i < kv; i += 256) hout[i] += hin[i];
     if (NRM && UPD && ga.H) {
-        // Givens update of the least-squares problem for column k = kv - 1:
-        // previous rotations on the new column of H (h[0..k+1], kept as it is
-        // for the normalisation that follows), then the rotation that zeroes
-        // h[k+1]; g updated and the residual estimate |g[k+1]| / ||b|| stored.
+        // h[i] += hin[i] (i < kv), then the Givens update of the least-squares
+        // problem for column k = kv - 1: previous rotations on the new column
+        // of H (h[0..k+1], kept as it is for the normalisation that follows),
+        // then the rotation that zeroes h[k+1]; g updated and the residual
+        // estimate |g[k+1]| / ||b|| stored. The column, the previous rotations
+        // and g[k] are staged in LDS in one round of loads (sacc is free by
+        // now), so the sequential sweep does not wait on a global load per
+        // rotation.
+        const int kc = kv - 1;
+        double *scol = &sacc[0][0], *scs = scol + kc + 2, *ssn = scs + kc;  // 3 kc + 2 < 4 kGsChunk
+        __shared__ double sgk;
+        __syncthreads();  // snrm set, sacc free
+        for (int l = threadIdx.x; l < kv; l += 256) {
+            const double v = hout[l] + hin[l];
+            hout[l] = v;
+            scol[l] = v;
+        }
+        for (int l = threadIdx.x; l < kc; l += 256) {
+            scs[l] = ga.cs[l];
+            ssn[l] = ga.sn[l];
+        }
+        if (threadIdx.x == 0) {
+            scol[kv] = snrm;
+            sgk = ga.g[kc];
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const int kc = kv - 1;
-            double *col = ga.H + (long)kc * ga.ldH;  // column kc of R, rows 0..kc+1
-            for (int l = 0; l <= kc + 1; ++l) col[l] = hout[l];
+            double cur = scol[0];  // entry l of the column after rotations 0..l-1
             for (int l = 0; l < kc; ++l) {
-                const double t = ga.cs[l] * col[l] + ga.sn[l] * col[l + 1];
-                col[l + 1] = -ga.sn[l] * col[l] + ga.cs[l] * col[l + 1];
-                col[l] = t;
+                const double nx = scol[l + 1];
+                scol[l] = scs[l] * cur + ssn[l] * nx;
+                cur = -ssn[l] * cur + scs[l] * nx;
             }
-            const double den = hypot(col[kc], col[kc + 1]);
-            const double cr = den > 0.0 ? col[kc] / den : 1.0, sr = den > 0.0 ? col[kc + 1] / den : 0.0;
+            const double hk1 = scol[kc + 1];
+            const double den = hypot(cur, hk1);
+            const double cr = den > 0.0 ? cur / den : 1.0, sr = den > 0.0 ? hk1 / den : 0.0;
             ga.cs[kc] = cr;
             ga.sn[kc] = sr;
-            col[kc] = den;
-            col[kc + 1] = 0.0;
-            const double gk = ga.g[kc];
-            ga.g[kc + 1] = -sr * gk;
-            ga.g[kc] = cr * gk;
+            scol[kc] = den;
+            scol[kc + 1] = 0.0;
+            ga.g[kc + 1] = -sr * sgk;
+            ga.g[kc] = cr * sgk;
             ga.res[0] = fabs(ga.g[kc + 1]) / ga.bnorm;  // host-visible memory
             __threadfence_system();
         }
+        __syncthreads();
+        double *col = ga.H + (long)kc * ga.ldH;  // column kc of R, rows 0..kc+1
+        for (int l = threadIdx.x; l <= kc + 1; l += 256) col[l] = scol[l];
     }
     if (threadIdx.x == 0) atomicExch(cnt, 0u);
 }
@@ -955,7 +979,7 @@ void launch_op_combine(hipStream_t st, long n, const double *sc, const double *x
 }
 
 long gs_blocks(long n) { return (n + kGsChunk - 1) / kGsChunk; }
-int gs_max_vectors() { return 256; }
+int gs_max_vectors() { return kGsMaxVectors; }
 constexpr long kGsFuseScale = 64;  // blocks up to which the last block also writes the scaled vector
 
 // pass 1 of classical Gram-Schmidt: h[i] = V_i . w, i < kv
