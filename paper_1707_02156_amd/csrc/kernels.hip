@@ -691,21 +691,24 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
     const long e0 = (long)b * kGsChunk + lane;
     double x[kGsR];
     bool ok[kGsR];
+    long eo[kGsR];  // entry read from each basis vector: lanes past n read entry 0 and weigh it by zero
 #pragma unroll
     for (int r = 0; r < kGsR; ++r) {
         const long e = e0 + r * 64;
         ok[r] = e < n;
+        eo[r] = ok[r] ? e : 0;
         x[r] = ok[r] ? w[e] : 0.0;
     }
+    // the basis loads are unconditional, so that a wavefront has all of them
+    // in flight at once (a guarded load waits before the next is issued)
     if (UPD) {
         double acc[kGsR] = {};
 #pragma unroll 4
         for (int i = wv; i < kv; i += 4) {
             const double hi = hin[i];
-            const double *Vi = V + i * ld + e0;
+            const double *Vi = V + i * ld;
 #pragma unroll
-            for (int r = 0; r < kGsR; ++r)
-                if (ok[r]) acc[r] = fma(hi, Vi[r * 64], acc[r]);
+            for (int r = 0; r < kGsR; ++r) acc[r] = fma(hi, Vi[eo[r]], acc[r]);
         }
 #pragma unroll
         for (int r = 0; r < kGsR; ++r) sacc[wv][r * 64 + lane] = acc[r];
@@ -713,7 +716,7 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
 #pragma unroll
         for (int r = 0; r < kGsR; ++r) {
             const int j = r * 64 + lane;
-            x[r] -= (sacc[0][j] + sacc[1][j]) + (sacc[2][j] + sacc[3][j]);
+            x[r] = ok[r] ? x[r] - ((sacc[0][j] + sacc[1][j]) + (sacc[2][j] + sacc[3][j])) : 0.0;
             if (wv == 0 && ok[r]) w[e0 + r * 64] = x[r];
         }
     }
@@ -728,11 +731,10 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
     } else {
 #pragma unroll 2
         for (int i = wv; i < kv; i += 4) {
-            const double *Vi = V + i * ld + e0;
+            const double *Vi = V + i * ld;
             double s = 0.0;
 #pragma unroll
-            for (int r = 0; r < kGsR; ++r)
-                if (ok[r]) s = fma(Vi[r * 64], x[r], s);
+            for (int r = 0; r < kGsR; ++r) s = fma(Vi[eo[r]], x[r], s);
             for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
             if (lane == 0) part[(long)i * nb + b] = s;
         }
