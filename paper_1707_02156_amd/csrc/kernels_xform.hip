@@ -155,7 +155,9 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
         double sn, cs;
         sincos(dphi * m, &sn, &cs);
         double ck = 1.0, sk = 0.0, fr = 0.0, fi = 0.0;
-#pragma unroll 4
+        // 16 longitudes per step: their loads are issued together (the loads do
+        // not depend on the recurrence, but a shorter step waits on each batch)
+#pragma unroll 16
         for (int k = 0; k < nk; ++k) {
             fr = fma(row[k], ck, fr);
             fi = fma(-row[k], sk, fi);
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(256) void k_anal_batch(AnaJobs jobs)
         const int e = n * (n + 1) / 2 + m;
         const double h = (m == q) ? 0.5 : 1.0;
         double sr = 0.0, si = 0.0;
-#pragma unroll 4
+#pragma unroll 8
         for (int j = 0; j < nj; ++j) {
             const double w = J.wq[j] * J.L[(long)j * J.ldn + e] * h;
             sr = fma(w, F[2 * (j * kAnaMC + mm)], sr);
