@@ -253,7 +253,8 @@ int bim_get_state(bim_ctx ctx, double *xcoef, double *gamma_coef, int mem_kind);
  * whose coefficient-magnitude tail sum_{n>=l} sum_m |x~_n^m| is below P_cut
  * times that of l = 1), then (theta, phi) += dtau alpha. It stops when the
  * largest |g| = |(I - n n) grad E| over the nodes is below eps or after
- * imax - 1 steps. The drop coefficients, and the surfactant coefficients when
+ * imax - 1 steps; each drop stops on its own residual (the drops of one
+ * degree run as one batch on the device). The drop coefficients, and the surfactant coefficients when
  * set, become the analysis of the initial expansions at the final angles,
  * truncated to degree p (the surfactant stays the same function of the
  * surface points). The paper's values are U_rep = 2, dtau = 1, imax = 30.
