@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <cmath>
@@ -304,9 +305,9 @@ struct Ctx {
     // reparametrization: initial expansions, current coefficients, node angles, evaluations
     DBuf rp_x0, rp_g0, rp_xt, rp_hp, rp_ang, rp_E, rp_gE, rp_g, rp_gmax, rp_rec;
     std::map<int, std::unique_ptr<DBuf>> rp_tab;  // Legendre recursion coefficients per degree
-    hipEvent_t ev[2] = {nullptr, nullptr};
     double *hhost = nullptr;       // pinned
-    double *hres = nullptr;        // pinned, coherent: GMRES residual estimates written by the device
+    double *hres = nullptr;        // pinned, coherent: GMRES residual estimates and their stamps, written by the device
+    double gm_seq = 0.0;           // stamp of the latest enqueued GMRES step (exact integer)
 
     bool nodes_ok = false, force_ok = false, regions_ok = false;
 
@@ -344,8 +345,6 @@ struct Ctx {
         rots.clear();
         if (hhost) (void)hipHostFree(hhost);
         if (hres) (void)hipHostFree(hres);
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -1676,10 +1675,6 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
         HIPC(hipMemsetAsync(c.gscnt.ptr, 0, sizeof(unsigned), c.stream));
     }
     if (!c.hhost) HIPC(hipHostMalloc((void **)&c.hhost, 4 * 256 * sizeof(double)));
-    if (!c.ev[0]) {
-        HIPC(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
-        HIPC(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
-    }
     double *V = c.V.d(), *h = c.hbuf.d(), *h2 = h + (m + 2), *w = c.wvec.d(), *part = c.gspart.d();
     unsigned *cnt = (unsigned *)c.gscnt.ptr;
     GivensArgs ga;
@@ -1689,8 +1684,12 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
     ga.sn = ga.cs + (m + 2);
     ga.g = ga.sn + (m + 2);
     // residual estimates of the two latest steps: coherent pinned host memory
-    // that the Givens step writes directly (read after the step's event)
-    if (!c.hres) HIPC(hipHostMalloc((void **)&c.hres, 2 * sizeof(double), hipHostMallocCoherent));
+    // that the Givens step writes directly, each slot {estimate, stamp}; the
+    // host waits for the step's stamp (no event in the stream between steps)
+    if (!c.hres) {
+        HIPC(hipHostMalloc((void **)&c.hres, 4 * sizeof(double), hipHostMallocCoherent));
+        std::fill(c.hres, c.hres + 4, 0.0);
+    }
     double *resdev = nullptr;
     HIPC(hipHostGetDevicePointer((void **)&resdev, c.hres, 0));
     HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
@@ -1730,21 +1729,36 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
         const int kmax = std::min(m, c.opt.gmres_maxit - iters);
         int kdone = 0;
         bool conv = false;
-        // step k: Arnoldi vector k + 1, column k of R, residual estimate -> resh[k & 1]
+        // step k: Arnoldi vector k + 1, column k of R, residual estimate and
+        // the step's stamp -> resh[2 (k & 1)], resh[2 (k & 1) + 1]
+        double stamp[2] = {0.0, 0.0};
         auto step = [&](int k) {
             apply(V + (long)k * n, w);
             GivensArgs gk = ga;
-            gk.res = resdev + (k & 1);  // written by the device into pinned host memory
+            gk.res = resdev + 2 * (k & 1);  // written by the device into pinned host memory
+            gk.stamp = stamp[k & 1] = (c.gm_seq += 1.0);
             launch_gs_dots(c.stream, n, k + 1, V, n, w, part, cnt, h);
             launch_gs_update_dots(c.stream, n, k + 1, V, n, h, w, part, cnt, h2);
             launch_gs_update_norm(c.stream, n, k + 1, V, n, h2, w, part, cnt, h, gk, V + (long)(k + 1) * n);
-            HIPC(hipEventRecord(c.ev[k & 1], c.stream));
+        };
+        // the estimate of step k once its stamp has arrived; a stream that
+        // ends or fails without it is an error (no unbounded wait)
+        auto wait_step = [&](int k) {
+            volatile double *st = resh + 2 * (k & 1) + 1;
+            for (long spin = 1; *st != stamp[k & 1]; ++spin) {
+                if (spin % 256 != 0) continue;
+                const hipError_t q = hipStreamQuery(c.stream);
+                if (q == hipErrorNotReady) continue;
+                HIPC(q);
+                if (*st != stamp[k & 1]) throw Error{BIM_EDEVICE, "GMRES step finished without its residual estimate"};
+            }
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return resh[2 * (k & 1)];
         };
         step(0);
         for (int k = 0; k < kmax; ++k) {
             if (k + 1 < kmax) step(k + 1);  // enqueue the next step before waiting on this one
-            HIPC(hipEventSynchronize(c.ev[k & 1]));
-            const double r = resh[k & 1];
+            const double r = wait_step(k);
             ++iters;
             ++nmv;
             kdone = k + 1;

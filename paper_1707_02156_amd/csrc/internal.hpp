@@ -43,8 +43,9 @@ constexpr int kPairContig = 2;
 struct GivensArgs {
     double *H = nullptr;
     long ldH = 0;
-    double *cs = nullptr, *sn = nullptr, *g = nullptr, *res = nullptr;
+    double *cs = nullptr, *sn = nullptr, *g = nullptr, *res = nullptr;  // res: {estimate, stamp}
     double bnorm = 1.0;
+    double stamp = 0.0;  // written to res[1] after the estimate
 };
 
 // Drops of one degree in a pass of the batched singular pipeline (kernel

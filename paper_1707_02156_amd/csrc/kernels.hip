@@ -829,6 +829,8 @@ __global__ __launch_bounds__(256) void k_gs(long n, int kv, const double *__rest
             ga.g[kc] = cr * sgk;
             ga.res[0] = fabs(ga.g[kc + 1]) / ga.bnorm;  // host-visible memory
             __threadfence_system();
+            ga.res[1] = ga.stamp;  // the host reads the estimate once it sees this step's stamp
+            __threadfence_system();
         }
         __syncthreads();
         double *col = ga.H + (long)kc * ga.ldH;  // column kc of R, rows 0..kc+1
