@@ -1653,8 +1653,9 @@ static void apply_operator(Ctx &c, const double *x, double *y, const std::vector
 // GMRES (restarted, classical Gram-Schmidt with one re-orthogonalisation,
 // Givens rotations and back substitution on the device). The host enqueues
 // Arnoldi step k + 1 before it reads the residual estimate of step k (one
-// step behind, through an event), so the device never waits for the host; a
-// step enqueued after convergence is discarded.
+// step behind, from pinned memory once the step's stamp is there), so the
+// device never waits for the host; a step enqueued after convergence is
+// discarded.
 // --------------------------------------------------------------------------
 using OpFn = std::function<void(const double *, double *)>;
 
