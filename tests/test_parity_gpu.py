@@ -447,3 +447,24 @@ def test_gmres_maxit_reports_noconv(B):
         c.eval_velocity(coefficients=True)
     assert e.value.status == B.BIM_ENOCONV
     c.close()
+
+
+def test_gmres_restarts_reach_the_same_solution(B):
+    """GMRES(m) with short restart cycles (m = 5 and 2) against the
+    unrestarted solve on the two-drop p = 8 workload. Every cycle recomputes
+    the residual b - A x and reuses the Krylov storage and the two slots of the
+    residual estimates, so the solutions must agree to the solve tolerance."""
+    print("gmres restarts", flush=True)
+    wl = W.two_drops(p=8)
+    ref, it0 = None, 0
+    for m in (50, 5, 2):
+        c = ctx_for(B, wl, gmres_restart=m, gmres_tol=1e-12, gmres_maxit=400)
+        u, rep = c.eval_velocity(coefficients=True)
+        c.close()
+        x = np.concatenate([np.ravel(v) for v in u])
+        print("restart", m, "iterations", rep.gmres_iterations, flush=True)
+        if ref is None:
+            ref, it0 = x, rep.gmres_iterations
+        else:
+            assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
+            assert rep.gmres_iterations >= it0
