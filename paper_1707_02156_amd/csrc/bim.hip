@@ -44,7 +44,9 @@ void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, 
 void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
                            const int *sys, const double *cb, const double *hj, double A, int exact, int8_t *reg,
                            double *dist, int *list, int *count);
-void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,
+void launch_drop_h(hipStream_t st, int nd, const double *vol, const double *hfac, double *hj, int *bad);
+void launch_classify_scan(hipStream_t st, const int *count, long nmax, const int *list, int nd, const double *tx,
+                          long tstride,
                           const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
                           int8_t *reg, double *dist);
 void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, const double *cs, const double *xc,
@@ -239,7 +241,7 @@ struct Ctx {
     DBuf xc, gc, fc, gU;
     DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
     DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
-    DBuf tdrop, vol, hj, noff, ncnt;
+    DBuf tdrop, vol, hj, noff, ncnt, hfac, hbad;
     DBuf unoff, uncnt, cbnd1;  // upsampled grids: node offsets, counts, centres and radii
     std::vector<int> sys_h;  // independent system of each drop (bim_set_systems)
     DBuf sysd;
@@ -1066,16 +1068,21 @@ static void build_regions(Ctx &c)
 {
     if (c.regions_ok) return;
     build_nodes(c);
-    std::vector<double> vol(c.nd), h(c.nd);
-    HIPC(hipMemcpyAsync(vol.data(), c.vol.ptr, c.nd * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
-    for (int i = 0; i < c.nd; ++i) {
-        REQUIRE(vol[i] > 0.0 && std::isfinite(vol[i]), BIM_EINVAL, "drop " + std::to_string(i) + " has non-positive volume");
-        const double R = std::cbrt(3.0 * vol[i] / (4.0 * kPi));
-        h[i] = R * kPi / (c.drops[i].p + 1);
-    }
+    // grid spacings from the volumes on the device; the volume check is read
+    // back with the regions (or on its own when there are no drop pairs)
     c.hj.ensure(c.nd * sizeof(double));
-    HIPC(hipMemcpyAsync(c.hj.ptr, h.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    c.hbad.ensure(sizeof(int));
+    launch_drop_h(c.stream, c.nd, c.vol.d(), c.hfac.d(), c.hj.d(), c.hbad.as<int>());
+    int bad = 0;
+    auto check_volumes = [&]() {
+        if (!bad) return;
+        std::vector<double> vol(c.nd);
+        HIPC(hipMemcpyAsync(vol.data(), c.vol.ptr, c.nd * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        for (int i = 0; i < c.nd; ++i)
+            REQUIRE(vol[i] > 0.0 && std::isfinite(vol[i]), BIM_EINVAL,
+                    "drop " + std::to_string(i) + " has non-positive volume");
+    };
     const long nreg = c.T * c.nd;
     c.reg.ensure(nreg);
     c.dist.ensure(nreg * sizeof(double));
@@ -1106,21 +1113,22 @@ static void build_regions(Ctx &c)
                 break;
             }
     if (pairs) {
-        int nscan = 0;
-        HIPC(hipMemcpyAsync(&nscan, c.ccount.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
         {
             ProfScope ps(c, "classify", 0.0, 0.0);
-            launch_classify_scan(c.stream, nscan, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(), c.T,
-                                 c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde, c.reg.as<int8_t>(),
-                                 c.dist.d());
+            launch_classify_scan(c.stream, c.ccount.as<int>(), nreg, c.clist.as<int>(), c.nd, c.tx.d(), c.T, c.tx.d(),
+                                 c.T, c.noff.as<int>(), c.ncnt.as<int>(), c.hj.d(), c.opt.A_tilde,
+                                 c.reg.as<int8_t>(), c.dist.d());
         }
         c.reg_h.resize(nreg);
         HIPC(hipMemcpyAsync(c.reg_h.data(), c.reg.ptr, nreg, hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipMemcpyAsync(&bad, c.hbad.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
     } else {
         c.reg_h.assign(nreg, -1);  // not read without pairs
+        HIPC(hipMemcpyAsync(&bad, c.hbad.ptr, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
     }
+    check_volumes();
     std::vector<double> cb0, cb1;
     if (c.opt.fmm_order != 0 && pairs) {
         cb0.resize(4 * c.nd);
@@ -2029,6 +2037,10 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         HIPC(hipMemcpyAsync(c.tdrop.ptr, tdrop.data(), c.T * sizeof(int), hipMemcpyHostToDevice, c.stream));
         HIPC(hipMemcpyAsync(c.noff.ptr, noff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
         HIPC(hipMemcpyAsync(c.ncnt.ptr, ncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        std::vector<double> hfac(c.nd);
+        for (int i = 0; i < c.nd; ++i) hfac[i] = kPi / (ds[i].p + 1);
+        c.hfac.ensure(c.nd * sizeof(double));
+        HIPC(hipMemcpyAsync(c.hfac.ptr, hfac.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
         c.unoff.ensure(c.nd * sizeof(int));
         c.uncnt.ensure(c.nd * sizeof(int));
         HIPC(hipMemcpyAsync(c.unoff.ptr, unoff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));

@@ -186,17 +186,15 @@ __global__ void k_classify_bound(int T, int nd, const double *__restrict__ tx, l
     if (scan) list[atomicAdd(count, 1)] = (int)idx;
 }
 
-__global__ __launch_bounds__(256) void k_classify_scan(int n, const int *__restrict__ list, int nd,
-                                                       const double *__restrict__ tx, long tstride,
-                                                       const double *__restrict__ sx, long sstride,
-                                                       const int *__restrict__ noff, const int *__restrict__ ncnt,
-                                                       const double *__restrict__ hj, double A,
-                                                       int8_t *__restrict__ reg, double *__restrict__ dist)
+// One list item (target t, drop j) = idx = t nd + j, on one wavefront: the
+// distance from the target to the nearest node of drop j and its region.
+__device__ inline void classify_scan_item(int idx, int nd, const double *__restrict__ tx, long tstride,
+                                          const double *__restrict__ sx, long sstride,
+                                          const int *__restrict__ noff, const int *__restrict__ ncnt,
+                                          const double *__restrict__ hj, double A, int8_t *__restrict__ reg,
+                                          double *__restrict__ dist)
 {
-    const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (wv >= n) return;
-    const int idx = list[wv];
     const int j = idx % nd;
     const int t = idx / nd;
     const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
@@ -213,6 +211,21 @@ __global__ __launch_bounds__(256) void k_classify_scan(int n, const int *__restr
         reg[idx] = (d > A * h) ? 0 : (d > h ? 1 : 2);
         if (dist) dist[idx] = d;
     }
+}
+
+__global__ __launch_bounds__(256) void k_classify_scan(const int *__restrict__ count, const int *__restrict__ list,
+                                                       int nd, const double *__restrict__ tx, long tstride,
+                                                       const double *__restrict__ sx, long sstride,
+                                                       const int *__restrict__ noff, const int *__restrict__ ncnt,
+                                                       const double *__restrict__ hj, double A,
+                                                       int8_t *__restrict__ reg, double *__restrict__ dist)
+{
+    // the list length is read on the device (written by k_classify_bound), so
+    // the host need not wait for it; wavefronts stride over the list
+    const int n = count[0];
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    for (int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv < n; wv += nw)
+        classify_scan_item(list[wv], nd, tx, tstride, sx, sstride, noff, ncnt, hj, A, reg, dist);
 }
 
 // Centre (mean node position) and bounding radius of each drop's standard nodes.
@@ -898,6 +911,28 @@ void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, 
     hipLaunchKernelGGL(k_nodes, dim3(nblk(npts(q))), dim3(256), 0, st, q, syn, wreg, sx, swN, swW, sstride, vol);
 }
 
+// Grid spacing of each drop, h_i = R_i pi / (p_i + 1) with R_i the radius of
+// the sphere of the drop's volume (hfac_i = pi / (p_i + 1)); bad[0] = 1 when a
+// volume is not positive and finite (h_i = 0 then), else 0. One block.
+__global__ __launch_bounds__(256) void k_drop_h(int nd, const double *__restrict__ vol,
+                                                const double *__restrict__ hfac, double *__restrict__ hj, int *bad)
+{
+    int b = 0;
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+        const double v = vol[i];
+        const bool ok = v > 0.0 && isfinite(v);
+        b |= !ok;
+        hj[i] = ok ? cbrt(3.0 * v / (4.0 * 3.14159265358979323846)) * hfac[i] : 0.0;
+    }
+    b = __syncthreads_or(b);
+    if (threadIdx.x == 0) bad[0] = b;
+}
+
+void launch_drop_h(hipStream_t st, int nd, const double *vol, const double *hfac, double *hj, int *bad)
+{
+    hipLaunchKernelGGL(k_drop_h, dim3(1), dim3(256), 0, st, nd, vol, hfac, hj, bad);
+}
+
 void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
                         double *cb)
 {
@@ -912,12 +947,14 @@ void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long
                        cb, hj, A, exact, reg, dist, list, count);
 }
 
-void launch_classify_scan(hipStream_t st, int n, const int *list, int nd, const double *tx, long tstride,
-                          const double *sx, long sstride, const int *noff, const int *ncnt, const double *hj, double A,
-                          int8_t *reg, double *dist)
+// count: device-side list length, at most nmax
+void launch_classify_scan(hipStream_t st, const int *count, long nmax, const int *list, int nd, const double *tx,
+                          long tstride, const double *sx, long sstride, const int *noff, const int *ncnt,
+                          const double *hj, double A, int8_t *reg, double *dist)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_classify_scan, dim3(nblk((long)n * 64)), dim3(256), 0, st, n, list, nd, tx, tstride, sx,
+    if (nmax <= 0) return;
+    const long waves = std::min<long>(nmax, 8192);
+    hipLaunchKernelGGL(k_classify_scan, dim3(nblk(waves * 64)), dim3(256), 0, st, count, list, nd, tx, tstride, sx,
                        sstride, noff, ncnt, hj, A, reg, dist);
 }
 

@@ -468,3 +468,21 @@ def test_gmres_restarts_reach_the_same_solution(B):
         else:
             assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
             assert rep.gmres_iterations >= it0
+
+
+@pytest.mark.parametrize("nd", [1, 2])
+def test_inverted_drop_is_rejected(B, nd):
+    """A drop whose parametrization is turned inside out (x mirrored, so the
+    enclosed volume is negative) is reported as invalid by the evaluation,
+    alone (no drop pairs) and next to a valid drop (drop pairs)."""
+    print("inverted drop, nd", nd, flush=True)
+    bad = W.sphere(8).copy()
+    bad[0] *= -1.0
+    xs = [bad] if nd == 1 else [bad, W.sphere(8, 1.0, (3.0, 0.0, 0.0))]
+    c = B.Context()
+    c.set_drops([8] * nd, xs, [1.0] * nd)
+    c.set_tension(None, 0)
+    with pytest.raises(B.BimError) as e:
+        c.eval_velocity()
+    assert e.value.status == B.BIM_EINVAL and "volume" in str(e.value)
+    c.close()
