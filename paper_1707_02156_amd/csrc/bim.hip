@@ -1166,9 +1166,10 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
             }
         }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
-    if (!keep.empty())
+    if (!keep.empty()) {
         HIPC(hipMemcpyAsync(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
+        HIPC(hipStreamSynchronize(c.stream));  // keep is freed on return
+    }
     e->n = (int)keep.size();
     if (!c.near_h.empty()) {
         std::vector<double> nw(c.near_h.size());
