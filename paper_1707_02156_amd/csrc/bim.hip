@@ -251,6 +251,12 @@ struct Ctx {
     std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
     struct WList {
         std::vector<double> wt;
+        // host images the device copies are made from (kept for the list's
+        // lifetime, so no upload waits; declared before the device buffers,
+        // whose release waits for the device, so they outlive any copy)
+        std::vector<PairWork> h_items;
+        std::vector<double> h_nw;
+        std::vector<FmmPair> h_fp;
         DBuf d;
         int n = 0;
         double pairs = 0.0;  // target-source pairs per application
@@ -1155,7 +1161,7 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
         if (e->wt == wt) return *e;
     auto e = std::make_unique<Ctx::WList>();
     e->wt = wt;
-    std::vector<PairWork> keep;
+    std::vector<PairWork> &keep = e->h_items;
     keep.reserve(c.w0h.size() + c.w1h.size());
     for (int u = 0; u < 2; ++u)
         for (PairWork pw : (u == 0 ? c.w0h : c.w1h)) {
@@ -1166,24 +1172,22 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
             }
         }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
-    if (!keep.empty()) {
+    if (!keep.empty())
         HIPC(hipMemcpyAsync(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));  // keep is freed on return
-    }
     e->n = (int)keep.size();
     if (!c.near_h.empty()) {
-        std::vector<double> nw(c.near_h.size());
+        std::vector<double> &nw = e->h_nw;
+        nw.resize(c.near_h.size());
         for (size_t it = 0; it < nw.size(); ++it) nw[it] = wt[(size_t)c.near_h[it].i * c.nd + c.near_h[it].j];
         e->nw.ensure(nw.size() * sizeof(double));
         HIPC(hipMemcpyAsync(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
     }
     if (!c.fmm.pairs.empty()) {
-        std::vector<FmmPair> fp = c.fmm.pairs;
+        std::vector<FmmPair> &fp = e->h_fp;
+        fp = c.fmm.pairs;
         for (size_t k = 0; k < fp.size(); ++k) fp[k].w = wt[c.fmm.pair_ij[k]];
         e->fp.ensure(fp.size() * sizeof(FmmPair));
         HIPC(hipMemcpyAsync(e->fp.ptr, fp.data(), fp.size() * sizeof(FmmPair), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
     }
     c.wlists.push_back(std::move(e));
     return *c.wlists.back();
