@@ -37,8 +37,7 @@ namespace bim {
 void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, const double *wq, const double *cs,
                     int nf, const double *v, long vstride, double *F, double *coef, long cstride);
 void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f);
-void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, double *sx, double *swN,
-                  double *swW, long sstride, double *vol);
+void launch_nodes(hipStream_t st, const NodeJob *jobs, int n);
 void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
                         double *cb);
 void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
@@ -655,13 +654,15 @@ static void build_nodes(Ctx &c)
         jobs.push_back(syn_job(c, d.p, d.qu, 3, x, c.Ctot, 0x7, c.synbuf.d() + o1[i], n1, 3 * n1));
     }
     syn_run(c, jobs);
+    std::vector<NodeJob> nj;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
-        launch_nodes(c.stream, d.p, c.synbuf.d() + o0[i], grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff,
-                     c.s0N.d() + d.toff, c.s0W.d() + d.toff, c.T, c.vol.d() + i);
-        launch_nodes(c.stream, d.qu, c.synbuf.d() + o1[i], grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
-                     c.s1N.d() + d.uoff, c.s1W.d() + d.uoff, c.S1, nullptr);
+        nj.push_back(NodeJob{c.synbuf.d() + o0[i], grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff, c.s0N.d() + d.toff,
+                             c.s0W.d() + d.toff, c.vol.d() + i, c.T, d.p});
+        nj.push_back(NodeJob{c.synbuf.d() + o1[i], grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
+                             c.s1N.d() + d.uoff, c.s1W.d() + d.uoff, nullptr, c.S1, d.qu});
     }
+    launch_nodes(c.stream, nj.data(), (int)nj.size());
     c.nodes_ok = true;
 }
 

@@ -25,6 +25,21 @@ void rotation_tables(int p, const std::vector<double> &theta, std::vector<double
 double legendre_sum(int q, double t);
 
 // ---- device-side work descriptors ----
+// Quadrature nodes of one drop's grid (k_nodes): the 9 synthesized fields
+// syn, the latitude weights wreg, the outputs at stride sstride and the
+// volume accumulator vol (nullptr: not accumulated).
+struct NodeJob {
+    const double *syn, *wreg;
+    double *sx, *swN, *swW, *vol;
+    long sstride;
+    int q;
+};
+constexpr int kMaxNodeJobs = 32;
+struct NodeJobs {
+    int n;
+    NodeJob j[kMaxNodeJobs];
+};
+
 struct PairWork {
     int tlist_off;  // first entry in the target index list, or the first target (kPairContig)
     int ntgt;       // targets in this item (<= 64)

@@ -105,22 +105,30 @@ __global__ void k_force(int npt, const double *__restrict__ syn, int eos, double
 }
 
 // ----------------------------------------------------------------------------
-// Quadrature nodes of one drop on a degree-q grid: positions, the weighted
+// Quadrature nodes of drop grids (one job per drop and grid, all in one
+// launch) on a degree-q grid: positions, the weighted
 // non-normalized normal wN = w_j (x_theta x x_phi), the weighted area element
 // wW = w_j |x_theta x x_phi|, w_j = (pi/q) w_j^G / sin theta_j (Sec. 2.1).
 // Accumulates the enclosed volume (1/3) sum wN . x into vol[0].
 // syn: 9 fields [x(3), xt(3), xp(3)], npt = 2q(q+1).
 // ----------------------------------------------------------------------------
-__global__ void k_nodes(int q, const double *__restrict__ syn, const double *__restrict__ wreg,
-                        double *__restrict__ sx, double *__restrict__ swN, double *__restrict__ swW, long sstride,
-                        double *__restrict__ vol)
+// Jobs of one launch (blockIdx.y = job): the grids of all drops at once.
+__global__ void k_nodes(NodeJobs jobs)
 {
+    const NodeJob &J = jobs.j[blockIdx.y];
+    const int q = J.q;
     const int npt = npts(q);
+    if ((int)(blockIdx.x * blockDim.x) >= npt) return;  // the whole block is past this grid
+    const double *__restrict__ syn = J.syn;
+    double *__restrict__ sx = J.sx;
+    double *__restrict__ swN = J.swN;
+    const long sstride = J.sstride;
+    double *vol = J.vol;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double contrib = 0.0;
     if (i < npt) {
         auto F = [&](int fld) { return syn[(long)fld * npt + i]; };
-        const double w = wreg[i / (2 * q)];
+        const double w = J.wreg[i / (2 * q)];
         const double at[3] = {F(3), F(4), F(5)};
         const double ap[3] = {F(6), F(7), F(8)};
         const double N[3] = {at[1] * ap[2] - at[2] * ap[1], at[2] * ap[0] - at[0] * ap[2], at[0] * ap[1] - at[1] * ap[0]};
@@ -128,7 +136,7 @@ __global__ void k_nodes(int q, const double *__restrict__ syn, const double *__r
             sx[c * sstride + i] = F(c);
             swN[c * sstride + i] = w * N[c];
         }
-        swW[i] = w * sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        J.swW[i] = w * sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
         contrib = w * (N[0] * F(0) + N[1] * F(1) + N[2] * F(2)) / 3.0;
     }
     if (vol) {
@@ -905,10 +913,18 @@ void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E,
     hipLaunchKernelGGL(k_force, dim3(nblk(npt)), dim3(256), 0, st, npt, syn, eos, E, xs, sigma0, f);
 }
 
-void launch_nodes(hipStream_t st, int q, const double *syn, const double *wreg, double *sx, double *swN,
-                  double *swW, long sstride, double *vol)
+void launch_nodes(hipStream_t st, const NodeJob *jobs, int n)
 {
-    hipLaunchKernelGGL(k_nodes, dim3(nblk(npts(q))), dim3(256), 0, st, q, syn, wreg, sx, swN, swW, sstride, vol);
+    for (int o = 0; o < n; o += kMaxNodeJobs) {
+        NodeJobs b{};
+        b.n = std::min(kMaxNodeJobs, n - o);
+        long maxp = 0;
+        for (int k = 0; k < b.n; ++k) {
+            b.j[k] = jobs[o + k];
+            maxp = std::max(maxp, (long)npts(jobs[o + k].q));
+        }
+        hipLaunchKernelGGL(k_nodes, dim3(nblk(maxp), b.n), dim3(256), 0, st, b);
+    }
 }
 
 // Grid spacing of each drop, h_i = R_i pi / (p_i + 1) with R_i the radius of
