@@ -499,6 +499,164 @@ def test_two_spheres_rigid_translation_zero_exterior_double_layer(orc):
         assert np.abs(D - e).max() < 1e-13
 
 
+# --- far field and the viscosity weight of the double layer -------------------
+#
+# The right-hand side of the equation of Sec. 1 carries 2 u_inf, and the double
+# layer of drop j is weighted by (lambda_j - 1)/(4 pi). The pins below fix both
+# from Stokes flow itself, not from the boundary integral equation.
+
+def _linear_flow():
+    """A divergence-free linear far field u_inf = U0 + G x and its parts
+    G = E + W (E symmetric traceless, W antisymmetric)."""
+    G = np.array([[0.2, 0.7, -0.3], [0.1, -0.5, 0.4], [0.6, -0.2, 0.3]])
+    G[2, 2] = -(G[0, 0] + G[1, 1])
+    U0 = np.array([0.3, -0.4, 0.25])
+    return U0, G, 0.5 * (G + G.T), 0.5 * (G - G.T)
+
+
+@pytest.mark.parametrize("lam", [0.3, 1.0, 5.0])
+def test_uniform_stream_sphere_moves_with_the_stream(orc, lam):
+    """A drop under uniform tension in a uniform stream U0 is carried along
+    rigidly (u = U0 everywhere is a Stokes flow with no disturbance stress),
+    for any viscosity ratio. Reading u_inf (not 2 u_inf) in the equation of
+    Sec. 1 gives u = U0/2."""
+    p = 8
+    U0 = np.array([0.3, -0.2, 0.5])
+    sysm = orc.System([orc.Drop(p, W.sphere(p, 1.1, (0.2, 0.1, -0.3)), lam)],
+                      orc.Options(U0=tuple(U0), gmres_tol=1e-14))
+    uc, it, hist = sysm.solve()
+    assert np.abs(sysm.velocity_grid(uc)[0] - U0).max() < 1e-13
+
+
+def test_uniform_stream_two_spheres_move_with_the_stream(orc):
+    """Two drops of different viscosity ratio in a uniform stream: both move
+    with it (the exterior double layer of a constant density vanishes)."""
+    p = 8
+    U0 = np.array([0.3, -0.2, 0.5])
+    drops = [orc.Drop(p, W.sphere(p, 1.0, (0, 0, 0)), 0.3), orc.Drop(p, W.sphere(p, 0.9, (2.6, 0.3, 0.1)), 5.0)]
+    sysm = orc.System(drops, orc.Options(U0=tuple(U0), gmres_tol=1e-14, U_tilde=8, A_tilde=1e30))
+    uc, it, hist = sysm.solve()
+    for ug in sysm.velocity_grid(uc):
+        assert np.abs(ug - U0).max() < 1e-12
+
+
+@pytest.mark.parametrize("lam", [0.3, 5.0])
+def test_rigid_rotation_far_field(orc, lam):
+    """u_inf = Omega x x (a rigid rotation of the whole fluid) has zero stress,
+    so a drop off the axis turns with it: u = Omega x x at its surface for any
+    lambda. A transposed velocity gradient would reverse Omega."""
+    p = 8
+    Om = np.array([0.4, -0.7, 0.5])
+    G = np.array([[0, -Om[2], Om[1]], [Om[2], 0, -Om[0]], [-Om[1], Om[0], 0]])
+    sysm = orc.System([orc.Drop(p, W.sphere(p, 0.8, (0.5, -0.3, 0.2)), lam)],
+                      orc.Options(gradU=tuple(G.ravel()), gmres_tol=1e-14))
+    uc, it, hist = sysm.solve()
+    x = sysm.nodes(0)
+    assert np.abs(sysm.velocity_grid(uc)[0] - np.cross(Om, x)).max() < 1e-13
+
+
+@pytest.mark.parametrize("lam", [0.3, 1.0, 5.0])
+def test_spherical_drop_in_linear_flow_closed_form(orc, lam):
+    """Spherical drop (centre c, uniform tension) in u_inf = U0 + G x, G = E + W.
+    Matching Lamb-type solutions inside (uniform strain) and outside (strain
+    plus a potential quadrupole and a stresslet) with continuous velocity and
+    traction on the sphere gives the interface velocity
+
+        u = u_inf(c) + W (x - c) + 5/(2 lambda + 3) E (x - c),
+
+    which is u_inf at lambda = 1 and a rigid motion (Faxen) as lambda -> inf."""
+    p = 8
+    U0, G, E, Wm = _linear_flow()
+    c = np.array([0.3, -0.2, 0.1])
+    sysm = orc.System([orc.Drop(p, W.sphere(p, 1.3, c), lam)],
+                      orc.Options(U0=tuple(U0), gradU=tuple(G.ravel()), gmres_tol=1e-14))
+    uc, it, hist = sysm.solve()
+    x = sysm.nodes(0)
+    ex = U0 + G @ c + (x - c) @ Wm.T + 5.0 / (2.0 * lam + 3.0) * (x - c) @ E.T
+    assert np.abs(sysm.velocity_grid(uc)[0] - ex).max() < 1e-13
+
+
+def _rigid_residual(x, u):
+    """Largest deviation of u from its least-squares rigid motion V + w x (x - c)."""
+    r = x - x.mean(0)
+    A = np.zeros((3 * len(x), 6))
+    for k, (a, b, c) in enumerate(r):
+        A[3 * k:3 * k + 3, :3] = np.eye(3)
+        A[3 * k:3 * k + 3, 3:] = [[0, c, -b], [-c, 0, a], [b, -a, 0]]
+    sol, *_ = np.linalg.lstsq(A, u.ravel(), rcond=None)
+    return np.abs(u.ravel() - A @ sol).max()
+
+
+def test_very_viscous_drop_moves_rigidly_next_to_a_drop_of_ratio_one(orc):
+    """Two perturbed drops in shear, lambda = (1, L). As L grows the second
+    drop becomes a rigid body: its velocity approaches a rigid motion at rate
+    1/L. This holds with the double layer of drop j weighted by lambda_j (the
+    source drop). Weighting by the target drop's lambda_i, as the equations
+    of Sec. 1 and 1.2 print it, leaves the drop deforming at O(1) and its
+    velocity growing with L."""
+    p = 8
+    rng = np.random.default_rng(3)
+    xa = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.05)
+    xb = W.perturbed_sphere(rng, p, 0.9, (2.3, 0.2, 0.1), 0.05)
+    G = np.zeros((3, 3))
+    G[0, 1] = 1.0
+    res = {}
+    for rule, L in ((0, 1e2), (0, 1e3), (1, 1e3)):
+        sysm = orc.System([orc.Drop(p, xa, 1.0), orc.Drop(p, xb, L)],
+                          orc.Options(gradU=tuple(G.ravel()), gmres_tol=1e-13, lambda_rule=rule,
+                                      gmres_restart=150, gmres_maxit=400))
+        uc, it, hist = sysm.solve()
+        ub = sysm.velocity_grid(uc)[1]
+        res[(rule, L)] = (_rigid_residual(sysm.nodes(1), ub), np.abs(ub).max())
+    (r2, s2), (r3, s3), (ri, si) = res[(0, 1e2)], res[(0, 1e3)], res[(1, 1e3)]
+    assert r3 < 3e-3 * s3 and 0.07 < r3 / r2 < 0.13 and abs(s3 / s2 - 1) < 0.05
+    assert ri > 0.1 * s3 and si > 20 * s3
+
+
+def test_solution_is_the_trace_of_the_exterior_representation(orc):
+    """Outside every drop the velocity is
+        u(x) = u_inf - 1/(8 pi) sum_j S_j[f] + sum_j (lambda_j - 1)/(8 pi) D_j[u],
+    which, at a point in the fluid, can only weight drop j by its own lambda_j
+    (no target drop exists there). The solved interfacial velocity must be its
+    limit on the surface. The limit is taken by evaluating the representation
+    with the regular rule on 32x upsampled grids at x0 + delta n, delta from
+    h/4 to 7h/8, and extrapolating the polynomial through those values to
+    delta = 0 (no jump relation is used). Two drops, lambda = (1, 5), in a
+    stream with shear: the source-weighted solve meets the limit to the
+    discretisation level of p = 8; the target-weighted solve misses it by
+    percents on the lambda = 5 drop."""
+    p = 8
+    rng = np.random.default_rng(3)
+    xa = W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.05)
+    xb = W.perturbed_sphere(rng, p, 0.9, (2.3, 0.2, 0.1), 0.05)
+    G = np.zeros((3, 3))
+    G[0, 1] = 1.0
+    frac = np.array([0.25, 0.375, 0.5, 0.625, 0.75, 0.875])
+
+    def exterior(s, uc, x):
+        out = s.u_inf(x).copy()
+        for j, d in enumerate(s.drops):
+            out -= orc.regular(d.p, 32 * d.p, d.xc, s.force(j), 0, x) / (8 * np.pi)
+            out += (d.lam - 1) / (8 * np.pi) * orc.regular(d.p, 32 * d.p, d.xc, uc[j], 1, x)
+        return out
+
+    errs = {}
+    for rule, targets in ((0, {0: [5, 77], 1: [40, 120]}), (1, {1: [40, 120]})):
+        s = orc.System([orc.Drop(p, xa, 1.0), orc.Drop(p, xb, 5.0)],
+                       orc.Options(U0=(0.2, -0.1, 0.3), gradU=tuple(G.ravel()), gmres_tol=1e-13, lambda_rule=rule))
+        uc, it, hist = s.solve()
+        ug = s.velocity_grid(uc)
+        for i, tg in targets.items():
+            x, n, Wa, K = orc.geometry(p, s.drops[i].xc, p)
+            ds = s.h(i) * frac
+            for k in tg:
+                v = exterior(s, uc, x[:, k][None, :] + ds[:, None] * n[:, k][None, :])
+                lim = np.linalg.solve(np.vander(ds, len(ds)), v)[-1]
+                errs[(rule, i, k)] = np.abs(lim - ug[i][k]).max() / np.abs(ug[i]).max()
+    assert max(e for (r, i, k), e in errs.items() if r == 0) < 1e-3
+    assert min(e for (r, i, k), e in errs.items() if r == 1) > 2e-2
+
+
 def test_gmres_textbook(orc):
     rng = np.random.default_rng(18)
     n = 60
