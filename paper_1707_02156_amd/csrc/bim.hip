@@ -38,6 +38,7 @@ void launch_analyze(hipStream_t st, int q, int p, int nmax, const double *L, con
                     int nf, const double *v, long vstride, double *F, double *coef, long cstride);
 void launch_force(hipStream_t st, int npt, const double *syn, int eos, double E, double xs, double sigma0, double *f);
 void launch_nodes(hipStream_t st, const NodeJob *jobs, int n);
+void launch_vol_sum(hipStream_t st, int nd, const double *part, const int *off, double *vol);
 void launch_drop_bounds(hipStream_t st, int nd, const double *sx, long sstride, const int *noff, const int *ncnt,
                         double *cb);
 void launch_classify_bound(hipStream_t st, int T, int nd, const double *tx, long tstride, const int *tdrop,
@@ -52,13 +53,16 @@ void launch_rotate(hipStream_t st, int p, const double *Ap, const double *Am, co
                    long xstride, const double *dc, long dstride, double *R);
 void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, const double *Ls, int ldn,
                      const double *wsing, const double *cs, double *out, long ostride, double scale);
-int pair_sources_per_item();
 void launch_near_setup(hipStream_t st, const NearArgs &a);
 void launch_near_interp(hipStream_t st, const NearArgs &a, int kind, const double *selfc, const double *dens,
                         const double *vacc, const double *wts, double *out);
-void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride,
-                 const double *cb32 = nullptr, int nd = 0);
+void launch_pair(hipStream_t st, int kind, int nbig, int nsmall, int tbig, const PairWork *work, const int *tlist,
+                 const double *tx, long tstride, const PairSrc &g0, const PairSrc &g1, double *part,
+                 const float4 *rec0 = nullptr, const float4 *rec1 = nullptr, const double *cb32 = nullptr, int nd = 0);
+void launch_pair_pack32(hipStream_t st, int kind, const void *jobs, int njobs, int maxn, const PairSrc &g,
+                        const double *cb, float4 *rec);
+void launch_pair_gather(hipStream_t st, int nt, int tile, const int *tile_of, const int *toff, const int *tent,
+                        const int *off, const int *ent, const double *part, double *out, long ostride, bool add);
 struct SingArgs {
     int p, qs, nt;
     const double *Ap, *Am, *ApT, *AmT;
@@ -241,13 +245,34 @@ struct Ctx {
     DBuf tx, s0N, s0W, s0d;        // standard-grid nodes [3][T]
     DBuf s1x, s1N, s1W, s1d;       // upsampled nodes [3][S1]
     DBuf tdrop, vol, hj, noff, ncnt, hfac, hbad;
+    DBuf volpart, voloff;  // per-wavefront partial volumes of the standard grids, and each drop's first
+    std::vector<int> voloff_h;
     DBuf unoff, uncnt, cbnd1;  // upsampled grids: node offsets, counts, centres and radii
     std::vector<int> sys_h;  // independent system of each drop (bim_set_systems)
     DBuf sysd;
     DBuf reg, dist, cbnd, clist, ccount;
     bool regions_exact = false;  // distances of every pair computed (bim_regions with dist)
     DBuf tlist;
+    std::vector<int> tlist_h;         // host image of tlist
     std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
+    int pair_ch = 0;                  // sources per pair work item (0: from the pair count)
+    int pair_T = 4;                   // targets per lane of the whole-tile pair items
+    DBuf pair_part;                   // partial sums of the pair work items [item][3][64 pair_T]
+    DBuf pack_jobs, rec32_0, rec32_1; // FP32 source records of the mixed form
+    std::vector<PackJob> pack_h;
+    int pack_n0 = 0, pack_n1 = 0, pack_max0 = 0, pack_max1 = 0;
+    // fixed-order reduction lists of a pair work list (k_pair_gather): per
+    // target tile for the items over contiguous tiles, per target for the
+    // items over index lists
+    struct Gather {
+        std::vector<int> h_toff, h_tent, h_off, h_ent;
+        DBuf toff, tent, off, ent;
+        long nt = 0;
+    };
+    // target tiles of the contiguous pair items: tile of each target, first
+    // target of each tile
+    std::vector<int> tile_of_h, tile_start_h;
+    DBuf tile_of;
     struct WList {
         std::vector<double> wt;
         // host images the device copies are made from (kept for the list's
@@ -257,8 +282,9 @@ struct Ctx {
         std::vector<double> h_nw;
         std::vector<FmmPair> h_fp;
         DBuf d;
-        int n = 0;
+        int n = 0, nbig = 0;  // items; the first nbig are whole tiles, the rest 64-target remainders
         double pairs = 0.0;  // target-source pairs per application
+        Gather g;
         DBuf nw;             // weight of each nearest-region item
         DBuf fp;             // far pairs of the fast summation with their weights
     };
@@ -298,6 +324,9 @@ struct Ctx {
     DBuf near_items, near_par, near_vx, near_vreg, near_Pst, near_vacc, near_self, near_selfc;
     DBuf near_dp, near_dcoff, near_dtoff, near_glt, near_gloff;
     DBuf near_work, near_tl;
+    Gather near_g;        // interpolation points: slots of the pair items
+    Gather near_tg;       // grid targets: their items' interpolated values, near_res [3][items]
+    DBuf near_res;
     int near_nwork = 0;
     long near_ldp = 0;
     double near_pairs = 0.0;
@@ -306,6 +335,7 @@ struct Ctx {
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
     DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt, givbuf;
+    DBuf bcorr, xcorr;  // per-system corrections of a joint solve
     // time step: states, stage velocities and surfactant terms, surface fields and outputs
     DBuf ts_x0, ts_g0, ts_u0, ts_uh, ts_xh, ts_gh, ts_fe, ts_ki, ts_ke, ts_sinv, ts_w, ts_lw, ts_z, ts_syn, ts_grid,
         ts_acc;
@@ -644,7 +674,11 @@ static void build_nodes(Ctx &c)
     syn_layout(c, o0, o1, og, tot);
     c.synbuf.ensure((size_t)tot * sizeof(double));
     c.vol.ensure(c.nd * sizeof(double));
-    HIPC(hipMemsetAsync(c.vol.ptr, 0, c.nd * sizeof(double), c.stream));
+    c.voloff_h.assign(c.nd + 1, 0);
+    for (int i = 0; i < c.nd; ++i) c.voloff_h[i + 1] = c.voloff_h[i] + (npts(c.drops[i].p) + 63) / 64;
+    c.volpart.ensure((size_t)c.voloff_h[c.nd] * sizeof(double));
+    c.voloff.ensure((size_t)(c.nd + 1) * sizeof(int));
+    HIPC(hipMemcpyAsync(c.voloff.ptr, c.voloff_h.data(), (c.nd + 1) * sizeof(int), hipMemcpyHostToDevice, c.stream));
     std::vector<SynJob> jobs;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
@@ -658,11 +692,12 @@ static void build_nodes(Ctx &c)
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
         nj.push_back(NodeJob{c.synbuf.d() + o0[i], grid(c, d.p, d.p).wreg.d(), c.tx.d() + d.toff, c.s0N.d() + d.toff,
-                             c.s0W.d() + d.toff, c.vol.d() + i, c.T, d.p});
+                             c.s0W.d() + d.toff, c.volpart.d() + c.voloff_h[i], c.T, d.p});
         nj.push_back(NodeJob{c.synbuf.d() + o1[i], grid(c, d.qu, d.p).wreg.d(), c.s1x.d() + d.uoff,
                              c.s1N.d() + d.uoff, c.s1W.d() + d.uoff, nullptr, c.S1, d.qu});
     }
     launch_nodes(c.stream, nj.data(), (int)nj.size());
+    launch_vol_sum(c.stream, c.nd, c.volpart.d(), c.voloff.as<int>(), c.vol.d());
     c.nodes_ok = true;
 }
 
@@ -729,6 +764,119 @@ static NearArgs near_args(Ctx &c)
     return a;
 }
 
+// Work-item shape of the pair sums from the pairs of one application:
+// targets per lane T of the whole tiles (4; 1 when even the shortest source
+// runs would leave fewer than kPairItemsMin items, as for two drops of
+// degree 32, where more, smaller items fill the chip better) and the
+// sources per item: about kPairItemsTarget items per application (about 28
+// wavefronts per SIMD: shorter items balance the tail better, down to where
+// the per-item set-up and partial writes start to show), a multiple of 64
+// between 64 and 4096. pair_ch > 0 fixes the sources per item.
+constexpr double kPairItemsTarget = 28672.0, kPairItemsMin = 8192.0;
+constexpr int kPairSmall = 4;  // PairWork.pad: a 64-target remainder item (one target per lane)
+static void pair_shape(Ctx &c, double pairs, int &T, int &ch)
+{
+    T = pairs / (64.0 * 4 * 64) < kPairItemsMin ? 1 : 4;
+    if (c.pair_ch > 0) {
+        ch = c.pair_ch;
+        return;
+    }
+    long n = (long)std::ceil(pairs / (64.0 * T * kPairItemsTarget) / 64.0) * 64;
+    ch = (int)std::min<long>(4096, std::max<long>(64, n));
+}
+
+// Items of (target set, source range): whole tiles of 64 T targets (T > 1),
+// the rest in 64-target remainder items (flag kPairSmall), each split into
+// runs of ch sources; appended to w.
+static void pair_items(std::vector<PairWork> &w, int tl_off, int cnt, bool contig, long soff, int ns, int pair,
+                       int grid, int T, int ch, double wt)
+{
+    for (int a = 0; a < cnt;) {
+        const bool whole = T > 1 && cnt - a >= 64 * T;
+        const int sz = whole ? 64 * T : std::min(64, cnt - a);
+        for (int b = 0; b < ns; b += ch) {
+            PairWork pw;
+            pw.tlist_off = tl_off + a;
+            pw.ntgt = sz;
+            pw.src_off = (int)(soff + b);
+            pw.nsrc = std::min(ch, ns - b);
+            pw.pair = pair;
+            pw.pad = grid | (contig ? kPairContig : 0) | (whole || T == 1 ? 0 : kPairSmall);
+            pw.w = wt;
+            w.push_back(pw);
+        }
+        a += sz;
+    }
+}
+
+// Reduction lists of the items over nt targets (k_pair_gather), for partial
+// blocks of 3 tile doubles per item, uploaded to g: an item over a
+// contiguous tile k adds its base slot minus the tile's first target to tile
+// k's list; an item over an index list adds the slot of each of its targets
+// to that target's list. Both in item order.
+static void gather_lists(Ctx &c, const std::vector<PairWork> &items, const std::vector<int> &tl, long nt, bool tiles,
+                         int tile, Ctx::Gather &g)
+{
+    REQUIRE((double)items.size() * 3 * tile < 2147483647.0, BIM_ENOMEM, "too many pair work items");
+    const size_t ntile = tiles ? c.tile_start_h.size() : 0;
+    g.nt = nt;
+    g.h_toff.assign(ntile + 1, 0);
+    g.h_off.assign(nt + 1, 0);
+    for (const PairWork &w : items) {
+        if (w.pad & kPairContig) {
+            REQUIRE(tiles, BIM_EDEVICE, "contiguous pair item without target tiles");
+            ++g.h_toff[c.tile_of_h[w.tlist_off] + 1];
+        } else {
+            for (int a = 0; a < w.ntgt; ++a) ++g.h_off[tl[w.tlist_off + a] + 1];
+        }
+    }
+    for (size_t k = 0; k < ntile; ++k) g.h_toff[k + 1] += g.h_toff[k];
+    for (long t = 0; t < nt; ++t) g.h_off[t + 1] += g.h_off[t];
+    g.h_tent.resize(g.h_toff[ntile]);
+    g.h_ent.resize(g.h_off[nt]);
+    std::vector<int> tpos(g.h_toff.begin(), g.h_toff.end() - 1), pos(g.h_off.begin(), g.h_off.end() - 1);
+    for (size_t it = 0; it < items.size(); ++it) {
+        const PairWork &w = items[it];
+        const int base = (int)it * 3 * tile;
+        if (w.pad & kPairContig) {
+            const int k = c.tile_of_h[w.tlist_off];
+            REQUIRE(c.tile_start_h[k] == w.tlist_off, BIM_EDEVICE, "pair item not aligned to its target tile");
+            g.h_tent[tpos[k]++] = base - w.tlist_off;
+        } else {
+            for (int a = 0; a < w.ntgt; ++a) g.h_ent[pos[tl[w.tlist_off + a]]++] = base + a;
+        }
+    }
+    auto up = [&](DBuf &d, const std::vector<int> &h) {
+        d.ensure(std::max<size_t>(1, h.size()) * sizeof(int));
+        if (!h.empty()) HIPC(hipMemcpyAsync(d.ptr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    };
+    up(g.toff, g.h_toff);
+    up(g.tent, g.h_tent);
+    up(g.off, g.h_off);
+    up(g.ent, g.h_ent);
+    c.pair_part.ensure(std::max<size_t>(1, items.size()) * 3 * tile * sizeof(double));
+}
+
+// Target tiles of each drop's consecutive targets, split as pair_items
+// splits a contiguous target set: whole tiles of 64 T, then tiles of 64.
+static void target_tiles(Ctx &c, int T)
+{
+    c.tile_of_h.resize(std::max<long>(1, c.T));
+    c.tile_start_h.clear();
+    for (const Drop &d : c.drops) {
+        const int nt = npts(d.p);
+        for (int a = 0; a < nt;) {
+            const int sz = T > 1 && nt - a >= 64 * T ? 64 * T : std::min(64, nt - a);
+            c.tile_start_h.push_back((int)(d.toff + a));
+            for (int b = a; b < a + sz; ++b) c.tile_of_h[d.toff + b] = (int)c.tile_start_h.size() - 1;
+            a += sz;
+        }
+    }
+    c.tile_of.ensure(c.tile_of_h.size() * sizeof(int));
+    HIPC(hipMemcpyAsync(c.tile_of.ptr, c.tile_of_h.data(), c.tile_of_h.size() * sizeof(int), hipMemcpyHostToDevice,
+                        c.stream));
+}
+
 static void near_setup(Ctx &c)
 {
     c.near_src.assign(c.nd, 0);
@@ -779,9 +927,10 @@ static void near_setup(Ctx &c)
     HIPC(hipMemcpyAsync(vreg.data(), c.near_vreg.ptr, V, hipMemcpyDeviceToHost, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
     // work list: interpolation points grouped by (source drop, grid)
-    const int TILE = 64, CH = pair_sources_per_item();
     std::vector<int> tl;
     std::vector<PairWork> w;
+    std::vector<std::pair<int, int>> runs;  // (start in tl, count) per (source drop, grid)
+    double npairs = 0.0;
     for (int j = 0; j < c.nd; ++j) {
         if (!c.near_src[j]) continue;
         const Drop &dj = c.drops[j];
@@ -792,32 +941,47 @@ static void near_setup(Ctx &c)
                 for (int l = 0; l < L; ++l)
                     if (vreg[(long)it * L + l] == g) tl.push_back(it * L + l);
             }
-            const int cnt = (int)tl.size() - start;
-            const long soff = g == 0 ? dj.toff : dj.uoff;
-            const int ns = g == 0 ? npts(dj.p) : npts(dj.qu);
-            for (int a = 0; a < cnt; a += TILE)
-                for (int b = 0; b < ns; b += CH) {
-                    PairWork pw;
-                    pw.tlist_off = start + a;
-                    pw.ntgt = std::min(TILE, cnt - a);
-                    pw.src_off = (int)(soff + b);
-                    pw.nsrc = std::min(CH, ns - b);
-                    pw.pair = j;
-                    pw.pad = g;
-                    pw.w = 1.0;
-                    w.push_back(pw);
-                    c.near_pairs += (double)pw.ntgt * pw.nsrc;
-                }
+            runs.emplace_back(start, (int)tl.size() - start);
+            npairs += (double)runs.back().second * (g == 0 ? npts(dj.p) : npts(dj.qu));
         }
     }
+    int Tn = 1, CH = 64;
+    pair_shape(c, npairs, Tn, CH);
+    size_t r = 0;
+    for (int j = 0; j < c.nd; ++j) {
+        if (!c.near_src[j]) continue;
+        const Drop &dj = c.drops[j];
+        for (int g = 0; g < 2; ++g, ++r) {
+            const long soff = g == 0 ? dj.toff : dj.uoff;
+            const int ns = g == 0 ? npts(dj.p) : npts(dj.qu);
+            pair_items(w, runs[r].first, runs[r].second, false, soff, ns, j, g, 1, CH, 1.0);
+        }
+    }
+    for (const PairWork &pw : w) c.near_pairs += (double)pw.ntgt * pw.nsrc;
     c.near_tl.ensure(std::max<size_t>(1, tl.size()) * sizeof(int));
     c.near_work.ensure(std::max<size_t>(1, w.size()) * sizeof(PairWork));
     if (!tl.empty())
         HIPC(hipMemcpyAsync(c.near_tl.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
     if (!w.empty())
         HIPC(hipMemcpyAsync(c.near_work.ptr, w.data(), w.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipStreamSynchronize(c.stream));
+    gather_lists(c, w, tl, V, false, 64, c.near_g);
+    {
+        // each item's interpolated value goes to its grid target, items in order
+        Ctx::Gather &g = c.near_tg;
+        g.nt = c.T;
+        g.h_off.assign(c.T + 1, 0);
+        for (const NearItem &it : c.near_h) ++g.h_off[it.t + 1];
+        for (long t = 0; t < c.T; ++t) g.h_off[t + 1] += g.h_off[t];
+        g.h_ent.resize(n);
+        std::vector<int> pos(g.h_off.begin(), g.h_off.end() - 1);
+        for (int it = 0; it < n; ++it) g.h_ent[pos[c.near_h[it].t]++] = it;
+        g.off.ensure((c.T + 1) * sizeof(int));
+        g.ent.ensure(std::max<size_t>(1, n) * sizeof(int));
+        HIPC(hipMemcpyAsync(g.off.ptr, g.h_off.data(), (c.T + 1) * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        HIPC(hipMemcpyAsync(g.ent.ptr, g.h_ent.data(), n * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        c.near_res.ensure((size_t)3 * n * sizeof(double));
+    }
+    HIPC(hipStreamSynchronize(c.stream));
     c.near_nwork = (int)w.size();
 }
 
@@ -920,7 +1084,16 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     std::vector<int> tl, k0, k1;
     std::vector<PairWork> w0, w1;
     std::vector<NearItem> near;
-    const int TILE = 64, CH = pair_sources_per_item();
+    // (target set, source range) segments, split into work items once the
+    // total pair count (and with it the items' source run) is known
+    struct Seg {
+        int tl_off, cnt;
+        bool contig;
+        long soff;
+        int ns, pair, grid;
+    };
+    std::vector<Seg> segs;
+    double npairs = 0.0;
     c.n_om1 = c.n_om2 = 0;
     for (int i = 0; i < c.nd; ++i) {
         const Drop &di = c.drops[i];
@@ -967,18 +1140,8 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
                 if (ru == 1) c.n_om1 += nti;
                 const long soff = ru == 0 ? dj.toff : dj.uoff;
                 const int ns = ru == 0 ? npts(dj.p) : npts(dj.qu);
-                for (int a = 0; a < nti; a += TILE)
-                    for (int b = 0; b < ns; b += CH) {
-                        PairWork pw;
-                        pw.tlist_off = (int)(di.toff + a);
-                        pw.ntgt = std::min(TILE, nti - a);
-                        pw.src_off = (int)(soff + b);
-                        pw.nsrc = std::min(CH, ns - b);
-                        pw.pair = i * c.nd + j;
-                        pw.pad = ru | kPairContig;
-                        pw.w = 0.0;
-                        (ru == 0 ? w0 : w1).push_back(pw);
-                    }
+                segs.push_back(Seg{(int)di.toff, nti, true, soff, ns, i * c.nd + j, ru});
+                npairs += (double)nti * ns;
                 continue;
             }
             // one pass over i's targets: region 0 to the standard grid, 1 (and 2 by
@@ -1007,25 +1170,22 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
                 const int cnt = (int)kl.size();
                 const long soff = kind == 0 ? dj.toff : dj.uoff;
                 const int ns = kind == 0 ? npts(dj.p) : npts(dj.qu);
-                for (int a = 0; a < cnt; a += TILE)
-                    for (int b = 0; b < ns; b += CH) {
-                        PairWork pw;
-                        pw.tlist_off = start + a;
-                        pw.ntgt = std::min(TILE, cnt - a);
-                        pw.src_off = (int)(soff + b);
-                        pw.nsrc = std::min(CH, ns - b);
-                        pw.pair = i * c.nd + j;
-                        pw.pad = kind;
-                        pw.w = 0.0;
-                        (kind == 0 ? w0 : w1).push_back(pw);
-                    }
+                if (cnt == 0) continue;
+                segs.push_back(Seg{start, cnt, false, soff, ns, i * c.nd + j, kind});
+                npairs += (double)cnt * ns;
             }
         }
     }
+    int CH = 64;
+    pair_shape(c, npairs, c.pair_T, CH);
+    target_tiles(c, c.pair_T);
+    for (const Seg &g : segs)
+        pair_items(g.grid == 0 ? w0 : w1, g.tl_off, g.cnt, g.contig, g.soff, g.ns, g.pair, g.grid, c.pair_T, CH, 0.0);
     c.tlist.ensure(std::max<size_t>(1, tl.size()) * sizeof(int));
     if (!tl.empty())
         HIPC(hipMemcpyAsync(c.tlist.ptr, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
     HIPC(hipStreamSynchronize(c.stream));
+    c.tlist_h = std::move(tl);
     if (!F.pairs.empty()) fmm_setup(c, cb0, cb1);
     c.w0h = std::move(w0);
     c.w1h = std::move(w1);
@@ -1164,18 +1324,23 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
     e->wt = wt;
     std::vector<PairWork> &keep = e->h_items;
     keep.reserve(c.w0h.size() + c.w1h.size());
-    for (int u = 0; u < 2; ++u)
-        for (PairWork pw : (u == 0 ? c.w0h : c.w1h)) {
-            pw.w = wt[pw.pair];
-            if (pw.w != 0.0) {
-                keep.push_back(pw);
-                e->pairs += (double)pw.ntgt * pw.nsrc;
+    for (int small = 0; small < 2; ++small) {  // whole-tile items first, then the remainders
+        for (int u = 0; u < 2; ++u)
+            for (PairWork pw : (u == 0 ? c.w0h : c.w1h)) {
+                if (((pw.pad & kPairSmall) != 0) != (small != 0)) continue;
+                pw.w = wt[pw.pair];
+                if (pw.w != 0.0) {
+                    keep.push_back(pw);
+                    e->pairs += (double)pw.ntgt * pw.nsrc;
+                }
             }
-        }
+        if (!small) e->nbig = (int)keep.size();
+    }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
     if (!keep.empty())
         HIPC(hipMemcpyAsync(e->d.ptr, keep.data(), keep.size() * sizeof(PairWork), hipMemcpyHostToDevice, c.stream));
     e->n = (int)keep.size();
+    gather_lists(c, keep, c.tlist_h, c.T, true, 64 * c.pair_T, e->g);
     if (!c.near_h.empty()) {
         std::vector<double> &nw = e->h_nw;
         nw.resize(c.near_h.size());
@@ -1220,6 +1385,31 @@ static void run_fmm(Ctx &c, int kind, Ctx::WList &L)
 
 // Pair sums with weight table wt, added into acc: one launch over the items
 // of both source grids.
+// FP32 source records of both grids for the mixed form (every drop's nodes,
+// relative to its centre), from the current densities.
+static void pack32(Ctx &c, int kind, const PairSrc &g0, const PairSrc &g1)
+{
+    if (c.pack_h.empty()) {
+        for (int g = 0; g < 2; ++g)
+            for (int j = 0; j < c.nd; ++j) {
+                const Drop &d = c.drops[j];
+                const int n = g == 0 ? npts(d.p) : npts(d.qu);
+                c.pack_h.push_back(PackJob{g == 0 ? d.toff : d.uoff, n, j});
+                (g == 0 ? c.pack_max0 : c.pack_max1) = std::max(g == 0 ? c.pack_max0 : c.pack_max1, n);
+            }
+        c.pack_n0 = c.pack_n1 = c.nd;
+        c.pack_jobs.ensure(c.pack_h.size() * sizeof(PackJob));
+        HIPC(hipMemcpyAsync(c.pack_jobs.ptr, c.pack_h.data(), c.pack_h.size() * sizeof(PackJob),
+                            hipMemcpyHostToDevice, c.stream));
+        c.rec32_0.ensure((size_t)std::max<long>(1, c.T) * 3 * sizeof(float4));
+        c.rec32_1.ensure((size_t)std::max<long>(1, c.S1) * 3 * sizeof(float4));
+    }
+    launch_pair_pack32(c.stream, kind, c.pack_jobs.as<PackJob>(), c.pack_n0, c.pack_max0, g0, c.cbnd.d(),
+                       c.rec32_0.as<float4>());
+    launch_pair_pack32(c.stream, kind, c.pack_jobs.as<PackJob>() + c.pack_n0, c.pack_n1, c.pack_max1, g1, c.cbnd.d(),
+                       c.rec32_1.as<float4>());
+}
+
 static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
 {
     Ctx::WList &L = work_lists(c, wt);
@@ -1227,9 +1417,20 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
     ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
-    const bool f32 = c.opt.precision == BIM_PREC_MIXED;
-    launch_pair(c.stream, kind, L.n, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0, g1, c.acc.d(), c.T,
-                f32 ? c.cbnd.d() : nullptr, c.nd);
+    if (L.n > 0) {
+        const int nb = L.nbig, ns = L.n - L.nbig;
+        if (c.opt.precision == BIM_PREC_MIXED) {
+            pack32(c, kind, g0, g1);
+            launch_pair(c.stream, kind, nb, ns, c.pair_T, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0,
+                        g1, c.pair_part.d(), c.rec32_0.as<float4>(), c.rec32_1.as<float4>(), c.cbnd.d(), c.nd);
+        } else {
+            launch_pair(c.stream, kind, nb, ns, c.pair_T, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0,
+                        g1, c.pair_part.d());
+        }
+        launch_pair_gather(c.stream, (int)c.T, 64 * c.pair_T, c.tile_of.as<int>(), L.g.toff.as<int>(),
+                           L.g.tent.as<int>(), L.g.off.as<int>(), L.g.ent.as<int>(), c.pair_part.d(), c.acc.d(), c.T,
+                           true);
+    }
     run_fmm(c, kind, L);
 }
 
@@ -1253,9 +1454,14 @@ static void run_near(Ctx &c, int kind, const double *dens, const std::vector<dou
     ProfScope ps(c, "near", c.near_pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
-    launch_pair(c.stream, kind, c.near_nwork, c.near_work.as<PairWork>(), c.near_tl.as<int>(), c.near_vx.d(), V, g0,
-                g1, c.near_vacc.d(), V);
-    launch_near_interp(c.stream, near_args(c), kind, c.near_selfc.d(), dens, c.near_vacc.d(), L.nw.d(), c.acc.d());
+    launch_pair(c.stream, kind, c.near_nwork, 0, 1, c.near_work.as<PairWork>(), c.near_tl.as<int>(), c.near_vx.d(), V,
+                g0, g1, c.pair_part.d());
+    launch_pair_gather(c.stream, (int)V, 64, nullptr, nullptr, nullptr, c.near_g.off.as<int>(),
+                       c.near_g.ent.as<int>(), c.pair_part.d(), c.near_vacc.d(), V, false);
+    launch_near_interp(c.stream, near_args(c), kind, c.near_selfc.d(), dens, c.near_vacc.d(), L.nw.d(),
+                       c.near_res.d());
+    launch_pair_gather(c.stream, (int)c.T, (int)c.near_h.size(), nullptr, nullptr, nullptr, c.near_tg.off.as<int>(),
+                       c.near_tg.ent.as<int>(), c.near_res.d(), c.acc.d(), c.T, true);
 }
 
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
@@ -1824,6 +2030,8 @@ static void invalidate(Ctx &c)
 {
     c.nodes_ok = c.force_ok = c.regions_ok = false;
     c.regions_exact = false;
+    c.pack_h.clear();
+    c.pack_max0 = c.pack_max1 = 0;
     std::fill(c.Mok.begin(), c.Mok.end(), 0);
 }
 
@@ -2649,6 +2857,72 @@ int bim_apply_double_layer(bim_ctx h, const double *u_coef, double *out, int mod
     });
 }
 
+// (a correction's tolerance relative to its own right-hand side is floored
+// like the joint solve's)
+constexpr double kTolFloorCorr = 1e-14;
+
+// Per-system check of a joint solve of independent systems: r = b - A x,
+// and for every system whose own relative residual ||r_s|| / ||b_s|| is
+// above tol, a GMRES solve of A d = r restricted to that system (zero
+// elsewhere) to tol ||b_s|| / ||r_s||, then x += d. hb is the host image of
+// b. relres becomes the largest per-system residual of the final check.
+static int correct_systems(Ctx &c, const std::vector<double> &wt, const std::vector<double> &hb, double tol,
+                           int &iters, double &relres, int &nmv)
+{
+    const long n = 3 * c.Ctot;
+    std::vector<double> hax(n), hr(n);
+    c.bcorr.ensure((size_t)n * sizeof(double));
+    c.xcorr.ensure((size_t)n * sizeof(double));
+    auto residuals = [&](std::map<int, std::pair<double, double>> &rs) {
+        apply_operator(c, c.xsol.d(), c.bcorr.d(), wt);
+        ++nmv;
+        HIPC(hipMemcpyAsync(hax.data(), c.bcorr.ptr, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPC(hipStreamSynchronize(c.stream));
+        rs.clear();
+        for (int i = 0; i < c.nd; ++i) {
+            auto &e = rs[c.sys_h[i]];
+            for (int comp = 0; comp < 3; ++comp)
+                for (long k = 0; k < 2L * ncoef(c.drops[i].p); ++k) {
+                    const long idx = comp * c.Ctot + c.drops[i].coff + k;
+                    hr[idx] = hb[idx] - hax[idx];
+                    e.first += hr[idx] * hr[idx];
+                    e.second += hb[idx] * hb[idx];
+                }
+        }
+    };
+    std::map<int, std::pair<double, double>> rs;
+    residuals(rs);
+    int rc = BIM_OK;
+    bool corrected = false;
+    for (auto &kv : rs) {
+        const double rn = std::sqrt(kv.second.first), bn = std::sqrt(kv.second.second);
+        if (rn <= tol * bn) continue;
+        std::vector<double> rsys(n, 0.0);
+        for (int i = 0; i < c.nd; ++i) {
+            if (c.sys_h[i] != kv.first) continue;
+            for (int comp = 0; comp < 3; ++comp)
+                for (long k = 0; k < 2L * ncoef(c.drops[i].p); ++k) {
+                    const long idx = comp * c.Ctot + c.drops[i].coff + k;
+                    rsys[idx] = hr[idx];
+                }
+        }
+        HIPC(hipMemcpyAsync(c.bcorr.ptr, rsys.data(), n * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        int it = 0, mv = 0;
+        double rr = 0.0;
+        const int r1 = gmres(c, c.bcorr.d(), c.xcorr.d(), wt, std::max(tol * bn / rn, kTolFloorCorr), it, rr, mv);
+        iters += it;
+        nmv += mv;
+        if (r1 != BIM_OK) rc = r1;
+        launch_scale_add(c.stream, n, 1.0, c.xcorr.d(), 1.0, c.xsol.d());
+        corrected = true;
+    }
+    if (corrected) residuals(rs);
+    relres = 0.0;
+    for (auto &kv : rs)
+        if (kv.second.second > 0.0) relres = std::max(relres, std::sqrt(kv.second.first / kv.second.second));
+    return rc;
+}
+
 // Velocity solve at the current drop and surfactant state: geometry, force,
 // single layer, right-hand side and GMRES on the second-kind operator; the
 // velocity coefficients are left in c.xsol [3][Ctot].
@@ -2682,12 +2956,20 @@ static int solve_velocity(Ctx &c, int &iters, double &relres, int &nmv)
     } else {
         // independent systems in one solve: a tolerance scaled by
         // min_s ||b_s|| / ||b|| bounds every system's own relative
-        // residual by gmres_tol (||r_s|| <= ||r||)
-        double tol = c.opt.gmres_tol, bound = 1.0;
+        // residual by gmres_tol (||r_s|| <= ||r||). It is floored at
+        // kTolFloor, below which rounding stalls GMRES; when the floor
+        // applies, every system's residual is checked afterwards and those
+        // above gmres_tol are corrected by their own solves (the operator
+        // does not couple systems, so a right-hand side that is zero outside
+        // one system keeps every Krylov vector there)
+        constexpr double kTolFloor = 1e-14;
+        const double tol = c.opt.gmres_tol;
+        double bound = 1.0;
         std::map<int, double> bs;
         for (int i = 0; i < c.nd; ++i) bs[c.sys_h[i]] = 0.0;
+        std::vector<double> hb;
         if (bs.size() > 1) {
-            std::vector<double> hb(n);
+            hb.resize(n);
             HIPC(hipMemcpyAsync(hb.data(), c.bvec.ptr, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
             HIPC(hipStreamSynchronize(c.stream));
             double tot = 0.0;
@@ -2701,13 +2983,13 @@ static int solve_velocity(Ctx &c, int &iters, double &relres, int &nmv)
             double bmin = 0.0;
             for (auto &kv : bs)
                 if (kv.second > 0.0 && (bmin == 0.0 || kv.second < bmin)) bmin = kv.second;
-            if (bmin > 0.0 && tot > 0.0) {
-                bound = std::sqrt(tot / bmin);
-                tol /= bound;
-            }
+            if (bmin > 0.0 && tot > 0.0) bound = std::sqrt(tot / bmin);
         }
-        rc = gmres(c, c.bvec.d(), c.xsol.d(), dl_weights(c), tol, iters, relres, nmv);
+        const std::vector<double> wt = dl_weights(c);
+        const bool floored = tol / bound < kTolFloor;
+        rc = gmres(c, c.bvec.d(), c.xsol.d(), wt, floored ? kTolFloor : tol / bound, iters, relres, nmv);
         relres *= bound;
+        if (floored && rc == BIM_OK) rc = correct_systems(c, wt, hb, tol, iters, relres, nmv);
     }
     return rc;
 }

@@ -40,9 +40,12 @@ struct NodeJobs {
     NodeJob j[kMaxNodeJobs];
 };
 
+// Pair sums: a work item is one wavefront's run of sources of one grid
+// against up to 64 T targets (T per lane: the launch's T for whole tiles, 1
+// for the remainders of a target set).
 struct PairWork {
     int tlist_off;  // first entry in the target index list, or the first target (kPairContig)
-    int ntgt;       // targets in this item (<= 64)
+    int ntgt;       // targets in this item (<= 64 T)
     int src_off;    // first source node in the source arrays
     int nsrc;       // source nodes in this item
     int pair;       // target drop * n_drops + source drop
@@ -157,6 +160,11 @@ struct NearArgs {
 struct PairSrc {
     const double *x, *wN, *wW, *d;
     long stride;
+};
+// Nodes [off, off + n) of drop `drop` in one source grid (FP32 record packing).
+struct PackJob {
+    long off;
+    int n, drop;
 };
 
 // Fast summation of far drop pairs (kernels_fmm.hip). Expansion order P <=

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace bim {
 
 static constexpr double kInvSqrt4Pi = 0.28209479177387814347;
@@ -109,7 +111,9 @@ __global__ void k_force(int npt, const double *__restrict__ syn, int eos, double
 // launch) on a degree-q grid: positions, the weighted
 // non-normalized normal wN = w_j (x_theta x x_phi), the weighted area element
 // wW = w_j |x_theta x x_phi|, w_j = (pi/q) w_j^G / sin theta_j (Sec. 2.1).
-// Accumulates the enclosed volume (1/3) sum wN . x into vol[0].
+// The enclosed volume (1/3) sum wN . x of the job's grid goes to vol as one
+// partial sum per wavefront, vol[i / 64] for the wavefront of node i (vol may
+// be null); k_vol_sum adds them in order.
 // syn: 9 fields [x(3), xt(3), xp(3)], npt = 2q(q+1).
 // ----------------------------------------------------------------------------
 // Jobs of one launch (blockIdx.y = job): the grids of all drops at once.
@@ -140,9 +144,10 @@ __global__ void k_nodes(NodeJobs jobs)
         contrib = w * (N[0] * F(0) + N[1] * F(1) + N[2] * F(2)) / 3.0;
     }
     if (vol) {
-        // wavefront reduction, one atomic per wave
+        // wavefront reduction, one partial per wavefront (fixed order)
         for (int o = 32; o > 0; o >>= 1) contrib += __shfl_down(contrib, o, 64);
-        if ((threadIdx.x & 63) == 0 && contrib != 0.0) atomicAdd(vol, contrib);
+        const int w0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+        if ((threadIdx.x & 63) == 0 && w0 < npt) vol[w0 >> 6] = contrib;
     }
 }
 
@@ -460,197 +465,277 @@ __global__ __launch_bounds__(256) void k_singular(int p, int qs, int kind, const
 
 // ----------------------------------------------------------------------------
 // Pair sums (Sec. 1 kernels by the regular rule of Sec. 2.1 on the standard
-// or upsampled grid of a source drop, Sec. 2.3). One block per work item: up
-// to 64 targets (one per lane, from an index list) against a range of sources
-// of one grid, staged through LDS in tiles of 256; the four wavefronts of the
-// block take a quarter of each tile and combine before the atomic add.
-// kind 0 (SL): sum wW G(x0, x) f;   kind 1 (DL): sum -6 xh (xh.u)(xh.wN) / r^5.
-// Results are added atomically: out[c][t] += w * sum.
+// or upsampled grid of a source drop, Sec. 2.3).
+//   kind 0 (SL): sum wW G(x0, x) f = sum wW (f / r + h (h.f) / r^3);
+//   kind 1 (DL): sum -6 h (h.u)(h.wN) / r^5,   h = x0 - x.
+// One wavefront per work item: up to 64 T targets, T per lane, against a run
+// of sources of one grid. The sources are the same for every lane, so they
+// are read through the scalar data path (constant address space: SGPR
+// operands of the VALU instructions) and each one feeds T pairs per lane,
+// with no LDS staging and no barriers. Item i of a launch writes w * sum for
+// each of its target slots into its own block of the partial buffer,
+// part[(item0 + i) * 3 * tile + c * tile + slot]; k_pair_gather then adds the
+// slots of each target in a fixed order, so the sums do not depend on
+// scheduling. Items of whole tiles run with T = the tile's targets per lane,
+// the 64-target remainders of a target set with T = 1.
 // ----------------------------------------------------------------------------
-constexpr int kPairSrc = 256;        // sources per LDS tile
-constexpr int kPairItem = kPairSrc;      // sources per work item (more items beat longer ones here)
+constexpr int kPairWaves = 4;  // wavefronts (independent items) per block
 
-template <int KIND>
-__global__ __launch_bounds__(256) void k_pair(const PairWork *__restrict__ work, const int *__restrict__ tlist,
-                                              const double *__restrict__ tx, long tstride, PairSrc g0, PairSrc g1,
-                                              double *__restrict__ out, long ostride)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) f32x4 cf32x4;
+__device__ inline cdouble *scalar_ptr(const double *p) { return (cdouble *)p; }
+__device__ inline cf32x4 *scalar_ptr(const float4 *p) { return (cf32x4 *)p; }
+
+// Target a of an item, clamped to the item's last target (surplus lanes
+// evaluate a duplicate and their slot is never read).
+__device__ inline int pair_target(const PairWork &w, const int *__restrict__ tlist, int a)
 {
-    // source record in LDS, weights folded in when staged:
-    //   DL (x,y)(z,u0)(u1,u2)(-6 wN0,-6 wN1)(-6 wN2,-)   SL (x,y)(z,wW f0)(wW f1,wW f2)
-    constexpr int NP = KIND == 0 ? 3 : 5;
-    __shared__ double2 sh[kPairSrc][NP];
-    __shared__ double red[3][3][64];
-    const PairWork w = work[blockIdx.x];
+    a = a < w.ntgt ? a : w.ntgt - 1;
+    return (w.pad & kPairContig) ? w.tlist_off + a : tlist[w.tlist_off + a];
+}
+
+template <int KIND, int T>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
+                                                         int tile, const int *__restrict__ tlist,
+                                                         const double *__restrict__ tx, long tstride, PairSrc g0,
+                                                         PairSrc g1, double *__restrict__ part)
+{
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
+    if (item >= nwork) return;
+    const PairWork w = work[item];
+    const int lane = threadIdx.x & 63;
+    double X[T], Y[T], Z[T], A0[T], A1[T], A2[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int t = pair_target(w, tlist, lane + 64 * k);
+        X[k] = tx[t];
+        Y[k] = tx[tstride + t];
+        Z[k] = tx[2 * tstride + t];
+        A0[k] = A1[k] = A2[k] = 0.0;
+    }
     const PairSrc &G = (w.pad & 1) ? g1 : g0;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool active = lane < w.ntgt;
-    const int t = (w.pad & kPairContig) ? w.tlist_off + (active ? lane : 0)
-                                        : (active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off]);
-    const double x0 = tx[t], y0 = tx[tstride + t], z0 = tx[2 * tstride + t];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int s0 = 0; s0 < w.nsrc; s0 += kPairSrc) {
-        const int ns = min(kPairSrc, w.nsrc - s0);
-        if (s0) __syncthreads();
-        for (int i = threadIdx.x; i < ns; i += 256) {
-            const long s = (long)w.src_off + s0 + i;
-            const long st = G.stride;
-            sh[i][0] = make_double2(G.x[s], G.x[st + s]);
-            if (KIND == 0) {
-                const double ww = G.wW[s];
-                sh[i][1] = make_double2(G.x[2 * st + s], ww * G.d[s]);
-                sh[i][2] = make_double2(ww * G.d[st + s], ww * G.d[2 * st + s]);
-            } else {
-                sh[i][1] = make_double2(G.x[2 * st + s], G.d[s]);
-                sh[i][2] = make_double2(G.d[st + s], G.d[2 * st + s]);
-                sh[i][3] = make_double2(-6.0 * G.wN[s], -6.0 * G.wN[st + s]);
-                sh[i][4] = make_double2(-6.0 * G.wN[2 * st + s], 0.0);
-            }
+    const long st = G.stride, o = w.src_off;
+    cdouble *sx = scalar_ptr(G.x + o), *sy = scalar_ptr(G.x + st + o), *sz = scalar_ptr(G.x + 2 * st + o);
+    cdouble *d0 = scalar_ptr(G.d + o), *d1 = scalar_ptr(G.d + st + o), *d2 = scalar_ptr(G.d + 2 * st + o);
+    cdouble *n0 = scalar_ptr((KIND == 0 ? G.wW : G.wN) + o), *n1 = scalar_ptr(G.wN + st + o),
+            *n2 = scalar_ptr(G.wN + 2 * st + o);
+    // r^-1: the hardware reciprocal square root (about 22 correct bits; r2 > 0
+    // for every pair of distinct drops, overlapping drops are rejected at input)
+    // refined by one Newton step y (1 + e/2), e = 1 - r2 y^2, which leaves a
+    // relative error of about 1.5 e^2 < 1e-12 (4 instructions; a third-order
+    // step would take 5 of the 24 FP64 VALU instructions of a pair for
+    // accuracy far below the 1e-10 the sums are held to)
+#pragma unroll 2
+    for (int s = 0; s < w.nsrc; ++s) {
+        const double px = sx[s], py = sy[s], pz = sz[s];
+        double u0 = d0[s], u1 = d1[s], u2 = d2[s], m0 = 0.0, m1 = 0.0, m2 = 0.0;
+        if (KIND == 0) {
+            const double ww = n0[s];
+            u0 *= ww;
+            u1 *= ww;
+            u2 *= ww;
+        } else {
+            m0 = n0[s];
+            m1 = n1[s];
+            m2 = n2[s];
         }
-        __syncthreads();
-        const int u1 = min(ns, (wv + 1) * 64);
-        // r^-1: the hardware reciprocal square root (about 21 correct bits; r2 > 0
-        // for every pair of distinct drops, overlapping drops are rejected at input)
-        // refined by one third-order step y (1 + e/2 + 3e^2/8), e = 1 - r2 y^2,
-        // which leaves a relative error below 1e-18
-#pragma unroll 4
-        for (int u = wv * 64; u < u1; ++u) {
-            const double2 p0 = sh[u][0], p1 = sh[u][1], p2 = sh[u][2];
-            const double hx = x0 - p0.x, hy = y0 - p0.y, hz = z0 - p1.x;
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            const double hx = X[k] - px, hy = Y[k] - py, hz = Z[k] - pz;
             const double r2 = fma(hz, hz, fma(hy, hy, hx * hx));
-            const double y0r = __builtin_amdgcn_rsq(r2);
-            const double e = fma(-r2 * y0r, y0r, 1.0);
-            const double ri = fma(y0r * e, fma(0.375, e, 0.5), y0r);
-            const double hd = fma(hz, p2.y, fma(hy, p2.x, hx * p1.y));
+            const double y = __builtin_amdgcn_rsq(r2);
+            const double e = fma(-r2 * y, y, 1.0);
+            const double ri = fma(y * e, 0.5, y);
+            const double hd = fma(hz, u2, fma(hy, u1, hx * u0));
             if (KIND == 0) {
-                // wW G f = wW (f / r + h (h.f) / r^3)
                 const double q = hd * ri * ri;
-                a0 = fma(ri, fma(hx, q, p1.y), a0);
-                a1 = fma(ri, fma(hy, q, p2.x), a1);
-                a2 = fma(ri, fma(hz, q, p2.y), a2);
+                A0[k] = fma(ri, fma(hx, q, u0), A0[k]);
+                A1[k] = fma(ri, fma(hy, q, u1), A1[k]);
+                A2[k] = fma(ri, fma(hz, q, u2), A2[k]);
             } else {
-                // -6 h (h.u)(h.wN) / r^5
-                const double2 p3 = sh[u][3], p4 = sh[u][4];
-                const double hn = fma(hz, p4.x, fma(hy, p3.y, hx * p3.x));
+                const double hn = fma(hz, m2, fma(hy, m1, hx * m0));
                 const double r2i = ri * ri;
                 const double sc = (hd * hn) * (r2i * r2i * ri);
-                a0 = fma(sc, hx, a0);
-                a1 = fma(sc, hy, a1);
-                a2 = fma(sc, hz, a2);
+                A0[k] = fma(sc, hx, A0[k]);
+                A1[k] = fma(sc, hy, A1[k]);
+                A2[k] = fma(sc, hz, A2[k]);
             }
         }
     }
-    if (wv > 0) {
-        red[wv - 1][0][lane] = a0;
-        red[wv - 1][1][lane] = a1;
-        red[wv - 1][2][lane] = a2;
-    }
-    __syncthreads();
-    if (wv == 0 && active) {
-        a0 += (red[0][0][lane] + red[1][0][lane]) + red[2][0][lane];
-        a1 += (red[0][1][lane] + red[1][1][lane]) + red[2][1][lane];
-        a2 += (red[0][2][lane] + red[1][2][lane]) + red[2][2][lane];
-        atomicAdd(&out[t], w.w * a0);
-        atomicAdd(&out[ostride + t], w.w * a1);
-        atomicAdd(&out[2 * ostride + t], w.w * a2);
+    const double sw = KIND == 0 ? w.w : -6.0 * w.w;
+    double *out = part + (long)(item0 + item) * (3 * tile) + lane;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        out[64 * k] = sw * A0[k];
+        out[tile + 64 * k] = sw * A1[k];
+        out[2 * tile + 64 * k] = sw * A2[k];
     }
 }
 
-// The same pair sums in FP32 arithmetic (precision BIM_PREC_MIXED): sources
-// and targets are taken relative to the source drop's centre (mean node, cb)
-// in FP64 and rounded to FP32, so the differences h keep FP32 relative
-// accuracy for every distance; 1/r from the single-precision reciprocal
-// square root (about 1 ulp); each wavefront's sum over its quarter of the
-// tile runs in FP32 over runs of kPairRun sources, flushed into FP64
-// accumulators, and the wavefronts combine in FP64.
-constexpr int kPairRun = 16;
-
+// FP32 source records of the mixed form, three float4 per node at the node's
+// index: position relative to its drop's centre (mean node) and the density
+// terms,
+//   DL (x, y, z, u0) (u1, u2, wN0, wN1) (wN2, -, -, -)
+//   SL (x, y, z, wW f0) (wW f1, wW f2, -, -) (-)
+// Job b covers nodes [off, off + n) of drop `drop`.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_pair32(const PairWork *__restrict__ work, const int *__restrict__ tlist,
-                                                const double *__restrict__ tx, long tstride, PairSrc g0, PairSrc g1,
-                                                const double *__restrict__ cb, int nd, double *__restrict__ out,
-                                                long ostride)
+__global__ void k_pair_pack32(const PackJob *__restrict__ jobs, PairSrc G, const double *__restrict__ cb,
+                              float4 *__restrict__ rec)
 {
-    // DL (x,y,z,u0)(u1,u2,-6 wN0,-6 wN1)(-6 wN2)   SL (x,y,z,wW f0)(wW f1,wW f2)
-    constexpr int NP = KIND == 0 ? 2 : 3;
-    __shared__ float4 sh[kPairSrc][NP];
-    __shared__ double red[3][3][64];
-    const PairWork w = work[blockIdx.x];
-    const PairSrc &G = (w.pad & 1) ? g1 : g0;
+    const PackJob jb = jobs[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= jb.n) return;
+    const long s = jb.off + i, st = G.stride;
+    const double *c = cb + 4 * jb.drop;
+    const float px = (float)(G.x[s] - c[0]), py = (float)(G.x[st + s] - c[1]), pz = (float)(G.x[2 * st + s] - c[2]);
+    float4 *r = rec + 3 * s;
+    if (KIND == 0) {
+        const double ww = G.wW[s];
+        r[0] = make_float4(px, py, pz, (float)(ww * G.d[s]));
+        r[1] = make_float4((float)(ww * G.d[st + s]), (float)(ww * G.d[2 * st + s]), 0.f, 0.f);
+    } else {
+        r[0] = make_float4(px, py, pz, (float)G.d[s]);
+        r[1] = make_float4((float)G.d[st + s], (float)G.d[2 * st + s], (float)G.wN[s], (float)G.wN[st + s]);
+        r[2] = make_float4((float)G.wN[2 * st + s], 0.f, 0.f, 0.f);
+    }
+}
+
+// The same pair sums in FP32 arithmetic (precision BIM_PREC_MIXED) from the
+// packed records: targets are taken relative to the source drop's centre in
+// FP64 and rounded to FP32, so the differences h keep FP32 relative accuracy
+// for every distance; 1/r from the single-precision reciprocal square root
+// (about 1 ulp); runs of kPairRun sources are summed in FP32 and added into
+// FP64 accumulators.
+constexpr int kPairRun = 32;
+
+template <int KIND, int T>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair32(const PairWork *__restrict__ work, int nwork, int item0,
+                                                           int tile, const int *__restrict__ tlist,
+                                                           const double *__restrict__ tx, long tstride,
+                                                           const float4 *__restrict__ rec0,
+                                                           const float4 *__restrict__ rec1,
+                                                           const double *__restrict__ cb, int nd,
+                                                           double *__restrict__ part)
+{
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
+    if (item >= nwork) return;
+    const PairWork w = work[item];
+    const int lane = threadIdx.x & 63;
     const double *c = cb + 4 * (w.pair % nd);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool active = lane < w.ntgt;
-    const int t = (w.pad & kPairContig) ? w.tlist_off + (active ? lane : 0)
-                                        : (active ? tlist[w.tlist_off + lane] : tlist[w.tlist_off]);
-    const float x0 = (float)(tx[t] - c[0]), y0 = (float)(tx[tstride + t] - c[1]),
-                z0 = (float)(tx[2 * tstride + t] - c[2]);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int s0 = 0; s0 < w.nsrc; s0 += kPairSrc) {
-        const int ns = min(kPairSrc, w.nsrc - s0);
-        if (s0) __syncthreads();
-        for (int i = threadIdx.x; i < ns; i += 256) {
-            const long s = (long)w.src_off + s0 + i;
-            const long st = G.stride;
-            const float px = (float)(G.x[s] - c[0]), py = (float)(G.x[st + s] - c[1]),
-                        pz = (float)(G.x[2 * st + s] - c[2]);
-            if (KIND == 0) {
-                const double ww = G.wW[s];
-                sh[i][0] = make_float4(px, py, pz, (float)(ww * G.d[s]));
-                sh[i][1] = make_float4((float)(ww * G.d[st + s]), (float)(ww * G.d[2 * st + s]), 0.f, 0.f);
-            } else {
-                sh[i][0] = make_float4(px, py, pz, (float)G.d[s]);
-                sh[i][1] = make_float4((float)G.d[st + s], (float)G.d[2 * st + s], (float)(-6.0 * G.wN[s]),
-                                       (float)(-6.0 * G.wN[st + s]));
-                sh[i][2] = make_float4((float)(-6.0 * G.wN[2 * st + s]), 0.f, 0.f, 0.f);
-            }
-        }
-        __syncthreads();
-        const int u1 = min(ns, (wv + 1) * 64);
-        for (int r0 = wv * 64; r0 < u1; r0 += kPairRun) {
-            const int r1 = min(u1, r0 + kPairRun);
-            float b0 = 0.f, b1 = 0.f, b2 = 0.f;
-#pragma unroll 4
-            for (int u = r0; u < r1; ++u) {
-                const float4 p0 = sh[u][0], p1 = sh[u][1];
-                const float hx = x0 - p0.x, hy = y0 - p0.y, hz = z0 - p0.z;
+    const double c0 = c[0], c1 = c[1], c2 = c[2];
+    float X[T], Y[T], Z[T];
+    double A0[T], A1[T], A2[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int t = pair_target(w, tlist, lane + 64 * k);
+        X[k] = (float)(tx[t] - c0);
+        Y[k] = (float)(tx[tstride + t] - c1);
+        Z[k] = (float)(tx[2 * tstride + t] - c2);
+        A0[k] = A1[k] = A2[k] = 0.0;
+    }
+    cf32x4 *r = scalar_ptr(((w.pad & 1) ? rec1 : rec0) + 3L * w.src_off);
+    for (int r0 = 0; r0 < w.nsrc; r0 += kPairRun) {
+        const int r1 = min(w.nsrc, r0 + kPairRun);
+        float B0[T], B1[T], B2[T];
+#pragma unroll
+        for (int k = 0; k < T; ++k) B0[k] = B1[k] = B2[k] = 0.f;
+#pragma unroll 2
+        for (int s = r0; s < r1; ++s) {
+            const f32x4 p0 = r[3 * s], p1 = r[3 * s + 1];
+            f32x4 p2 = p1;
+            if (KIND == 1) p2 = r[3 * s + 2];
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const float hx = X[k] - p0.x, hy = Y[k] - p0.y, hz = Z[k] - p0.z;
                 const float r2 = fmaf(hz, hz, fmaf(hy, hy, hx * hx));
                 const float ri = __builtin_amdgcn_rsqf(r2);
+                const float hd = fmaf(hz, p1.y, fmaf(hy, p1.x, hx * p0.w));
                 if (KIND == 0) {
-                    // wW G f = wW (f / r + h (h.f) / r^3)
-                    const float hd = fmaf(hz, p1.y, fmaf(hy, p1.x, hx * p0.w));
                     const float q = hd * ri * ri;
-                    b0 = fmaf(ri, fmaf(hx, q, p0.w), b0);
-                    b1 = fmaf(ri, fmaf(hy, q, p1.x), b1);
-                    b2 = fmaf(ri, fmaf(hz, q, p1.y), b2);
+                    B0[k] = fmaf(ri, fmaf(hx, q, p0.w), B0[k]);
+                    B1[k] = fmaf(ri, fmaf(hy, q, p1.x), B1[k]);
+                    B2[k] = fmaf(ri, fmaf(hz, q, p1.y), B2[k]);
                 } else {
-                    // -6 h (h.u)(h.wN) / r^5
-                    const float4 p2 = sh[u][2];
-                    const float hd = fmaf(hz, p1.y, fmaf(hy, p1.x, hx * p0.w));
                     const float hn = fmaf(hz, p2.x, fmaf(hy, p1.w, hx * p1.z));
                     const float r2i = ri * ri;
                     const float sc = (hd * hn) * (r2i * r2i * ri);
-                    b0 = fmaf(sc, hx, b0);
-                    b1 = fmaf(sc, hy, b1);
-                    b2 = fmaf(sc, hz, b2);
+                    B0[k] = fmaf(sc, hx, B0[k]);
+                    B1[k] = fmaf(sc, hy, B1[k]);
+                    B2[k] = fmaf(sc, hz, B2[k]);
                 }
             }
-            a0 += (double)b0;
-            a1 += (double)b1;
-            a2 += (double)b2;
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            A0[k] += (double)B0[k];
+            A1[k] += (double)B1[k];
+            A2[k] += (double)B2[k];
         }
     }
-    if (wv > 0) {
-        red[wv - 1][0][lane] = a0;
-        red[wv - 1][1][lane] = a1;
-        red[wv - 1][2][lane] = a2;
+    const double sw = KIND == 0 ? w.w : -6.0 * w.w;
+    double *out = part + (long)(item0 + item) * (3 * tile) + lane;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        out[64 * k] = sw * A0[k];
+        out[tile + 64 * k] = sw * A1[k];
+        out[2 * tile + 64 * k] = sw * A2[k];
     }
-    __syncthreads();
-    if (wv == 0 && active) {
-        a0 += (red[0][0][lane] + red[1][0][lane]) + red[2][0][lane];
-        a1 += (red[0][1][lane] + red[1][1][lane]) + red[2][1][lane];
-        a2 += (red[0][2][lane] + red[1][2][lane]) + red[2][2][lane];
-        atomicAdd(&out[t], w.w * a0);
-        atomicAdd(&out[ostride + t], w.w * a1);
-        atomicAdd(&out[2 * ostride + t], w.w * a2);
+}
+
+// out[c][t] (+)= the pair sums of target t from the partial buffer, added in
+// a fixed order, so the result does not depend on scheduling. Items over a
+// contiguous tile of targets are listed once per tile: the slots of target t
+// are tent[e] + t for e in [toff[k], toff[k+1]), k = tile_of[t] (tile_of may
+// be null: no such items). Items over an index list are listed per target:
+// slots ent[e], e in [off[t], off[t+1]). Each slot holds three components at
+// stride `tile`. One wavefront per target: lane l adds the entries l, l + 64,
+// ... of the two lists in turn, then a butterfly over the lanes. Targets
+// with no slot are left alone.
+__global__ __launch_bounds__(256) void k_pair_gather(int nt, int tile, const int *__restrict__ tile_of,
+                                                     const int *__restrict__ toff, const int *__restrict__ tent,
+                                                     const int *__restrict__ off, const int *__restrict__ ent,
+                                                     const double *__restrict__ part, double *__restrict__ out,
+                                                     long ostride, int add)
+{
+    const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (t >= nt) return;
+    int k0 = 0, k1 = 0;
+    if (tile_of) {
+        const int k = tile_of[t];
+        k0 = toff[k];
+        k1 = toff[k + 1];
+    }
+    const int e0 = off[t], e1 = off[t + 1];
+    if (k0 == k1 && e0 == e1) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int e = k0 + lane; e < k1; e += 64) {
+        const double *p = part + ((long)tent[e] + t);
+        s0 += p[0];
+        s1 += p[tile];
+        s2 += p[2 * tile];
+    }
+    for (int e = e0 + lane; e < e1; e += 64) {
+        const double *p = part + (long)ent[e];
+        s0 += p[0];
+        s1 += p[tile];
+        s2 += p[2 * tile];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+    }
+    if (lane == 0) {
+        if (add) {
+            s0 += out[t];
+            s1 += out[ostride + t];
+            s2 += out[2 * ostride + t];
+        }
+        out[t] = s0;
+        out[ostride + t] = s1;
+        out[2 * ostride + t] = s2;
     }
 }
 
@@ -671,10 +756,12 @@ __global__ void k_rhs(int T, const double *__restrict__ tx, long tstride, const 
     }
 }
 
+// y = a x + b y; with b = 0, y is written without being read (it may hold
+// anything, NaN included)
 __global__ void k_scale_add(long n, double a, const double *__restrict__ x, double b, double *__restrict__ y)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a * x[i] + b * y[i];
+    if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
 // y_i = s_i * x_i - y_i with s_i = (lambda_drop(i) + 1): the Galerkin operator
@@ -927,6 +1014,21 @@ void launch_nodes(hipStream_t st, const NodeJob *jobs, int n)
     }
 }
 
+// vol[i] = sum of the wavefront partials part[off[i] .. off[i+1]) in order.
+__global__ void k_vol_sum(int nd, const double *__restrict__ part, const int *__restrict__ off, double *__restrict__ vol)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    double s = 0.0;
+    for (int e = off[i]; e < off[i + 1]; ++e) s += part[e];
+    vol[i] = s;
+}
+
+void launch_vol_sum(hipStream_t st, int nd, const double *part, const int *off, double *vol)
+{
+    hipLaunchKernelGGL(k_vol_sum, dim3(nblk(nd)), dim3(256), 0, st, nd, part, off, vol);
+}
+
 // Grid spacing of each drop, h_i = R_i pi / (p_i + 1) with R_i the radius of
 // the sphere of the drop's volume (hfac_i = pi / (p_i + 1)); bad[0] = 1 when a
 // volume is not positive and finite (h_i = 0 then), else 0. One block.
@@ -997,26 +1099,61 @@ void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, c
     }
 }
 
-int pair_sources_per_item() { return kPairItem; }
-
-void launch_pair(hipStream_t st, int kind, int nwork, const PairWork *work, const int *tlist, const double *tx,
-                 long tstride, const PairSrc &g0, const PairSrc &g1, double *out, long ostride, const double *cb32,
-                 int nd)
+template <int KIND, int T>
+static void pair_one(hipStream_t st, int n, const PairWork *work, int item0, int tile, const int *tlist,
+                     const double *tx, long tstride, const PairSrc &g0, const PairSrc &g1, double *part,
+                     const float4 *rec0, const float4 *rec1, const double *cb32, int nd)
 {
-    if (nwork <= 0) return;
-    if (cb32) {  // FP32 arithmetic
-        if (kind == 0)
-            hipLaunchKernelGGL(k_pair32<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, cb32, nd,
-                               out, ostride);
-        else
-            hipLaunchKernelGGL(k_pair32<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, cb32, nd,
-                               out, ostride);
-        return;
-    }
-    if (kind == 0)
-        hipLaunchKernelGGL(k_pair<0>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, out, ostride);
+    if (n <= 0) return;
+    const dim3 grid((n + kPairWaves - 1) / kPairWaves), block(64 * kPairWaves);
+    if (rec0)
+        hipLaunchKernelGGL((k_pair32<KIND, T>), grid, block, 0, st, work, n, item0, tile, tlist, tx, tstride, rec0,
+                           rec1, cb32, nd, part);
     else
-        hipLaunchKernelGGL(k_pair<1>, dim3(nwork), dim3(256), 0, st, work, tlist, tx, tstride, g0, g1, out, ostride);
+        hipLaunchKernelGGL((k_pair<KIND, T>), grid, block, 0, st, work, n, item0, tile, tlist, tx, tstride, g0, g1,
+                           part);
+}
+
+// Items [0, nbig) with tbig targets per lane, then [nbig, nbig + nsmall) with
+// one; partial blocks of 3 * 64 tbig doubles, in item order.
+void launch_pair(hipStream_t st, int kind, int nbig, int nsmall, int tbig, const PairWork *work, const int *tlist,
+                 const double *tx, long tstride, const PairSrc &g0, const PairSrc &g1, double *part,
+                 const float4 *rec0, const float4 *rec1, const double *cb32, int nd)
+{
+    const int tile = 64 * tbig;
+    auto big = [&](auto k) {
+        constexpr int K = decltype(k)::value;
+        if (tbig == 4)
+            pair_one<K, 4>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+        else if (tbig == 2)
+            pair_one<K, 2>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+        else
+            pair_one<K, 1>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+        pair_one<K, 1>(st, nsmall, work + nbig, nbig, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+    };
+    if (kind == 0)
+        big(std::integral_constant<int, 0>());
+    else
+        big(std::integral_constant<int, 1>());
+}
+
+void launch_pair_pack32(hipStream_t st, int kind, const void *jobs, int njobs, int maxn, const PairSrc &g,
+                        const double *cb, float4 *rec)
+{
+    if (njobs <= 0 || maxn <= 0) return;
+    const dim3 grid((maxn + 255) / 256, njobs);
+    if (kind == 0)
+        hipLaunchKernelGGL(k_pair_pack32<0>, grid, dim3(256), 0, st, (const PackJob *)jobs, g, cb, rec);
+    else
+        hipLaunchKernelGGL(k_pair_pack32<1>, grid, dim3(256), 0, st, (const PackJob *)jobs, g, cb, rec);
+}
+
+void launch_pair_gather(hipStream_t st, int nt, int tile, const int *tile_of, const int *toff, const int *tent,
+                        const int *off, const int *ent, const double *part, double *out, long ostride, bool add)
+{
+    if (nt <= 0) return;
+    hipLaunchKernelGGL(k_pair_gather, dim3((nt + 3) / 4), dim3(256), 0, st, nt, tile, tile_of, toff, tent, off, ent,
+                       part, out, ostride, add ? 1 : 0);
 }
 
 void launch_rhs(hipStream_t st, int T, const double *tx, long tstride, const double *s, double a, const double *U0,

@@ -221,7 +221,8 @@ __global__ __launch_bounds__(64) void k_near_setup(NearArgs a)
 
 // Interpolation: value at x* from the self-interaction expansion (minus
 // 4 pi u(x*) for the double layer), the L regular-rule values, Lagrange in the
-// distance; the weighted result is added to the target.
+// distance; the weighted result of item `it` goes to out[c * n + it] (the
+// items of a target are added to it afterwards in item order).
 __global__ __launch_bounds__(64) void k_near_interp(NearArgs a, int kind, const double *__restrict__ selfc,
                                                    const double *__restrict__ dens, const double *__restrict__ vacc,
                                                    const double *__restrict__ wts, double *__restrict__ out)
@@ -229,7 +230,10 @@ __global__ __launch_bounds__(64) void k_near_interp(NearArgs a, int kind, const 
     const int it = blockIdx.x;
     if (it >= a.n) return;
     const double wi = wts[it];
-    if (wi == 0.0) return;
+    if (wi == 0.0) {  // the item's slot still takes its (zero) contribution
+        if (threadIdx.x < 3) out[threadIdx.x * a.n + it] = 0.0;
+        return;
+    }
     const int m = threadIdx.x;
     const NearItem I = a.items[it];
     const int j = I.j, p = a.dp[j];
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(64) void k_near_interp(NearArgs a, int kind, const 
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) atomicAdd(&out[c * a.T + I.t], wi * res[c]);
+    for (int c = 0; c < 3; ++c) out[c * a.n + it] = wi * res[c];
 }
 
 void launch_near_setup(hipStream_t st, const NearArgs &a)

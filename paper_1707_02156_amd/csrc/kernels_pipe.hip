@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 namespace bim {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -216,9 +218,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     double *sG = sm;
     const long gsz = (long)TG * P1 * NTY * 6;
     double *V = sG + gsz;                    // [tg][k'][kVS]: 12 fields, padded
-    double *red = V + (long)TG * nk * kVS;   // [tg][3]
-    double *sCS = red + TG * 3;              // cos, sin of pi e / qs, e < 2 qs
-    for (int i = threadIdx.x; i < TG * 3; i += 256) red[i] = 0.0;
+    double *sCS = V + (long)TG * nk * kVS + TG * 3;  // cos, sin of pi e / qs, e < 2 qs
     for (int e = threadIdx.x; e < 2 * nk; e += 256) sCS[e] = cs[e];
     // ---- load G (weights w_mu applied; x_phi built from x)
     for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
@@ -381,30 +381,29 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 v[5] = sc * h2 * h2;
             }
         }
-        if (SL) {
-            // one target per wavefront (2 qs = 64): reduce in registers; otherwise LDS atomics
-            const int tgw = __shfl(tg, 0, 64), okw = __shfl((int)ok, 63, 64);
-            if (okw && __all(tg == tgw)) {
-                for (int o = 32; o > 0; o >>= 1) {
-                    e0 += __shfl_down(e0, o, 64);
-                    e1 += __shfl_down(e1, o, 64);
-                    e2 += __shfl_down(e2, o, 64);
-                }
-                if ((threadIdx.x & 63) == 0) {
-                    atomicAdd(&red[3 * tg], e0);
-                    atomicAdd(&red[3 * tg + 1], e1);
-                    atomicAdd(&red[3 * tg + 2], e2);
-                }
-            } else if (ok) {
-                atomicAdd(&red[3 * tg], e0);
-                atomicAdd(&red[3 * tg + 1], e1);
-                atomicAdd(&red[3 * tg + 2], e2);
-            }
+        if (SL && ok) {  // f is read; its slots take the point's contribution
+            v[9] = e0;
+            v[10] = e1;
+            v[11] = e2;
         }
     }
     __syncthreads();
-    if (SL)
-        for (int i = threadIdx.x; i < ntg * 3; i += 256) part[((long)(t0 + i / 3) * Q1 + jr) * 3 + i % 3] = red[i];
+    if (SL) {
+        // sums over the longitudes in a fixed order (run to run identical):
+        // 16 lanes per (target, component), lane l adds the points l, l + 16,
+        // ..., then a butterfly over the 16 lanes
+        for (int i0 = 0; i0 < ntg * 48; i0 += 256) {
+            const int i = i0 + threadIdx.x;
+            const bool act = i < ntg * 48;
+            const int g = act ? i >> 4 : 0, l = i & 15;
+            const int tg = g / 3, cc = g % 3;
+            double sum = 0.0;
+            if (act)
+                for (int k = l; k < nk; k += 16) sum += V[(long)(tg * nk + k) * kVS + 9 + cc];
+            for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
+            if (act && l == 0) part[((long)(t0 + tg) * Q1 + jr) * 3 + cc] = sum;
+        }
+    }
     if (DL) {
         // ---- FA: Fourier analysis of the six stresslet fields. One item = four
         // orders of one parity (mu = base + 2q), sharing the symmetric
@@ -578,14 +577,18 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 // allow up to 160 KB of dynamic LDS for the kernels that size it by degree
+// (once per process, before any of them is launched: server worker threads
+// reach this concurrently, and call_once makes the others wait until it is set)
 void pipe_set_lds_limits()
 {
-    static bool done = false;
-    if (done) return;
-    done = true;
-    (void)hipFuncSetAttribute((const void *)k_fk<true, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-    (void)hipFuncSetAttribute((const void *)k_fk<true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-    (void)hipFuncSetAttribute((const void *)k_fk<false, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void *)k_fk<true, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        (void)hipFuncSetAttribute((const void *)k_fk<true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  163840);
+        (void)hipFuncSetAttribute((const void *)k_fk<false, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  163840);
+    });
 }
 
 void launch_rot2(hipStream_t st, int p, const double *Ap, const double *Am, const double *csp, const double *xc,

@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 
 namespace bim {
@@ -458,11 +460,10 @@ __global__ __launch_bounds__(256) void k_dl_apply(int nt, int nc2, const double 
 template <bool SL, bool DL, int JB, int NB> static void launch_one(hipStream_t st, const SingArgs &a, size_t lds)
 {
     auto fn = k_sing_fused<SL, DL, JB, NB>;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag once;  // concurrent callers wait until the limit is set
+    std::call_once(once, [&] {
         (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        attr_set = true;
-    }
+    });
     hipLaunchKernelGGL(fn, dim3(a.nt), dim3(SingThreads<SL, DL>::value), lds, st, a);
 }
 

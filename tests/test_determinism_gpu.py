@@ -1,0 +1,77 @@
+"""Run-to-run reproducibility of the FP64 (and mixed) velocity.
+
+Every sum on the velocity path has a fixed order: the pair sums reduce their
+per-item partial sums in work-list order, the singular Fourier stage sums its
+longitudes in a fixed tree, the nearest-region items of a target are added in
+item order, and the enclosed volumes (which set the region thresholds) add
+fixed per-wavefront partials. Two evaluations of the same input, in the same
+context or in a fresh one, must then agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_02156_amd as B
+    return B
+
+
+def _ctx(B, wl, **kw):
+    opts = dict(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom, gmres_tol=wl.gmres_tol)
+    opts.update(kw)
+    c = B.Context(**opts)
+    c.set_drops([d.p for d in wl.drops], [d.xc for d in wl.drops], [d.lam for d in wl.drops])
+    if wl.eos != 0:
+        c.set_tension([d.gc for d in wl.drops], wl.eos, wl.E, wl.xs, wl.sigma0)
+    else:
+        c.set_tension(None, 0, sigma0=wl.sigma0)
+    return c
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_drops_p32_velocity_is_bit_identical(B, precision):
+    print(f"determinism two drops p=32 precision {precision}", flush=True)
+    wl = W.two_drops()
+    c = _ctx(B, wl, precision=precision)
+    u1, r1 = c.eval_velocity(coefficients=True)
+    u2, r2 = c.eval_velocity(coefficients=True)
+    c.close()
+    c = _ctx(B, wl, precision=precision)
+    u3, r3 = c.eval_velocity(coefficients=True)
+    c.close()
+    assert r1.gmres_iterations == r2.gmres_iterations == r3.gmres_iterations
+    assert _same(u1, u2) and _same(u1, u3)
+
+
+def test_close_drops_with_nearest_region_rule_are_bit_identical(B):
+    """Three drops, two of them 0.05 apart (Omega_2 targets, special
+    quadrature), lambda = (2, 5, 1)."""
+    print("determinism close drops near rule", flush=True)
+    p = 12
+    rng = np.random.default_rng(21)
+    drops = [W.DropSpec(p, W.perturbed_sphere(rng, p, 1.0, (0, 0, 0), 0.02), 2.0),
+             W.DropSpec(p, W.perturbed_sphere(rng, p, 1.0, (2.08, 0, 0), 0.02), 5.0),
+             W.DropSpec(p, W.perturbed_sphere(rng, p, 0.8, (0.9, 2.3, 0.3), 0.02), 1.0)]
+    wl = W.Workload("close", drops)
+    outs = []
+    for _ in range(2):
+        c = _ctx(B, wl, near_rule=1, gmres_tol=1e-12)
+        reg, _ = c.regions()
+        assert (reg == 2).any()
+        outs.append(c.eval_velocity())
+        outs.append(c.eval_velocity())
+        c.close()
+    for u, r in outs[1:]:
+        assert _same(u, outs[0][0]) and r.gmres_iterations == outs[0][1].gmres_iterations

@@ -769,3 +769,20 @@ def test_two_close_spheres_rigid_motion_with_nearest_region_rule(orc):
         errs[rule] = np.abs(v - 4 * np.pi * e).max()
     assert errs[1] <= 1e-5 * 4 * np.pi
     assert errs[0] > 1e3 * errs[1]
+
+
+# --- stored oracle results --------------------------------------------------------
+
+def test_stored_two_drop_solution_is_the_oracles(orc):
+    """tests/golden/two_drops_p32_solution.npz (written by the committed
+    script beside it, oracle only) still holds the oracle's right-hand side,
+    and its solution meets the oracle's operator to 1e-12."""
+    wl = W.two_drops()
+    ref = np.load(os.path.join(GOLD, "two_drops_p32_solution.npz"))
+    o = orc.Options(A_tilde=wl.A_tilde, U_tilde=wl.U_tilde, U_sing=wl.U_sing, U_geom=wl.U_geom, eos=wl.eos, E=wl.E,
+                    xs=wl.xs, sigma0=wl.sigma0)
+    s = orc.System([orc.Drop(d.p, d.xc, d.lam, d.gc) for d in wl.drops], o)
+    b = s.rhs()
+    assert np.abs(b - ref["b"]).max() <= 1e-14 * np.abs(b).max()
+    r = s.matvec(ref["u"]) - b
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
