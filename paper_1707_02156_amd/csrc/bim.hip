@@ -56,7 +56,7 @@ void launch_singular(hipStream_t st, int p, int qs, int kind, const double *R, c
 void launch_near_setup(hipStream_t st, const NearArgs &a);
 void launch_near_interp(hipStream_t st, const NearArgs &a, int kind, const double *selfc, const double *dens,
                         const double *vacc, const double *wts, double *out);
-void launch_pair(hipStream_t st, int kind, int nbig, int nsmall, int tbig, const PairWork *work, const int *tlist,
+void launch_pair(hipStream_t st, int kind, int T, int n, const PairWork *work, int item0, int tile, const int *tlist,
                  const double *tx, long tstride, const PairSrc &g0, const PairSrc &g1, double *part,
                  const float4 *rec0 = nullptr, const float4 *rec1 = nullptr, const double *cb32 = nullptr, int nd = 0);
 void launch_pair_pack32(hipStream_t st, int kind, const void *jobs, int njobs, int maxn, const PairSrc &g,
@@ -284,6 +284,7 @@ struct Ctx {
         DBuf d;
         int n = 0, nbig = 0;  // items; the first nbig are whole tiles, the rest 64-target remainders
         double pairs = 0.0;  // target-source pairs per application
+        double pairs_big = 0.0;  // of them, in the whole-tile items
         Gather g;
         DBuf nw;             // weight of each nearest-region item
         DBuf fp;             // far pairs of the fast summation with their weights
@@ -1334,7 +1335,10 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
                     e->pairs += (double)pw.ntgt * pw.nsrc;
                 }
             }
-        if (!small) e->nbig = (int)keep.size();
+        if (!small) {
+            e->nbig = (int)keep.size();
+            e->pairs_big = e->pairs;
+        }
     }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
     if (!keep.empty())
@@ -1414,22 +1418,34 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
 {
     Ctx::WList &L = work_lists(c, wt);
     const double fpp = kind == 0 ? 29.0 : 30.0;  // flops per pair (SL / DL)
-    ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
     if (L.n > 0) {
-        const int nb = L.nbig, ns = L.n - L.nbig;
-        if (c.opt.precision == BIM_PREC_MIXED) {
+        const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+        if (f32) {  // (allocates the record buffers on first use: their addresses are taken after it)
+            ProfScope ps(c, "pair_pack", 0.0, 0.0);
             pack32(c, kind, g0, g1);
-            launch_pair(c.stream, kind, nb, ns, c.pair_T, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0,
-                        g1, c.pair_part.d(), c.rec32_0.as<float4>(), c.rec32_1.as<float4>(), c.cbnd.d(), c.nd);
-        } else {
-            launch_pair(c.stream, kind, nb, ns, c.pair_T, L.d.as<PairWork>(), c.tlist.as<int>(), c.tx.d(), c.T, g0,
-                        g1, c.pair_part.d());
         }
-        launch_pair_gather(c.stream, (int)c.T, 64 * c.pair_T, c.tile_of.as<int>(), L.g.toff.as<int>(),
-                           L.g.tent.as<int>(), L.g.off.as<int>(), L.g.ent.as<int>(), c.pair_part.d(), c.acc.d(), c.T,
-                           true);
+        const float4 *r0 = f32 ? c.rec32_0.as<float4>() : nullptr, *r1 = f32 ? c.rec32_1.as<float4>() : nullptr;
+        REQUIRE(!f32 || (r0 && r1), BIM_EDEVICE, "FP32 source records missing");
+        const int tile = 64 * c.pair_T, nb = L.nbig, ns = L.n - L.nbig;
+        {
+            // the whole-tile items: the pair-sum kernel proper
+            ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs_big * fpp, 0.0);
+            launch_pair(c.stream, kind, c.pair_T, nb, L.d.as<PairWork>(), 0, tile, c.tlist.as<int>(), c.tx.d(), c.T,
+                        g0, g1, c.pair_part.d(), r0, r1, c.cbnd.d(), c.nd);
+        }
+        if (ns > 0) {
+            // the 64-target remainders of the target sets, one target per lane
+            ProfScope ps(c, kind == 0 ? "pair_sl_rem" : "pair_dl_rem", (L.pairs - L.pairs_big) * fpp, 0.0);
+            launch_pair(c.stream, kind, 1, ns, L.d.as<PairWork>() + nb, nb, tile, c.tlist.as<int>(), c.tx.d(), c.T,
+                        g0, g1, c.pair_part.d(), r0, r1, c.cbnd.d(), c.nd);
+        }
+        {
+            ProfScope ps(c, "pair_gather", 0.0, 8.0 * 3.0 * ((double)L.g.h_tent.size() * tile + L.g.h_ent.size()));
+            launch_pair_gather(c.stream, (int)c.T, tile, c.tile_of.as<int>(), L.g.toff.as<int>(), L.g.tent.as<int>(),
+                               L.g.off.as<int>(), L.g.ent.as<int>(), c.pair_part.d(), c.acc.d(), c.T, true);
+        }
     }
     run_fmm(c, kind, L);
 }
@@ -1454,8 +1470,8 @@ static void run_near(Ctx &c, int kind, const double *dens, const std::vector<dou
     ProfScope ps(c, "near", c.near_pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
-    launch_pair(c.stream, kind, c.near_nwork, 0, 1, c.near_work.as<PairWork>(), c.near_tl.as<int>(), c.near_vx.d(), V,
-                g0, g1, c.pair_part.d());
+    launch_pair(c.stream, kind, 1, c.near_nwork, c.near_work.as<PairWork>(), 0, 64, c.near_tl.as<int>(), c.near_vx.d(),
+                V, g0, g1, c.pair_part.d());
     launch_pair_gather(c.stream, (int)V, 64, nullptr, nullptr, nullptr, c.near_g.off.as<int>(),
                        c.near_g.ent.as<int>(), c.pair_part.d(), c.near_vacc.d(), V, false);
     launch_near_interp(c.stream, near_args(c), kind, c.near_selfc.d(), dens, c.near_vacc.d(), L.nw.d(),
@@ -1628,9 +1644,17 @@ static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl
             if (sl) launch_leg_mfma(c.stream, P1, Q1, pt.bsd.ptr, pt.syn.d(), c.pBd.d(), c.pGd.d(), NC6);
         }
         {
-            const double KK = qs / 2 + 1, NP = npts(qs);
-            double fl = (double)Q1 * KK * P1 * 4.0 * (sl ? 12.0 : 9.0) + (sl ? NP * 35.0 : 0.0);
-            if (dl) fl += NP * 40.0 + 6.0 * Q1 * P1 * KK * 10.0;
+            // algorithmic flops per target: each real field column of the
+            // rotated grid as a length-2qs FFT per latitude, 2.5 n log2 n with
+            // n = 2 qs, over qs + 1 latitudes (x, x_theta, x_phi and, for the
+            // single layer, f: 12 or 9 columns; the stresslet analysis: 6),
+            // plus the pointwise kernels (35 flops per node SL, 40 DL). The
+            // kernel itself evaluates the Fourier sums directly with the
+            // phi -> -phi symmetry (more flops), which this count ignores.
+            const double NP = npts(qs), n2 = 2.0 * qs;
+            const double fft = 2.5 * n2 * std::log2(n2) * Q1;
+            double fl = fft * (sl ? 12.0 : 9.0) + (sl ? NP * 35.0 : 0.0);
+            if (dl) fl += NP * 40.0 + 6.0 * fft;
             ProfScope ps(c, "pipe_fourier", nt * fl,
                          8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)));
             launch_fk(c.stream, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),

@@ -495,24 +495,63 @@ __device__ inline int pair_target(const PairWork &w, const int *__restrict__ tli
     return (w.pad & kPairContig) ? w.tlist_off + a : tlist[w.tlist_off + a];
 }
 
+// One pair of the sums above (FP64): adds target (X, Y, Z)'s term of the
+// source (px, py, pz, u, m) to (A0, A1, A2). u = wW f (SL) or the density,
+// m = wN (DL).
+template <int KIND>
+__device__ inline void pair64(double X, double Y, double Z, double px, double py, double pz, double u0, double u1,
+                              double u2, double m0, double m1, double m2, double &A0, double &A1, double &A2)
+{
+    const double hx = X - px, hy = Y - py, hz = Z - pz;
+    const double r2 = fma(hz, hz, fma(hy, hy, hx * hx));
+    // r^-1: the hardware reciprocal square root (about 22 correct bits; r2 > 0
+    // for every pair of distinct drops, overlapping drops are rejected at
+    // input) refined by one Newton step y (1 + e/2), e = 1 - r2 y^2, which
+    // leaves a relative error of about 1.5 e^2 < 1e-12 (4 instructions; a
+    // third-order step would take 5 of the 24 FP64 VALU instructions of a
+    // pair for accuracy far below the 1e-10 the sums are held to)
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y, y, 1.0);
+    const double ri = fma(y * e, 0.5, y);
+    const double hd = fma(hz, u2, fma(hy, u1, hx * u0));
+    if (KIND == 0) {
+        const double q = hd * ri * ri;
+        A0 = fma(ri, fma(hx, q, u0), A0);
+        A1 = fma(ri, fma(hy, q, u1), A1);
+        A2 = fma(ri, fma(hz, q, u2), A2);
+    } else {
+        const double hn = fma(hz, m2, fma(hy, m1, hx * m0));
+        const double r2i = ri * ri;
+        const double sc = (hd * hn) * (r2i * r2i * ri);
+        A0 = fma(sc, hx, A0);
+        A1 = fma(sc, hy, A1);
+        A2 = fma(sc, hz, A2);
+    }
+}
+
+// T targets per lane; U = 8 / T consecutive sources per step, each into its
+// own accumulators (independent work for one lane when T is small), added in
+// a fixed order at the end.
 template <int KIND, int T>
 __global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
                                                          int tile, const int *__restrict__ tlist,
                                                          const double *__restrict__ tx, long tstride, PairSrc g0,
                                                          PairSrc g1, double *__restrict__ part)
 {
+    constexpr int U = T >= 4 ? 1 : 8 / T;
     const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
     if (item >= nwork) return;
     const PairWork w = work[item];
     const int lane = threadIdx.x & 63;
-    double X[T], Y[T], Z[T], A0[T], A1[T], A2[T];
+    double X[T], Y[T], Z[T], A0[T][U], A1[T][U], A2[T][U];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int t = pair_target(w, tlist, lane + 64 * k);
         X[k] = tx[t];
         Y[k] = tx[tstride + t];
         Z[k] = tx[2 * tstride + t];
-        A0[k] = A1[k] = A2[k] = 0.0;
+#pragma unroll
+        for (int v = 0; v < U; ++v) A0[k][v] = A1[k][v] = A2[k][v] = 0.0;
     }
     const PairSrc &G = (w.pad & 1) ? g1 : g0;
     const long st = G.stride, o = w.src_off;
@@ -520,14 +559,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__rest
     cdouble *d0 = scalar_ptr(G.d + o), *d1 = scalar_ptr(G.d + st + o), *d2 = scalar_ptr(G.d + 2 * st + o);
     cdouble *n0 = scalar_ptr((KIND == 0 ? G.wW : G.wN) + o), *n1 = scalar_ptr(G.wN + st + o),
             *n2 = scalar_ptr(G.wN + 2 * st + o);
-    // r^-1: the hardware reciprocal square root (about 22 correct bits; r2 > 0
-    // for every pair of distinct drops, overlapping drops are rejected at input)
-    // refined by one Newton step y (1 + e/2), e = 1 - r2 y^2, which leaves a
-    // relative error of about 1.5 e^2 < 1e-12 (4 instructions; a third-order
-    // step would take 5 of the 24 FP64 VALU instructions of a pair for
-    // accuracy far below the 1e-10 the sums are held to)
-#pragma unroll 2
-    for (int s = 0; s < w.nsrc; ++s) {
+    auto step = [&](int s, int v) {
         const double px = sx[s], py = sy[s], pz = sz[s];
         double u0 = d0[s], u1 = d1[s], u2 = d2[s], m0 = 0.0, m1 = 0.0, m2 = 0.0;
         if (KIND == 0) {
@@ -541,35 +573,32 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__rest
             m2 = n2[s];
         }
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
-            const double hx = X[k] - px, hy = Y[k] - py, hz = Z[k] - pz;
-            const double r2 = fma(hz, hz, fma(hy, hy, hx * hx));
-            const double y = __builtin_amdgcn_rsq(r2);
-            const double e = fma(-r2 * y, y, 1.0);
-            const double ri = fma(y * e, 0.5, y);
-            const double hd = fma(hz, u2, fma(hy, u1, hx * u0));
-            if (KIND == 0) {
-                const double q = hd * ri * ri;
-                A0[k] = fma(ri, fma(hx, q, u0), A0[k]);
-                A1[k] = fma(ri, fma(hy, q, u1), A1[k]);
-                A2[k] = fma(ri, fma(hz, q, u2), A2[k]);
-            } else {
-                const double hn = fma(hz, m2, fma(hy, m1, hx * m0));
-                const double r2i = ri * ri;
-                const double sc = (hd * hn) * (r2i * r2i * ri);
-                A0[k] = fma(sc, hx, A0[k]);
-                A1[k] = fma(sc, hy, A1[k]);
-                A2[k] = fma(sc, hz, A2[k]);
-            }
-        }
+        for (int k = 0; k < T; ++k)
+            pair64<KIND>(X[k], Y[k], Z[k], px, py, pz, u0, u1, u2, m0, m1, m2, A0[k][v], A1[k][v], A2[k][v]);
+    };
+    int s = 0;
+    if (U == 1) {
+#pragma unroll 2
+        for (; s < w.nsrc; ++s) step(s, 0);
+    } else {
+        for (; s + U <= w.nsrc; s += U)
+#pragma unroll
+            for (int v = 0; v < U; ++v) step(s + v, v);
+        for (; s < w.nsrc; ++s) step(s, 0);
     }
     const double sw = KIND == 0 ? w.w : -6.0 * w.w;
     double *out = part + (long)(item0 + item) * (3 * tile) + lane;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-        out[64 * k] = sw * A0[k];
-        out[tile + 64 * k] = sw * A1[k];
-        out[2 * tile + 64 * k] = sw * A2[k];
+#pragma unroll
+        for (int v = 1; v < U; ++v) {
+            A0[k][0] += A0[k][v];
+            A1[k][0] += A1[k][v];
+            A2[k][0] += A2[k][v];
+        }
+        out[64 * k] = sw * A0[k][0];
+        out[tile + 64 * k] = sw * A1[k][0];
+        out[2 * tile + 64 * k] = sw * A2[k][0];
     }
 }
 
@@ -607,7 +636,7 @@ __global__ void k_pair_pack32(const PackJob *__restrict__ jobs, PairSrc G, const
 // for every distance; 1/r from the single-precision reciprocal square root
 // (about 1 ulp); runs of kPairRun sources are summed in FP32 and added into
 // FP64 accumulators.
-constexpr int kPairRun = 32;
+constexpr int kPairRun = 16;
 
 template <int KIND, int T>
 __global__ __launch_bounds__(64 * kPairWaves) void k_pair32(const PairWork *__restrict__ work, int nwork, int item0,
@@ -1114,27 +1143,25 @@ static void pair_one(hipStream_t st, int n, const PairWork *work, int item0, int
                            part);
 }
 
-// Items [0, nbig) with tbig targets per lane, then [nbig, nbig + nsmall) with
-// one; partial blocks of 3 * 64 tbig doubles, in item order.
-void launch_pair(hipStream_t st, int kind, int nbig, int nsmall, int tbig, const PairWork *work, const int *tlist,
+// Items [0, n) of a work list with T targets per lane (1, 2 or 4); their
+// partial blocks of 3 tile doubles start at block item0.
+void launch_pair(hipStream_t st, int kind, int T, int n, const PairWork *work, int item0, int tile, const int *tlist,
                  const double *tx, long tstride, const PairSrc &g0, const PairSrc &g1, double *part,
                  const float4 *rec0, const float4 *rec1, const double *cb32, int nd)
 {
-    const int tile = 64 * tbig;
-    auto big = [&](auto k) {
+    auto go = [&](auto k) {
         constexpr int K = decltype(k)::value;
-        if (tbig == 4)
-            pair_one<K, 4>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
-        else if (tbig == 2)
-            pair_one<K, 2>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+        if (T == 4)
+            pair_one<K, 4>(st, n, work, item0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+        else if (T == 2)
+            pair_one<K, 2>(st, n, work, item0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
         else
-            pair_one<K, 1>(st, nbig, work, 0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
-        pair_one<K, 1>(st, nsmall, work + nbig, nbig, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
+            pair_one<K, 1>(st, n, work, item0, tile, tlist, tx, tstride, g0, g1, part, rec0, rec1, cb32, nd);
     };
     if (kind == 0)
-        big(std::integral_constant<int, 0>());
+        go(std::integral_constant<int, 0>());
     else
-        big(std::integral_constant<int, 1>());
+        go(std::integral_constant<int, 1>());
 }
 
 void launch_pair_pack32(hipStream_t st, int kind, const void *jobs, int njobs, int maxn, const PairSrc &g,

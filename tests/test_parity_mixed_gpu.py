@@ -1,11 +1,13 @@
 """Mixed precision (precision = BIM_PREC_MIXED): the direct pair sums in FP32
 arithmetic, every other step in FP64.
 
-Bar: 1e-5 of the largest value, per output, against the FP64 oracle on
-sampled targets and against the FP64 GPU path on every target (the FP32
-pair sums round each pair to about 1e-7 relative; runs of 16 sources are
-summed in FP32 and accumulated in FP64). The error is also required to be
-above FP64 rounding, so the FP32 kernel is known to have run.
+Bar: 1e-5 per output, where an output is one drop and one component:
+||gpu - ref||_inf / ||ref||_inf over that drop's targets (sampled ones
+against the FP64 oracle, all of them against the FP64 GPU path). The FP32
+pair sums round each pair to about 1e-7 relative; runs of sources are summed
+in FP32 and accumulated in FP64. The error is also required to be above
+FP64 rounding, so the FP32 kernel is known to have run. Each test prints
+the per-output error it measured.
 """
 import numpy as np
 import pytest
@@ -34,12 +36,17 @@ def _density(rng, p):
     return c
 
 
-def _rel(got, ref):
-    return np.abs(np.asarray(got) - np.asarray(ref)).max() / np.abs(ref).max()
-
-
-def _flat(xs):
-    return np.concatenate([np.ravel(x) for x in xs])
+def _rel_out(got, ref):
+    """Largest per-drop, per-component relative error; got/ref: per drop,
+    arrays (targets, 3) of grid values or (3, ncoef, 2) of coefficients."""
+    e = 0.0
+    for g, r in zip(got, ref):
+        g, r = np.asarray(g), np.asarray(r)
+        if g.ndim == 2:
+            g, r = g.T, r.T
+        for c in range(3):
+            e = max(e, float(np.abs(g[c] - r[c]).max() / np.abs(r[c]).max()))
+    return e
 
 
 def test_mixed_two_drops_against_oracle(B, orc):
@@ -54,10 +61,13 @@ def test_mixed_two_drops_against_oracle(B, orc):
     u = c.single_layer()
     D = c.double_layer(dens, mode=0)
     forces = [s.force(j) for j in range(2)]
+    es, ed = 0.0, 0.0
     for i in (0, 1):
         tg = np.sort(rng.choice(B.npts(32), 8, replace=False))
-        assert _rel(u[i][tg], -s.layer(i, forces, 0, targets=tg) / (8 * np.pi)) <= TOL32
-        assert _rel(D[i][tg], s.layer(i, dens, 1, targets=tg) / (4 * np.pi)) <= TOL32
+        es = max(es, _rel_out([u[i][tg]], [-s.layer(i, forces, 0, targets=tg) / (8 * np.pi)]))
+        ed = max(ed, _rel_out([D[i][tg]], [s.layer(i, dens, 1, targets=tg) / (4 * np.pi)]))
+    print("per-output error SL", es, "DL", ed, flush=True)
+    assert 1e-12 < es <= TOL32 and ed <= TOL32
     c.close()
 
 
@@ -70,11 +80,11 @@ def test_mixed_many_drops_against_fp64(B):
     res = {}
     for prec in (B.BIM_PREC_FP64, B.BIM_PREC_MIXED):
         c = ctx_for(B, wl, precision=prec)
-        res[prec] = (_flat(c.single_layer()), _flat(c.double_layer(dens, mode=0)))
+        res[prec] = (c.single_layer(), c.double_layer(dens, mode=0))
         c.close()
     for k in range(2):
-        e = _rel(res[B.BIM_PREC_MIXED][k], res[B.BIM_PREC_FP64][k])
-        print("layer", k, "rel err", e, flush=True)
+        e = _rel_out(res[B.BIM_PREC_MIXED][k], res[B.BIM_PREC_FP64][k])
+        print("layer", k, "per-output error", e, flush=True)
         assert 1e-12 < e <= TOL32
 
 
@@ -86,10 +96,10 @@ def test_mixed_velocity_solve(B):
     for prec in (B.BIM_PREC_FP64, B.BIM_PREC_MIXED):
         c = ctx_for(B, wl, precision=prec)
         u, rep = c.eval_velocity(coefficients=True)
-        out[prec] = (_flat(u), rep.gmres_iterations)
+        out[prec] = (u, rep.gmres_iterations)
         c.close()
-    e = _rel(out[B.BIM_PREC_MIXED][0], out[B.BIM_PREC_FP64][0])
-    print("solve rel err", e, flush=True)
+    e = _rel_out(out[B.BIM_PREC_MIXED][0], out[B.BIM_PREC_FP64][0])
+    print("solve per-output error", e, flush=True)
     assert 1e-12 < e <= TOL32
     assert abs(out[B.BIM_PREC_MIXED][1] - out[B.BIM_PREC_FP64][1]) <= 1
 
@@ -108,6 +118,58 @@ def test_mixed_with_fast_summation(B, eps):
     um, rm = cm.eval_velocity(coefficients=True)
     cm.close()
     assert rm.n_fmm_pairs > 0
-    e = _rel(_flat(um), _flat(ud))
-    print("rel err", e, flush=True)
+    e = _rel_out(um, ud)
+    print("per-output error", e, flush=True)
     assert e <= TOL32
+
+
+@pytest.fixture(scope="module")
+def deformed_both(B):
+    """The 16 deformed drops p = 48: single layer, raw double layer of a smooth
+    random density and the full velocity solve, in FP64 and mixed."""
+    wl = W.deformed_drops()
+    rng = np.random.default_rng(57)
+    dens = [_density(rng, 48) for _ in wl.drops]
+    out = {}
+    for prec in (B.BIM_PREC_FP64, B.BIM_PREC_MIXED):
+        c = ctx_for(B, wl, precision=prec)
+        sl, dl = c.single_layer(), c.double_layer(dens, mode=0)
+        u, rep = c.eval_velocity()
+        reg, _ = c.regions() if prec == B.BIM_PREC_MIXED else (None, None)
+        out[prec] = (sl, dl, u, rep, reg)
+        c.close()
+    return wl, dens, out
+
+
+def test_mixed_deformed_drops_every_target_against_fp64(B, deformed_both):
+    """Every target of the 16 deformed drops: single layer, double layer and
+    the solved velocity of the mixed form against the FP64 form."""
+    print("mixed: 16 deformed drops p=48 vs FP64", flush=True)
+    wl, dens, out = deformed_both
+    m, d = out[B.BIM_PREC_MIXED], out[B.BIM_PREC_FP64]
+    for k, name in ((0, "SL"), (1, "DL"), (2, "velocity")):
+        e = _rel_out(m[k], d[k])
+        print(name, "per-output error", e, flush=True)
+        assert 1e-12 < e <= TOL32
+    assert abs(m[3].gmres_iterations - d[3].gmres_iterations) <= 1
+
+
+def test_mixed_deformed_drops_sampled_against_oracle(B, orc, deformed_both):
+    """Sampled targets of two drops, near their partner (Omega_1) and far:
+    the mixed single and double layer against the FP64 oracle."""
+    print("mixed: 16 deformed drops p=48 vs oracle, sampled", flush=True)
+    wl, dens, out = deformed_both
+    sl, dl, _, _, reg = out[B.BIM_PREC_MIXED]
+    rng = np.random.default_rng(58)
+    s = osys(orc, wl)
+    n = B.npts(48)
+    forces = [s.force(j) for j in range(len(wl.drops))]
+    es, ed = 0.0, 0.0
+    for i in (0, 13):
+        r = reg[i * n:(i + 1) * n, i ^ 1]
+        near, far = np.nonzero(r != 0)[0], np.nonzero(r == 0)[0]
+        tg = np.sort(np.concatenate([rng.choice(near, 4, replace=False), rng.choice(far, 4, replace=False)]))
+        es = max(es, _rel_out([sl[i][tg]], [-s.layer(i, forces, 0, targets=tg) / (8 * np.pi)]))
+        ed = max(ed, _rel_out([dl[i][tg]], [s.layer(i, dens, 1, targets=tg) / (4 * np.pi)]))
+    print("per-output error SL", es, "DL", ed, flush=True)
+    assert 1e-12 < es <= TOL32 and ed <= TOL32

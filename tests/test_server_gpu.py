@@ -177,3 +177,42 @@ def test_batched_server_small_and_large_requests(B):
         ref = _alone_drops(B, drops)[0]
         for a, b in zip(u, ref):
             assert np.abs(a - b).max() <= 1e-8 * np.abs(b).max()
+
+
+def test_served_results_match_the_oracle(B, orc):
+    """Requests of degree 8 served concurrently (server and oracle both to
+    GMRES tol 1e-12): every served velocity matches the oracle's solve per
+    drop and component to 1e-10."""
+    print("served vs oracle", flush=True)
+    reqs = [r for r in W.serving_requests(n=64) if r.p == 8 and 2 <= len(r.drops) <= 3][:3]
+    assert len(reqs) == 3
+    srv = B.Server(slots=3, gmres_tol=1e-12)
+    ids = [srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]) for r in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for r, (u, rep, t) in zip(reqs, got):
+        s = orc.System([orc.Drop(d.p, d.xc, d.lam) for d in r.drops], orc.Options(gmres_tol=1e-12))
+        uc, it, hist = s.solve()
+        ref = s.velocity_grid(uc)
+        for a, b in zip(u, ref):
+            for c in range(3):
+                assert np.abs(a[:, c] - b[:, c]).max() <= 1e-10 * np.abs(b[:, c]).max()
+
+
+def test_mixed_results_in_the_mix_equal_results_alone(B):
+    """The serving stream's form (FP32 far field, FP64 singular steps and
+    GMRES): results in the mix equal the same request alone bit for bit."""
+    print("server mix vs alone, mixed precision", flush=True)
+    reqs = _requests(8)
+    srv = B.Server(slots=4, precision=B.BIM_PREC_MIXED)
+    ids = [srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]) for r in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for r, (u, rep, t) in zip(reqs, got):
+        c = B.Context(precision=B.BIM_PREC_MIXED)
+        c.set_drops([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops])
+        c.set_tension(None, 0, sigma0=1.0)
+        ref, _ = c.eval_velocity()
+        c.close()
+        for a, b in zip(u, ref):
+            assert np.array_equal(a, b)
