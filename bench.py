@@ -65,8 +65,8 @@ WORKLOADS = {
 # HBM bytes per launch of a kernel from committed rocprofv3 counters
 # (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors a plain copy of known
 # size gives), valid while the kernel's source file is unchanged.
-TRAFFIC = {("pipe_fourier", "two_drops"): ("profiles/pipe_fourier_two_drops_p32_counters.md",
-                                           "paper_1707_02156_amd/csrc/kernels_pipe.hip")}
+TRAFFIC = {("pair_dl", "deformed_drops"): ("profiles/pair_dl_deformed_drops_p48_counters.md",
+                                            "paper_1707_02156_amd/csrc/kernels.hip")}
 
 
 def workload(name):
