@@ -198,6 +198,23 @@ int bim_single_layer(bim_ctx ctx, const double *f_coef, double *out, int mem_kin
  *         P_i the analysis of Sec. 2.1 on drop i's grid. */
 int bim_apply_double_layer(bim_ctx ctx, const double *u_coef, double *out, int mode, int mem_kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operator as bim_apply_double_layer (modes 0 and 1) with nothing allocated.
+ * u_coef and out are device pointers (HIP device memory on the context's
+ * device), written/read on the context stream. The pair partial sums use a
+ * static device array of 256 MiB (one per GPU, held until the process ends);
+ * every other buffer is the context's own, so the context must have applied
+ * bim_apply_double_layer in the same mode to the same drops first (regions,
+ * work lists, stored singular rows and buffers built). Errors: BIM_ESTATE when
+ * that preparation is missing, kernel timing is on, or a step would need to
+ * allocate; BIM_ENOMEM when the partial sums need more than the 256 MiB (the
+ * message gives the size); BIM_EDEVICE when the array's device address is
+ * unavailable. Calls that overlap on one GPU (other contexts or threads)
+ * share the array and race; the array keeps the last call's contents and
+ * needs no clearing (every slot read in a call is written in it). */
+int bim_apply_double_layer_noalloc(bim_ctx ctx, const double *u_coef, double *out, int mode);
+
 /* Full velocity: right-hand side 2 u_inf - (1/4pi) sum_j S_j[f], Galerkin
  * projection and GMRES solve of the second-kind equation when any lambda != 1.
  * out_kind bit 0: 0 = grid values, 1 = coefficients; bit 1: 0 = host, 1 = device.

@@ -123,6 +123,7 @@ EXPORTS = {
     "bim_regions": ([_vp, _vp, _vp, _i], _i),
     "bim_single_layer": ([_vp, _vp, _vp, _i], _i),
     "bim_apply_double_layer": ([_vp, _vp, _vp, _i, _i], _i),
+    "bim_apply_double_layer_noalloc": ([_vp, _vp, _vp, _i], _i),
     "bim_eval_velocity": ([_vp, _vp, _i, ctypes.POINTER(bim_report)], _i),
     "bim_time_step": ([_vp, _d, _d, _d, ctypes.POINTER(bim_step_report)], _i),
     "bim_get_state": ([_vp, _vp, _vp, _i], _i),
@@ -261,6 +262,15 @@ def bim_apply_double_layer(ctx, u_coef, out, mode):
     up, mk = _ptr(u_coef)
     op, _ = _ptr(out)
     return _check(ctx, lib().bim_apply_double_layer(ctx, up, op, mode, mk))
+
+
+def bim_apply_double_layer_noalloc(ctx, u_coef, out, mode):
+    """bim_apply_double_layer without device allocation (device tensors only)."""
+    up, mk = _ptr(u_coef)
+    op, mo = _ptr(out)
+    if mk != BIM_MEM_DEVICE or mo != BIM_MEM_DEVICE:
+        raise ValueError("bim_apply_double_layer_noalloc takes device tensors")
+    return _check(ctx, lib().bim_apply_double_layer_noalloc(ctx, up, op, mode))
 
 
 def bim_eval_velocity(ctx, out, coefficients=False, allow_noconv=False):

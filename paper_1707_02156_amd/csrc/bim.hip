@@ -28,6 +28,7 @@
 #include <map>
 #include <set>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -173,6 +174,11 @@ struct Error {
         if (!(cond)) throw Error{code, msg}; \
     } while (0)
 
+// Set while an entry point that must not allocate device memory runs on
+// this thread (bim_apply_double_layer_noalloc): DBuf::ensure then fails with
+// BIM_ESTATE instead of allocating.
+static thread_local bool t_no_alloc = false;
+
 // Device buffer owned by a context.
 struct DBuf {
     void *ptr = nullptr;
@@ -190,6 +196,9 @@ struct DBuf {
     void ensure(size_t b)
     {
         if (b <= bytes && ptr) return;
+        if (t_no_alloc)
+            throw Error{BIM_ESTATE, "the call would allocate device memory (" + std::to_string(b) +
+                                        " bytes): apply bim_apply_double_layer once to these drops first"};
         release();
         if (b == 0) b = 8;
         // grow with slack: freeing device memory waits for the whole device,
@@ -258,6 +267,7 @@ struct Ctx {
     int pair_ch = 0;                  // sources per pair work item (0: from the pair count)
     int pair_T = 4;                   // targets per lane of the whole-tile pair items
     DBuf pair_part;                   // partial sums of the pair work items [item][3][64 pair_T]
+    double *part_override = nullptr;  // the no-allocation scratch in place of pair_part (during such a call)
     DBuf pack_jobs, rec32_0, rec32_1; // FP32 source records of the mixed form
     std::vector<PackJob> pack_h;
     int pack_n0 = 0, pack_n1 = 0, pack_max0 = 0, pack_max1 = 0;
@@ -1429,22 +1439,23 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
         const float4 *r0 = f32 ? c.rec32_0.as<float4>() : nullptr, *r1 = f32 ? c.rec32_1.as<float4>() : nullptr;
         REQUIRE(!f32 || (r0 && r1), BIM_EDEVICE, "FP32 source records missing");
         const int tile = 64 * c.pair_T, nb = L.nbig, ns = L.n - L.nbig;
+        double *part = c.part_override ? c.part_override : c.pair_part.d();
         {
             // the whole-tile items: the pair-sum kernel proper
             ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs_big * fpp, 0.0);
             launch_pair(c.stream, kind, c.pair_T, nb, L.d.as<PairWork>(), 0, tile, c.tlist.as<int>(), c.tx.d(), c.T,
-                        g0, g1, c.pair_part.d(), r0, r1, c.cbnd.d(), c.nd);
+                        g0, g1, part, r0, r1, c.cbnd.d(), c.nd);
         }
         if (ns > 0) {
             // the 64-target remainders of the target sets, one target per lane
             ProfScope ps(c, kind == 0 ? "pair_sl_rem" : "pair_dl_rem", (L.pairs - L.pairs_big) * fpp, 0.0);
             launch_pair(c.stream, kind, 1, ns, L.d.as<PairWork>() + nb, nb, tile, c.tlist.as<int>(), c.tx.d(), c.T,
-                        g0, g1, c.pair_part.d(), r0, r1, c.cbnd.d(), c.nd);
+                        g0, g1, part, r0, r1, c.cbnd.d(), c.nd);
         }
         {
             ProfScope ps(c, "pair_gather", 0.0, 8.0 * 3.0 * ((double)L.g.h_tent.size() * tile + L.g.h_ent.size()));
             launch_pair_gather(c.stream, (int)c.T, tile, c.tile_of.as<int>(), L.g.toff.as<int>(), L.g.tent.as<int>(),
-                               L.g.off.as<int>(), L.g.ent.as<int>(), c.pair_part.d(), c.acc.d(), c.T, true);
+                               L.g.off.as<int>(), L.g.ent.as<int>(), part, c.acc.d(), c.T, true);
         }
     }
     run_fmm(c, kind, L);
@@ -1464,16 +1475,18 @@ static void run_near(Ctx &c, int kind, const double *dens, const std::vector<dou
         jobs.push_back(ana_job(c, d.p, d.p, 3, c.near_self.d() + d.toff, c.T, c.near_selfc.d() + d.coff, c.Ctot));
     }
     ana_run(c, jobs);
+    // every interpolation point belongs to one item list (its grid), so the
+    // gather below writes all of near_vacc
     const long V = (long)c.near_h.size() * c.opt.near_L;
-    HIPC(hipMemsetAsync(c.near_vacc.ptr, 0, 3 * V * sizeof(double), c.stream));
+    double *part = c.part_override ? c.part_override : c.pair_part.d();
     const double fpp = kind == 0 ? 29.0 : 30.0;
     ProfScope ps(c, "near", c.near_pairs * fpp, 0.0);
     const PairSrc g0{c.tx.d(), c.s0N.d(), c.s0W.d(), c.s0d.d(), c.T};
     const PairSrc g1{c.s1x.d(), c.s1N.d(), c.s1W.d(), c.s1d.d(), c.S1};
     launch_pair(c.stream, kind, 1, c.near_nwork, c.near_work.as<PairWork>(), 0, 64, c.near_tl.as<int>(), c.near_vx.d(),
-                V, g0, g1, c.pair_part.d());
+                V, g0, g1, part);
     launch_pair_gather(c.stream, (int)V, 64, nullptr, nullptr, nullptr, c.near_g.off.as<int>(),
-                       c.near_g.ent.as<int>(), c.pair_part.d(), c.near_vacc.d(), V, false);
+                       c.near_g.ent.as<int>(), part, c.near_vacc.d(), V, false);
     launch_near_interp(c.stream, near_args(c), kind, c.near_selfc.d(), dens, c.near_vacc.d(), L.nw.d(),
                        c.near_res.d());
     launch_pair_gather(c.stream, (int)c.T, (int)c.near_h.size(), nullptr, nullptr, nullptr, c.near_tg.off.as<int>(),
@@ -2133,6 +2146,35 @@ int bim_default_options(bim_options *o)
     return BIM_OK;
 }
 
+// --------------------------------------------------------------------------
+// Scratch of bim_apply_double_layer_noalloc: the partial sums of the pair
+// work items (the buffer pair_part of the other entry points), in a
+// file-scope device array. Every GPU the library runs on holds its own copy
+// until the process ends; its device address is looked up once per device
+// (in bim_create, with the device current) and kept in g_scratch.
+// --------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = (size_t)1 << 25;  // 256 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch[kMaxDevices];
+static bool g_scratch_tried[kMaxDevices];
+
+// The device address of `scratch` on the current device `dev` (nullptr if the
+// lookup failed or dev is out of range).
+static double *scratch_on(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_tried[dev]) {
+        g_scratch_tried[dev] = true;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[dev] = static_cast<double *>(p);
+        else (void)hipGetLastError();
+    }
+    return g_scratch[dev];
+}
+
 int bim_create(const bim_options *opt, bim_ctx *out)
 {
     if (!opt || !out) return BIM_EINVAL;
@@ -2162,6 +2204,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
         delete h;
         return BIM_EDEVICE;
     }
+    (void)scratch_on(opt->device);  // once per device: the no-allocation entry point's scratch
     if (opt->stream) {
         c.stream = static_cast<hipStream_t>(opt->stream);
     } else {
@@ -2876,6 +2919,58 @@ int bim_apply_double_layer(bim_ctx h, const double *u_coef, double *out, int mod
             c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
             apply_operator(c, c.xsol.d(), c.bvec.d(), dl_weights(c));
             copy_out(c, out, c.bvec.ptr, (size_t)3 * c.Ctot * sizeof(double), mem_kind);
+        }
+        return BIM_OK;
+    });
+}
+
+// The same operator with nothing allocated: the pair partial sums go to the
+// static scratch of the context's device, every other buffer must exist
+// (t_no_alloc turns an allocation into BIM_ESTATE). Device pointers only.
+int bim_apply_double_layer_noalloc(bim_ctx h, const double *u_coef, double *out, int mode)
+{
+    return guarded(h ? &h->c : nullptr, [&]() {
+        Ctx &c = h->c;
+        require_drops(c);
+        REQUIRE(u_coef && out, BIM_EINVAL, "null argument");
+        REQUIRE(mode == 0 || mode == 1, BIM_EINVAL, "mode must be 0 or 1");
+        double *sp = scratch_on(c.device);
+        REQUIRE(sp, BIM_EDEVICE, "the device address of the no-allocation scratch is not available");
+        REQUIRE(!c.prof_on, BIM_ESTATE, "kernel timing is on (it creates events): bim_profile(ctx, 0) first");
+        REQUIRE(c.regions_ok, BIM_ESTATE,
+                "the drops' regions and pair work lists are not built: apply bim_apply_double_layer once first");
+        const std::vector<double> wt =
+            mode == 0 ? std::vector<double>((size_t)c.nd * c.nd, 1.0 / (4.0 * kPi)) : dl_weights(c);
+        const Ctx::WList *L = nullptr;
+        for (auto &e : c.wlists)
+            if (e->wt == wt) L = e.get();
+        REQUIRE(L, BIM_ESTATE, "the pair work list of this mode is not built: apply bim_apply_double_layer once first");
+        const double need = std::max((double)L->n * 3 * 64 * c.pair_T, (double)c.near_nwork * 3 * 64);
+        REQUIRE(need <= (double)kScratchDoubles, BIM_ENOMEM,
+                "the pair partial sums need " + std::to_string((long)(need * 8 / (1 << 20))) +
+                    " MiB, above the " + std::to_string((long)(kScratchDoubles * 8 >> 20)) + " MiB scratch");
+        struct Guard {  // restores the context and the thread flag, also when a step throws
+            Ctx &c;
+            Guard(Ctx &cc, double *p) : c(cc)
+            {
+                t_no_alloc = true;
+                c.part_override = p;
+            }
+            ~Guard()
+            {
+                t_no_alloc = false;
+                c.part_override = nullptr;
+            }
+        } guard(c, sp);
+        c.xsol.ensure((size_t)3 * c.Ctot * sizeof(double));
+        copy_in(c, c.xsol.ptr, u_coef, (size_t)3 * c.Ctot * sizeof(double), BIM_MEM_DEVICE);
+        if (mode == 0) {
+            double_layer_grid(c, c.xsol.d(), wt);
+            copy_out(c, out, c.acc.ptr, (size_t)3 * c.T * sizeof(double), BIM_MEM_DEVICE);
+        } else {
+            c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
+            apply_operator(c, c.xsol.d(), c.bvec.d(), wt);
+            copy_out(c, out, c.bvec.ptr, (size_t)3 * c.Ctot * sizeof(double), BIM_MEM_DEVICE);
         }
         return BIM_OK;
     });
