@@ -113,6 +113,12 @@ typedef struct {
                             and centres of i's nodes and of j's source grid); the others are
                             summed directly */
     double fmm_eps;      /* truncation bound of a far pair, in (0, 1) */
+    int pair_tune;       /* 1: the work-item shape of the direct pair sums (targets per lane 1, 2
+                            or 4; sources per item) is chosen by timing a double-layer pair pass
+                            of each candidate at the first evaluation after bim_set_drops, and
+                            kept for later contexts of the same problem shape (same number of
+                            pairs to two digits, targets, fast-summation order) in the process;
+                            0: a rule from the pair count. Only the speed depends on it */
 } bim_options;
 
 typedef struct {
@@ -125,6 +131,8 @@ typedef struct {
     double ms_total;          /* wall time of the call */
     int n_fmm_pairs;          /* drop pairs taken by the fast summation (fmm_order != 0) */
     int fmm_order;            /* multipole order in use (0: every pair summed directly) */
+    int pair_targets_per_lane;  /* work-item shape of the direct pair sums in use: targets per lane */
+    int pair_sources_per_item;  /* and sources per item (0: from the pair count) */
 } bim_report;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -133,7 +141,7 @@ int bim_version(void);
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
- * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10. */
+ * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10, pair_tune 1. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */

@@ -42,6 +42,7 @@ class bim_options(ctypes.Structure):
         ("near_L", ctypes.c_int),
         ("fmm_order", ctypes.c_int),
         ("fmm_eps", ctypes.c_double),
+        ("pair_tune", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,8 @@ class bim_report(ctypes.Structure):
         ("ms_total", ctypes.c_double),
         ("n_fmm_pairs", ctypes.c_int),
         ("fmm_order", ctypes.c_int),
+        ("pair_targets_per_lane", ctypes.c_int),
+        ("pair_sources_per_item", ctypes.c_int),
     ]
 
     def as_dict(self):

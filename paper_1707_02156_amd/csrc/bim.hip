@@ -31,6 +31,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace bim {
@@ -265,7 +266,10 @@ struct Ctx {
     std::vector<int> tlist_h;         // host image of tlist
     std::vector<PairWork> w0h, w1h;   // pair work templates (weights per pass)
     int pair_ch = 0;                  // sources per pair work item (0: from the pair count)
-    int pair_T = 4;                   // targets per lane of the whole-tile pair items
+    int pair_T_fix = 0;               // targets per lane of whole tiles (0: from the pair count)
+    int pair_T = 4;                   // targets per lane of the whole-tile pair items in use
+    bool pair_tuned = false;          // pair_T_fix / pair_ch chosen by tune_pairs for these drops
+    double npairs_direct = 0.0;       // direct pairs of one application (the last build_lists)
     DBuf pair_part;                   // partial sums of the pair work items [item][3][64 pair_T]
     double *part_override = nullptr;  // the no-allocation scratch in place of pair_part (during such a call)
     DBuf pack_jobs, rec32_0, rec32_1; // FP32 source records of the mixed form
@@ -787,7 +791,7 @@ constexpr double kPairItemsTarget = 28672.0, kPairItemsMin = 8192.0;
 constexpr int kPairSmall = 4;  // PairWork.pad: a 64-target remainder item (one target per lane)
 static void pair_shape(Ctx &c, double pairs, int &T, int &ch)
 {
-    T = pairs / (64.0 * 4 * 64) < kPairItemsMin ? 1 : 4;
+    T = c.pair_T_fix > 0 ? c.pair_T_fix : pairs / (64.0 * 4 * 64) < kPairItemsMin ? 1 : 4;
     if (c.pair_ch > 0) {
         ch = c.pair_ch;
         return;
@@ -1189,6 +1193,7 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     }
     int CH = 64;
     pair_shape(c, npairs, c.pair_T, CH);
+    c.npairs_direct = npairs;
     target_tiles(c, c.pair_T);
     for (const Seg &g : segs)
         pair_items(g.grid == 0 ? w0 : w1, g.tl_off, g.cnt, g.contig, g.soff, g.ns, g.pair, g.grid, c.pair_T, CH, 0.0);
@@ -1240,6 +1245,99 @@ static int tune_fmm(Ctx &c, const std::vector<double> &cb0, const std::vector<do
     (void)hipEventDestroy(e1);
     HIPC(hipMemsetAsync(c.acc.ptr, 0, (size_t)3 * c.T * sizeof(double), c.stream));
     return best;
+}
+
+// Work-item shape of the pair sums chosen by timing (option pair_tune):
+// targets per lane T in {1, 2, 4} and sources per item ch in {ch0/2, ch0,
+// 2 ch0} (ch0 the pair-count rule's choice for that T), double-layer pair
+// passes (unit weights, after a warm-up pass) timed with HIP events on the
+// context stream, two rounds over the candidates, the faster of each
+// candidate's two counted. The rule's own shape is kept unless a candidate
+// beats it by more than kTuneMargin (a single pass varies by a few percent
+// run to run; a smaller gain is not worth a shape chosen on noise). The
+// choice depends on the
+// problem's shape only, so it is cached for the process under (direct pairs
+// of an application to two significant digits, targets, order of the fast
+// summation): later contexts of the same shape reuse it without timing, and
+// contexts that time the same shape concurrently all adopt the first result
+// stored, so results in one process do not depend on which context tuned.
+struct PairShapeKey {
+    long mant, targets;  // pairs = mant 10^expo, mant in [10, 99]
+    int expo, P;
+    bool operator<(const PairShapeKey &o) const
+    {
+        return std::tie(mant, expo, targets, P) < std::tie(o.mant, o.expo, o.targets, o.P);
+    }
+};
+static std::mutex g_shape_mu;
+static std::map<PairShapeKey, std::pair<int, int>> g_shapes;
+constexpr float kTuneMargin = 0.03f;
+
+static void tune_pairs(Ctx &c, int P, const std::vector<double> &cb0, const std::vector<double> &cb1)
+{
+    c.pair_T_fix = 0;
+    c.pair_ch = 0;
+    build_lists(c, P, cb0, cb1);
+    c.pair_tuned = true;
+    if (c.npairs_direct <= 0.0) return;
+    const int expo = (int)std::floor(std::log10(c.npairs_direct)) - 1;
+    const PairShapeKey key{(long)std::llround(c.npairs_direct / std::pow(10.0, expo)), c.T, expo, P};
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        auto it = g_shapes.find(key);
+        if (it != g_shapes.end()) {
+            c.pair_T_fix = it->second.first;
+            c.pair_ch = it->second.second;
+            return;
+        }
+    }
+    const std::vector<double> ones((size_t)c.nd * c.nd, 1.0);
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    int rT = 0, rch = 0;  // the rule's shape
+    c.pair_T_fix = 0;
+    c.pair_ch = 0;
+    pair_shape(c, c.npairs_direct, rT, rch);
+    std::vector<std::pair<int, int>> cand;
+    for (int T : {4, 2, 1}) {
+        int T0 = T, ch0 = 64;
+        c.pair_T_fix = T;
+        c.pair_ch = 0;
+        pair_shape(c, c.npairs_direct, T0, ch0);
+        for (int ch : {ch0 / 2, ch0, 2 * ch0}) {
+            ch = std::min(4096, std::max(64, ch / 64 * 64));
+            if (std::find(cand.begin(), cand.end(), std::make_pair(T, ch)) == cand.end()) cand.emplace_back(T, ch);
+        }
+    }
+    if (std::find(cand.begin(), cand.end(), std::make_pair(rT, rch)) == cand.end()) cand.emplace_back(rT, rch);
+    std::vector<float> best(cand.size(), 0.0f);
+    for (int round = 0; round < 2; ++round)
+        for (size_t k = 0; k < cand.size(); ++k) {
+            c.pair_T_fix = cand[k].first;
+            c.pair_ch = cand[k].second;
+            build_lists(c, P, cb0, cb1);
+            if (round == 0) run_pairs(c, 1, ones);  // warm-up
+            HIPC(hipEventRecord(e0, c.stream));
+            run_pairs(c, 1, ones);
+            HIPC(hipEventRecord(e1, c.stream));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            best[k] = round == 0 ? ms : std::min(best[k], ms);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPC(hipMemsetAsync(c.acc.ptr, 0, (size_t)3 * c.T * sizeof(double), c.stream));
+    size_t kr = std::find(cand.begin(), cand.end(), std::make_pair(rT, rch)) - cand.begin(), kb = kr;
+    for (size_t k = 0; k < cand.size(); ++k)
+        if (best[k] < best[kb]) kb = k;
+    if (!(best[kb] < (1.0f - kTuneMargin) * best[kr])) kb = kr;
+    const int bestT = cand[kb].first, bestch = cand[kb].second;
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    const auto it = g_shapes.emplace(key, std::make_pair(bestT, bestch)).first;  // the first stored wins
+    c.pair_T_fix = it->second.first;
+    c.pair_ch = it->second.second;
 }
 
 static void build_regions(Ctx &c)
@@ -1320,6 +1418,7 @@ static void build_regions(Ctx &c)
         if (c.fmm_tuned < 0) c.fmm_tuned = tune_fmm(c, cb0, cb1);
         P = c.fmm_tuned;
     }
+    if (c.opt.pair_tune && pairs && !c.pair_tuned) tune_pairs(c, P, cb0, cb1);
     build_lists(c, P, cb0, cb1);
     near_setup(c);
     c.regions_ok = true;
@@ -2143,6 +2242,7 @@ int bim_default_options(bim_options *o)
     o->near_L = 8;
     o->fmm_order = 0;
     o->fmm_eps = 1e-10;
+    o->pair_tune = 1;
     return BIM_OK;
 }
 
@@ -2246,6 +2346,8 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         REQUIRE(n_drops >= 1 && p && xcoef && lambda, BIM_EINVAL, "bim_set_drops: null argument or no drops");
         REQUIRE(mem_kind == BIM_MEM_HOST || mem_kind == BIM_MEM_DEVICE, BIM_EINVAL, "bad mem_kind");
         c.fmm_tuned = -1;  // a new system: choose the fast-summation order again
+        c.pair_tuned = false;
+        c.pair_T_fix = c.pair_ch = 0;
         std::vector<Drop> ds(n_drops);
         long coff = 0, toff = 0, uoff = 0;
         for (int i = 0; i < n_drops; ++i) {
@@ -2362,6 +2464,8 @@ int bim_set_systems(bim_ctx h, const int *system_of_drop)
         c.regions_ok = false;
         c.regions_exact = false;
         c.fmm_tuned = -1;  // other drop pairs: choose the fast-summation order again
+        c.pair_tuned = false;
+        c.pair_T_fix = c.pair_ch = 0;
         return BIM_OK;
     });
 }
@@ -3141,6 +3245,8 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
             rep->n_omega2 = c.n_om2;
             rep->n_fmm_pairs = (int)c.fmm.pairs.size();
             rep->fmm_order = c.fmm.P;
+            rep->pair_targets_per_lane = c.pair_T;
+            rep->pair_sources_per_item = c.pair_ch;
             rep->n_matvec = nmv;
             rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }

@@ -224,7 +224,11 @@ int bim_server_default_options(bim_server_options *o)
     o->hbm_budget_gb = 64.0;
     o->max_batch = 1;
     o->max_batch_drops = 128;
-    return bim_default_options(&o->opt);
+    const int rc = bim_default_options(&o->opt);
+    // requests are mostly one-off problem shapes: timing the pair work shape
+    // of each would cost more than it saves and add to the latency tail
+    o->opt.pair_tune = 0;
+    return rc;
 }
 
 int bim_server_create(const bim_server_options *opt, bim_server *out)

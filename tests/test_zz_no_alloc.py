@@ -96,3 +96,55 @@ def test_noalloc_error_paths(B):
     assert B.lib().bim_apply_double_layer_noalloc(ctx.h, u.data_ptr(), out.data_ptr(), 0) == B.BIM_OK
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_noalloc_operator_replayed_from_a_graph(B):
+    """The allocation-free operator captured once in a HIP graph (torch's graph
+    capture on the context's stream) and replayed four times, with a new
+    density written in place (eager) between replays: every replay equals
+    the eager operator on the same density."""
+    import torch
+    print("no-alloc operator in a graph", flush=True)
+    s = torch.cuda.Stream()
+    rng = np.random.default_rng(74)
+    ps = [10, 10]
+    xs = [W.perturbed_sphere(rng, p, 1.0, c, 0.05) for p, c in zip(ps, [(0, 0, 0), (2.3, 0.1, 0)])]
+    ctx = B.Context(stream=s.cuda_stream)
+    ctx.set_drops(ps, xs, [2.0, 4.0])
+    ctx.set_tension(None, 0, sigma0=1.0)
+
+    def dens():
+        out = []
+        for p in ps:
+            d = rng.standard_normal((3, B.ncoef(p), 2))
+            d[..., [n * (n + 1) // 2 for n in range(p + 1)], 1] = 0.0
+            d[..., p * (p + 1) // 2 + p, 1] = 0.0
+            out.append(d)
+        return torch.tensor(B.pack_coefficients(out), dtype=torch.float64, device="cuda")
+
+    n = 3 * sum(B_npts(p) for p in ps)
+    u = dens()
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s):
+        B.bim_apply_double_layer(ctx.h, u, ref, 0)        # prepares the context
+        assert B.lib().bim_apply_double_layer_noalloc(ctx.h, u.data_ptr(), out.data_ptr(), 0) == B.BIM_OK
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rc = B.lib().bim_apply_double_layer_noalloc(ctx.h, u.data_ptr(), out.data_ptr(), 0)
+    assert rc == B.BIM_OK, B.lib().bim_last_error(ctx.h)
+    for r in range(4):
+        u.copy_(dens())                                     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            B.bim_apply_double_layer(ctx.h, u, ref, 0)
+        torch.cuda.synchronize()
+        a, b = out.cpu().numpy(), ref.cpu().numpy()
+        e = _per_output_err(a, b, ps, True)
+        print("replay", r, "per-output error", e, "bit-identical", bool(np.array_equal(a, b)), flush=True)
+        assert e <= 1e-10
+    del g
+    ctx.close()
