@@ -191,6 +191,12 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
 // point records of 12 fields padded to an odd number of doubles, so that
 // lanes reading consecutive points hit distinct LDS banks
 constexpr int kVS = 13;
+// Each target's block of point records starts 6 doubles (12 banks) further
+// round the LDS banks than the previous one: the Fourier-analysis stage reads
+// the same point of up to 4 targets x 6 stresslet fields in one instruction,
+// and with blocks a multiple of 32 doubles apart (2 qs 13 is, for even qs)
+// those 24 reads fell on 6 bank pairs.
+__host__ __device__ inline long fk_vt(int nk) { return (long)nk * kVS + ((6 - (long)nk * kVS % 32) % 32 + 32) % 32; }
 
 // 1/sqrt(x) to full double precision: hardware estimate plus one third-order
 // correction (relative error of the estimate e -> O(e^3))
@@ -217,8 +223,9 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     constexpr int NTY = SL ? 4 : 3;
     double *sG = sm;
     const long gsz = (long)TG * P1 * NTY * 6;
-    double *V = sG + gsz;                    // [tg][k'][kVS]: 12 fields, padded
-    double *sCS = V + (long)TG * nk * kVS + TG * 3;  // cos, sin of pi e / qs, e < 2 qs
+    const long VT = fk_vt(nk);
+    double *V = sG + gsz;                    // [tg][k'][kVS] at tg VT: 12 fields, padded
+    double *sCS = V + (long)TG * VT + TG * 3;  // cos, sin of pi e / qs, e < 2 qs
     for (int e = threadIdx.x; e < 2 * nk; e += 256) sCS[e] = cs[e];
     // ---- load G (weights w_mu applied; x_phi built from x)
     for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 }
             }
         }
-        double *Vb = V + (long)tg * nk * kVS;
+        double *Vb = V + (long)tg * VT;
         // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -347,7 +354,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     for (int it = threadIdx.x; it < ((ntg * nk + 63) & ~63); it += 256) {
         const bool ok = it < ntg * nk;
         const int tg = ok ? it / nk : 0;
-        double *v = V + (long)(ok ? it : 0) * kVS;
+        double *v = V + (long)tg * VT + (long)(ok ? it % nk : 0) * kVS;
         const int t = t0 + tg;
         double e0 = 0.0, e1 = 0.0, e2 = 0.0;
         if (ok) {
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
             const int tg = g / 3, cc = g % 3;
             double sum = 0.0;
             if (act)
-                for (int k = l; k < nk; k += 16) sum += V[(long)(tg * nk + k) * kVS + 9 + cc];
+                for (int k = l; k < nk; k += 16) sum += V[(long)tg * VT + (long)k * kVS + 9 + cc];
             for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
             if (act && l == 0) part[((long)(t0 + tg) * Q1 + jr) * 3 + cc] = sum;
         }
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
             const bool odd = gidx >= NGe;
             const int base = odd ? 8 * (gidx - NGe) + 1 : 8 * gidx;
             const double sg = odd ? -1.0 : 1.0;
-            const double *Vb = V + (long)tg * nk * kVS + pr;
+            const double *Vb = V + (long)tg * VT + pr;
             double tq[4], cq[4], sq[4], cp[4], sp[4], fc[4], fs[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -631,7 +638,7 @@ int leg_mfma_max_depth() { return 52; }
 size_t fk_lds_bytes(int p, int qs, bool sl, int tg)
 {
     const int nty = sl ? 4 : 3;
-    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * 2 * qs * kVS + (size_t)tg * 3 + 4 * (size_t)qs) *
+    return ((size_t)tg * (p + 1) * nty * 6 + (size_t)tg * fk_vt(2 * qs) + (size_t)tg * 3 + 4 * (size_t)qs) *
            sizeof(double);
 }
 
