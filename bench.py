@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X peaks: FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz), HBM3E
 PEAK = {"alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
-BOUND = {"sing_fused": "alu", "pair_sl": "alu", "pair_dl": "alu", "pair_sl_rem": "alu", "pair_dl_rem": "alu",
+BOUND = {"sing_fused": "alu", "pair_sl": "alu", "pair_dl": "alu",
          "pair_gather": "hbm", "pair_pack": "hbm", "dl_apply": "hbm",
          "synthesis": "hbm", "analysis": "hbm", "sing_v1": "alu", "sing_rotate": "alu", "classify": "alu",
          "pipe_rotate": "alu", "pipe_legendre": "hbm", "pipe_fourier": "alu", "pipe_adjrot": "alu", "near": "alu",

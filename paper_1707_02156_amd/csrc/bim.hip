@@ -296,9 +296,8 @@ struct Ctx {
         std::vector<double> h_nw;
         std::vector<FmmPair> h_fp;
         DBuf d;
-        int n = 0, nbig = 0;  // items; the first nbig are whole tiles, the rest 64-target remainders
+        int n = 0;           // items: whole tiles first, then the remainder items
         double pairs = 0.0;  // target-source pairs per application
-        double pairs_big = 0.0;  // of them, in the whole-tile items
         Gather g;
         DBuf nw;             // weight of each nearest-region item
         DBuf fp;             // far pairs of the fast summation with their weights
@@ -780,7 +779,7 @@ static NearArgs near_args(Ctx &c)
 }
 
 // Work-item shape of the pair sums from the pairs of one application:
-// targets per lane T of the whole tiles (4; 1 when even the shortest source
+// targets per lane T of the whole tiles (2; 1 when even the shortest source
 // runs would leave fewer than kPairItemsMin items, as for two drops of
 // degree 32, where more, smaller items fill the chip better) and the
 // sources per item: about kPairItemsTarget items per application (about 28
@@ -788,10 +787,9 @@ static NearArgs near_args(Ctx &c)
 // the per-item set-up and partial writes start to show), a multiple of 64
 // between 64 and 4096. pair_ch > 0 fixes the sources per item.
 constexpr double kPairItemsTarget = 28672.0, kPairItemsMin = 8192.0;
-constexpr int kPairSmall = 4;  // PairWork.pad: a 64-target remainder item (one target per lane)
 static void pair_shape(Ctx &c, double pairs, int &T, int &ch)
 {
-    T = c.pair_T_fix > 0 ? c.pair_T_fix : pairs / (64.0 * 4 * 64) < kPairItemsMin ? 1 : 4;
+    T = c.pair_T_fix > 0 ? c.pair_T_fix : pairs / (64.0 * 2 * 64) < kPairItemsMin ? 1 : 2;
     if (c.pair_ch > 0) {
         ch = c.pair_ch;
         return;
@@ -800,15 +798,25 @@ static void pair_shape(Ctx &c, double pairs, int &T, int &ch)
     ch = (int)std::min<long>(4096, std::max<long>(64, n));
 }
 
-// Items of (target set, source range): whole tiles of 64 T targets (T > 1),
-// the rest in 64-target remainder items (flag kPairSmall), each split into
-// runs of ch sources; appended to w.
+// Targets of the next item of a target set with r targets left: a whole
+// tile of 64 T targets while that many remain; a shorter tail as one ragged
+// whole tile when its 64-target pieces would fill T of them anyway (r > 64
+// (T - 1)), else as 64-target remainder items (whole = false).
+static int pair_chunk(int T, int r, bool &whole)
+{
+    whole = r > 64 * (T - 1);
+    return std::min(whole ? 64 * T : 64, r);
+}
+
+// Items of (target set, source range): whole tiles of 64 T targets, the rest
+// in remainder items of one target per lane (flag kPairSmall), each split
+// into runs of ch sources; appended to w.
 static void pair_items(std::vector<PairWork> &w, int tl_off, int cnt, bool contig, long soff, int ns, int pair,
                        int grid, int T, int ch, double wt)
 {
     for (int a = 0; a < cnt;) {
-        const bool whole = T > 1 && cnt - a >= 64 * T;
-        const int sz = whole ? 64 * T : std::min(64, cnt - a);
+        bool whole = true;
+        const int sz = pair_chunk(T, cnt - a, whole);
         for (int b = 0; b < ns; b += ch) {
             PairWork pw;
             pw.tlist_off = tl_off + a;
@@ -816,7 +824,7 @@ static void pair_items(std::vector<PairWork> &w, int tl_off, int cnt, bool conti
             pw.src_off = (int)(soff + b);
             pw.nsrc = std::min(ch, ns - b);
             pw.pair = pair;
-            pw.pad = grid | (contig ? kPairContig : 0) | (whole || T == 1 ? 0 : kPairSmall);
+            pw.pad = grid | (contig ? kPairContig : 0) | (whole ? 0 : kPairSmall);
             pw.w = wt;
             w.push_back(pw);
         }
@@ -873,7 +881,7 @@ static void gather_lists(Ctx &c, const std::vector<PairWork> &items, const std::
 }
 
 // Target tiles of each drop's consecutive targets, split as pair_items
-// splits a contiguous target set: whole tiles of 64 T, then tiles of 64.
+// splits a contiguous target set.
 static void target_tiles(Ctx &c, int T)
 {
     c.tile_of_h.resize(std::max<long>(1, c.T));
@@ -881,7 +889,8 @@ static void target_tiles(Ctx &c, int T)
     for (const Drop &d : c.drops) {
         const int nt = npts(d.p);
         for (int a = 0; a < nt;) {
-            const int sz = T > 1 && nt - a >= 64 * T ? 64 * T : std::min(64, nt - a);
+            bool whole = true;
+            const int sz = pair_chunk(T, nt - a, whole);
             c.tile_start_h.push_back((int)(d.toff + a));
             for (int b = a; b < a + sz; ++b) c.tile_of_h[d.toff + b] = (int)c.tile_start_h.size() - 1;
             a += sz;
@@ -1444,10 +1453,6 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
                     e->pairs += (double)pw.ntgt * pw.nsrc;
                 }
             }
-        if (!small) {
-            e->nbig = (int)keep.size();
-            e->pairs_big = e->pairs;
-        }
     }
     e->d.ensure(std::max<size_t>(1, keep.size()) * sizeof(PairWork));
     if (!keep.empty())
@@ -1537,18 +1542,12 @@ static void run_pairs(Ctx &c, int kind, const std::vector<double> &wt)
         }
         const float4 *r0 = f32 ? c.rec32_0.as<float4>() : nullptr, *r1 = f32 ? c.rec32_1.as<float4>() : nullptr;
         REQUIRE(!f32 || (r0 && r1), BIM_EDEVICE, "FP32 source records missing");
-        const int tile = 64 * c.pair_T, nb = L.nbig, ns = L.n - L.nbig;
+        const int tile = 64 * c.pair_T;
         double *part = c.part_override ? c.part_override : c.pair_part.d();
         {
-            // the whole-tile items: the pair-sum kernel proper
-            ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs_big * fpp, 0.0);
-            launch_pair(c.stream, kind, c.pair_T, nb, L.d.as<PairWork>(), 0, tile, c.tlist.as<int>(), c.tx.d(), c.T,
-                        g0, g1, part, r0, r1, c.cbnd.d(), c.nd);
-        }
-        if (ns > 0) {
-            // the 64-target remainders of the target sets, one target per lane
-            ProfScope ps(c, kind == 0 ? "pair_sl_rem" : "pair_dl_rem", (L.pairs - L.pairs_big) * fpp, 0.0);
-            launch_pair(c.stream, kind, 1, ns, L.d.as<PairWork>() + nb, nb, tile, c.tlist.as<int>(), c.tx.d(), c.T,
+            // whole tiles first, the remainder items after them (they fill the launch's tail)
+            ProfScope ps(c, kind == 0 ? "pair_sl" : "pair_dl", L.pairs * fpp, 0.0);
+            launch_pair(c.stream, kind, c.pair_T, L.n, L.d.as<PairWork>(), 0, tile, c.tlist.as<int>(), c.tx.d(), c.T,
                         g0, g1, part, r0, r1, c.cbnd.d(), c.nd);
         }
         {

@@ -50,10 +50,12 @@ struct PairWork {
     int nsrc;       // source nodes in this item
     int pair;       // target drop * n_drops + source drop
     int pad;        // bit 0: source grid (0 standard, 1 upsampled); kPairContig: targets
-                    // tlist_off .. tlist_off + ntgt - 1, no index list
+                    // tlist_off .. tlist_off + ntgt - 1, no index list; kPairSmall: a
+                    // remainder item (<= 64 targets, one per lane)
     double w;       // weight applied to the sum
 };
 constexpr int kPairContig = 2;
+constexpr int kPairSmall = 4;
 
 // Device state of the GMRES least-squares problem (Givens rotations applied
 // on the device): R by columns, rotations, right-hand side g, and the

@@ -477,7 +477,8 @@ __global__ __launch_bounds__(256) void k_singular(int p, int qs, int kind, const
 // part[(item0 + i) * 3 * tile + c * tile + slot]; k_pair_gather then adds the
 // slots of each target in a fixed order, so the sums do not depend on
 // scheduling. Items of whole tiles run with T = the tile's targets per lane,
-// the 64-target remainders of a target set with T = 1.
+// the remainder items of a target set (flag kPairSmall) with T = 1, in the
+// same launch.
 // ----------------------------------------------------------------------------
 constexpr int kPairWaves = 4;  // wavefronts (independent items) per block
 
@@ -532,16 +533,13 @@ __device__ inline void pair64(double X, double Y, double Z, double px, double py
 // T targets per lane; U = 8 / T consecutive sources per step, each into its
 // own accumulators (independent work for one lane when T is small), added in
 // a fixed order at the end.
-template <int KIND, int T>
-__global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
-                                                         int tile, const int *__restrict__ tlist,
-                                                         const double *__restrict__ tx, long tstride, PairSrc g0,
-                                                         PairSrc g1, double *__restrict__ part)
+// One item of the FP64 sums with T targets per lane and U independent
+// accumulators per target (consecutive sources alternate between them).
+template <int KIND, int T, int U>
+__device__ inline void pair_item64(const PairWork &w, int item, int tile, const int *__restrict__ tlist,
+                                   const double *__restrict__ tx, long tstride, const PairSrc &g0,
+                                   const PairSrc &g1, double *__restrict__ part)
 {
-    constexpr int U = T >= 4 ? 1 : 8 / T;
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
-    if (item >= nwork) return;
-    const PairWork w = work[item];
     const int lane = threadIdx.x & 63;
     double X[T], Y[T], Z[T], A0[T][U], A1[T][U], A2[T][U];
 #pragma unroll
@@ -587,7 +585,7 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__rest
         for (; s < w.nsrc; ++s) step(s, 0);
     }
     const double sw = KIND == 0 ? w.w : -6.0 * w.w;
-    double *out = part + (long)(item0 + item) * (3 * tile) + lane;
+    double *out = part + (long)item * (3 * tile) + lane;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
 #pragma unroll
@@ -600,6 +598,25 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__rest
         out[tile + 64 * k] = sw * A1[k][0];
         out[2 * tile + 64 * k] = sw * A2[k][0];
     }
+}
+
+// Items [0, nwork) of a work list: whole tiles (ntgt <= 64 T; a ragged last
+// tile of a target set repeats its last target in the surplus slots) with T
+// targets per lane, remainder items (flag kPairSmall, at most 64 targets)
+// with one. The item index is uniform over the wavefront, so the branch is.
+template <int KIND, int T>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
+                                                         int tile, const int *__restrict__ tlist,
+                                                         const double *__restrict__ tx, long tstride, PairSrc g0,
+                                                         PairSrc g1, double *__restrict__ part)
+{
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
+    if (item >= nwork) return;
+    const PairWork w = work[item];
+    if (T > 1 && (w.pad & kPairSmall))
+        pair_item64<KIND, 1, (T >= 4 ? 2 : 4)>(w, item0 + item, tile, tlist, tx, tstride, g0, g1, part);
+    else
+        pair_item64<KIND, T, (T >= 4 ? 1 : 8 / T)>(w, item0 + item, tile, tlist, tx, tstride, g0, g1, part);
 }
 
 // FP32 source records of the mixed form, three float4 per node at the node's
@@ -639,17 +656,11 @@ __global__ void k_pair_pack32(const PackJob *__restrict__ jobs, PairSrc G, const
 constexpr int kPairRun = 16;
 
 template <int KIND, int T>
-__global__ __launch_bounds__(64 * kPairWaves) void k_pair32(const PairWork *__restrict__ work, int nwork, int item0,
-                                                           int tile, const int *__restrict__ tlist,
-                                                           const double *__restrict__ tx, long tstride,
-                                                           const float4 *__restrict__ rec0,
-                                                           const float4 *__restrict__ rec1,
-                                                           const double *__restrict__ cb, int nd,
-                                                           double *__restrict__ part)
+__device__ inline void pair_item32(const PairWork &w, int item, int tile, const int *__restrict__ tlist,
+                                   const double *__restrict__ tx, long tstride, const float4 *__restrict__ rec0,
+                                   const float4 *__restrict__ rec1, const double *__restrict__ cb, int nd,
+                                   double *__restrict__ part)
 {
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
-    if (item >= nwork) return;
-    const PairWork w = work[item];
     const int lane = threadIdx.x & 63;
     const double *c = cb + 4 * (w.pair % nd);
     const double c0 = c[0], c1 = c[1], c2 = c[2];
@@ -703,13 +714,33 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair32(const PairWork *__re
         }
     }
     const double sw = KIND == 0 ? w.w : -6.0 * w.w;
-    double *out = part + (long)(item0 + item) * (3 * tile) + lane;
+    double *out = part + (long)item * (3 * tile) + lane;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         out[64 * k] = sw * A0[k];
         out[tile + 64 * k] = sw * A1[k];
         out[2 * tile + 64 * k] = sw * A2[k];
     }
+}
+
+// Items of a work list as k_pair takes them (remainder items with one target
+// per lane), the sums of the FP32 records.
+template <int KIND, int T>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair32(const PairWork *__restrict__ work, int nwork, int item0,
+                                                           int tile, const int *__restrict__ tlist,
+                                                           const double *__restrict__ tx, long tstride,
+                                                           const float4 *__restrict__ rec0,
+                                                           const float4 *__restrict__ rec1,
+                                                           const double *__restrict__ cb, int nd,
+                                                           double *__restrict__ part)
+{
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kPairWaves + (threadIdx.x >> 6));
+    if (item >= nwork) return;
+    const PairWork w = work[item];
+    if (T > 1 && (w.pad & kPairSmall))
+        pair_item32<KIND, 1>(w, item0 + item, tile, tlist, tx, tstride, rec0, rec1, cb, nd, part);
+    else
+        pair_item32<KIND, T>(w, item0 + item, tile, tlist, tx, tstride, rec0, rec1, cb, nd, part);
 }
 
 // out[c][t] (+)= the pair sums of target t from the partial buffer, added in
