@@ -526,6 +526,9 @@ def main():
                    "operator_applications": reps[-1].n_matvec,
                    "pair_shape": {"targets_per_lane": reps[-1].pair_targets_per_lane,
                                   "sources_per_item": reps[-1].pair_sources_per_item,
+                                  "chosen_by_timing": True},
+                   "transforms": {"synthesis": "matrix cores" if reps[-1].xform_matrix_cores & 1 else "scalar",
+                                  "analysis": "matrix cores" if reps[-1].xform_matrix_cores & 2 else "scalar",
                                   "chosen_by_timing": True}},
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic(dom, args.workload),

@@ -73,9 +73,12 @@ typedef struct {
                             coordinates taken relative to the source drop's centre, runs of 16
                             sources summed in FP32 and accumulated in FP64; the fast summation
                             keeps its stored source harmonics in FP32 (multipoles accumulated in
-                            FP64); the singular self-integrals, transforms, nearest-region
-                            quadrature and GMRES stay in FP64 (relative error of the velocity
-                            about 1e-6) */
+                            FP64); on the matrix-core transform path (xform_path) the density
+                            synthesis of the double-layer operator and the analyses of the
+                            operator output and right-hand side take FP32 operands with FP32
+                            accumulation (Sec. 1.1, 2.1); the singular self-integrals, the single
+                            layer's force density, nearest-region quadrature and GMRES stay in
+                            FP64 (relative error of the velocity about 1e-6) */
     double A_tilde;      /* Omega_1 threshold in units of h (Sec. 2.3; paper uses 5) */
     int U_tilde;         /* Omega_1 grid degree factor: sources on the degree U_tilde*p grid */
     int U_sing;          /* singular rule grid degree factor (q = U_sing*p; 1 = paper) */
@@ -119,6 +122,14 @@ typedef struct {
                             kept for later contexts of the same problem shape (same number of
                             pairs to two digits, targets, fast-summation order) in the process;
                             0: a rule from the pair count. Only the speed depends on it */
+    int xform_path;      /* spherical-harmonic transforms of value fields inside the velocity
+                            evaluation (density values on the nodes, Galerkin analysis; Sec. 1.1,
+                            2.1): 1: scalar FMA kernels (FP64); 2: Legendre and Fourier sums as
+                            16x16x4 matrix-core contractions (FP64, or FP32 in the mixed form);
+                            0: whichever of the two is faster, timed once per problem shape and
+                            precision at first use and kept for the process. Derivative fields
+                            and degrees above 63 (analysis grids above 63) take the scalar
+                            kernels */
 } bim_options;
 
 typedef struct {
@@ -133,6 +144,7 @@ typedef struct {
     int fmm_order;            /* multipole order in use (0: every pair summed directly) */
     int pair_targets_per_lane;  /* work-item shape of the direct pair sums in use: targets per lane */
     int pair_sources_per_item;  /* and sources per item (0: from the pair count) */
+    int xform_matrix_cores;     /* transforms on the matrix cores: bit 0 synthesis, bit 1 analysis */
 } bim_report;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -141,7 +153,8 @@ int bim_version(void);
 const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
- * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10, pair_tune 1. */
+ * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10, pair_tune 1,
+ * xform_path 0. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */
@@ -299,7 +312,10 @@ int bim_reparametrize(bim_ctx ctx, int U_rep, double P_cut, double eps, int imax
  * consecutive) to grid values on the degree-q grid (q >= p), derivative
  * orders (dt, dp) in theta and phi, dt + dp <= 2; grid [field][N(q)].
  * Analysis: nf grid fields on the degree-q grid to coefficients of degree
- * p <= q. Pointers are device pointers when mem_kind = 1. */
+ * p <= q. Pointers are device pointers when mem_kind = 1. Value fields with
+ * p <= 63 (analysis: q <= 63) run on the matrix cores, with FP32 operands and
+ * accumulation in a mixed-precision context; the rest on the scalar FP64
+ * kernels. */
 int bim_sh_synthesize(bim_ctx ctx, int p, int q, int nf, const double *coef, int dt, int dp,
                       double *grid, int mem_kind);
 int bim_sh_analyze(bim_ctx ctx, int q, int p, int nf, const double *grid, double *coef, int mem_kind);

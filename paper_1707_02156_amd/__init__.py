@@ -43,6 +43,7 @@ class bim_options(ctypes.Structure):
         ("fmm_order", ctypes.c_int),
         ("fmm_eps", ctypes.c_double),
         ("pair_tune", ctypes.c_int),
+        ("xform_path", ctypes.c_int),
     ]
 
 
@@ -69,6 +70,7 @@ class bim_report(ctypes.Structure):
         ("fmm_order", ctypes.c_int),
         ("pair_targets_per_lane", ctypes.c_int),
         ("pair_sources_per_item", ctypes.c_int),
+        ("xform_matrix_cores", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -114,6 +114,10 @@ void launch_synth_batch(hipStream_t st, const SynJob *jobs, int n, double *z0 = 
                         double *z1 = nullptr, long nz1 = 0);
 void launch_anal_batch(hipStream_t st, const AnaJob *jobs, int n);
 size_t anal_batch_lds(int p, int q);
+bool xform_fits(int p, int q, bool analysis);
+void launch_xsynth(hipStream_t st, bool f32, const XJob *jobs, int n, const double *x, double *z0, long nz0,
+                   double *z1, long nz1);
+void launch_xanal(hipStream_t st, bool f32, const XJob *jobs, int n, const double *x, double *y, double sgn);
 bool sing_fused_fits(int p, int qs, bool sl, bool dl);
 void launch_dl_apply(hipStream_t st, int nt, int nc2, const double *M, const double *u, long ustride, double w,
                      double *out, long ostride);
@@ -216,6 +220,7 @@ struct DBuf {
 struct GridTab {
     int q = 0, nmax = 0;
     DBuf L, wq, wreg, wsing, cs;
+    DBuf xtrig[2][2];  // matrix-core Fourier tables [analysis][FP32]
     std::vector<double> t, w, th;
 };
 
@@ -374,6 +379,20 @@ struct Ctx {
     std::vector<hipEvent_t> evpool;
     std::map<std::pair<int, int>, std::unique_ptr<GridTab>> grids;
     std::map<int, std::unique_ptr<RotTab>> rots;
+
+    // matrix-core transforms of value fields: one plan per degree group of
+    // the drops (their three components as fields), built on first use after
+    // bim_set_drops, and plans of stand-alone calls by (p, q, nf)
+    struct XPlan {
+        int p = 0, qu = 0, nf = 0;
+        std::vector<long> h_cb, h_gb0, h_gb1;  // coefficient offsets [2 nf], standard / upsampled grid offsets [nf]
+        std::vector<double> h_csc;             // lambda + 1 per field
+        DBuf cb, gb0, gb1, csc;
+    };
+    std::vector<std::unique_ptr<XPlan>> xplans;
+    std::map<std::tuple<int, int, int>, std::unique_ptr<XPlan>> xfields;
+    DBuf xG;  // their intermediate [m][j][col]
+    int xmode[2][2] = {{-1, -1}, {-1, -1}};  // [synthesis, analysis][FP32]: 1 matrix cores, 0 scalar, -1 undecided
 
     // batched singular pipeline: contraction tables per (p, qs) and work buffers
     struct PipeTab {
@@ -1591,19 +1610,256 @@ static void run_near(Ctx &c, int kind, const double *dens, const std::vector<dou
                        c.near_tg.ent.as<int>(), c.near_res.d(), c.acc.d(), c.T, true);
 }
 
+// --------------------------------------------------------------------------
+// matrix-core transforms of value fields (kernels_xform.hip), FP32 operands in
+// the mixed form
+// --------------------------------------------------------------------------
+// Fourier table of grid g for orders m <= g.nmax: [2 m + ri][k], k < q, the
+// values (cos, -sin)(m pi k / q), times w_m (1 at m = 0, else 2) for synthesis.
+static const void *xtrig(Ctx &c, GridTab &g, bool analysis, bool f32)
+{
+    DBuf &b = g.xtrig[analysis][f32];
+    if (b.ptr) return b.ptr;
+    const int q = g.q, p = g.nmax;
+    std::vector<double> t((size_t)2 * (p + 1) * q);
+    for (int m = 0; m <= p; ++m) {
+        const double w = analysis || m == 0 ? 1.0 : 2.0;
+        for (int k = 0; k < q; ++k) {
+            const double a = kPi * (double)(((long)m * k) % (2L * q)) / q;
+            t[(size_t)(2 * m) * q + k] = w * std::cos(a);
+            t[(size_t)(2 * m + 1) * q + k] = -w * std::sin(a);
+        }
+    }
+    if (f32) {
+        const std::vector<float> f(t.begin(), t.end());
+        b.ensure(f.size() * sizeof(float));
+        HIPC(hipMemcpyAsync(b.ptr, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    } else {
+        b.ensure(t.size() * sizeof(double));
+        HIPC(hipMemcpyAsync(b.ptr, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    }
+    HIPC(hipStreamSynchronize(c.stream));
+    return b.ptr;
+}
+
+static void xplan_upload(Ctx &c, Ctx::XPlan &pl)
+{
+    auto up = [&](DBuf &d, const void *h, size_t bytes) {
+        d.ensure(std::max<size_t>(8, bytes));
+        if (bytes) HIPC(hipMemcpyAsync(d.ptr, h, bytes, hipMemcpyHostToDevice, c.stream));
+    };
+    up(pl.cb, pl.h_cb.data(), pl.h_cb.size() * sizeof(long));
+    up(pl.gb0, pl.h_gb0.data(), pl.h_gb0.size() * sizeof(long));
+    up(pl.gb1, pl.h_gb1.data(), pl.h_gb1.size() * sizeof(long));
+    up(pl.csc, pl.h_csc.data(), pl.h_csc.size() * sizeof(double));
+    HIPC(hipStreamSynchronize(c.stream));
+}
+
+// Plans of the drops: drops of equal degree (and upsampled degree) in one
+// plan, the fields (drop, component) in drop order.
+static std::vector<std::unique_ptr<Ctx::XPlan>> &xplans(Ctx &c)
+{
+    if (!c.xplans.empty()) return c.xplans;
+    for (int i = 0; i < c.nd; ++i) {
+        const Drop &d = c.drops[i];
+        Ctx::XPlan *pl = nullptr;
+        for (auto &e : c.xplans)
+            if (e->p == d.p && e->qu == d.qu) pl = e.get();
+        if (!pl) {
+            c.xplans.push_back(std::make_unique<Ctx::XPlan>());
+            pl = c.xplans.back().get();
+            pl->p = d.p;
+            pl->qu = d.qu;
+        }
+        for (int cc = 0; cc < 3; ++cc) {
+            pl->h_cb.push_back(cc * c.Ctot + d.coff);
+            pl->h_cb.push_back(cc * c.Ctot + d.coff + 1);
+            pl->h_gb0.push_back(cc * c.T + d.toff);
+            pl->h_gb1.push_back(cc * c.S1 + d.uoff);
+            pl->h_csc.push_back(d.lam + 1.0);
+            ++pl->nf;
+        }
+    }
+    for (auto &e : c.xplans) xplan_upload(c, *e);
+    return c.xplans;
+}
+
+// Plan of a stand-alone call: nf fields of degree p, consecutive
+// coefficient blocks of 2 ncoef(p) doubles and grids of N(q) values.
+static Ctx::XPlan &xfield_plan(Ctx &c, int p, int q, int nf)
+{
+    auto &e = c.xfields[std::make_tuple(p, q, nf)];
+    if (e) return *e;
+    e = std::make_unique<Ctx::XPlan>();
+    e->p = p;
+    e->qu = q;
+    e->nf = nf;
+    for (int f = 0; f < nf; ++f) {
+        e->h_cb.push_back((long)f * 2 * ncoef(p));
+        e->h_cb.push_back((long)f * 2 * ncoef(p) + 1);
+        e->h_gb0.push_back((long)f * npts(q));
+    }
+    xplan_upload(c, *e);
+    return *e;
+}
+
+static bool xform_drops_ok(const Ctx &c, bool analysis)
+{
+    for (const Drop &d : c.drops)
+        if (!xform_fits(d.p, analysis ? d.p : d.qu, analysis)) return false;
+    return true;
+}
+
+static XJob xjob(Ctx &c, Ctx::XPlan &pl, int q, const DBuf &gb, double *gridv, bool analysis, bool combine,
+                 bool f32, size_t &goff)
+{
+    GridTab &g = grid(c, q, pl.p);
+    XJob j{};
+    j.cb = pl.cb.as<long>();
+    j.gb = gb.as<long>();
+    j.csc = combine ? pl.csc.d() : nullptr;
+    j.L = g.L.d();
+    j.wq = g.wq.d();
+    j.trig = xtrig(c, g, analysis, f32);
+    j.G = reinterpret_cast<void *>(goff);  // offset inside xG until the buffer is sized
+    j.grid = gridv;
+    j.p = pl.p;
+    j.q = q;
+    j.nf = pl.nf;
+    j.ldn = ncoef(pl.p);
+    const size_t bytes = (size_t)(pl.p + 1) * (q + 1) * 2 * pl.nf * (f32 ? sizeof(float) : sizeof(double));
+    goff += (bytes + 255) / 256 * 256;
+    return j;
+}
+
+static void xjobs_place(Ctx &c, std::vector<XJob> &jobs, size_t goff)
+{
+    c.xG.ensure(std::max<size_t>(256, goff));
+    for (XJob &j : jobs) j.G = static_cast<char *>(c.xG.ptr) + reinterpret_cast<size_t>(j.G);
+}
+
+// Synthesis of value fields on the grids named by the jobs, FP32 operands
+// when f32 (flops and bytes as the scalar path counts them).
+static void xsynth_run(Ctx &c, std::vector<XJob> &jobs, size_t goff, const double *x, bool f32,
+                       double *z0 = nullptr, long nz0 = 0, double *z1 = nullptr, long nz1 = 0)
+{
+    xjobs_place(c, jobs, goff);
+    double fl = 0.0, by = 0.0;
+    for (const XJob &j : jobs) {
+        fl += (double)j.nf * (j.q + 1) * ncoef(j.p) * 8.0 + (double)j.nf * npts(j.q) * (j.p + 1) * 4.0;
+        by += (double)j.nf * (2.0 * ncoef(j.p) + npts(j.q)) * 8.0;
+    }
+    ProfScope ps(c, "synthesis", fl, by);
+    launch_xsynth(c.stream, f32, jobs.data(), (int)jobs.size(), x, z0, nz0, z1, nz1);
+}
+
+static void xanal_run(Ctx &c, std::vector<XJob> &jobs, size_t goff, const double *x, double *y, double sgn,
+                      bool f32)
+{
+    xjobs_place(c, jobs, goff);
+    double fl = 0.0, by = 0.0;
+    for (const XJob &j : jobs) {
+        fl += (double)j.nf * ((j.q + 1) * ncoef(j.p) * 4.0 + (double)npts(j.q) * (j.p + 1) * 4.0);
+        by += (double)j.nf * (2.0 * ncoef(j.p) + npts(j.q)) * 8.0;
+    }
+    ProfScope ps(c, "analysis", fl, by);
+    launch_xanal(c.stream, f32, jobs.data(), (int)jobs.size(), x, y, sgn);
+}
+
+// Path of the value-field transforms of the drops (option xform_path): the
+// matrix-core kernels or the scalar ones; with xform_path 0 both are timed
+// (run(false) scalar, run(true) matrix cores; each run is complete and
+// repeatable, and the caller runs the chosen path once more), two rounds
+// after a warm-up, with HIP events on the context stream, the faster of
+// each path's two counted; the matrix cores are taken when faster by more
+// than kTuneMargin. The choice is kept for the context and, under the
+// problem's shape (kind, precision, degrees and field counts of the plans),
+// for the process: the first stored wins, so concurrent contexts of one
+// shape agree and their results do not depend on which of them timed.
+static std::mutex g_xmode_mu;
+static std::map<std::vector<long>, int> g_xmodes;
+
+template <class Run> static bool xform_mfma(Ctx &c, int kind, bool f32, Run &&run)
+{
+    int &mode = c.xmode[kind][f32];
+    if (!xform_drops_ok(c, kind == 1)) return (mode = 0) == 1;
+    if (c.opt.xform_path != 0) return (mode = c.opt.xform_path == 2 ? 1 : 0) == 1;
+    if (mode >= 0) return mode == 1;
+    std::vector<long> key{kind, f32 ? 1 : 0};
+    for (auto &pl : xplans(c)) key.insert(key.end(), {pl->p, pl->qu, pl->nf});
+    {
+        std::lock_guard<std::mutex> lk(g_xmode_mu);
+        auto it = g_xmodes.find(key);
+        if (it != g_xmodes.end()) return (mode = it->second) == 1;
+    }
+    REQUIRE(!t_no_alloc, BIM_ESTATE, "transform path not chosen yet: call the allocating entry point first");
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    float best[2] = {0.0f, 0.0f};
+    run(false);
+    run(true);
+    for (int round = 0; round < 2; ++round)
+        for (int m = 0; m < 2; ++m) {
+            HIPC(hipEventRecord(e0, c.stream));
+            run(m == 1);
+            HIPC(hipEventRecord(e1, c.stream));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            best[m] = round == 0 ? ms : std::min(best[m], ms);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int pick = best[1] < (1.0f - kTuneMargin) * best[0] ? 1 : 0;
+    std::lock_guard<std::mutex> lk(g_xmode_mu);
+    return (mode = g_xmodes.emplace(key, pick).first->second) == 1;
+}
+
+// Standard-grid values gridv [3][T] of every drop to coefficients: y =
+// (lambda + 1) x - P[gridv] with combine, else y = P[gridv]; FP32 operands in
+// the mixed form.
+static void xanal_drops(Ctx &c, const double *gridv, const double *x, double *y, bool combine)
+{
+    const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+    std::vector<XJob> jobs;
+    size_t goff = 0;
+    for (auto &pl : xplans(c))
+        jobs.push_back(xjob(c, *pl, pl->p, pl->gb0, const_cast<double *>(gridv), true, combine, f32, goff));
+    xanal_run(c, jobs, goff, x, y, combine ? -1.0 : 1.0, f32);
+}
+
 // Density values (3 components, coefficients dens [3][Ctot]) on the standard
-// and upsampled nodes of the drops whose flag is set.
-static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need, double *z0 = nullptr,
+// and upsampled nodes of the drops whose flag is set (the matrix-core path
+// writes every drop's). f32: FP32 operands in the mixed form (the density of
+// the double-layer operator); the force density of the single layer stays
+// FP64: its layer is the sum of terms that nearly cancel for a drop close to
+// equilibrium, and FP32 node values would set the error of that small sum.
+static void density_nodes(Ctx &c, const double *dens, const std::vector<char> &need, bool f32, double *z0 = nullptr,
                           long nz0 = 0, double *z1 = nullptr, long nz1 = 0)
 {
-    std::vector<SynJob> jobs;
-    for (int i = 0; i < c.nd; ++i) {
-        if (!need[i]) continue;
-        const Drop &d = c.drops[i];
-        jobs.push_back(syn_job(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0x1, c.s0d.d() + d.toff, c.T, 0));
-        jobs.push_back(syn_job(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0x1, c.s1d.d() + d.uoff, c.S1, 0));
-    }
-    syn_run(c, jobs, z0, nz0, z1, nz1);
+    f32 = f32 && c.opt.precision == BIM_PREC_MIXED;
+    auto run = [&](bool mfma) {
+        if (mfma) {
+            std::vector<XJob> xj;
+            size_t goff = 0;
+            for (auto &pl : xplans(c)) {
+                xj.push_back(xjob(c, *pl, pl->p, pl->gb0, c.s0d.d(), false, false, f32, goff));
+                xj.push_back(xjob(c, *pl, pl->qu, pl->gb1, c.s1d.d(), false, false, f32, goff));
+            }
+            xsynth_run(c, xj, goff, dens, f32, z0, nz0, z1, nz1);
+            return;
+        }
+        std::vector<SynJob> jobs;
+        for (int i = 0; i < c.nd; ++i) {
+            if (!need[i]) continue;
+            const Drop &d = c.drops[i];
+            jobs.push_back(syn_job(c, d.p, d.p, 3, dens + d.coff, c.Ctot, 0x1, c.s0d.d() + d.toff, c.T, 0));
+            jobs.push_back(syn_job(c, d.p, d.qu, 3, dens + d.coff, c.Ctot, 0x1, c.s1d.d() + d.uoff, c.S1, 0));
+        }
+        syn_run(c, jobs, z0, nz0, z1, nz1);
+    };
+    run(xform_mfma(c, 0, f32, run));
 }
 
 // Singular self-integral of drop i with density coefficients dens [3][Ctot]
@@ -1878,7 +2134,7 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
     for (const NearItem &it : c.near_h)
         if (wt[(size_t)it.i * c.nd + it.j] != 0.0) selfraw[it.j] = 1;
     // acc (and near_self) cleared by the density synthesis launch
-    density_nodes(c, ucoef, need, c.acc.d(), 3 * c.T, c.near_h.empty() ? nullptr : c.near_self.d(),
+    density_nodes(c, ucoef, need, true, c.acc.d(), 3 * c.T, c.near_h.empty() ? nullptr : c.near_self.d(),
                   c.near_h.empty() ? 0 : 3 * c.T);
     // stored rows: build those missing (pipeline drops grouped by degree)
     std::vector<int> build;
@@ -1929,7 +2185,7 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
 {
     build_regions(c);
     std::vector<char> need(c.nd, 1);
-    density_nodes(c, fcoef, need, c.acc.d(), 3 * c.T);  // acc cleared by the same launch
+    density_nodes(c, fcoef, need, false, c.acc.d(), 3 * c.T);  // acc cleared by the same launch
     // pipeline drops grouped by degree, separately with and without the rows
     std::vector<int> with_rows, without_rows;
     for (int i = 0; i < c.nd; ++i) {
@@ -1962,12 +2218,19 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
 // analysis of grid vectors [3][T] into coefficients [3][Ctot]
 static void project(Ctx &c, const double *grid_vals, double *coef)
 {
-    std::vector<AnaJob> jobs;
-    for (int i = 0; i < c.nd; ++i) {
-        const Drop &d = c.drops[i];
-        jobs.push_back(ana_job(c, d.p, d.p, 3, grid_vals + d.toff, c.T, coef + d.coff, c.Ctot));
-    }
-    ana_run(c, jobs);
+    auto run = [&](bool mfma) {
+        if (mfma) {
+            xanal_drops(c, grid_vals, nullptr, coef, false);
+            return;
+        }
+        std::vector<AnaJob> jobs;
+        for (int i = 0; i < c.nd; ++i) {
+            const Drop &d = c.drops[i];
+            jobs.push_back(ana_job(c, d.p, d.p, 3, grid_vals + d.toff, c.T, coef + d.coff, c.Ctot));
+        }
+        ana_run(c, jobs);
+    };
+    run(xform_mfma(c, 1, c.opt.precision == BIM_PREC_MIXED, run));
 }
 
 static void synth_grid_all(Ctx &c, const double *coef, double *grid_vals)
@@ -1984,24 +2247,36 @@ static void synth_grid_all(Ctx &c, const double *coef, double *grid_vals)
 static void apply_operator(Ctx &c, const double *x, double *y, const std::vector<double> &wt)
 {
     double_layer_grid(c, x, wt);
-    // y = (lambda + 1) x - P[acc]: the combine rides on the batched analysis
-    // when every drop's grid fits it
-    std::vector<AnaJob> jobs;
-    bool fused = true;
-    for (int i = 0; i < c.nd; ++i) {
-        const Drop &d = c.drops[i];
-        AnaJob j = ana_job(c, d.p, d.p, 3, c.acc.d() + d.toff, c.T, y + d.coff, c.Ctot);
-        j.cx = x + d.coff;
-        j.csc = d.lam + 1.0;
-        fused = fused && anal_batch_lds(d.p, d.p) <= 163840;
-        jobs.push_back(j);
-    }
-    if (fused) {
-        ana_run(c, jobs);
-    } else {
-        project(c, c.acc.d(), y);
-        launch_op_combine(c.stream, 3 * c.Ctot, c.scl.d(), x, y);
-    }
+    // y = (lambda + 1) x - P[acc]: the combine rides on the analysis (the
+    // scalar one when every drop's grid fits it)
+    auto run = [&](bool mfma) {
+        if (mfma) {
+            xanal_drops(c, c.acc.d(), x, y, true);
+            return;
+        }
+        std::vector<AnaJob> jobs;
+        bool fused = true;
+        for (int i = 0; i < c.nd; ++i) {
+            const Drop &d = c.drops[i];
+            AnaJob j = ana_job(c, d.p, d.p, 3, c.acc.d() + d.toff, c.T, y + d.coff, c.Ctot);
+            j.cx = x + d.coff;
+            j.csc = d.lam + 1.0;
+            fused = fused && anal_batch_lds(d.p, d.p) <= 163840;
+            jobs.push_back(j);
+        }
+        if (fused) {
+            ana_run(c, jobs);
+        } else {
+            std::vector<AnaJob> pj;
+            for (int i = 0; i < c.nd; ++i) {
+                const Drop &d = c.drops[i];
+                pj.push_back(ana_job(c, d.p, d.p, 3, c.acc.d() + d.toff, c.T, y + d.coff, c.Ctot));
+            }
+            ana_run(c, pj);
+            launch_op_combine(c.stream, 3 * c.Ctot, c.scl.d(), x, y);
+        }
+    };
+    run(xform_mfma(c, 1, c.opt.precision == BIM_PREC_MIXED, run));
 }
 
 // --------------------------------------------------------------------------
@@ -2242,6 +2517,7 @@ int bim_default_options(bim_options *o)
     o->fmm_order = 0;
     o->fmm_eps = 1e-10;
     o->pair_tune = 1;
+    o->xform_path = 0;
     return BIM_OK;
 }
 
@@ -2283,7 +2559,7 @@ int bim_create(const bim_options *opt, bim_ctx *out)
         (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
         (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL ||
         (opt->fmm_order != 0 && opt->fmm_order != -1 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder)) ||
-        !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0))
+        !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0) || opt->xform_path < 0 || opt->xform_path > 2)
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {
@@ -2376,6 +2652,8 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         for (double v : hx) REQUIRE(std::isfinite(v), BIM_EINVAL, "non-finite surface coefficient");
         c.nd = n_drops;
         c.drops = ds;
+        c.xplans.clear();
+        for (auto &row : c.xmode) row[0] = row[1] = -1;
         c.Mdl.clear();
         c.Mok.assign(n_drops, 0);
         c.Ctot = coff;
@@ -3246,6 +3524,8 @@ int bim_eval_velocity(bim_ctx h, double *u_out, int out_kind, bim_report *rep)
             rep->fmm_order = c.fmm.P;
             rep->pair_targets_per_lane = c.pair_T;
             rep->pair_sources_per_item = c.pair_ch;
+            rep->xform_matrix_cores = (c.xmode[0][c.opt.precision == BIM_PREC_MIXED] == 1 ? 1 : 0) |
+                                      (c.xmode[1][c.opt.precision == BIM_PREC_MIXED] == 1 ? 2 : 0);
             rep->n_matvec = nmv;
             rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
@@ -3272,7 +3552,16 @@ int bim_sh_synthesize(bim_ctx h, int p, int q, int nf, const double *coef, int d
             cin = ci.d();
             gout = go.d();
         }
-        synth(c, p, q, nf, cin, 2L * ncoef(p), dt, dp, gout, npts(q));
+        if (dt == 0 && dp == 0 && xform_fits(p, q, false)) {
+            Ctx::XPlan &pl = xfield_plan(c, p, q, nf);
+            std::vector<XJob> jobs;
+            size_t goff = 0;
+            const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+            jobs.push_back(xjob(c, pl, q, pl.gb0, gout, false, false, f32, goff));
+            xsynth_run(c, jobs, goff, cin, f32);
+        } else {
+            synth(c, p, q, nf, cin, 2L * ncoef(p), dt, dp, gout, npts(q));
+        }
         if (mem_kind != BIM_MEM_DEVICE) {
             HIPC(hipMemcpyAsync(grid_out, gout, gb, hipMemcpyDeviceToHost, c.stream));
             HIPC(hipStreamSynchronize(c.stream));
@@ -3297,7 +3586,16 @@ int bim_sh_analyze(bim_ctx h, int q, int p, int nf, const double *grid_in, doubl
             gin = gi.d();
             cout = co.d();
         }
-        analyze(c, q, p, nf, gin, npts(q), cout, 2L * ncoef(p));
+        if (xform_fits(p, q, true)) {
+            Ctx::XPlan &pl = xfield_plan(c, p, q, nf);
+            std::vector<XJob> jobs;
+            size_t goff = 0;
+            const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+            jobs.push_back(xjob(c, pl, q, pl.gb0, const_cast<double *>(gin), true, false, f32, goff));
+            xanal_run(c, jobs, goff, nullptr, cout, 1.0, f32);
+        } else {
+            analyze(c, q, p, nf, gin, npts(q), cout, 2L * ncoef(p));
+        }
         if (mem_kind != BIM_MEM_DEVICE) {
             HIPC(hipMemcpyAsync(coef, cout, cb, hipMemcpyDeviceToHost, c.stream));
             HIPC(hipStreamSynchronize(c.stream));

@@ -96,6 +96,24 @@ struct AnaJob {
     double csc;
 };
 
+// Matrix-core transforms of value fields (kernels_xform.hip): nf fields of
+// degree p on the degree-q grid. Field f's coefficients (complex n-major
+// triangle, (re, im) interleaved) start at cb[2 f] (real parts) and cb[2 f +
+// 1] (imaginary parts) inside the coefficient vector, its grid values [j][k]
+// (2q longitudes per latitude) at gb[f] inside the grid array.
+struct XJob {
+    const long *cb;     // [2 nf]
+    const long *gb;     // [nf]
+    const double *csc;  // analysis: [nf] factor of x in the output (nullptr: none)
+    const double *L;    // Ptilde_n^m(t_j) at L[j * ldn + tri(n, m)]
+    const double *wq;   // analysis: (pi/q) w_j
+    const void *trig;   // [2 (p+1)][q] (the job's type): synthesis w_m (cos, -sin)(m phi_k), analysis (cos, -sin)
+    void *G;            // intermediate [p+1][q+1][2 nf] (the job's type)
+    double *grid;       // synthesis output, analysis input
+    int p, q, nf, ldn;
+};
+constexpr int kMaxXJobs = 8;
+
 // One drop of the surface-operator kernel (kernels_surf.hip). syn holds, per
 // grid point (np of them): x fields f = 0..5 (value, d_theta, d_phi,
 // d_theta^2, d_theta d_phi, d_phi^2) x 3 components at (3 f + c) np; Gamma

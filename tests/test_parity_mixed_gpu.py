@@ -1,5 +1,8 @@
 """Mixed precision (precision = BIM_PREC_MIXED): the direct pair sums in FP32
-arithmetic, every other step in FP64.
+arithmetic; the operator's density synthesis and the analyses (operator
+output, right-hand side) as FP32 matrix-core contractions with FP32
+accumulation; rotation, the singular rule, the single layer's force
+density and GMRES in FP64.
 
 Bar: 1e-5 per output, where an output is one drop and one component:
 ||gpu - ref||_inf / ||ref||_inf over that drop's targets (sampled ones
@@ -88,6 +91,44 @@ def test_mixed_many_drops_against_fp64(B):
         assert 1e-12 < e <= TOL32
 
 
+def test_mixed_two_drops_solve_against_oracle_solution(B, orc):
+    """The two-drop p = 32 solve in the mixed form against the oracle's
+    stored solution (GMRES 1e-12, written by the oracle only): velocity
+    coefficients per drop and component."""
+    print("mixed: two drops p=32 solve vs oracle solution", flush=True)
+    from test_parity_gpu import GOLDEN_C2
+    ref = np.load(GOLDEN_C2)
+    wl = W.two_drops()
+    c = ctx_for(B, wl, precision=B.BIM_PREC_MIXED)
+    uc, rep = c.eval_velocity(coefficients=True)
+    c.close()
+    uo = osys(orc, wl).split(ref["u"])
+    e = _rel_out(uc, uo)
+    print("per-output error", e, flush=True)
+    assert 1e-12 < e <= TOL32
+
+
+def test_mixed_many_drops_operator_and_solve_against_fp64(B):
+    """The 64-drop workload: the full operator A u in coefficients (FP32
+    density synthesis and analysis) and the solved velocity on the grid,
+    mixed against FP64, per drop and component. (The error of this velocity
+    is set by the FP32 pair sums of the single layer: with the transforms in
+    FP64 it is the same to two digits.)"""
+    print("mixed: 64 drops operator and solve vs FP64", flush=True)
+    wl = W.many_drops()
+    rng = np.random.default_rng(63)
+    dens = [_density(rng, 16) for _ in wl.drops]
+    res = {}
+    for prec in (B.BIM_PREC_FP64, B.BIM_PREC_MIXED):
+        c = ctx_for(B, wl, precision=prec)
+        res[prec] = (c.double_layer(dens, mode=1), c.eval_velocity()[0])
+        c.close()
+    for k, name in ((0, "operator"), (1, "velocity")):
+        e = _rel_out(res[B.BIM_PREC_MIXED][k], res[B.BIM_PREC_FP64][k])
+        print(name, "per-output error", e, flush=True)
+        assert 1e-12 < e <= TOL32
+
+
 def test_mixed_velocity_solve(B):
     """Full velocity solve of the two-drop workload in both precisions."""
     print("mixed: velocity solve", flush=True)
@@ -136,18 +177,20 @@ def deformed_both(B):
         sl, dl = c.single_layer(), c.double_layer(dens, mode=0)
         u, rep = c.eval_velocity()
         reg, _ = c.regions() if prec == B.BIM_PREC_MIXED else (None, None)
-        out[prec] = (sl, dl, u, rep, reg)
+        op = c.double_layer(dens, mode=1)
+        out[prec] = (sl, dl, u, rep, reg, op)
         c.close()
     return wl, dens, out
 
 
 def test_mixed_deformed_drops_every_target_against_fp64(B, deformed_both):
-    """Every target of the 16 deformed drops: single layer, double layer and
-    the solved velocity of the mixed form against the FP64 form."""
+    """Every target of the 16 deformed drops: single layer, double layer, the
+    solved velocity and the full operator in coefficients of the mixed form
+    against the FP64 form."""
     print("mixed: 16 deformed drops p=48 vs FP64", flush=True)
     wl, dens, out = deformed_both
     m, d = out[B.BIM_PREC_MIXED], out[B.BIM_PREC_FP64]
-    for k, name in ((0, "SL"), (1, "DL"), (2, "velocity")):
+    for k, name in ((0, "SL"), (1, "DL"), (2, "velocity"), (5, "operator")):
         e = _rel_out(m[k], d[k])
         print(name, "per-output error", e, flush=True)
         assert 1e-12 < e <= TOL32
@@ -159,7 +202,7 @@ def test_mixed_deformed_drops_sampled_against_oracle(B, orc, deformed_both):
     the mixed single and double layer against the FP64 oracle."""
     print("mixed: 16 deformed drops p=48 vs oracle, sampled", flush=True)
     wl, dens, out = deformed_both
-    sl, dl, _, _, reg = out[B.BIM_PREC_MIXED]
+    sl, dl, _, _, reg, _ = out[B.BIM_PREC_MIXED]
     rng = np.random.default_rng(58)
     s = osys(orc, wl)
     n = B.npts(48)
