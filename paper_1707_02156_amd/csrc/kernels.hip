@@ -505,36 +505,42 @@ __device__ inline void pair64(double X, double Y, double Z, double px, double py
 {
     const double hx = X - px, hy = Y - py, hz = Z - pz;
     const double r2 = fma(hz, hz, fma(hy, hy, hx * hx));
-    // r^-1: the hardware reciprocal square root (about 22 correct bits; r2 > 0
-    // for every pair of distinct drops, overlapping drops are rejected at
-    // input) refined by one Newton step y (1 + e/2), e = 1 - r2 y^2, which
-    // leaves a relative error of about 1.5 e^2 < 1e-12 (4 instructions; a
-    // third-order step would take 5 of the 24 FP64 VALU instructions of a
-    // pair for accuracy far below the 1e-10 the sums are held to)
+    // y = the hardware reciprocal square root of r2 (r2 > 0 for every pair of
+    // distinct drops; overlapping drops are rejected at input), relative error
+    // d below 5.3e-8 (measured over twelve decades), refined to the accuracy
+    // of the sums (1e-10 and below) by the first-order correction of the
+    // power the kernel needs: with e = r2 y^2 - 1 = 2 d + d^2,
+    //   r^-1 = y (1 + e)^(-1/2) ~ y (1 - e/2)          (SL; one Newton step),
+    //   r^-5 = y^5 (1 + e)^(-5/2) ~ y^5 (1 - 5 e / 2)  (DL),
+    // leaving relative errors of 3/8 e^2 and 35/8 e^2 (below 5e-14): 4 and 6
+    // FP64 instructions on top of the estimate.
     const double y = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-r2 * y, y, 1.0);
-    const double ri = fma(y * e, 0.5, y);
     const double hd = fma(hz, u2, fma(hy, u1, hx * u0));
     if (KIND == 0) {
+        const double e = fma(-r2 * y, y, 1.0);
+        const double ri = fma(y * e, 0.5, y);
         const double q = hd * ri * ri;
         A0 = fma(ri, fma(hx, q, u0), A0);
         A1 = fma(ri, fma(hy, q, u1), A1);
         A2 = fma(ri, fma(hz, q, u2), A2);
     } else {
         const double hn = fma(hz, m2, fma(hy, m1, hx * m0));
-        const double r2i = ri * ri;
-        const double sc = (hd * hn) * (r2i * r2i * ri);
+        const double z = y * y;
+        const double e = fma(r2, z, -1.0);
+        const double y5 = z * z * y;
+        const double sc = (hd * hn) * fma(y5 * -2.5, e, y5);
         A0 = fma(sc, hx, A0);
         A1 = fma(sc, hy, A1);
         A2 = fma(sc, hz, A2);
     }
 }
 
-// T targets per lane; U = 8 / T consecutive sources per step, each into its
-// own accumulators (independent work for one lane when T is small), added in
-// a fixed order at the end.
 // One item of the FP64 sums with T targets per lane and U independent
-// accumulators per target (consecutive sources alternate between them).
+// accumulators per target: consecutive sources alternate between them
+// (independent work for one lane when T is small), added in a fixed order at
+// the end. With one target per lane the kernel takes 8 (its 8 steps of 9
+// source values overflow the scalar registers into vector lanes, and it is
+// still the faster of 4 and 8 on the two-drop workload it serves).
 template <int KIND, int T, int U>
 __device__ inline void pair_item64(const PairWork &w, int item, int tile, const int *__restrict__ tlist,
                                    const double *__restrict__ tx, long tstride, const PairSrc &g0,
