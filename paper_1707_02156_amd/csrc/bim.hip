@@ -2281,12 +2281,16 @@ static void apply_operator(Ctx &c, const double *x, double *y, const std::vector
 
 // --------------------------------------------------------------------------
 // GMRES (restarted, classical Gram-Schmidt with one re-orthogonalisation,
-// Givens rotations and back substitution on the device). The host enqueues
-// Arnoldi step k + 1 before it reads the residual estimate of step k (one
-// step behind, from pinned memory once the step's stamp is there), so the
-// device never waits for the host; a step enqueued after convergence is
-// discarded.
+// Givens rotations and back substitution on the device). The residual
+// estimate of each Arnoldi step reaches the host through pinned memory once
+// the step's stamp is there. While steps are short the host enqueues step k
+// + 1 before it reads the estimate of step k, so the device never waits for
+// the host, and a step enqueued after convergence is discarded; once a step
+// takes longer than kAheadMs the host reads each estimate first (the device
+// then waits for the host's next launches, some 20 us per step, which is
+// less than the one discarded step it saves).
 // --------------------------------------------------------------------------
+constexpr double kAheadMs = 1.0;
 using OpFn = std::function<void(const double *, double *)>;
 
 static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *x, double tol, int &iters,
@@ -2386,10 +2390,20 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
             std::atomic_thread_fence(std::memory_order_acquire);
             return resh[2 * (k & 1)];
         };
-        step(0);
+        int next = 0;  // the next step to enqueue
+        auto enqueue_to = [&](int k) {
+            while (next <= k && next < kmax) step(next++);
+        };
+        enqueue_to(0);
+        auto t_prev = std::chrono::steady_clock::now();
+        double t_step = 0.0;  // host-observed duration of the latest step, ms
         for (int k = 0; k < kmax; ++k) {
-            if (k + 1 < kmax) step(k + 1);  // enqueue the next step before waiting on this one
+            enqueue_to(k);                                        // (already there when enqueued ahead)
+            if (k == 0 || t_step < kAheadMs) enqueue_to(k + 1);  // one step ahead while steps are short
             const double r = wait_step(k);
+            const auto t_now = std::chrono::steady_clock::now();
+            t_step = std::chrono::duration<double, std::milli>(t_now - t_prev).count();
+            t_prev = t_now;
             ++iters;
             ++nmv;
             kdone = k + 1;
