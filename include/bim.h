@@ -368,6 +368,9 @@ typedef struct {
     int max_batch_drops;    /* drops per batch at most (default 128) */
 } bim_server_options;
 
+/* Defaults: 4 slots, 64 GB, max_batch 1, max_batch_drops 128, opt from
+ * bim_default_options with pair_tune 0 and xform_path 1 (no timing of work
+ * shapes on the request path). */
 int bim_server_default_options(bim_server_options *opt);
 int bim_server_create(const bim_server_options *opt, bim_server *out);
 /* Finishes the running requests, drops the queued ones, frees everything. */

@@ -226,8 +226,11 @@ int bim_server_default_options(bim_server_options *o)
     o->max_batch_drops = 128;
     const int rc = bim_default_options(&o->opt);
     // requests are mostly one-off problem shapes: timing the pair work shape
-    // of each would cost more than it saves and add to the latency tail
+    // or the transform path of each would cost more than it saves and add to
+    // the latency tail; the transforms of small systems are latency-bound,
+    // where the scalar kernels are the faster
     o->opt.pair_tune = 0;
+    o->opt.xform_path = 1;
     return rc;
 }
 

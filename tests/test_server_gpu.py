@@ -5,7 +5,8 @@ Requests are independent drop systems from the serving stream (1-8 drops of
 one degree in {8, 16, 24, 32}, lambda in {1, 2, 5}, uniform tension). Each
 result of a request run concurrently with others must equal the same request
 run alone on a plain context with the server's options (the pair work
-shape by its rule, pair_tune = 0) bit for bit: every sum on the path has a
+shape by its rule, pair_tune = 0; scalar transforms, xform_path = 1) bit
+for bit: every sum on the path has a
 fixed order, so overlapping work on the device changes nothing.
 """
 import numpy as np
@@ -30,7 +31,7 @@ def _requests(n, pmax=24):
 
 
 def _alone(B, req):
-    c = B.Context(pair_tune=0)
+    c = B.Context(pair_tune=0, xform_path=1)
     c.set_drops([d.p for d in req.drops], [d.xc for d in req.drops], [d.lam for d in req.drops])
     c.set_tension(None, 0, sigma0=1.0)
     u, rep = c.eval_velocity()
@@ -132,7 +133,7 @@ def _small_and_large_systems():
 
 
 def _alone_drops(B, drops):
-    c = B.Context(pair_tune=0)
+    c = B.Context(pair_tune=0, xform_path=1)
     c.set_drops([d.p for d in drops], [d.xc for d in drops], [d.lam for d in drops])
     c.set_tension(None, 0, sigma0=1.0)
     u, rep = c.eval_velocity()
@@ -210,7 +211,7 @@ def test_mixed_results_in_the_mix_equal_results_alone(B):
     got = [srv.wait(i) for i in ids]
     srv.close()
     for r, (u, rep, t) in zip(reqs, got):
-        c = B.Context(precision=B.BIM_PREC_MIXED, pair_tune=0)
+        c = B.Context(precision=B.BIM_PREC_MIXED, pair_tune=0, xform_path=1)
         c.set_drops([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops])
         c.set_tension(None, 0, sigma0=1.0)
         ref, _ = c.eval_velocity()
