@@ -139,9 +139,10 @@ def serving_opts(B, args):
 
 
 def capacity(B, reqs, opts, nsample):
-    """One-at-a-time capacity (requests/s) of a plain context over the first
-    nsample requests (after 8 warm-up requests)."""
-    ctx = B.Context(**opts)
+    """One-at-a-time capacity (requests/s) of a plain context with the
+    server's work-shape options (no timing of shapes) over the first nsample
+    requests (after 8 warm-up requests)."""
+    ctx = B.Context(pair_tune=0, xform_path=1, **opts)
 
     def alone(r):
         ctx.set_drops([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops])
@@ -159,14 +160,15 @@ def capacity(B, reqs, opts, nsample):
     return 1.0 / mean_s, mean_s
 
 
-def stream(B, reqs, opts, slots, rate, batch=1):
+def stream(B, reqs, opts, slots, rate, batch=1, max_queue=0):
     """The requests through a server of `slots` slots (batches of up to
-    `batch`), submitted at their Poisson arrival times scaled to `rate`;
-    p50/p99 arrival-to-finish latency and throughput."""
+    `batch`, at most `max_queue` waiting, 0: no limit), submitted at their
+    Poisson arrival times scaled to `rate`; p50/p99 arrival-to-finish latency
+    of the served requests, throughput, and the fraction refused."""
     import threading
 
     import numpy as np
-    srv = B.Server(slots=slots, max_batch=batch, **opts)
+    srv = B.Server(slots=slots, max_batch=batch, max_queue=max_queue, **opts)
     for r in reqs[:8]:   # warm the contexts' tables
         srv.wait(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
     ids, lat, evals = [], [], [0]
@@ -178,9 +180,10 @@ def stream(B, reqs, opts, slots, rate, batch=1):
             if k >= len(ids):
                 time.sleep(0.0005)
                 continue
-            u, rep, t = srv.wait(ids[k])
-            lat.append(t[2])
-            evals[0] += rep.n_targets * (1 + rep.n_matvec)
+            if ids[k] is not None:   # None: refused at submission
+                u, rep, t = srv.wait(ids[k])
+                lat.append(t[2])
+                evals[0] += rep.n_targets * (1 + rep.n_matvec)
             k += 1
         done.set()
 
@@ -191,15 +194,20 @@ def stream(B, reqs, opts, slots, rate, batch=1):
         delay = start + r.arrival / rate - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        ids.append(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
+        try:
+            ids.append(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
+        except B.BimError as e:
+            if e.status != B.BIM_EBUSY:
+                raise
+            ids.append(None)
     done.wait()
     th.join()
     span = time.perf_counter() - start
     srv.close()
     lat = np.array(lat)
     return {"slots": slots, "max_batch": batch, "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "throughput_req_s": len(reqs) / span,
-            "evals_per_s": evals[0] / span}
+            "p99_ms": float(np.percentile(lat, 99)), "throughput_req_s": len(lat) / span,
+            "evals_per_s": evals[0] / span, "refused": sum(i is None for i in ids) / len(ids)}
 
 
 def serve(args):
@@ -247,12 +255,18 @@ def latency(args):
     served = stream(B, reqs, opts, args.slots, rate)
     single = stream(B, reqs, opts, 1, rate)
     over = {k: stream(B, reqs, opts, s_, 1.5 * cap) for k, s_ in (("served", args.slots), ("one_at_a_time", 1))}
+    # overload: 3x the capacity, with and without a bound on the waiting requests
+    shed = {k: stream(B, reqs, opts, args.slots, 3.0 * cap, max_queue=mq)
+            for k, mq in ((f"max_queue_{2 * args.slots}", 2 * args.slots), ("unbounded", 0))}
     return {"p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
             "throughput_req_s": served["throughput_req_s"], "evals_per_s": served["evals_per_s"],
             "one_at_a_time": {"p50_ms": single["p50_ms"], "p99_ms": single["p99_ms"],
                               "throughput_req_s": single["throughput_req_s"]},
             "at_1.5x_capacity": {k: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"],
                                      "throughput_req_s": v["throughput_req_s"]} for k, v in over.items()},
+            "at_3x_capacity": {k: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"],
+                                   "throughput_req_s": v["throughput_req_s"], "refused": v["refused"]}
+                               for k, v in shed.items()},
             "requests": len(reqs), "slots": args.slots, "rate_req_s": rate, "capacity_one_at_a_time_req_s": cap,
             "workload": "serving stream: systems of 1-8 drops, p in {8,16,24,32}, lambda in {1,2,5}, gap >= 0.2, "
                         "Poisson arrivals at 0.8x the one-at-a-time capacity; FP32 far field, FP64 singular "

@@ -54,7 +54,8 @@ enum {
     BIM_EDEVICE = -3,  /* HIP runtime error */
     BIM_ENOCONV = -4,  /* GMRES did not reach the tolerance; output holds the last iterate */
     BIM_ESTATE = -5,   /* call out of order (e.g. evaluation before bim_set_drops) */
-    BIM_EAGAIN = -6    /* server request not finished within the wait time */
+    BIM_EAGAIN = -6,   /* server request not finished within the wait time */
+    BIM_EBUSY = -7     /* server queue full: the request was refused (max_queue) */
 };
 
 enum { BIM_MEM_HOST = 0, BIM_MEM_DEVICE = 1 };
@@ -366,9 +367,13 @@ typedef struct {
     int max_batch;          /* requests a free slot takes from the queue at once, run as independent
                                systems of one context (bim_set_systems); 1 = one at a time (default) */
     int max_batch_drops;    /* drops per batch at most (default 128) */
+    int max_queue;          /* requests waiting for a slot at most; a submit beyond it is refused
+                               with BIM_EBUSY, so an overloaded server sheds load at the door
+                               instead of growing its queue without bound (0 = no limit, the
+                               default) */
 } bim_server_options;
 
-/* Defaults: 4 slots, 64 GB, max_batch 1, max_batch_drops 128, opt from
+/* Defaults: 4 slots, 64 GB, max_batch 1, max_batch_drops 128, max_queue 0, opt from
  * bim_default_options with pair_tune 0 and xform_path 1 (no timing of work
  * shapes on the request path). */
 int bim_server_default_options(bim_server_options *opt);

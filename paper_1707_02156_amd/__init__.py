@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbim.so")
 
-BIM_OK, BIM_EINVAL, BIM_ENOMEM, BIM_EDEVICE, BIM_ENOCONV, BIM_ESTATE, BIM_EAGAIN = 0, -1, -2, -3, -4, -5, -6
+BIM_OK, BIM_EINVAL, BIM_ENOMEM, BIM_EDEVICE, BIM_ENOCONV, BIM_ESTATE, BIM_EAGAIN, BIM_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 BIM_MEM_HOST, BIM_MEM_DEVICE = 0, 1
 BIM_EOS_UNIFORM, BIM_EOS_LINEAR, BIM_EOS_LANGMUIR = 0, 1, 2
 BIM_PREC_FP64, BIM_PREC_MIXED = 0, 1
@@ -54,6 +54,7 @@ class bim_server_options(ctypes.Structure):
         ("opt", bim_options),
         ("max_batch", ctypes.c_int),
         ("max_batch_drops", ctypes.c_int),
+        ("max_queue", ctypes.c_int),
     ]
 
 
@@ -489,13 +490,14 @@ class Server:
     for their velocities. Options: slots, hbm_budget_gb, and any context
     option by name."""
 
-    def __init__(self, slots=4, hbm_budget_gb=64.0, max_batch=1, max_batch_drops=128, **opts):
+    def __init__(self, slots=4, hbm_budget_gb=64.0, max_batch=1, max_batch_drops=128, max_queue=0, **opts):
         so = bim_server_options()
         _check(None, lib().bim_server_default_options(ctypes.byref(so)))
         so.slots = slots
         so.hbm_budget_gb = hbm_budget_gb
         so.max_batch = max_batch
         so.max_batch_drops = max_batch_drops
+        so.max_queue = max_queue
         for k, v in opts.items():
             setattr(so.opt, k, v)
         h = ctypes.c_void_p()

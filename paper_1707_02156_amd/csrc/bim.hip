@@ -2506,6 +2506,7 @@ const char *bim_status_string(int s)
     case BIM_ENOCONV: return "GMRES did not converge";
     case BIM_ESTATE: return "invalid call order";
     case BIM_EAGAIN: return "request not finished";
+    case BIM_EBUSY: return "server queue full";
     default: return "unknown status";
     }
 }

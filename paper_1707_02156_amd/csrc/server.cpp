@@ -239,7 +239,7 @@ int bim_server_create(const bim_server_options *opt, bim_server *out)
     if (!opt || !out) return BIM_EINVAL;
     *out = nullptr;
     if (opt->slots < 1 || opt->slots > 64 || !(opt->hbm_budget_gb > 0.0) || opt->opt.stream || opt->max_batch < 1 ||
-        opt->max_batch_drops < 1)
+        opt->max_batch_drops < 1 || opt->max_queue < 0)
         return BIM_EINVAL;
     std::unique_ptr<bim_server_s> s;
     try {
@@ -314,6 +314,7 @@ int bim_server_submit(bim_server s, int n_drops, const int *p, const double *xco
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if (s->opt.max_queue > 0 && (long)s->queue.size() >= s->opt.max_queue) return BIM_EBUSY;
         r->id = s->next_id++;
         *id = r->id;
         s->queue.push_back(r.get());

@@ -218,3 +218,26 @@ def test_mixed_results_in_the_mix_equal_results_alone(B):
         c.close()
         for a, b in zip(u, ref):
             assert np.array_equal(a, b)
+
+
+def test_full_queue_refuses_requests(B):
+    """max_queue 2 with one slot: while a large first request runs, the
+    submits beyond two waiting requests are refused with BIM_EBUSY (the
+    server sheds load instead of growing its queue); every accepted request
+    is served."""
+    print("server max_queue", flush=True)
+    big = [r for r in W.serving_requests(n=256) if r.p == 32 and len(r.drops) >= 6][0]
+    small = _requests(8, pmax=16)
+    srv = B.Server(slots=1, max_queue=2)
+    ids, refused = [], 0
+    for r in [big] + small:
+        try:
+            ids.append(srv.submit([d.p for d in r.drops], [d.xc for d in r.drops], [d.lam for d in r.drops]))
+        except B.BimError as e:
+            assert e.status == B.BIM_EBUSY
+            refused += 1
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    assert refused >= 1 and len(ids) <= 1 + 2 + 1
+    for u, rep, t in got:
+        assert rep.gmres_residual <= 1e-10
