@@ -131,6 +131,10 @@ typedef struct {
                             precision at first use and kept for the process. Derivative fields
                             and degrees above 63 (analysis grids above 63) take the scalar
                             kernels */
+    double pipe_budget_gb; /* device memory for the intermediates of the batched singular pipeline
+                            (singular_path 0), GB: the (drop, latitude) units of a degree group
+                            run in chunks that fit it (about 80 MB per latitude at p = 48, 24 MB
+                            at p = 32); larger chunks mean fewer, fuller launches. Default 8 */
 } bim_options;
 
 typedef struct {
@@ -155,7 +159,7 @@ const char *bim_status_string(int status);
 /* Fill defaults: A_tilde 5, U_tilde 4, U_sing 1, U_geom 2, lambda_rule 0,
  * gmres_tol 1e-10, restart 50, maxit 500, singular_path 0, device 0, FP64,
  * stream NULL, near_rule 1, near_L 8, fmm_order 0 (off), fmm_eps 1e-10, pair_tune 1,
- * xform_path 0. */
+ * xform_path 0, pipe_budget_gb 8. */
 int bim_default_options(bim_options *opt);
 
 /* Create a context on opt->device. Allocates nothing large until drops are set. */

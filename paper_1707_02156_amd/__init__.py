@@ -44,6 +44,7 @@ class bim_options(ctypes.Structure):
         ("fmm_eps", ctypes.c_double),
         ("pair_tune", ctypes.c_int),
         ("xform_path", ctypes.c_int),
+        ("pipe_budget_gb", ctypes.c_double),
     ]
 
 

@@ -1980,7 +1980,7 @@ static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl
     const double per_lat = (double)nk * 8.0 *
                            ((double)nc * 6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * 6 + (sl ? (double)P1 * Q1 * 6 : 0.0) +
                             (dl ? (double)P1 * Q1 * 12 + (double)nc * 12 : 0.0) + Q1 * 3 + 3);
-    const double budget = 768.0 * 1024 * 1024;
+    const double budget = c.opt.pipe_budget_gb * 1024.0 * 1024 * 1024;
     const int nu = pd.n * P1;
     const int nj = std::max(1, std::min(nu, (int)(budget / per_lat)));
     const long NTc = (long)nj * nk;
@@ -2533,6 +2533,7 @@ int bim_default_options(bim_options *o)
     o->fmm_eps = 1e-10;
     o->pair_tune = 1;
     o->xform_path = 0;
+    o->pipe_budget_gb = 8.0;
     return BIM_OK;
 }
 
@@ -2574,7 +2575,8 @@ int bim_create(const bim_options *opt, bim_ctx *out)
         (opt->lambda_rule != 0 && opt->lambda_rule != 1) || (opt->singular_path < 0 || opt->singular_path > 2) ||
         (opt->near_rule != 0 && opt->near_rule != 1) || opt->near_L < 2 || opt->near_L > kNearMaxL ||
         (opt->fmm_order != 0 && opt->fmm_order != -1 && (opt->fmm_order < 2 || opt->fmm_order > kFmmMaxOrder)) ||
-        !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0) || opt->xform_path < 0 || opt->xform_path > 2)
+        !(opt->fmm_eps > 0.0 && opt->fmm_eps < 1.0) || opt->xform_path < 0 || opt->xform_path > 2 ||
+        !(opt->pipe_budget_gb > 0.0 && opt->pipe_budget_gb < 1e6))
         return BIM_EINVAL;
     bim_ctx h = nullptr;
     try {

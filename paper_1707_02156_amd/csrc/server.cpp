@@ -210,8 +210,9 @@ int bim_server_footprint(const bim_options *opt, int n_drops, const int *p, doub
     // singular pipeline intermediates for the largest degree (capped chunk)
     const double P1 = pmax + 1, Q1 = opt->U_sing * pmax + 1, nc = ncoef_s(pmax), nk = 2.0 * pmax;
     const double per_lat = nk * 8.0 * (nc * 12 + P1 * 3 * Q1 * 6 + P1 * Q1 * 12 + nc * 12 + Q1 * 3 + 3);
-    const double pipe = per_lat * P1;
-    b += pipe < 768.0 * 1024 * 1024 ? pipe : 768.0 * 1024 * 1024;
+    const double pipe = per_lat * P1 * n_drops;
+    const double cap = opt->pipe_budget_gb * 1024.0 * 1024 * 1024;
+    b += pipe < cap ? pipe : cap;
     *bytes = b;
     return BIM_OK;
 }

@@ -38,7 +38,7 @@ def test_status_strings_and_defaults(B):
     assert o.A_tilde == 5.0 and o.U_tilde == 4 and o.U_sing == 1 and o.U_geom == 2
     assert o.gmres_tol == 1e-10 and o.gmres_restart == 50 and o.precision == B.BIM_PREC_FP64
     assert o.near_rule == 1 and o.near_L == 8 and o.fmm_order == 0 and o.fmm_eps == 1e-10
-    assert o.pair_tune == 1 and o.xform_path == 0
+    assert o.pair_tune == 1 and o.xform_path == 0 and o.pipe_budget_gb == 8.0
     assert B.lib().bim_status_string(B.BIM_EBUSY).decode() == "server queue full"
     import ctypes
     so = B.bim_server_options()
@@ -56,7 +56,7 @@ def test_invalid_options_rejected_without_device(B):
     assert B.lib().bim_create(ctypes.byref(o), ctypes.byref(h)) == B.BIM_EINVAL
     for bad in (dict(near_rule=2), dict(near_L=1), dict(near_L=17), dict(fmm_order=1), dict(fmm_order=31),
                 dict(fmm_order=8, fmm_eps=0.0), dict(fmm_order=8, fmm_eps=1.0), dict(xform_path=3),
-                dict(xform_path=-1)):
+                dict(xform_path=-1), dict(pipe_budget_gb=0.0), dict(pipe_budget_gb=float("nan"))):
         o = B.bim_default_options(**bad)
         assert B.lib().bim_create(ctypes.byref(o), ctypes.byref(h)) == B.BIM_EINVAL
     assert B.lib().bim_destroy(None) == B.BIM_EINVAL
