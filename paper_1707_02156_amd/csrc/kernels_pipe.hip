@@ -142,14 +142,17 @@ struct LegBatch {
     long out_row;      // first OUT row
 };
 
-template <int MT>
+// CT column tiles of 16 per wavefront (64 CT columns per block): each table
+// value read from LDS feeds CT products, and the table block staged per block
+// serves CT times as many columns.
+template <int MT, int CT>
 __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
                                                   const double *__restrict__ in, double *__restrict__ out, long NC)
 {
     __shared__ double sT[MT * 16 * 53];   // rows padded to MT*16, depth padded to 4 (up to 52), odd row stride
     const LegBatch b = bt[blockIdx.y];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const long col0 = (long)blockIdx.x * 64 + wv * 16;
+    const long col0 = (long)blockIdx.x * 64 * CT + wv * 16 * CT;
     const int Kp = (b.K + 3) & ~3, Ks = Kp + 1;
     // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp, row stride Ks
     for (int i = threadIdx.x; i < MT * 16 * Kp; i += 256) {
@@ -157,29 +160,42 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
         sT[r * Ks + k] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
     }
     __syncthreads();
-    d4_t acc[MT];
+    d4_t acc[CT][MT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = (d4_t){0, 0, 0, 0};
-    const long col = col0 + (lane & 15);
-    const bool cok = col < NC;
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[c][m] = (d4_t){0, 0, 0, 0};
+    long col[CT];
+    bool cok[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        col[c] = col0 + 16 * c + (lane & 15);
+        cok[c] = col[c] < NC;
+    }
     const int kl = lane >> 4;
     for (int k0 = 0; k0 < Kp; k0 += 4) {
         const int k = k0 + kl;
-        const double bv = (cok && k < b.K) ? in[(b.in_row + k) * NC + col] : 0.0;
+        double bv[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) bv[c] = (cok[c] && k < b.K) ? in[(b.in_row + k) * NC + col[c]] : 0.0;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const double av = sT[(m * 16 + (lane & 15)) * Ks + k];
-            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c][m], 0, 0, 0);
         }
     }
-    if (!cok) return;
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int c = 0; c < CT; ++c) {
+        if (!cok[c]) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = m * 16 + 4 * v + kl;
-            if (r < b.R) out[(b.out_row + r) * NC + col] = acc[m][v];
-        }
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = m * 16 + 4 * v + kl;
+                if (r < b.R) out[(b.out_row + r) * NC + col[c]] = acc[c][m][v];
+            }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -618,18 +634,28 @@ size_t rot_lds_bytes(int p)
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
                      double *out, long NC)
 {
-    const dim3 grid(cdiv(NC, 64), nbatch);
     const LegBatch *b = static_cast<const LegBatch *>(batches);
     const int MT = (maxrows + 15) / 16;
-    switch (MT) {
-    case 1: hipLaunchKernelGGL(k_leg_mfma<1>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    case 2: hipLaunchKernelGGL(k_leg_mfma<2>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    case 3: hipLaunchKernelGGL(k_leg_mfma<3>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    case 4: hipLaunchKernelGGL(k_leg_mfma<4>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    case 5: hipLaunchKernelGGL(k_leg_mfma<5>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    case 6: hipLaunchKernelGGL(k_leg_mfma<6>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    default: hipLaunchKernelGGL(k_leg_mfma<7>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-    }
+    // two column tiles per wavefront once the grid keeps some 16 blocks per
+    // CU for every batch row (large chunks); one below that
+    const bool wide = cdiv(NC, 128) * (long)nbatch >= 16L * 256;
+    auto go = [&](auto ct) {
+        constexpr int CT = decltype(ct)::value;
+        const dim3 grid(cdiv(NC, 64 * CT), nbatch);
+        switch (MT) {
+        case 1: hipLaunchKernelGGL((k_leg_mfma<1, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        case 2: hipLaunchKernelGGL((k_leg_mfma<2, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        case 3: hipLaunchKernelGGL((k_leg_mfma<3, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        case 4: hipLaunchKernelGGL((k_leg_mfma<4, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        case 5: hipLaunchKernelGGL((k_leg_mfma<5, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        case 6: hipLaunchKernelGGL((k_leg_mfma<6, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        default: hipLaunchKernelGGL((k_leg_mfma<7, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+        }
+    };
+    if (wide)
+        go(std::integral_constant<int, 2>());
+    else
+        go(std::integral_constant<int, 1>());
 }
 
 int leg_mfma_max_rows() { return 7 * 16; }
