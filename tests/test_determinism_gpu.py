@@ -75,3 +75,18 @@ def test_close_drops_with_nearest_region_rule_are_bit_identical(B):
         c.close()
     for u, r in outs[1:]:
         assert _same(u, outs[0][0]) and r.gmres_iterations == outs[0][1].gmres_iterations
+
+
+def test_pipeline_chunking_does_not_change_the_velocity(B):
+    """The singular pipeline runs the (drop, latitude) units in chunks sized
+    by pipe_budget_gb; every unit is computed the same way in any chunk, so a
+    budget of 50 MB (two latitudes per chunk here) and the default give the
+    same velocity bit for bit."""
+    print("determinism: pipeline chunking", flush=True)
+    wl = W.two_drops()
+    out = []
+    for gb in (8.0, 0.05):
+        c = _ctx(B, wl, pipe_budget_gb=gb)
+        out.append(c.eval_velocity(coefficients=True)[0])
+        c.close()
+    assert _same(out[0], out[1])
