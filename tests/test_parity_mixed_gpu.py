@@ -216,3 +216,29 @@ def test_mixed_deformed_drops_sampled_against_oracle(B, orc, deformed_both):
         ed = max(ed, _rel_out([dl[i][tg]], [s.layer(i, dens, 1, targets=tg) / (4 * np.pi)]))
     print("per-output error SL", es, "DL", ed, flush=True)
     assert 1e-12 < es <= TOL32 and ed <= TOL32
+
+
+@pytest.mark.parametrize("which", ["many_drops", "deformed_drops"])
+def test_mixed_matrix_core_transforms_at_full_size(B, which):
+    """The 64-drop and the 16-deformed-drop workloads with the FP32
+    matrix-core transforms forced (xform_path 2; timing may pick the scalar
+    ones): the Galerkin operator in coefficients and the solved velocity
+    against the FP64 GPU path with scalar transforms (itself held to the
+    oracle at 1e-10), per drop and component."""
+    print(f"mixed, FP32 matrix-core transforms forced: {which}", flush=True)
+    wl = W.many_drops() if which == "many_drops" else W.deformed_drops()
+    p = wl.drops[0].p
+    rng = np.random.default_rng(64)
+    dens = [_density(rng, p) for _ in wl.drops]
+    res = {}
+    for prec, path in ((B.BIM_PREC_FP64, 1), (B.BIM_PREC_MIXED, 2)):
+        c = ctx_for(B, wl, precision=prec, xform_path=path)
+        op = c.double_layer(dens, mode=1)
+        u, rep = c.eval_velocity()
+        assert rep.xform_matrix_cores == (3 if path == 2 else 0)
+        res[prec] = (op, u)
+        c.close()
+    for k, name in ((0, "operator"), (1, "velocity")):
+        e = _rel_out(res[B.BIM_PREC_MIXED][k], res[B.BIM_PREC_FP64][k])
+        print(name, "per-output error", e, flush=True)
+        assert 1e-12 < e <= TOL32
