@@ -142,60 +142,53 @@ struct LegBatch {
     long out_row;      // first OUT row
 };
 
-// CT column tiles of 16 per wavefront (64 CT columns per block): each table
-// value read from LDS feeds CT products, and the table block staged per block
-// serves CT times as many columns.
-template <int MT, int CT>
+template <int MT>
 __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
                                                   const double *__restrict__ in, double *__restrict__ out, long NC)
 {
     __shared__ double sT[MT * 16 * 53];   // rows padded to MT*16, depth padded to 4 (up to 52), odd row stride
     const LegBatch b = bt[blockIdx.y];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const long col0 = (long)blockIdx.x * 64 * CT + wv * 16 * CT;
+    const long col = (long)blockIdx.x * 64 + wv * 16 + (lane & 15);
+    const bool cok = col < NC;
     const int Kp = (b.K + 3) & ~3, Ks = Kp + 1;
+    const int kl = lane >> 4;
+    // every B value of the lane loaded before the first product (13 depth
+    // steps at most): one memory latency per block instead of one per step
+    constexpr int KS = 13;
+    double bv[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + kl;
+        bv[s] = (cok && k < b.K) ? in[(b.in_row + k) * NC + col] : 0.0;
+    }
     // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp, row stride Ks
     for (int i = threadIdx.x; i < MT * 16 * Kp; i += 256) {
         const int r = i / Kp, k = i % Kp;
         sT[r * Ks + k] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
     }
     __syncthreads();
-    d4_t acc[CT][MT];
+    d4_t acc[MT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
+    for (int m = 0; m < MT; ++m) acc[m] = (d4_t){0, 0, 0, 0};
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[c][m] = (d4_t){0, 0, 0, 0};
-    long col[CT];
-    bool cok[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-        col[c] = col0 + 16 * c + (lane & 15);
-        cok[c] = col[c] < NC;
-    }
-    const int kl = lane >> 4;
-    for (int k0 = 0; k0 < Kp; k0 += 4) {
-        const int k = k0 + kl;
-        double bv[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) bv[c] = (cok[c] && k < b.K) ? in[(b.in_row + k) * NC + col[c]] : 0.0;
+    for (int s = 0; s < KS; ++s) {
+        if (4 * s >= Kp) break;
+        const int k = 4 * s + kl;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const double av = sT[(m * 16 + (lane & 15)) * Ks + k];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) acc[c][m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[c][m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[s], acc[m], 0, 0, 0);
         }
     }
+    if (!cok) return;
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-        if (!cok[c]) continue;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = m * 16 + 4 * v + kl;
-                if (r < b.R) out[(b.out_row + r) * NC + col[c]] = acc[c][m][v];
-            }
-    }
+        for (int v = 0; v < 4; ++v) {
+            const int r = m * 16 + 4 * v + kl;
+            if (r < b.R) out[(b.out_row + r) * NC + col] = acc[m][v];
+        }
 }
 
 // ----------------------------------------------------------------------------
@@ -243,19 +236,37 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
     double *V = sG + gsz;                    // [tg][k'][kVS] at tg VT: 12 fields, padded
     double *sCS = V + (long)TG * VT + TG * 3;  // cos, sin of pi e / qs, e < 2 qs
     for (int e = threadIdx.x; e < 2 * nk; e += 256) sCS[e] = cs[e];
-    // ---- load G (weights w_mu applied; x_phi built from x)
-    for (int i = threadIdx.x; i < P1 * ntg * 6; i += 256) {
-        const int e = i % 6;           // c*2 + re/im
-        const int r = i / 6;
-        const int tg = r % ntg, mu = r / ntg;
-        const long colx = (long)(t0 + tg) * 6 + e;
-        const double w = mu ? 2.0 : 1.0;
-        const double gx = w * Gx[((long)mu * 2 * Q1 + jr) * NC6 + colx];
-        const double gdth = w * Gx[((long)mu * 2 * Q1 + Q1 + jr) * NC6 + colx];
-        double *g = sG + ((long)(tg * P1 + mu) * NTY) * 6;
-        g[e] = gx;
-        g[6 + e] = gdth;
-        if (SL) g[18 + e] = w * Gd[((long)mu * Q1 + jr) * NC6 + colx];
+    // ---- load G (weights w_mu applied; x_phi built from x). All loads of a
+    // thread are issued before the first LDS store (P1 <= 52: at most 5
+    // rounds of 3 values), so the block waits for one memory latency.
+    constexpr int kGR = (52 * TG * 6 + 255) / 256;
+    double lx[kGR], lt[kGR], ld[kGR];
+#pragma unroll
+    for (int u = 0; u < kGR; ++u) {
+        const int i = threadIdx.x + 256 * u;
+        lx[u] = lt[u] = ld[u] = 0.0;
+        if (i < P1 * ntg * 6) {
+            const int e = i % 6, r = i / 6;
+            const int tg = r % ntg, mu = r / ntg;
+            const long colx = (long)(t0 + tg) * 6 + e;
+            lx[u] = Gx[((long)mu * 2 * Q1 + jr) * NC6 + colx];
+            lt[u] = Gx[((long)mu * 2 * Q1 + Q1 + jr) * NC6 + colx];
+            if (SL) ld[u] = Gd[((long)mu * Q1 + jr) * NC6 + colx];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kGR; ++u) {
+        const int i = threadIdx.x + 256 * u;
+        if (i < P1 * ntg * 6) {
+            const int e = i % 6;           // c*2 + re/im
+            const int r = i / 6;
+            const int tg = r % ntg, mu = r / ntg;
+            const double w = mu ? 2.0 : 1.0;
+            double *g = sG + ((long)(tg * P1 + mu) * NTY) * 6;
+            g[e] = w * lx[u];
+            g[6 + e] = w * lt[u];
+            if (SL) g[18 + e] = w * ld[u];
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < P1 * ntg * 3; i += 256) {
@@ -634,28 +645,18 @@ size_t rot_lds_bytes(int p)
 void launch_leg_mfma(hipStream_t st, int nbatch, int maxrows, const void *batches, const double *tab, const double *in,
                      double *out, long NC)
 {
+    const dim3 grid(cdiv(NC, 64), nbatch);
     const LegBatch *b = static_cast<const LegBatch *>(batches);
     const int MT = (maxrows + 15) / 16;
-    // two column tiles per wavefront once the grid keeps some 16 blocks per
-    // CU for every batch row (large chunks); one below that
-    const bool wide = cdiv(NC, 128) * (long)nbatch >= 16L * 256;
-    auto go = [&](auto ct) {
-        constexpr int CT = decltype(ct)::value;
-        const dim3 grid(cdiv(NC, 64 * CT), nbatch);
-        switch (MT) {
-        case 1: hipLaunchKernelGGL((k_leg_mfma<1, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        case 2: hipLaunchKernelGGL((k_leg_mfma<2, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        case 3: hipLaunchKernelGGL((k_leg_mfma<3, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        case 4: hipLaunchKernelGGL((k_leg_mfma<4, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        case 5: hipLaunchKernelGGL((k_leg_mfma<5, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        case 6: hipLaunchKernelGGL((k_leg_mfma<6, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        default: hipLaunchKernelGGL((k_leg_mfma<7, CT>), grid, dim3(256), 0, st, b, tab, in, out, NC); break;
-        }
-    };
-    if (wide)
-        go(std::integral_constant<int, 2>());
-    else
-        go(std::integral_constant<int, 1>());
+    switch (MT) {
+    case 1: hipLaunchKernelGGL(k_leg_mfma<1>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 2: hipLaunchKernelGGL(k_leg_mfma<2>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 3: hipLaunchKernelGGL(k_leg_mfma<3>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 4: hipLaunchKernelGGL(k_leg_mfma<4>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 5: hipLaunchKernelGGL(k_leg_mfma<5>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    case 6: hipLaunchKernelGGL(k_leg_mfma<6>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    default: hipLaunchKernelGGL(k_leg_mfma<7>, grid, dim3(256), 0, st, b, tab, in, out, NC); break;
+    }
 }
 
 int leg_mfma_max_rows() { return 7 * 16; }
