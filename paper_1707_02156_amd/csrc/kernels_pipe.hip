@@ -41,6 +41,33 @@ __host__ __device__ inline long koff(int mu, int P1) { return (long)mu * P1 - (l
 // registers per lane, one 16-column tile per wavefront at a time.
 // Output by order mu: B^mu[koff(mu) + n - mu][t*6 + comp*2 + re/im].
 // ----------------------------------------------------------------------------
+// Stage the N1 x N1 blocks of A+ and A- at lat into LDS ([nu][mu], NP x NP,
+// zero padded, row stride NS), the loads of four rounds issued before their
+// stores.
+__device__ inline void stage_rot(const double *__restrict__ Ap, const double *__restrict__ Am, size_t lat, int N1,
+                                 int NP, int NS, double *sAp, double *sAm)
+{
+    for (int i0 = threadIdx.x; i0 < NP * NP; i0 += 1024) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 256 * u, nu = i / NP, mu = i % NP;
+            const bool in = i < NP * NP && nu < N1 && mu < N1;
+            a[u] = in ? Ap[lat + nu * N1 + mu] : 0.0;
+            b[u] = in ? Am[lat + nu * N1 + mu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 256 * u;
+            if (i < NP * NP) {
+                const int nu = i / NP, mu = i % NP;
+                sAp[nu * NS + mu] = a[u];
+                sAm[nu * NS + mu] = b[u];
+            }
+        }
+    }
+}
+
 constexpr int kRotMaxPad = 64;  // degree p <= 63
 
 __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
@@ -62,12 +89,7 @@ __global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restric
     double *sC = sAm + NP * NS;        // [f][nu][re,im]
     double *sCS = sC + nf * N1 * 2;    // cos, sin of the target longitudes [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
-    for (int i = threadIdx.x; i < NP * NP; i += 256) {
-        const int nu = i / NP, mu = i % NP;
-        const bool in = nu < N1 && mu < N1;
-        sAp[nu * NS + mu] = in ? Ap[lat + nu * N1 + mu] : 0.0;
-        sAm[nu * NS + mu] = in ? Am[lat + nu * N1 + mu] : 0.0;
-    }
+    stage_rot(Ap, Am, lat, N1, NP, NS, sAp, sAm);
     const int b0 = n * (n + 1) / 2;
     for (int i = threadIdx.x; i < nf * N1; i += 256) {
         const int f = i / N1, nu = i % N1;
@@ -548,12 +570,7 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
     double *sAm = sAp + NP * NS;
     double *sCS = sAm + NP * NS;       // [2][nk]
     const size_t lat = rot_lat_size(p) * j + rot_off(n);
-    for (int i = threadIdx.x; i < NP * NP; i += 256) {
-        const int nu = i / NP, mu = i % NP;
-        const bool in = nu < N1 && mu < N1;
-        sAp[nu * NS + mu] = in ? Ap[lat + nu * N1 + mu] : 0.0;
-        sAm[nu * NS + mu] = in ? Am[lat + nu * N1 + mu] : 0.0;
-    }
+    stage_rot(Ap, Am, lat, N1, NP, NS, sAp, sAm);
     for (int i = threadIdx.x; i < 2 * nk; i += 256) sCS[i] = csp[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
