@@ -379,7 +379,7 @@ typedef struct {
 
 /* Defaults: 4 slots, 64 GB, max_batch 1, max_batch_drops 128, max_queue 0, opt from
  * bim_default_options with pair_tune 0 and xform_path 1 (no timing of work
- * shapes on the request path). */
+ * shapes on the request path) and pipe_budget_gb 0.75. */
 int bim_server_default_options(bim_server_options *opt);
 int bim_server_create(const bim_server_options *opt, bim_server *out);
 /* Finishes the running requests, drops the queued ones, frees everything. */

@@ -229,9 +229,12 @@ int bim_server_default_options(bim_server_options *o)
     // requests are mostly one-off problem shapes: timing the pair work shape
     // or the transform path of each would cost more than it saves and add to
     // the latency tail; the transforms of small systems are latency-bound,
-    // where the scalar kernels are the faster
+    // where the scalar kernels are the faster; and concurrent slots keep
+    // small singular-pipeline chunks (with 8 GB chunks an overloaded stream
+    // served half as many requests per second)
     o->opt.pair_tune = 0;
     o->opt.xform_path = 1;
+    o->opt.pipe_budget_gb = 0.75;
     return rc;
 }
 
