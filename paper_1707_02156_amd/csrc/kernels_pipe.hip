@@ -184,10 +184,20 @@ __global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ b
         const int k = 4 * s + kl;
         bv[s] = (cok && k < b.K) ? in[(b.in_row + k) * NC + col] : 0.0;
     }
-    // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp, row stride Ks
-    for (int i = threadIdx.x; i < MT * 16 * Kp; i += 256) {
-        const int r = i / Kp, k = i % Kp;
-        sT[r * Ks + k] = (r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
+    // stage the table block, zero padded: sT[r][k], r < MT*16, k < Kp, row
+    // stride Ks; the loads of eight rounds issued before their stores
+    for (int i0 = threadIdx.x; i0 < MT * 16 * Kp; i0 += 8 * 256) {
+        double tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 256 * u, r = i / Kp, k = i % Kp;
+            tv[u] = (i < MT * 16 * Kp && r < b.R && k < b.K) ? tab[b.tab_off + (long)r * b.K + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 256 * u;
+            if (i < MT * 16 * Kp) sT[(i / Kp) * Ks + i % Kp] = tv[u];
+        }
     }
     __syncthreads();
     d4_t acc[MT];
