@@ -248,7 +248,7 @@ __device__ inline double rsq_full(double x)
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-template <bool SL, bool DL, int TG>
+template <bool SL, bool DL, int TG, int FQ>
 __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double *__restrict__ Gx,
                                             const double *__restrict__ Gd, long NC6,
                                             const double *__restrict__ wsing, const double *__restrict__ cs,
@@ -471,22 +471,24 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
         }
     }
     if (DL) {
-        // ---- FA: Fourier analysis of the six stresslet fields. One item = four
+        // ---- FA: Fourier analysis of the six stresslet fields. One item = FQ
         // orders of one parity (mu = base + 2q), sharing the symmetric
-        // combinations of the four points kk, -kk, kk + qs, qs - kk.
+        // combinations of the four points kk, -kk, kk + qs, qs - kk; FQ is
+        // the smallest that lets one pass of the block's threads take every
+        // item (a second, mostly idle pass would cost a whole item's time).
         const int nE = p / 2 + 1, nO = (p + 1) / 2;
-        const int NGe = (nE + 3) / 4, NG = NGe + (nO + 3) / 4;
+        const int NGe = (nE + FQ - 1) / FQ, NG = NGe + (nO + FQ - 1) / FQ;
         for (int it = threadIdx.x; it < NG * ntg * 6; it += 256) {
             const int pr = it % 6;
             const int r = it / 6;
             const int tg = r % ntg, gidx = r / ntg;
             const bool odd = gidx >= NGe;
-            const int base = odd ? 8 * (gidx - NGe) + 1 : 8 * gidx;
+            const int base = odd ? 2 * FQ * (gidx - NGe) + 1 : 2 * FQ * gidx;
             const double sg = odd ? -1.0 : 1.0;
             const double *Vb = V + (long)tg * VT + pr;
-            double tq[4], cq[4], sq[4], cp[4], sp[4], fc[4], fs[4];
+            double tq[FQ], cq[FQ], sq[FQ], cp[FQ], sp[FQ], fc[FQ], fs[FQ];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < FQ; ++q) {
                 const int mu = min(base + 2 * q, p);
                 const double c1 = sCS[mu], s1 = sCS[nk + mu];
                 tq[q] = 2.0 * c1;
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 const double A = fma(sg, K3 + K4, K1 + K2);
                 const double Bv = fma(sg, K3 - K4, K1 - K2);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < FQ; ++q) {
                     fc[q] = fma(cq[q], A, fc[q]);
                     fs[q] = fma(sq[q], Bv, fs[q]);
                     const double cn = fma(tq[q], cq[q], -cp[q]), sn = fma(tq[q], sq[q], -sp[q]);
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < FQ; ++q) {
                 const int mu = base + 2 * q;
                 if (mu <= p) {
                     double *o = Fa + ((long)mu * Q1 + jr) * NC12 + (long)(t0 + tg) * 12 + pr * 2;
@@ -644,11 +646,13 @@ void pipe_set_lds_limits()
 {
     static std::once_flag once;
     std::call_once(once, [] {
-        (void)hipFuncSetAttribute((const void *)k_fk<true, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        (void)hipFuncSetAttribute((const void *)k_fk<true, false, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  163840);
-        (void)hipFuncSetAttribute((const void *)k_fk<false, true, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  163840);
+        for (const void *fn : {(const void *)k_fk<true, true, 4, 2>, (const void *)k_fk<true, true, 4, 3>,
+                               (const void *)k_fk<true, true, 4, 4>, (const void *)k_fk<true, true, 4, 5>,
+                               (const void *)k_fk<true, true, 4, 7>, (const void *)k_fk<true, false, 4, 4>,
+                               (const void *)k_fk<false, true, 4, 2>, (const void *)k_fk<false, true, 4, 3>,
+                               (const void *)k_fk<false, true, 4, 4>, (const void *)k_fk<false, true, 4, 5>,
+                               (const void *)k_fk<false, true, 4, 7>})
+            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
     });
 }
 
@@ -702,12 +706,34 @@ void launch_fk(hipStream_t st, bool sl, bool dl, int p, int qs, int nt, const do
     constexpr int TG = 4;
     const dim3 grid(cdiv(nt, TG), qs + 1);
     const size_t lds = fk_lds_bytes(p, qs, sl, TG);
-    if (sl && dl)
-        hipLaunchKernelGGL((k_fk<true, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
-    else if (sl)
-        hipLaunchKernelGGL((k_fk<true, false, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
-    else
-        hipLaunchKernelGGL((k_fk<false, true, TG>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs, X0, part, Fa, NC12);
+    // orders per item of the stresslet analysis: the smallest with every item
+    // in one pass of the 256 threads
+    const int nE = p / 2 + 1, nO = (p + 1) / 2;
+    int fq = 7;
+    for (int q : {2, 3, 4, 5, 7})
+        if (((nE + q - 1) / q + (nO + q - 1) / q) * TG * 6 <= 256) {
+            fq = q;
+            break;
+        }
+    auto go = [&](auto fqc) {
+        constexpr int FQ = decltype(fqc)::value;
+        if (sl && dl)
+            hipLaunchKernelGGL((k_fk<true, true, TG, FQ>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs,
+                               X0, part, Fa, NC12);
+        else if (sl)
+            hipLaunchKernelGGL((k_fk<true, false, TG, 4>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs,
+                               X0, part, Fa, NC12);
+        else
+            hipLaunchKernelGGL((k_fk<false, true, TG, FQ>), grid, dim3(256), lds, st, p, qs, nt, Gx, Gd, NC6, wsing, cs,
+                               X0, part, Fa, NC12);
+    };
+    switch (fq) {
+    case 2: go(std::integral_constant<int, 2>()); break;
+    case 3: go(std::integral_constant<int, 3>()); break;
+    case 4: go(std::integral_constant<int, 4>()); break;
+    case 5: go(std::integral_constant<int, 5>()); break;
+    default: go(std::integral_constant<int, 7>()); break;
+    }
 }
 
 void launch_sum_part(hipStream_t st, int nt, int Q1, int nk, int P1, const double *part, const PipeDrops &pd, int u0,
