@@ -597,15 +597,19 @@ __global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__rest
         d4_t al[4], be[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) al[m] = be[m] = (d4_t){0, 0, 0, 0};
+        // the next depth step's B operand is loaded while this one's products run
+        auto bload = [&](int ks) {
+            const int mu = ks * 4 + k4;
+            return (cok && mu < N1) ? *reinterpret_cast<const double2 *>(Bt + (koff(mu, P1) + (n - mu)) * NC12 + tcol)
+                                    : make_double2(0.0, 0.0);
+        };
+        double2 vn = bload(0);
         for (int ks = 0; ks < KS; ++ks) {
             const int mu = ks * 4 + k4;
-            double av = 0.0, bv = 0.0;
-            if (cok && mu < N1) {
-                const double2 v = *reinterpret_cast<const double2 *>(Bt + (koff(mu, P1) + (n - mu)) * NC12 + tcol);
-                const double w = mu ? 2.0 : 1.0;
-                av = w * v.x;
-                bv = -w * v.y;
-            }
+            const double2 v = vn;
+            if (ks + 1 < KS) vn = bload(ks + 1);
+            const double w = mu ? 2.0 : 1.0;
+            const double av = w * v.x, bv = -w * v.y;
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 if (m < MT) {
