@@ -339,18 +339,24 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
 #pragma unroll
             for (int q = 0; q < NTY; ++q) { CE[b][q] = 0; CO[b][q] = 0; SE[b][q] = 0; SO[b][q] = 0; }
         }
-        int mu = 0;
-        for (; mu + 1 <= p; mu += 2) {
-            const double *ge = g + (long)mu * NTY * 6, *go = ge + NTY * 6;
+        // Two register sets of G values (orders mu, mu + 1), filled alternately:
+        // the next two orders are read while the current ones are summed.
+        // Indexes are clamped to p; values past the last order are never used.
+        double ac[NTY], as[NTY], aoc[NTY], aos[NTY], bc[NTY], bs[NTY], boc[NTY], bos[NTY];
+        auto gload = [&](int m, double *gc, double *gs) {
+            const double *gm = g + (long)m * NTY * 6;
 #pragma unroll
-            for (int q = 0; q < NTY; ++q) {
-                const double gc = ge[6 * q], gs = ge[6 * q + 1];
+            for (int q = 0; q < NTY; ++q) { gc[q] = gm[6 * q]; gs[q] = gm[6 * q + 1]; }
+        };
+        // orders mu (even) and mu + 1 (odd) added; the recurrences advance by two
+        auto step = [&](const double *ec, const double *es, const double *oc, const double *os) {
+#pragma unroll
+            for (int q = 0; q < NTY; ++q)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    CE[b][q] = fma(gc, c0[b], CE[b][q]);
-                    SE[b][q] = fma(gs, s0[b], SE[b][q]);
+                    CE[b][q] = fma(ec[q], c0[b], CE[b][q]);
+                    SE[b][q] = fma(es[q], s0[b], SE[b][q]);
                 }
-            }
             double c1n[2], s1n[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
@@ -358,14 +364,12 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 s1n[b] = fma(tc[b], s0[b], -sm1[b]);
             }
 #pragma unroll
-            for (int q = 0; q < NTY; ++q) {
-                const double gc = go[6 * q], gs = go[6 * q + 1];
+            for (int q = 0; q < NTY; ++q)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    CO[b][q] = fma(gc, c1n[b], CO[b][q]);
-                    SO[b][q] = fma(gs, s1n[b], SO[b][q]);
+                    CO[b][q] = fma(oc[q], c1n[b], CO[b][q]);
+                    SO[b][q] = fma(os[q], s1n[b], SO[b][q]);
                 }
-            }
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 cm1[b] = c1n[b];
@@ -373,18 +377,42 @@ __global__ __launch_bounds__(256) void k_fk(int p, int qs, int nt, const double 
                 c0[b] = fma(tc[b], c1n[b], -c0[b]);
                 s0[b] = fma(tc[b], s1n[b], -s0[b]);
             }
-        }
-        if (mu <= p) {  // last order (even)
-            const double *ge = g + (long)mu * NTY * 6;
+        };
+        auto last_even = [&](const double *ec, const double *es) {
 #pragma unroll
-            for (int q = 0; q < NTY; ++q) {
-                const double gc = ge[6 * q], gs = ge[6 * q + 1];
+            for (int q = 0; q < NTY; ++q)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    CE[b][q] = fma(gc, c0[b], CE[b][q]);
-                    SE[b][q] = fma(gs, s0[b], SE[b][q]);
+                    CE[b][q] = fma(ec[q], c0[b], CE[b][q]);
+                    SE[b][q] = fma(es[q], s0[b], SE[b][q]);
                 }
+        };
+        gload(0, ac, as);
+        gload(min(1, p), aoc, aos);
+        int mu = 0;
+#pragma unroll 1
+        for (; mu + 3 <= p; mu += 4) {
+            gload(mu + 2, bc, bs);
+            gload(mu + 3, boc, bos);
+            __builtin_amdgcn_sched_barrier(0);
+            step(ac, as, aoc, aos);
+            __builtin_amdgcn_sched_barrier(0);
+            gload(min(mu + 4, p), ac, as);
+            gload(min(mu + 5, p), aoc, aos);
+            __builtin_amdgcn_sched_barrier(0);
+            step(bc, bs, boc, bos);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // the set a holds orders mu and mu + 1 (clamped)
+        if (mu + 1 <= p) {
+            step(ac, as, aoc, aos);
+            mu += 2;
+            if (mu <= p) {
+                gload(mu, bc, bs);
+                last_even(bc, bs);
             }
+        } else if (mu <= p) {
+            last_even(ac, as);
         }
         double *Vb = V + (long)tg * VT;
         // value(phi) = (CE - SE) + (CO - SO); at -phi the sine terms flip; at phi + pi the odd orders flip
