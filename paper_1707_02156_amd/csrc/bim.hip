@@ -204,17 +204,38 @@ struct DBuf {
         if (t_no_alloc)
             throw Error{BIM_ESTATE, "the call would allocate device memory (" + std::to_string(b) +
                                         " bytes): apply bim_apply_double_layer once to these drops first"};
+        const bool regrow = ptr != nullptr;
         release();
         if (b == 0) b = 8;
         // grow with slack: freeing device memory waits for the whole device,
         // so a context reused for inputs of varying size should rarely regrow
-        if (bytes) b += b / 4;
+        if (regrow) b += b / 4;
         HIPC(hipMalloc(&ptr, b));
         bytes = b;
     }
     double *d() const { return static_cast<double *>(ptr); }
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
+
+// Host vectors in pinned memory: the lists uploaded at every evaluation are
+// copied from them without staging, so an upload neither waits for the work
+// ahead of it in the stream nor makes the device wait for the host. Their
+// storage is kept across evaluations (cleared, refilled, grown rarely).
+template <class T> struct PinnedAlloc {
+    using value_type = T;
+    PinnedAlloc() = default;
+    template <class U> PinnedAlloc(const PinnedAlloc<U> &) {}
+    T *allocate(size_t n)
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+        return static_cast<T *>(p);
+    }
+    void deallocate(T *p, size_t) { (void)hipHostFree(p); }
+    template <class U> bool operator==(const PinnedAlloc<U> &) const { return true; }
+    template <class U> bool operator!=(const PinnedAlloc<U> &) const { return false; }
+};
+template <class T> using HVec = std::vector<T, PinnedAlloc<T>>;
 
 // Tables of a degree-q grid with Legendre functions up to degree nmax.
 struct GridTab {
@@ -243,6 +264,13 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream: the singular pipeline of the single-layer pass runs on
+    // it while the context's stream classifies the regions and the host
+    // builds the pair lists; the context's stream waits for ev_join before
+    // the pipeline's results are used
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool join_pending = false;
     std::string err;
 
     int nd = 0;
@@ -284,7 +312,7 @@ struct Ctx {
     // target tile for the items over contiguous tiles, per target for the
     // items over index lists
     struct Gather {
-        std::vector<int> h_toff, h_tent, h_off, h_ent;
+        HVec<int> h_toff, h_tent, h_off, h_ent;
         DBuf toff, tent, off, ent;
         long nt = 0;
     };
@@ -294,12 +322,15 @@ struct Ctx {
     DBuf tile_of;
     struct WList {
         std::vector<double> wt;
+        // stale: built for earlier regions; refilled in place (its buffers
+        // kept) by the next request for a weight table
+        bool stale = false;
         // host images the device copies are made from (kept for the list's
         // lifetime, so no upload waits; declared before the device buffers,
         // whose release waits for the device, so they outlive any copy)
-        std::vector<PairWork> h_items;
-        std::vector<double> h_nw;
-        std::vector<FmmPair> h_fp;
+        HVec<PairWork> h_items;
+        HVec<double> h_nw;
+        HVec<FmmPair> h_fp;
         DBuf d;
         int n = 0;           // items: whole tiles first, then the remainder items
         double pairs = 0.0;  // target-source pairs per application
@@ -350,6 +381,7 @@ struct Ctx {
     long near_ldp = 0;
     double near_pairs = 0.0;
     DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
+    DBuf acc2;                     // [3][T] the single-layer pipeline's part when it runs on the second stream
     DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
     std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
     std::vector<char> Mok;
@@ -415,6 +447,12 @@ struct Ctx {
         rots.clear();
         if (hhost) (void)hipHostFree(hhost);
         if (hres) (void)hipHostFree(hres);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -440,7 +478,9 @@ struct ProfScope {
     Ctx &c;
     Ctx::ProfEntry *e = nullptr;
     hipEvent_t a = nullptr;
-    ProfScope(Ctx &cc, const char *name, double flops, double bytes) : c(cc)
+    hipStream_t st;
+    ProfScope(Ctx &cc, const char *name, double flops, double bytes, hipStream_t s = nullptr)
+        : c(cc), st(s ? s : cc.stream)
     {
         if (!c.prof_on) return;
         Ctx::ProfEntry *pe = &c.prof[name];
@@ -450,19 +490,20 @@ struct ProfScope {
         if (!c.prof_sel.empty() && !c.prof_sel.count(name)) return;
         e = pe;
         a = prof_event(c);
-        HIPC(hipEventRecord(a, c.stream));
+        HIPC(hipEventRecord(a, st));
     }
     ~ProfScope()
     {
         if (!e) return;
         hipEvent_t b = prof_event(c);
-        if (hipEventRecord(b, c.stream) == hipSuccess) e->pend.emplace_back(a, b);
+        if (hipEventRecord(b, st) == hipSuccess) e->pend.emplace_back(a, b);
     }
 };
 
 static void prof_drain(Ctx &c)
 {
     HIPC(hipStreamSynchronize(c.stream));
+    if (c.side) HIPC(hipStreamSynchronize(c.side));
     for (auto &kv : c.prof) {
         for (auto &pr : kv.second.pend) {
             float ms = 0.0f;
@@ -856,8 +897,9 @@ static void pair_items(std::vector<PairWork> &w, int tl_off, int cnt, bool conti
 // contiguous tile k adds its base slot minus the tile's first target to tile
 // k's list; an item over an index list adds the slot of each of its targets
 // to that target's list. Both in item order.
-static void gather_lists(Ctx &c, const std::vector<PairWork> &items, const std::vector<int> &tl, long nt, bool tiles,
-                         int tile, Ctx::Gather &g)
+template <class Items>
+static void gather_lists(Ctx &c, const Items &items, const std::vector<int> &tl, long nt, bool tiles, int tile,
+                         Ctx::Gather &g)
 {
     REQUIRE((double)items.size() * 3 * tile < 2147483647.0, BIM_ENOMEM, "too many pair work items");
     const size_t ntile = tiles ? c.tile_start_h.size() : 0;
@@ -888,7 +930,7 @@ static void gather_lists(Ctx &c, const std::vector<PairWork> &items, const std::
             for (int a = 0; a < w.ntgt; ++a) g.h_ent[pos[tl[w.tlist_off + a]]++] = base + a;
         }
     }
-    auto up = [&](DBuf &d, const std::vector<int> &h) {
+    auto up = [&](DBuf &d, const HVec<int> &h) {
         d.ensure(std::max<size_t>(1, h.size()) * sizeof(int));
         if (!h.empty()) HIPC(hipMemcpyAsync(d.ptr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
     };
@@ -1233,7 +1275,7 @@ static void build_lists(Ctx &c, int P, const std::vector<double> &cb0, const std
     if (!F.pairs.empty()) fmm_setup(c, cb0, cb1);
     c.w0h = std::move(w0);
     c.w1h = std::move(w1);
-    c.wlists.clear();
+    for (auto &e : c.wlists) e->stale = true;
     c.near_h = std::move(near);
 }
 
@@ -1457,10 +1499,22 @@ static void build_regions(Ctx &c)
 static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
 {
     for (auto &e : c.wlists)
-        if (e->wt == wt) return *e;
-    auto e = std::make_unique<Ctx::WList>();
+        if (!e->stale && e->wt == wt) return *e;
+    // refill a stale list (the one of this table if there is one): its
+    // device buffers and pinned host images are kept, so a new evaluation
+    // of the same drops allocates and frees nothing here
+    Ctx::WList *e = nullptr;
+    for (auto &x : c.wlists)
+        if (x->stale && (!e || x->wt == wt)) e = x.get();
+    if (!e) {
+        c.wlists.push_back(std::make_unique<Ctx::WList>());
+        e = c.wlists.back().get();
+    }
+    e->stale = false;
     e->wt = wt;
-    std::vector<PairWork> &keep = e->h_items;
+    e->pairs = 0.0;
+    HVec<PairWork> &keep = e->h_items;
+    keep.clear();
     keep.reserve(c.w0h.size() + c.w1h.size());
     for (int small = 0; small < 2; ++small) {  // whole-tile items first, then the remainders
         for (int u = 0; u < 2; ++u)
@@ -1479,21 +1533,20 @@ static Ctx::WList &work_lists(Ctx &c, const std::vector<double> &wt)
     e->n = (int)keep.size();
     gather_lists(c, keep, c.tlist_h, c.T, true, 64 * c.pair_T, e->g);
     if (!c.near_h.empty()) {
-        std::vector<double> &nw = e->h_nw;
+        HVec<double> &nw = e->h_nw;
         nw.resize(c.near_h.size());
         for (size_t it = 0; it < nw.size(); ++it) nw[it] = wt[(size_t)c.near_h[it].i * c.nd + c.near_h[it].j];
         e->nw.ensure(nw.size() * sizeof(double));
         HIPC(hipMemcpyAsync(e->nw.ptr, nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
     }
     if (!c.fmm.pairs.empty()) {
-        std::vector<FmmPair> &fp = e->h_fp;
-        fp = c.fmm.pairs;
+        HVec<FmmPair> &fp = e->h_fp;
+        fp.assign(c.fmm.pairs.begin(), c.fmm.pairs.end());
         for (size_t k = 0; k < fp.size(); ++k) fp[k].w = wt[c.fmm.pair_ij[k]];
         e->fp.ensure(fp.size() * sizeof(FmmPair));
         HIPC(hipMemcpyAsync(e->fp.ptr, fp.data(), fp.size() * sizeof(FmmPair), hipMemcpyHostToDevice, c.stream));
     }
-    c.wlists.push_back(std::move(e));
-    return *c.wlists.back();
+    return *e;
 }
 
 // Far drop pairs by the fast summation (plan of build_regions), added into
@@ -1947,9 +2000,14 @@ static bool pipe_fits(int p, int qs)
 // the batched pipeline: single layer of dens added into acc (sl) and/or the
 // stored double-layer rows of each drop (dl). Chunks are sets of (drop,
 // latitude) units sized by a memory budget for the intermediates.
-static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl, const double *dens)
+// st: the stream of the launches (the context's by default); acc_out: where
+// the single layer's longitude sums are added (acc by default).
+static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl, const double *dens,
+                           hipStream_t st = nullptr, double *acc_out = nullptr)
 {
     if (ids.empty()) return;
+    if (!st) st = c.stream;
+    if (!acc_out) acc_out = c.acc.d();
     const Drop &d0 = c.drops[ids[0]];
     const int p = d0.p, qs = d0.qs, P1 = p + 1, Q1 = qs + 1, nk = 2 * p, nc = ncoef(p);
     RotTab &r = rot(c, p);
@@ -1999,16 +2057,16 @@ static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl
         const int nuc = std::min(nj, nu - u0);
         const long nt = (long)nuc * nk, NC6 = nt * 6, NC12 = nt * 12;
         {
-            ProfScope ps(c, "pipe_rotate", nt * (sl ? 6.0 : 3.0) * rotlat * 4.0, nt * (sl ? 2.0 : 1.0) * nc * 6 * 8.0);
-            launch_rot2(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d(), c.Ctot, sl ? dens : nullptr, c.Ctot,
+            ProfScope ps(c, "pipe_rotate", nt * (sl ? 6.0 : 3.0) * rotlat * 4.0, nt * (sl ? 2.0 : 1.0) * nc * 6 * 8.0, st);
+            launch_rot2(st, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.xc.d(), c.Ctot, sl ? dens : nullptr, c.Ctot,
                         pd, u0, nuc, c.pBx.d(), sl ? c.pBd.d() : nullptr, NC6);
-            launch_pole(c.stream, p, (int)nt, c.pBx.d(), NC6, c.pX0.d());
+            launch_pole(st, p, (int)nt, c.pBx.d(), NC6, c.pX0.d());
         }
         {
             ProfScope ps(c, "pipe_legendre", 2.0 * 2 * Q1 * nc * NC6 + (sl ? 2.0 * Q1 * nc * NC6 : 0.0),
-                         8.0 * ((double)nc * NC6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * NC6 + (sl ? (double)P1 * Q1 * NC6 : 0.0)));
-            launch_leg_mfma(c.stream, P1, pt.maxrows_syn, pt.bsx.ptr, pt.syn.d(), c.pBx.d(), c.pGx.d(), NC6);
-            if (sl) launch_leg_mfma(c.stream, P1, Q1, pt.bsd.ptr, pt.syn.d(), c.pBd.d(), c.pGd.d(), NC6);
+                         8.0 * ((double)nc * NC6 * (sl ? 2 : 1) + (double)P1 * 2 * Q1 * NC6 + (sl ? (double)P1 * Q1 * NC6 : 0.0)), st);
+            launch_leg_mfma(st, P1, pt.maxrows_syn, pt.bsx.ptr, pt.syn.d(), c.pBx.d(), c.pGx.d(), NC6);
+            if (sl) launch_leg_mfma(st, P1, Q1, pt.bsd.ptr, pt.syn.d(), c.pBd.d(), c.pGd.d(), NC6);
         }
         {
             // algorithmic flops per target: each real field column of the
@@ -2023,19 +2081,19 @@ static void run_pipe_group(Ctx &c, const std::vector<int> &ids, bool sl, bool dl
             double fl = fft * (sl ? 12.0 : 9.0) + (sl ? NP * 35.0 : 0.0);
             if (dl) fl += NP * 40.0 + 6.0 * fft;
             ProfScope ps(c, "pipe_fourier", nt * fl,
-                         8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)));
-            launch_fk(c.stream, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),
+                         8.0 * ((double)P1 * (sl ? 3 : 2) * Q1 * NC6 + (dl ? (double)P1 * Q1 * NC12 : 0.0)), st);
+            launch_fk(st, sl, dl, p, qs, (int)nt, c.pGx.d(), sl ? c.pGd.d() : nullptr, NC6, gs.wsing.d(),
                       gs.cs.d(), c.pX0.d(), c.pPart.d(), dl ? c.pFa.d() : nullptr, NC12);
-            if (sl) launch_sum_part(c.stream, (int)nt, Q1, nk, P1, c.pPart.d(), pd, u0, 1.0, c.acc.d(), c.T);
+            if (sl) launch_sum_part(st, (int)nt, Q1, nk, P1, c.pPart.d(), pd, u0, 1.0, acc_out, c.T);
         }
         if (dl) {
             {
-                ProfScope ps(c, "pipe_legendre", 2.0 * Q1 * nc * NC12, 8.0 * ((double)P1 * Q1 * NC12 + (double)nc * NC12));
-                launch_leg_mfma(c.stream, P1, pt.maxrows_ana, pt.ban.ptr, pt.ana.d(), c.pFa.d(), c.pBt.d(), NC12);
+                ProfScope ps(c, "pipe_legendre", 2.0 * Q1 * nc * NC12, 8.0 * ((double)P1 * Q1 * NC12 + (double)nc * NC12), st);
+                launch_leg_mfma(st, P1, pt.maxrows_ana, pt.ban.ptr, pt.ana.d(), c.pFa.d(), c.pBt.d(), NC12);
             }
             {
-                ProfScope ps(c, "pipe_adjrot", nt * 6.0 * rotlat * 4.0, 8.0 * ((double)nc * NC12 + (double)nt * 6 * 2 * nc));
-                launch_adjrot(c.stream, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.pBt.d(), NC12, pd, u0, nuc);
+                ProfScope ps(c, "pipe_adjrot", nt * 6.0 * rotlat * 4.0, 8.0 * ((double)nc * NC12 + (double)nt * 6 * 2 * nc), st);
+                launch_adjrot(st, p, r.Ap.d(), r.Am.d(), gp.cs.d(), c.pBt.d(), NC12, pd, u0, nuc);
             }
         }
     }
@@ -2179,13 +2237,64 @@ static void double_layer_grid(Ctx &c, const double *ucoef, const std::vector<dou
     run_near(c, 1, ucoef, wt);
 }
 
-// Single layer of fcoef at all targets into acc. with_dl[i] also builds the
-// stored double-layer rows of drop i in the same pass.
-static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<char> *with_dl = nullptr)
+// Whether two drops of one system interact (there are pair sums).
+static bool drop_pairs(const Ctx &c)
 {
-    build_regions(c);
-    std::vector<char> need(c.nd, 1);
-    density_nodes(c, fcoef, need, false, c.acc.d(), 3 * c.T);  // acc cleared by the same launch
+    for (int i = 0; i < c.nd; ++i)
+        for (int j = i + 1; j < c.nd; ++j)
+            if (c.sys_h[i] == c.sys_h[j]) return true;
+    return false;
+}
+
+// Whether a choice by timing (pair work shape, fast-summation order,
+// transform path) is still to be made: its timed launches must not share the
+// device with other work.
+static bool timing_pending(const Ctx &c)
+{
+    const bool f32 = c.opt.precision == BIM_PREC_MIXED;
+    if (c.opt.xform_path == 0 && (c.xmode[0][f32] < 0 || c.xmode[1][f32] < 0)) return true;
+    if (!drop_pairs(c)) return false;
+    return (c.opt.pair_tune && !c.pair_tuned) || (c.opt.fmm_order < 0 && c.fmm_tuned < 0);
+}
+
+// The context's stream waits for the work of the second stream (a no-op
+// when nothing is pending there).
+static void join_side(Ctx &c)
+{
+    if (!c.join_pending) return;
+    c.join_pending = false;
+    HIPC(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+}
+
+// Orders the second stream after the work enqueued so far on the context's
+// stream (creating the stream and its events on first use).
+static void fork_side(Ctx &c)
+{
+    join_side(c);
+    if (!c.side) {
+        HIPC(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+        HIPC(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    }
+    HIPC(hipEventRecord(c.ev_fork, c.stream));
+    HIPC(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+}
+
+// Single layer of fcoef at all targets into acc. with_dl[i] also builds the
+// stored double-layer rows of drop i in the same pass; wt_dl: the weights of
+// the double-layer operator that will follow, whose pair lists are built
+// while the device runs the pipeline.
+//
+// The singular pipeline needs neither the regions nor the node densities.
+// When the regions are still to be built, it runs on the second stream,
+// adding into acc2, while the context's stream classifies the regions and
+// the host builds the pair lists (with no timing pending, whose launches
+// must have the device to themselves). acc then starts as a copy of acc2:
+// the same values, added in the same order, as when the pipeline adds into a
+// cleared acc on the context's stream.
+static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<char> *with_dl = nullptr,
+                              const std::vector<double> *wt_dl = nullptr)
+{
     // pipeline drops grouped by degree, separately with and without the rows
     std::vector<int> with_rows, without_rows;
     for (int i = 0; i < c.nd; ++i) {
@@ -2193,8 +2302,32 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
         const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
         (dl ? with_rows : without_rows).push_back(i);
     }
-    for (auto &g : pipe_groups(c, with_rows)) run_pipe_group(c, g, true, true, fcoef);
-    for (auto &g : pipe_groups(c, without_rows)) run_pipe_group(c, g, true, false, fcoef);
+    const bool side = !c.regions_ok && !(with_rows.empty() && without_rows.empty()) && !timing_pending(c);
+    const size_t accb = (size_t)3 * c.T * sizeof(double);
+    if (side) {
+        c.acc2.ensure(accb);
+        fork_side(c);
+        HIPC(hipMemsetAsync(c.acc2.ptr, 0, accb, c.side));
+        for (auto &g : pipe_groups(c, with_rows)) run_pipe_group(c, g, true, true, fcoef, c.side, c.acc2.d());
+        for (auto &g : pipe_groups(c, without_rows)) run_pipe_group(c, g, true, false, fcoef, c.side, c.acc2.d());
+        HIPC(hipEventRecord(c.ev_join, c.side));
+        c.join_pending = true;
+    }
+    build_regions(c);
+    std::vector<double> wt((size_t)c.nd * c.nd, 1.0);
+    if (side) {
+        (void)work_lists(c, wt);  // uploads enqueued now run beside the pipeline
+        if (wt_dl) (void)work_lists(c, *wt_dl);
+    }
+    std::vector<char> need(c.nd, 1);
+    density_nodes(c, fcoef, need, false, c.acc.d(), 3 * c.T);  // acc cleared by the same launch
+    if (side) {
+        join_side(c);
+        HIPC(hipMemcpyAsync(c.acc.ptr, c.acc2.ptr, accb, hipMemcpyDeviceToDevice, c.stream));
+    } else {
+        for (auto &g : pipe_groups(c, with_rows)) run_pipe_group(c, g, true, true, fcoef);
+        for (auto &g : pipe_groups(c, without_rows)) run_pipe_group(c, g, true, false, fcoef);
+    }
     for (int i = 0; i < c.nd; ++i) {
         const Drop &d = c.drops[i];
         const bool dl = with_dl && (*with_dl)[i] && !dl_matrix_ready(c, i);
@@ -2210,7 +2343,6 @@ static void single_layer_grid(Ctx &c, const double *fcoef, const std::vector<cha
     }
     if (!c.near_h.empty())
         HIPC(hipMemcpyAsync(c.near_self.ptr, c.acc.ptr, 3 * c.T * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-    std::vector<double> wt((size_t)c.nd * c.nd, 1.0);
     run_pairs(c, 0, wt);
     run_near(c, 0, fcoef, wt);
 }
@@ -3341,7 +3473,7 @@ int bim_apply_double_layer_noalloc(bim_ctx h, const double *u_coef, double *out,
             mode == 0 ? std::vector<double>((size_t)c.nd * c.nd, 1.0 / (4.0 * kPi)) : dl_weights(c);
         const Ctx::WList *L = nullptr;
         for (auto &e : c.wlists)
-            if (e->wt == wt) L = e.get();
+            if (!e->stale && e->wt == wt) L = e.get();
         REQUIRE(L, BIM_ESTATE, "the pair work list of this mode is not built: apply bim_apply_double_layer once first");
         const double need = std::max((double)L->n * 3 * 64 * c.pair_T, (double)c.near_nwork * 3 * 64);
         REQUIRE(need <= (double)kScratchDoubles, BIM_ENOMEM,
@@ -3456,7 +3588,8 @@ static int solve_velocity(Ctx &c, int &iters, double &relres, int &nmv)
         const std::vector<double> wt = dl_weights(c);
         for (int i = 0; i < c.nd; ++i) with_dl[i] = wt[(size_t)i * c.nd + i] != 0.0;
     }
-    single_layer_grid(c, c.fc.d(), &with_dl);
+    const std::vector<double> wt_dl = all_one ? std::vector<double>() : dl_weights(c);
+    single_layer_grid(c, c.fc.d(), &with_dl, all_one ? nullptr : &wt_dl);
     // b = 2 u_inf - S / (4 pi) on the grid, then Galerkin projection
     c.tmp.ensure((size_t)3 * std::max<long>(c.Ctot, c.T) * sizeof(double));
     launch_rhs(c.stream, (int)c.T, c.tx.d(), c.T, c.acc.d(), -1.0 / (4.0 * kPi), c.U0, c.gU.d(), c.tmp.d());
