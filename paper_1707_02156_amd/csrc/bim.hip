@@ -2460,16 +2460,12 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
     double *resdev = nullptr;
     HIPC(hipHostGetDevicePointer((void **)&resdev, c.hres, 0));
     HIPC(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
-    // ||b||
-    launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, const_cast<double *>(b), part, cnt, h);
-    HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HIPC(hipStreamSynchronize(c.stream));
-    const double bn = c.hhost[0];
-    ga.bnorm = bn;
+    // ||b|| is the first residual norm (r = b at x = 0: the same kernel and
+    // summation order), read with it
+    double bn = 0.0;
     iters = 0;
     nmv = 0;
     relres = 0.0;
-    if (bn == 0.0) return BIM_OK;
     double *gh = c.hhost + 256;  // host image of g at a restart
     volatile double *resh = c.hres;
     bool first = true;
@@ -2482,11 +2478,16 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
             ++nmv;
             launch_scale_add(c.stream, n, 1.0, b, -1.0, c.rvec.d());
         }
-        first = false;
         launch_gs_update_norm(c.stream, n, 0, nullptr, n, nullptr, c.rvec.d(), part, cnt, h, GivensArgs{}, V);
         HIPC(hipMemcpyAsync(c.hhost, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
         HIPC(hipStreamSynchronize(c.stream));
         const double beta = c.hhost[0];
+        if (first) {
+            bn = beta;
+            ga.bnorm = bn;
+            if (bn == 0.0) return BIM_OK;
+        }
+        first = false;
         relres = beta / bn;
         if (relres <= tol) return BIM_OK;
         if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
@@ -2545,11 +2546,12 @@ static int gmres_op(Ctx &c, long n, const OpFn &apply, const double *b, double *
                 break;
             }
         }
-        // x += V y with R y = g over the completed steps
+        // x += V y with R y = g over the completed steps (stream-ordered for
+        // what follows: a converged solve returns without waiting for it)
         launch_backsub(c.stream, kdone, ga.H, ldH, ga.g, c.ybuf.d());
         launch_lincomb(c.stream, n, kdone, V, n, c.ybuf.d(), x);
-        HIPC(hipStreamSynchronize(c.stream));
         if (conv) return BIM_OK;
+        HIPC(hipStreamSynchronize(c.stream));
         if (iters >= c.opt.gmres_maxit) return BIM_ENOCONV;
     }
 }
