@@ -383,7 +383,14 @@ struct Ctx {
     DBuf acc, tmp, bvec, scl;      // [3][T] accumulators, [3][Ctot] vectors
     DBuf acc2;                     // [3][T] the single-layer pipeline's part when it runs on the second stream
     DBuf synbuf, Gbuf, Rbuf, Fbuf, fgrid;
-    std::vector<std::unique_ptr<DBuf>> Mdl;  // per drop: stored singular double-layer rows
+    // per drop: stored singular double-layer rows. The buffers are kept
+    // (grown, never freed) when new drops are set: freeing device memory
+    // waits for the whole device and a fresh large allocation is slow, which
+    // a server slot would pay at every request
+    std::vector<std::unique_ptr<DBuf>> Mdl;
+    // pinned host images of the per-drop tables set_drops uploads
+    HVec<int> h_tdrop, h_noff, h_ncnt, h_unoff, h_uncnt, h_sys;
+    HVec<double> h_xc, h_hfac, h_scl, h_gU;
     std::vector<char> Mok;
     DBuf V, hbuf, ybuf, wvec, xsol, rvec, gspart, gscnt, givbuf;
     DBuf bcorr, xcorr;  // per-system corrections of a joint solve
@@ -2805,13 +2812,20 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         c.drops = ds;
         c.xplans.clear();
         for (auto &row : c.xmode) row[0] = row[1] = -1;
-        c.Mdl.clear();
+        if ((int)c.Mdl.size() < n_drops) c.Mdl.resize(n_drops);
         c.Mok.assign(n_drops, 0);
         c.Ctot = coff;
         c.T = toff;
         c.S1 = uoff;
-        c.xc.ensure(hx.size() * sizeof(double));
-        HIPC(hipMemcpyAsync(c.xc.ptr, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        // uploads from pinned host images: enqueued without waiting, all
+        // complete at the synchronisation that ends this call
+        auto up = [&](DBuf &d, auto &img) {
+            d.ensure(std::max<size_t>(1, img.size()) * sizeof(img[0]));
+            if (!img.empty())
+                HIPC(hipMemcpyAsync(d.ptr, img.data(), img.size() * sizeof(img[0]), hipMemcpyHostToDevice, c.stream));
+        };
+        c.h_xc.assign(hx.begin(), hx.end());
+        up(c.xc, c.h_xc);
         c.gc.ensure((size_t)coff * sizeof(double));
         HIPC(hipMemsetAsync(c.gc.ptr, 0, (size_t)coff * sizeof(double), c.stream));
         c.fc.ensure((size_t)3 * coff * sizeof(double));
@@ -2831,7 +2845,12 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
         c.tmp.ensure((size_t)3 * c.T * sizeof(double));
         c.bvec.ensure((size_t)3 * c.Ctot * sizeof(double));
         c.xsol.ensure((size_t)3 * c.Ctot * sizeof(double));
-        std::vector<int> tdrop(c.T), noff(c.nd), ncnt(c.nd), unoff(c.nd), uncnt(c.nd);
+        HVec<int> &tdrop = c.h_tdrop, &noff = c.h_noff, &ncnt = c.h_ncnt, &unoff = c.h_unoff, &uncnt = c.h_uncnt;
+        tdrop.resize(c.T);
+        noff.resize(c.nd);
+        ncnt.resize(c.nd);
+        unoff.resize(c.nd);
+        uncnt.resize(c.nd);
         for (int i = 0; i < c.nd; ++i) {
             for (int t = 0; t < npts(ds[i].p); ++t) tdrop[ds[i].toff + t] = i;
             noff[i] = (int)ds[i].toff;
@@ -2840,31 +2859,25 @@ int bim_set_drops(bim_ctx h, int n_drops, const int *p, const double *xcoef, con
             uncnt[i] = npts(ds[i].qu);
         }
         c.sys_h.assign(c.nd, 0);
-        c.sysd.ensure(c.nd * sizeof(int));
-        HIPC(hipMemcpyAsync(c.sysd.ptr, c.sys_h.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        c.tdrop.ensure(c.T * sizeof(int));
-        c.noff.ensure(c.nd * sizeof(int));
-        c.ncnt.ensure(c.nd * sizeof(int));
-        HIPC(hipMemcpyAsync(c.tdrop.ptr, tdrop.data(), c.T * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipMemcpyAsync(c.noff.ptr, noff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipMemcpyAsync(c.ncnt.ptr, ncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        std::vector<double> hfac(c.nd);
-        for (int i = 0; i < c.nd; ++i) hfac[i] = kPi / (ds[i].p + 1);
-        c.hfac.ensure(c.nd * sizeof(double));
-        HIPC(hipMemcpyAsync(c.hfac.ptr, hfac.data(), c.nd * sizeof(double), hipMemcpyHostToDevice, c.stream));
-        c.unoff.ensure(c.nd * sizeof(int));
-        c.uncnt.ensure(c.nd * sizeof(int));
-        HIPC(hipMemcpyAsync(c.unoff.ptr, unoff.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
-        HIPC(hipMemcpyAsync(c.uncnt.ptr, uncnt.data(), c.nd * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        c.h_sys.assign(c.nd, 0);
+        up(c.sysd, c.h_sys);
+        up(c.tdrop, tdrop);
+        up(c.noff, noff);
+        up(c.ncnt, ncnt);
+        c.h_hfac.resize(c.nd);
+        for (int i = 0; i < c.nd; ++i) c.h_hfac[i] = kPi / (ds[i].p + 1);
+        up(c.hfac, c.h_hfac);
+        up(c.unoff, unoff);
+        up(c.uncnt, uncnt);
         // Galerkin operator diagonal (lambda_i + 1)
-        std::vector<double> scl((size_t)3 * c.Ctot);
+        HVec<double> &scl = c.h_scl;
+        scl.resize((size_t)3 * c.Ctot);
         for (int comp = 0; comp < 3; ++comp)
             for (int i = 0; i < c.nd; ++i)
                 for (long e = 0; e < 2L * ncoef(ds[i].p); ++e) scl[comp * c.Ctot + ds[i].coff + e] = ds[i].lam + 1.0;
-        c.scl.ensure(scl.size() * sizeof(double));
-        HIPC(hipMemcpyAsync(c.scl.ptr, scl.data(), scl.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-        c.gU.ensure(9 * sizeof(double));
-        HIPC(hipMemcpyAsync(c.gU.ptr, c.gradU, 9 * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        up(c.scl, scl);
+        c.h_gU.assign(c.gradU, c.gradU + 9);
+        up(c.gU, c.h_gU);
         invalidate(c);
         // tables for every grid in use
         for (auto &d : ds) {
