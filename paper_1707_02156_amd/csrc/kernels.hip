@@ -611,7 +611,7 @@ __device__ inline void pair_item64(const PairWork &w, int item, int tile, const 
 // targets per lane, remainder items (flag kPairSmall, at most 64 targets)
 // with one. The item index is uniform over the wavefront, so the branch is.
 template <int KIND, int T>
-__global__ __launch_bounds__(64 * kPairWaves) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
+__global__ __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(T == 1 ? 1 : 6, 8))) void k_pair(const PairWork *__restrict__ work, int nwork, int item0,
                                                          int tile, const int *__restrict__ tlist,
                                                          const double *__restrict__ tx, long tstride, PairSrc g0,
                                                          PairSrc g1, double *__restrict__ part)
