@@ -70,7 +70,7 @@ __device__ inline void stage_rot(const double *__restrict__ Ap, const double *__
 
 constexpr int kRotMaxPad = 64;  // degree p <= 63
 
-__global__ __launch_bounds__(256) void k_rot_mfma(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_rot_mfma(int p, const double *__restrict__ Ap, const double *__restrict__ Am,
                                                   const double *__restrict__ csp, const double *__restrict__ xc0,
                                                   long xstride, const double *__restrict__ dc0, long dstride,
                                                   PipeDrops pd, int u0, double *__restrict__ Bx,
@@ -165,7 +165,7 @@ struct LegBatch {
 };
 
 template <int MT>
-__global__ __launch_bounds__(256) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_leg_mfma(const LegBatch *__restrict__ bt, const double *__restrict__ tab,
                                                   const double *__restrict__ in, double *__restrict__ out, long NC)
 {
     __shared__ double sT[MT * 16 * 53];   // rows padded to MT*16, depth padded to 4 (up to 52), odd row stride
@@ -595,7 +595,7 @@ __global__ void k_pole(int p, int nt, const double *__restrict__ Bx, long NC, do
 // both results of one (nu, col) land in the same lane, which writes
 // M[t][pair][2 tri(n,nu)] = alpha cos(nu phi_k) + beta sin, [+1] = -alpha sin + beta cos.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adjrot_mfma(int p, const double *__restrict__ Ap,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_adjrot_mfma(int p, const double *__restrict__ Ap,
                                                      const double *__restrict__ Am, const double *__restrict__ csp,
                                                      const double *__restrict__ Bt, long NC12, PipeDrops pd,
                                                      int u0)
