@@ -2607,6 +2607,9 @@ template <class F> static int guarded(Ctx *c, F &&f)
     if (!c) return BIM_EINVAL;
     try {
         HIPC(hipSetDevice(c->device));
+        // work left on the second stream by a call that failed midway is
+        // ordered before anything this call enqueues
+        join_side(*c);
         int rc = f();
         if (rc == BIM_OK) c->err.clear();
         return rc;

@@ -498,3 +498,33 @@ def test_inverted_drop_is_rejected(B, nd):
         c.eval_velocity()
     assert e.value.status == B.BIM_EINVAL and "volume" in str(e.value)
     c.close()
+
+
+def test_context_recovers_after_a_rejected_evaluation(B):
+    """An evaluation rejected midway (an inverted drop next to a valid one,
+    found after the singular pipeline has been started on the context's
+    second stream) leaves the context usable: the next evaluation of valid
+    drops equals a fresh context's bit for bit."""
+    print("recovery after a rejected evaluation", flush=True)
+    bad = W.sphere(8).copy()
+    bad[0] *= -1.0
+    good = [W.sphere(8, 1.0, (0.0, 0.0, 0.0)), W.sphere(8, 0.9, (2.6, 0.3, 0.0))]
+    lam = [2.0, 5.0]
+
+    def ev(c):
+        c.set_drops([8, 8], good, lam)
+        c.set_tension(None, 0)
+        return c.eval_velocity(coefficients=True)[0]
+
+    c = B.Context(pair_tune=0, xform_path=1)
+    c.set_drops([8, 8], [bad, good[1]], lam)
+    c.set_tension(None, 0)
+    with pytest.raises(B.BimError) as e:
+        c.eval_velocity()
+    assert e.value.status == B.BIM_EINVAL
+    u = ev(c)
+    c.close()
+    c = B.Context(pair_tune=0, xform_path=1)
+    ref = ev(c)
+    c.close()
+    assert all(np.array_equal(a, b) for a, b in zip(u, ref))
