@@ -433,7 +433,7 @@ def main():
                          "size against which the HBM byte counters are scaled)")
     ap.add_argument("--serve", action="store_true", help="run the serving stream instead of the step benchmark")
     ap.add_argument("--requests", type=int, default=2048)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--rate-factor", type=float, default=0.8)
     ap.add_argument("--capacity-sample", type=int, default=128)
     ap.add_argument("--max-batch", type=int, default=16)

@@ -356,7 +356,10 @@ int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, 
  * resident between requests. A queued request is admitted, first come first
  * served, when a slot is free and its estimated device memory
  * (bim_server_footprint) fits in hbm_budget_gb next to the running requests;
- * the device work of admitted requests overlaps. With max_batch > 1 a free
+ * the device work of admitted requests overlaps (three slots by default: on
+ * the serving stream of 1-8 drops of degree 8-32 they keep the median latency
+ * of four and a lower tail, since a large request shares the device with
+ * fewer others). With max_batch > 1 a free
  * slot also takes further queued requests of the same tension parameters and
  * solves them together as independent systems (bim_set_systems): each
  * result then meets gmres_tol on its own but differs from the result of the
@@ -365,7 +368,7 @@ int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, 
 typedef struct bim_server_s *bim_server;
 
 typedef struct {
-    int slots;              /* concurrent batches, 1..64 (default 4) */
+    int slots;              /* concurrent batches, 1..64 (default 3) */
     double hbm_budget_gb;   /* admission budget, GB of estimated device memory (default 64) */
     bim_options opt;        /* options of every context; opt.stream must be NULL */
     int max_batch;          /* requests a free slot takes from the queue at once, run as independent
@@ -377,7 +380,7 @@ typedef struct {
                                default) */
 } bim_server_options;
 
-/* Defaults: 4 slots, 64 GB, max_batch 1, max_batch_drops 128, max_queue 0, opt from
+/* Defaults: 3 slots, 64 GB, max_batch 1, max_batch_drops 128, max_queue 0, opt from
  * bim_default_options with pair_tune 0 and xform_path 1 (no timing of work
  * shapes on the request path) and pipe_budget_gb 0.75. */
 int bim_server_default_options(bim_server_options *opt);

@@ -491,7 +491,7 @@ class Server:
     for their velocities. Options: slots, hbm_budget_gb, and any context
     option by name."""
 
-    def __init__(self, slots=4, hbm_budget_gb=64.0, max_batch=1, max_batch_drops=128, max_queue=0, **opts):
+    def __init__(self, slots=3, hbm_budget_gb=64.0, max_batch=1, max_batch_drops=128, max_queue=0, **opts):
         so = bim_server_options()
         _check(None, lib().bim_server_default_options(ctypes.byref(so)))
         so.slots = slots

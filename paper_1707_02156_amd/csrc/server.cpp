@@ -221,7 +221,7 @@ int bim_server_default_options(bim_server_options *o)
 {
     if (!o) return BIM_EINVAL;
     std::memset(o, 0, sizeof(*o));
-    o->slots = 4;
+    o->slots = 3;
     o->hbm_budget_gb = 64.0;
     o->max_batch = 1;
     o->max_batch_drops = 128;

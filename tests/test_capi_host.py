@@ -43,7 +43,7 @@ def test_status_strings_and_defaults(B):
     import ctypes
     so = B.bim_server_options()
     assert B.lib().bim_server_default_options(ctypes.byref(so)) == B.BIM_OK
-    assert so.slots == 4 and so.max_batch == 1 and so.max_queue == 0
+    assert so.slots == 3 and so.max_batch == 1 and so.max_queue == 0
     assert so.opt.pair_tune == 0 and so.opt.xform_path == 1 and so.opt.pipe_budget_gb == 0.75
 
 
