@@ -328,8 +328,9 @@ int bim_sh_analyze(bim_ctx ctx, int q, int p, int nf, const double *grid, double
 /* Block until all work queued by the context is complete. */
 int bim_synchronize(bim_ctx ctx);
 
-/* Kernel timing: HIP events recorded on the context stream around each launch
- * of the main kernels. enable = 1 clears the totals and starts recording,
+/* Kernel timing: HIP events recorded around each launch of the main kernels,
+ * on the stream the launch goes to (the context stream; the singular pipeline
+ * of a velocity evaluation runs on a second stream of the context). enable = 1 clears the totals and starts recording,
  * 0 stops. Kernel names: "pipe_rotate", "pipe_legendre", "pipe_fourier",
  * "pipe_adjrot" (batched singular pipeline), "sing_fused" (fused singular
  * rule), "sing_rotate" and "sing_v1" (per-application singular path),
@@ -345,7 +346,7 @@ int bim_profile(bim_ctx ctx, int enable);
 int bim_profile_select(bim_ctx ctx, const char *names);
 /* Totals since the last enable: launches, summed event time (ms), algorithmic
  * flops and bytes of those launches. Unknown names give zeros. Synchronizes
- * the context stream. */
+ * the context's streams. */
 int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, double *flops, double *bytes);
 
 /* ------------------------------------------------------------------------
