@@ -266,10 +266,12 @@ def test_double_layer_raw_three_drops(B, orc, path):
 
 
 @pytest.mark.parametrize("p,us", [(5, 1), (11, 2), (24, 1)])
-def test_fused_single_and_double_layer_degrees(B, orc, p, us):
-    """Fused kernel for odd and even degrees and an upsampled singular grid
-    (U_sing = 2): single layer and raw double layer against the oracle."""
-    print(f"fused p={p} U_sing={us}", flush=True)
+def test_singular_path_single_and_double_layer_degrees(B, orc, p, us):
+    """The default singular path (the batched pipeline) for an odd singular
+    grid (p = 5, qs = 5: no longitude pairs folded in the Fourier stage), an
+    upsampled one (U_sing = 2) and an even one: single layer and raw double
+    layer against the oracle."""
+    print(f"singular path p={p} U_sing={us}", flush=True)
     rng = np.random.default_rng(500 + p)
     wl = W.single_drop(p=p, seed=60 + p)
     wl.U_sing = us
