@@ -353,8 +353,10 @@ int bim_profile_query(bim_ctx ctx, const char *name, int *launches, double *ms, 
  * Request server: independent drop systems (each a full velocity
  * evaluation, bim_eval_velocity) submitted at any time and run concurrently.
  * The server holds `slots` contexts, each with its own HIP stream (default
- * priority) and host worker thread; the per-degree tables of a context stay
- * resident between requests. A queued request is admitted, first come first
+ * priority) and host worker thread; the per-degree tables of a context and
+ * its device buffers stay resident between requests (buffers grow to the
+ * largest request a slot has served and are not freed until the server is
+ * destroyed; the admission budget counts each running request's estimate). A queued request is admitted, first come first
  * served, when a slot is free and its estimated device memory
  * (bim_server_footprint) fits in hbm_budget_gb next to the running requests;
  * the device work of admitted requests overlaps (three slots by default: on
